@@ -1,0 +1,221 @@
+"""VOctree rendering benchmark on one MI355X.
+
+Default workload: the forward-render configuration at full size: a depth-9
+VOctree (~2M occupied leaves from 12 seeded ellipsoids forming a human-sized
+blob), 16 HH coefficients x 3 channels + 8 density weights per leaf, density
+basis [300 x 8], a ring of 8 cameras at 1920x1080 (16.6 M rays), one seeded
+time per ring, FP32 storage, early stop at T < 1e-4. All inputs are seeded
+and synthetic and resident in HBM before timing.
+
+One step = the whole hot path over the ring: render forward (ray setup,
+octree traversal, leaf evaluation, compositing, outputs) and the adjoint
+(replay + atomic scatter into leaf coefficients and the density basis) for a
+seeded upstream gradient. `value` = rays per step / step time (Mrays/s,
+fwd+bwd); the forward-only rate is reported beside it.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mrays/s fwd and fwd+bwd at 1080p; achieved HBM GB/s vs peak; PSNR vs FP64"
+PEAK_HBM_GBS = 8000.0
+FWD_PAYLOAD_B = {0: 224, 1: 112, 2: 112}    # per sample: 48 HH + 8 density values
+FWD_RAY_IO_B = 24 + 24                      # o, d in; rgb, alpha, depth, nsamp out
+BWD_RAY_IO_B = 24 + 20 + 12                 # o, d; rgb, alpha, nsamp; grad_rgb
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("render.hip", "neuvv_device.h"):
+        with open(os.path.join(ROOT, "paper_2202_06088_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was
+    taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    e = rec.get(workload, {}).get(kernel)
+    if not e or e.get("source_hash") != kernel_source_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--dtype", choices=["f32", "f16", "bf16"], default="f32")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}). "
+              "Rays are independent, so N GPUs would each render a share of the ring; run with --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2202_06088_amd import _lib, ops
+    from paper_2202_06088_amd.voctree import VOctree
+    from workloads import ring_cameras, scene_for_config
+
+    dt = {"f32": _lib.F32, "f16": _lib.F16, "bf16": _lib.BF16}[args.dtype]
+    t0 = time.time()
+    log("generating the depth-9 humanoid scene (seeded)")
+    sc = scene_for_config(2)
+    cams = ring_cameras(sc, 8, 1920, 1080, 40.0, 10.0, seed=2)
+    t_frame = float(np.random.default_rng(2002).uniform(0, sc.T))
+    log(f"scene: {sc.n_leaves} leaves, T={sc.T}, t={t_frame:.3f} ({time.time() - t0:.1f}s)")
+    dev = "cuda"
+    tree = VOctree.build(sc.depth, sc.leaf_ijk, sc.hh, sc.wsig, sc.basis, sc.gamma, dt, dev)
+    W, H = 1920, 1080
+    n_cam = W * H
+    n = 8 * n_cam
+    ray_o = torch.empty(n, 3, device=dev)
+    ray_d = torch.empty(n, 3, device=dev)
+    for i, c in enumerate(cams):
+        cs = _lib.make_camera(c.width, c.height, c.fx, c.fy, c.cx, c.cy, c.c2w)
+        _lib.neuvv_pinhole_rays(cs, n_cam, None, ray_o[i * n_cam:(i + 1) * n_cam], ray_d[i * n_cam:(i + 1) * n_cam])
+    rgb = torch.empty(n, 3, device=dev)
+    alpha = torch.empty(n, device=dev)
+    depth = torch.empty(n, device=dev)
+    nsamp = torch.empty(n, dtype=torch.int32, device=dev)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(2003)
+    g_rgb = torch.randn(n, 3, device=dev, generator=gen)
+    grads = tree.zero_grads()
+    stream = torch.cuda.current_stream()
+    t_stop = 1e-4
+
+    def fwd():
+        _lib.neuvv_render(tree.struct(), None, n, ray_o, ray_d, None, t_frame, W, t_stop, rgb, alpha, depth, nsamp,
+                          stream)
+
+    def bwd():
+        _lib.neuvv_render_backward(tree.struct(), None, n, ray_o, ray_d, None, t_frame, W, t_stop, rgb, alpha, nsamp,
+                                   g_rgb, None, grads[0], grads[1], grads[2], stream)
+
+    log(f"warmup {args.warmup} steps")
+    for _ in range(args.warmup):
+        fwd()
+        bwd()
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    log(f"timing {args.steps} steps")
+    torch.cuda.synchronize()
+    h0 = time.perf_counter()
+    for s in range(args.steps):
+        ev[s][0].record(stream)
+        fwd()
+        ev[s][1].record(stream)
+        bwd()
+        ev[s][2].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - h0
+    fwd_ms = float(np.mean([ev[s][0].elapsed_time(ev[s][1]) for s in range(args.steps)]))
+    bwd_ms = float(np.mean([ev[s][1].elapsed_time(ev[s][2]) for s in range(args.steps)]))
+    ms_step = wall * 1e3 / args.steps
+    ns = nsamp.cpu().numpy().astype(np.int64)
+    total_samples = int(ns.sum())
+    hit = int((ns > 0).sum())
+    fwd_bytes = total_samples * FWD_PAYLOAD_B[dt] + n * FWD_RAY_IO_B
+    bwd_bytes = total_samples * (FWD_PAYLOAD_B[dt] + 448) + n * BWD_RAY_IO_B
+    log(f"fwd {fwd_ms:.3f} ms, bwd {bwd_ms:.3f} ms per launch; step {ms_step:.3f} ms; "
+        f"{total_samples} samples, {hit} hit rays")
+    kern = {"render_fwd": (fwd_ms, fwd_bytes), "render_bwd": (bwd_ms, bwd_bytes)}
+    dom = max(kern, key=lambda k: kern[k][0])
+    dms, dbytes = kern[dom]
+    achieved = dbytes / (dms * 1e-3) / 1e9
+    workload = "forward_ring_d9_2M_8x1080p"
+    roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(dom, workload),
+            "algorithmic_bytes_per_launch": dbytes, "launch_ms": round(dms, 4)}
+    other = [k for k in kern if k != dom][0]
+    roof_other = {"kernel": other, "achieved": round(kern[other][1] / (kern[other][0] * 1e-3) / 1e9, 1),
+                  "launch_ms": round(kern[other][0], 4), "algorithmic_bytes_per_launch": kern[other][1],
+                  "traffic": measured_traffic(other, workload)}
+
+    result = {
+        "metric": METRIC, "value": round(n / (ms_step * 1e-3) / 1e6, 2), "unit": "Mrays/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
+        "config": {"workload": workload, "depth": sc.depth, "leaves": sc.n_leaves, "K": sc.K, "C": sc.C,
+                   "T": sc.T, "rays_per_step": n, "image": "8 x 1920x1080", "t_stop": t_stop,
+                   "step": "render fwd + adjoint"},
+        "fwd_mrays_s": round(n / (fwd_ms * 1e-3) / 1e6, 2),
+        "samples_per_step": total_samples, "hit_rays": hit,
+        "roofline": roof, "roofline_other_kernel": roof_other,
+    }
+
+    if not args.no_cpu_baseline:
+        result.update(cpu_leg(sc, cams, t_frame, t_stop, rgb, g_rgb, grads, tree, args.cpu_seconds))
+    print(json.dumps(result), flush=True)
+
+
+def cpu_leg(sc, cams, t_frame, t_stop, rgb_gpu, g_rgb, grads, tree, budget_s):
+    """FP64 oracle (as written, untuned) on a strided sample of camera 0's rays, forward +
+    gradient, on the host cores; also the GPU's error against it on those rays."""
+    from oracle import core as OC
+    W, H = 1920, 1080
+    cam = cams[0]
+    threads = OC.default_threads()
+    OC.build(force=False)
+
+    def run(stride, offset=0):
+        pix = np.arange(offset, W * H, stride, dtype=np.int32)
+        o, d = OC.pinhole_rays(W, H, cam.intr(), cam.c2w, pix)
+        g = g_rgb[:W * H][pix.astype(np.int64)].cpu().numpy().astype(np.float64)
+        t1 = time.perf_counter()
+        ref = OC.render(sc.depth, sc.leaf_ijk, sc.hh, sc.wsig, sc.basis, sc.gamma, o, d, None, t_frame, t_stop,
+                        g_rgb=g, threads=threads)
+        return pix, ref, time.perf_counter() - t1
+
+    log(f"cpu baseline pilot ({threads} threads)")
+    pix, ref, dt = run(997)
+    rate = len(pix) / max(dt, 1e-6)
+    stride = max(1, int(W * H / max(rate * budget_s, 1)))
+    log(f"pilot {len(pix)} rays in {dt:.2f}s; sample stride {stride}")
+    pix, ref, dt = run(stride, 1)
+    gpu = rgb_gpu[:W * H][pix.astype(np.int64)].cpu().numpy().astype(np.float64)
+    ok = ref["margin"][:, 1] >= 1e-4
+    err = np.abs(gpu - ref["rgb"])[ok]
+    mse = float(np.mean(err ** 2)) if err.size else 0.0
+    psnr = 10 * math.log10(1.0 / mse) if mse > 0 else float("inf")
+    log(f"oracle {len(pix)} rays fwd+grad in {dt:.2f}s; GPU max-abs {err.max(initial=0):.3e} PSNR {psnr:.1f} dB")
+    return {
+        "cpu_baseline": {"value": round(len(pix) / dt / 1e6, 5), "unit": "Mrays/s", "cores": threads,
+                         "kind": "oracle",
+                         "sample": f"every {stride}th pixel of camera 0 ({len(pix)} rays), FP64 forward + gradient"},
+        "psnr_vs_fp64_db": None if math.isinf(psnr) else round(psnr, 2),
+        "maxabs_vs_fp64": float(f"{err.max(initial=0):.3e}"),
+        "fp64_compare_rays": int(ok.sum()),
+    }
+
+
+if __name__ == "__main__":
+    main()

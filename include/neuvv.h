@@ -1,0 +1,269 @@
+/*
+ * neuvv.h - C ABI of libneuvv.so, a VOctree renderer for MI355X (gfx950).
+ *
+ * Implements the rendering hot path of NeuVV (arXiv 2202.06088): a Video
+ * Octree (VOctree) whose leaves hold hyperspherical-harmonic (HH) colour
+ * coefficients and density weights on a shared temporal basis, rendered per
+ * ray by octree traversal and front-to-back compositing (Sec. 4.3), its
+ * adjoint (Sec. 4.3 "Optimization"), instance placement and re-timing
+ * (Sec. 5.1, Eq. 13) and depth-aware blending of rendered layers (Alg. 1).
+ *
+ * Conventions shared by every call
+ *   - Pointers named "device" are HIP device pointers owned by the caller;
+ *     pointers named "host" are host memory owned by the caller. The library
+ *     keeps no pointer after a call returns and allocates no device memory.
+ *   - "stream" is a hipStream_t (NULL = the null stream). GPU work is queued
+ *     on it asynchronously; the caller synchronises. Argument errors are
+ *     detected on the host before anything is queued.
+ *   - Every call returns NEUVV_OK (0) or a negative neuvv_status; then
+ *     neuvv_last_error() gives a message (thread-local, valid until the next
+ *     call on the same thread). No C++ exception crosses this boundary.
+ *   - Floating-point outputs are float32; integer outputs int32/int64.
+ *   - Gradient outputs accumulate (+=) into caller-zeroed float32 buffers, so
+ *     several instances of one tree (Sec. 5.1, "varied manifestations") sum
+ *     their gradients into the same leaves.
+ */
+#ifndef NEUVV_H
+#define NEUVV_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    NEUVV_OK = 0,
+    NEUVV_ERR_ARG = -1,         /* null pointer, negative size, bad enum */
+    NEUVV_ERR_RANGE = -2,       /* a value outside its documented range */
+    NEUVV_ERR_DUPLICATE = -3,   /* the same leaf cell listed twice */
+    NEUVV_ERR_CAPACITY = -4,    /* an output buffer smaller than required */
+    NEUVV_ERR_UNSUPPORTED = -5, /* K, C or dtype without a compiled kernel */
+    NEUVV_ERR_HIP = -6          /* a HIP launch or runtime error */
+} neuvv_status;
+
+/* Storage type of the leaf coefficients. Evaluation and compositing are
+   always float32; 16-bit storage is converted with round-to-nearest-even. */
+typedef enum { NEUVV_F32 = 0, NEUVV_F16 = 1, NEUVV_BF16 = 2 } neuvv_dtype;
+
+/*
+ * Leaf payload layout ("16-byte-vector structure of arrays").
+ * A leaf has R_hh = 3K colour coefficients, value r = ch*K + k for colour
+ * channel ch and HH function k (Eq. 5), and R_sig = C density weights
+ * (Eq. 8). Let V = 16 / sizeof(element) (4 for float32, 8 for 16-bit). The
+ * values of all leaves are stored as
+ *     hh  [ceil(R_hh / V)][n_leaves][V]
+ *     wsig[ceil(R_sig / V)][n_leaves][V]
+ * i.e. value r of leaf slot s lives at element (r / V) * n_leaves * V + s * V
+ * + r % V; padding values (r >= R) are zero. A wavefront whose lanes visit
+ * neighbouring leaf slots reads one contiguous run of 16-byte vectors per
+ * vector index. Gradients use the same layout with float32 (V = 4).
+ * neuvv_payload_words() gives the sizes; neuvv_pack_leaves() fills them.
+ */
+
+/* A built tree on the device. All pointers are device pointers. */
+typedef struct {
+    int32_t depth;        /* D in [1, 12]: leaf grid [0, 2^D)^3 in tree-local units */
+    int32_t K;            /* HH functions per colour channel (compiled: 16) */
+    int32_t C;            /* density basis size (compiled: 8) */
+    int32_t dtype;        /* neuvv_dtype of hh and wsig */
+    int64_t n_nodes;      /* rows of child */
+    int64_t n_leaves;     /* leaf slots */
+    const int32_t* child; /* [n_nodes][8] from neuvv_build_voctree */
+    const void* hh;       /* colour coefficients, layout above */
+    const void* wsig;     /* density weights, layout above */
+    int32_t T;            /* frames of the temporal tables */
+    const float* basis;   /* [T][C] density basis, row t = frame t (Eq. 8: A transposed) */
+    const float* gamma;   /* [T] hyperangle per frame, in [0, pi] (Eq. 5's gamma(t)) */
+} neuvv_tree;
+
+/* Placement and re-timing of one tree instance (Eq. 13). A world point x is
+   the tree-local point R^T (x - trans) / scale (R = rot, row-major 3x3,
+   orthonormal); a world time t is the tree-local time tau = t + time_offset,
+   wrapped into [0, T) when time_wrap != 0 (looping) and clamped into
+   [0, T-1] otherwise. NULL instance = identity rotation, zero translation,
+   scale 1, no offset, clamping. */
+typedef struct {
+    float rot[9];
+    float trans[3];
+    float scale;
+    float time_offset;
+    int32_t time_wrap;
+} neuvv_instance;
+
+/* Pinhole camera, OpenCV axes (x right, y down, z forward), pixel (u, v)
+   centred at (u + 0.5, v + 0.5); c2w is the row-major 3x4 camera-to-world
+   matrix [R | centre]. */
+typedef struct {
+    int32_t width, height;
+    float fx, fy, cx, cy;
+    float c2w[12];
+} neuvv_camera;
+
+/*
+ * neuvv_build_voctree - host-side construction of the sparse octree over
+ * the occupied leaf cells (Sec. 4.3 "Initialization" leaves the voxels with
+ * non-negligible density; this call receives them as a list of cells).
+ *
+ * depth           D in [1, 12].
+ * n_leaves        number of cells, >= 0.
+ * leaf_ijk        host [n_leaves][3] int32, each in [0, 2^D); no duplicates.
+ * child           host [node_capacity][8] int32 output, or NULL to only count.
+ *                 Node 0 is the root; nodes are stored level by level from
+ *                 the root (breadth first), Morton order within a level.
+ *                 child[n][o] for octant o = (i&1) | (j&1)<<1 | (k&1)<<2 of
+ *                 the cell bits at that level: -1 for an empty octant, else
+ *                 the child node index, or at the last level the leaf slot.
+ * node_capacity   rows available in child (ignored when child is NULL).
+ * n_nodes_out     host output, the number of nodes (always written on OK).
+ * slot_of_input   host [n_leaves] int64 output or NULL: the leaf slot
+ *                 (rank in Morton order) of input cell i.
+ * Errors: ARG (null leaf_ijk with n_leaves > 0, null n_nodes_out), RANGE
+ * (depth, coordinates), DUPLICATE, CAPACITY (node_capacity < n_nodes).
+ */
+int neuvv_build_voctree(int32_t depth, int64_t n_leaves, const int32_t* leaf_ijk, int32_t* child,
+                        int64_t node_capacity, int64_t* n_nodes_out, int64_t* slot_of_input);
+
+/*
+ * neuvv_payload_words - element counts of the payload arrays for n_leaves
+ * leaves: *hh_elems = ceil(3K/V)*n_leaves*V, *wsig_elems = ceil(C/V)*n_leaves*V
+ * for the storage dtype (V = 4 for float32, 8 for 16-bit). Host only.
+ */
+int neuvv_payload_words(int32_t K, int32_t C, int32_t dtype, int64_t n_leaves, int64_t* hh_elems,
+                        int64_t* wsig_elems);
+
+/*
+ * neuvv_pack_leaves - convert leaf coefficients given per input leaf into
+ * the payload layout above, in Morton slot order and in the storage dtype
+ * (round to nearest even for 16-bit).
+ * hh_in           device [n_leaves][3][K] float32, input leaf order.
+ * wsig_in         device [n_leaves][C] float32, input leaf order.
+ * slot_of_input   device [n_leaves] int64 from neuvv_build_voctree, or NULL
+ *                 when the inputs are already in slot order.
+ * hh_out, wsig_out device outputs of neuvv_payload_words() elements; the
+ *                 padding elements are written with zero.
+ * Errors: ARG, UNSUPPORTED (dtype).
+ */
+int neuvv_pack_leaves(int32_t K, int32_t C, int32_t dtype, int64_t n_leaves, const float* hh_in,
+                      const float* wsig_in, const int64_t* slot_of_input, void* hh_out, void* wsig_out,
+                      void* stream);
+
+/*
+ * neuvv_render - volume rendering of a VOctree along n rays (Sec. 4.3
+ * "Rendering", Eq. 5, 8, 10, 11).
+ *
+ * For ray r with world origin o, direction d (need not be unit) and time t:
+ * the tree-local ray is x_l(u) = R^T (o + u d - trans) / scale, u >= 0; the
+ * leaves it crosses are found by descending the octree, empty space being
+ * skipped one empty node at a time; delta is the length of the ray inside a
+ * leaf in leaf units (cells are half-open [i, i+1); zero-length crossings are
+ * not samples). Per ray: h = the first K real HH at the unit local view
+ * direction and gamma(tau), b = the density basis at tau, both linearly
+ * interpolated between frames floor(tau) and floor(tau)+1 (the last frame
+ * is held on [T-1, T)). Per sample in front-to-back order:
+ *     sigma = softplus(sum_c wsig_c b_c),  c_ch = sigmoid(sum_k hh_ch,k h_k),
+ *     a = 1 - exp(-sigma delta), w = T a, rgb += w c, T *= exp(-sigma delta),
+ * stopping after the first sample that leaves T < t_stop (t_stop = 0 never
+ * stops early). The K = 16 HH functions are n <= 2 (14) then (3,0,0), (3,1,-1)
+ * in the order n, l, m.
+ *
+ * tree            device tree (pointer to a host struct).
+ * inst            host struct or NULL (identity).
+ * n_rays          >= 0.
+ * ray_o, ray_d    device [n][3] world origins and directions.
+ * ray_t           device [n] world times, or NULL to use t_scalar for all.
+ * image_width     0, or W > 0 when rays are a row-major image W pixels wide:
+ *                 each wavefront then takes 8x8 pixel tiles (coherence hint,
+ *                 results are identical).
+ * t_stop          early-termination threshold on transmittance, >= 0.
+ * rgb             device [n][3] premultiplied colour (Eq. 10).
+ * alpha           device [n] 1 - T_final = sum of weights (Eq. 11).
+ * depth           device [n] or NULL: sum(w * s_mid) / sum(w), s_mid the world
+ *                 distance |d| u of the segment midpoint; +inf if sum(w) = 0.
+ * nsamp           device [n] int32 samples composited (needed by backward).
+ * Errors: ARG, RANGE, UNSUPPORTED, HIP.
+ */
+int neuvv_render(const neuvv_tree* tree, const neuvv_instance* inst, int64_t n_rays, const float* ray_o,
+                 const float* ray_d, const float* ray_t, float t_scalar, int32_t image_width, float t_stop,
+                 float* rgb, float* alpha, float* depth, int32_t* nsamp, void* stream);
+
+/*
+ * neuvv_render_backward - adjoint of neuvv_render (Sec. 4.3 "Optimization")
+ * for L = sum_r <grad_rgb_r, rgb_r> + grad_alpha_r alpha_r. Each ray replays
+ * its nsamp samples front to back with the transmittance recomputed (nothing
+ * per sample is stored by the forward pass):
+ *     dL/dsigma_k = delta_k (T_{k+1} <g, c_k> - <g, rgb - rgb_{<=k}>) + g_a delta_k T_final
+ *     dL/dz_k,ch  = g_ch w_k c_k,ch (1 - c_k,ch)
+ * and scatter-adds (atomically) into the leaf gradients and the basis rows.
+ * Arguments as neuvv_render, plus
+ * rgb, alpha, nsamp  device forward outputs for the same rays and inputs.
+ * grad_rgb        device [n][3]; grad_alpha device [n] or NULL (zero).
+ * grad_hh         device float32, hh layout with V = 4, accumulated (+=).
+ * grad_wsig       device float32, wsig layout with V = 4, accumulated.
+ * grad_basis      device [T][C] float32 accumulated, or NULL to skip.
+ * The gradient with respect to the gamma table is not computed.
+ * Errors: ARG, RANGE, UNSUPPORTED, HIP.
+ */
+int neuvv_render_backward(const neuvv_tree* tree, const neuvv_instance* inst, int64_t n_rays,
+                          const float* ray_o, const float* ray_d, const float* ray_t, float t_scalar,
+                          int32_t image_width, float t_stop, const float* rgb, const float* alpha,
+                          const int32_t* nsamp, const float* grad_rgb, const float* grad_alpha,
+                          float* grad_hh, float* grad_wsig, float* grad_basis, void* stream);
+
+/*
+ * neuvv_compose - depth-aware alpha blending of L rendered layers (Alg. 1),
+ * per pixel: sort the layers by depth (equal depth: the later layer is in
+ * front), then premultiplied "over":
+ *     out_rgb = sum_k prod_{j<k} (1 - A_j) P_k,  out_alpha = 1 - prod_k (1 - A_k),
+ *     out_depth = depth of the front layer.
+ * L in [1, 16]; rgb device [L][n][3] premultiplied; alpha, depth device
+ * [L][n]; outputs device [n][3], [n], [n] (out_depth may be NULL).
+ * Errors: ARG, RANGE, HIP.
+ */
+int neuvv_compose(int32_t L, int64_t n_pix, const float* rgb, const float* alpha, const float* depth,
+                  float* out_rgb, float* out_alpha, float* out_depth, void* stream);
+
+/*
+ * neuvv_compose_backward - gradient of <g_rgb, out_rgb> + <g_alpha, out_alpha>
+ * with respect to every layer's rgb and alpha (depth is a sort key and has
+ * none). grad_rgb device [L][n][3], grad_alpha device [L][n] are overwritten
+ * (not accumulated). grad_out_alpha may be NULL (zero).
+ * Errors: ARG, RANGE, HIP.
+ */
+int neuvv_compose_backward(int32_t L, int64_t n_pix, const float* rgb, const float* alpha,
+                           const float* depth, const float* grad_out_rgb, const float* grad_out_alpha,
+                           float* grad_rgb, float* grad_alpha, void* stream);
+
+/*
+ * neuvv_pinhole_rays - world rays of a pinhole camera: origin = camera
+ * centre, direction = normalize(R (x_c, y_c, 1)) with x_c = (u + 0.5 - cx)/fx,
+ * y_c = (v + 0.5 - cy)/fy, computed in compensated float32 arithmetic and
+ * rounded once (agrees with the correctly rounded result except within
+ * about 2^-40 relative of a rounding boundary).
+ * cam             host struct. n >= 0.
+ * pix             device [n] int32 linear pixel indices v*W + u, or NULL for
+ *                 all W*H pixels in row-major order (then n must be W*H).
+ * ray_o, ray_d    device [n][3] outputs.
+ * Errors: ARG, RANGE, HIP.
+ */
+int neuvv_pinhole_rays(const neuvv_camera* cam, int64_t n, const int32_t* pix, float* ray_o, float* ray_d,
+                       void* stream);
+
+/*
+ * neuvv_eval_hh - the first K real HH (K in {1..30}) at unit directions
+ * dirs device [n][3] and hyperangles gam device [n] into out device [n][K]
+ * (the per-ray basis of Eq. 5; exposed for testing).
+ * Errors: ARG, RANGE, HIP.
+ */
+int neuvv_eval_hh(int32_t K, int64_t n, const float* dirs, const float* gam, float* out, void* stream);
+
+/* Thread-local message for the last non-OK return on this thread. */
+const char* neuvv_last_error(void);
+
+/* Library ABI version (major * 100 + minor). */
+int neuvv_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NEUVV_H */

@@ -1,0 +1,272 @@
+// C ABI of libneuvv.so (declared in include/neuvv.h): argument validation,
+// dtype/K/C dispatch and error reporting around the kernels. Nothing here
+// allocates device memory or keeps pointers beyond a call.
+#include <hip/hip_runtime.h>
+#include <stdarg.h>
+#include <stdio.h>
+
+#include <cmath>
+#include <exception>
+#include <string>
+
+#include "../../include/neuvv.h"
+#include "launch.h"
+
+namespace neuvv {
+int build_voctree_host(int32_t depth, int64_t n, const int32_t* ijk, int32_t* child, int64_t capacity,
+                       int64_t* n_nodes_out, int64_t* slot_of_input, std::string& err);
+}
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_status(hipError_t e, const char* what) {
+    if (e == hipSuccess) return NEUVV_OK;
+    return fail(NEUVV_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+int check_tree(const neuvv_tree* t) {
+    if (!t) return fail(NEUVV_ERR_ARG, "tree is NULL");
+    if (t->depth < 1 || t->depth > neuvv::kMaxDepth) return fail(NEUVV_ERR_RANGE, "depth %d outside [1, 12]", t->depth);
+    if (t->dtype < 0 || t->dtype > 2) return fail(NEUVV_ERR_ARG, "unknown dtype %d", t->dtype);
+    if (!neuvv::render_supported(t->K, t->C, t->dtype))
+        return fail(NEUVV_ERR_UNSUPPORTED, "no kernel compiled for K=%d C=%d (have K=16, C=8)", t->K, t->C);
+    if (t->n_nodes < 1 || t->n_nodes > INT32_MAX) return fail(NEUVV_ERR_RANGE, "n_nodes %lld", (long long)t->n_nodes);
+    if (t->n_leaves < 0 || t->n_leaves > INT32_MAX)
+        return fail(NEUVV_ERR_RANGE, "n_leaves %lld", (long long)t->n_leaves);
+    if (t->T < 1) return fail(NEUVV_ERR_RANGE, "T = %d must be >= 1", t->T);
+    if (!t->child || !t->basis || !t->gamma) return fail(NEUVV_ERR_ARG, "tree child/basis/gamma pointer is NULL");
+    if (t->n_leaves > 0 && (!t->hh || !t->wsig)) return fail(NEUVV_ERR_ARG, "tree payload pointer is NULL");
+    return NEUVV_OK;
+}
+
+int make_inst(const neuvv_instance* in, neuvv::InstArgs& a) {
+    if (!in) {
+        for (int i = 0; i < 9; ++i) a.rot[i] = (i % 4 == 0) ? 1.0f : 0.0f;
+        a.trans[0] = a.trans[1] = a.trans[2] = 0.0f;
+        a.scale = 1.0f;
+        a.time_offset = 0.0f;
+        a.wrap = 0;
+        a.identity = 1;
+        return NEUVV_OK;
+    }
+    if (!(in->scale > 0.0f) || !std::isfinite(in->scale)) return fail(NEUVV_ERR_RANGE, "instance scale must be > 0");
+    if (!std::isfinite(in->time_offset)) return fail(NEUVV_ERR_RANGE, "instance time_offset must be finite");
+    for (int i = 0; i < 9; ++i) {
+        if (!std::isfinite(in->rot[i])) return fail(NEUVV_ERR_RANGE, "instance rotation must be finite");
+        a.rot[i] = in->rot[i];
+    }
+    for (int i = 0; i < 3; ++i) {
+        if (!std::isfinite(in->trans[i])) return fail(NEUVV_ERR_RANGE, "instance translation must be finite");
+        a.trans[i] = in->trans[i];
+    }
+    a.scale = in->scale;
+    a.time_offset = in->time_offset;
+    a.wrap = in->time_wrap != 0;
+    a.identity = 0;
+    return NEUVV_OK;
+}
+
+int make_rays(int64_t n, const float* o, const float* d, const float* t, float t_scalar, int32_t image_width,
+              neuvv::RayArgs& ra) {
+    if (n < 0) return fail(NEUVV_ERR_ARG, "n_rays < 0");
+    if (n > 0 && (!o || !d)) return fail(NEUVV_ERR_ARG, "ray_o / ray_d is NULL");
+    if (image_width < 0) return fail(NEUVV_ERR_RANGE, "image_width < 0");
+    if (!std::isfinite(t_scalar)) return fail(NEUVV_ERR_RANGE, "t_scalar must be finite");
+    ra.o = o;
+    ra.d = d;
+    ra.t = t;
+    ra.t_scalar = t_scalar;
+    ra.n = n;
+    ra.img_w = image_width;
+    if (image_width > 0) {
+        const int64_t rows = (n + image_width - 1) / image_width;
+        ra.tiles_x = (image_width + 7) / 8;
+        ra.n_slots = (int64_t)ra.tiles_x * ((rows + 7) / 8) * 64;
+    } else {
+        ra.tiles_x = 0;
+        ra.n_slots = n;
+    }
+    return NEUVV_OK;
+}
+
+neuvv::TreeArgs tree_args(const neuvv_tree* t) {
+    neuvv::TreeArgs a;
+    a.child = t->child;
+    a.hh = t->hh;
+    a.wsig = t->wsig;
+    a.basis = t->basis;
+    a.gamma = t->gamma;
+    a.n_nodes = t->n_nodes;
+    a.n_leaves = t->n_leaves;
+    a.depth = t->depth;
+    a.T = t->T;
+    return a;
+}
+
+}  // namespace
+
+#define NEUVV_GUARD_BEGIN try {
+#define NEUVV_GUARD_END                                                   \
+    }                                                                     \
+    catch (const std::exception& e) {                                     \
+        return fail(NEUVV_ERR_ARG, "internal exception: %s", e.what());   \
+    }                                                                     \
+    catch (...) {                                                         \
+        return fail(NEUVV_ERR_ARG, "internal exception");                 \
+    }
+
+extern "C" {
+
+int neuvv_version(void) { return 100; }
+
+const char* neuvv_last_error(void) { return g_err.c_str(); }
+
+int neuvv_build_voctree(int32_t depth, int64_t n_leaves, const int32_t* leaf_ijk, int32_t* child,
+                        int64_t node_capacity, int64_t* n_nodes_out, int64_t* slot_of_input) {
+    NEUVV_GUARD_BEGIN
+    if (depth < 1 || depth > neuvv::kMaxDepth) return fail(NEUVV_ERR_RANGE, "depth %d outside [1, 12]", depth);
+    if (n_leaves < 0) return fail(NEUVV_ERR_ARG, "n_leaves < 0");
+    if (n_leaves > 0 && !leaf_ijk) return fail(NEUVV_ERR_ARG, "leaf_ijk is NULL");
+    if (!n_nodes_out) return fail(NEUVV_ERR_ARG, "n_nodes_out is NULL");
+    std::string err;
+    const int rc = neuvv::build_voctree_host(depth, n_leaves, leaf_ijk, child, node_capacity, n_nodes_out,
+                                             slot_of_input, err);
+    if (rc != 0) return fail(rc, "%s", err.c_str());
+    return NEUVV_OK;
+    NEUVV_GUARD_END
+}
+
+int neuvv_payload_words(int32_t K, int32_t C, int32_t dtype, int64_t n_leaves, int64_t* hh_elems,
+                        int64_t* wsig_elems) {
+    if (K < 1 || K > 30 || C < 1 || C > 64) return fail(NEUVV_ERR_RANGE, "K in [1,30] and C in [1,64] required");
+    if (dtype < 0 || dtype > 2) return fail(NEUVV_ERR_ARG, "unknown dtype %d", dtype);
+    if (n_leaves < 0 || !hh_elems || !wsig_elems) return fail(NEUVV_ERR_ARG, "bad n_leaves or NULL output");
+    const int V = dtype == NEUVV_F32 ? 4 : 8;
+    *hh_elems = (int64_t)((3 * K + V - 1) / V) * n_leaves * V;
+    *wsig_elems = (int64_t)((C + V - 1) / V) * n_leaves * V;
+    return NEUVV_OK;
+}
+
+int neuvv_pack_leaves(int32_t K, int32_t C, int32_t dtype, int64_t n_leaves, const float* hh_in,
+                      const float* wsig_in, const int64_t* slot_of_input, void* hh_out, void* wsig_out,
+                      void* stream) {
+    NEUVV_GUARD_BEGIN
+    if (K < 1 || K > 30 || C < 1 || C > 64) return fail(NEUVV_ERR_RANGE, "K in [1,30] and C in [1,64] required");
+    if (dtype < 0 || dtype > 2) return fail(NEUVV_ERR_UNSUPPORTED, "unknown dtype %d", dtype);
+    if (n_leaves < 0) return fail(NEUVV_ERR_ARG, "n_leaves < 0");
+    if (n_leaves > 0 && (!hh_in || !wsig_in || !hh_out || !wsig_out)) return fail(NEUVV_ERR_ARG, "NULL buffer");
+    return hip_status(neuvv::launch_pack(K, C, dtype, n_leaves, hh_in, wsig_in, slot_of_input, hh_out, wsig_out,
+                                         (hipStream_t)stream),
+                      "pack_leaves launch");
+    NEUVV_GUARD_END
+}
+
+int neuvv_render(const neuvv_tree* tree, const neuvv_instance* inst, int64_t n_rays, const float* ray_o,
+                 const float* ray_d, const float* ray_t, float t_scalar, int32_t image_width, float t_stop,
+                 float* rgb, float* alpha, float* depth, int32_t* nsamp, void* stream) {
+    NEUVV_GUARD_BEGIN
+    int rc = check_tree(tree);
+    if (rc) return rc;
+    neuvv::InstArgs in;
+    if ((rc = make_inst(inst, in))) return rc;
+    neuvv::RayArgs ra;
+    if ((rc = make_rays(n_rays, ray_o, ray_d, ray_t, t_scalar, image_width, ra))) return rc;
+    if (!(t_stop >= 0.0f) || !std::isfinite(t_stop)) return fail(NEUVV_ERR_RANGE, "t_stop must be >= 0");
+    if (n_rays > 0 && (!rgb || !alpha || !nsamp)) return fail(NEUVV_ERR_ARG, "rgb / alpha / nsamp is NULL");
+    neuvv::RenderOut out{rgb, alpha, depth, nsamp};
+    return hip_status(neuvv::launch_render_fwd(tree->K, tree->C, tree->dtype, tree_args(tree), in, ra, t_stop, out,
+                                               (hipStream_t)stream),
+                      "render launch");
+    NEUVV_GUARD_END
+}
+
+int neuvv_render_backward(const neuvv_tree* tree, const neuvv_instance* inst, int64_t n_rays,
+                          const float* ray_o, const float* ray_d, const float* ray_t, float t_scalar,
+                          int32_t image_width, float t_stop, const float* rgb, const float* alpha,
+                          const int32_t* nsamp, const float* grad_rgb, const float* grad_alpha, float* grad_hh,
+                          float* grad_wsig, float* grad_basis, void* stream) {
+    NEUVV_GUARD_BEGIN
+    int rc = check_tree(tree);
+    if (rc) return rc;
+    neuvv::InstArgs in;
+    if ((rc = make_inst(inst, in))) return rc;
+    neuvv::RayArgs ra;
+    if ((rc = make_rays(n_rays, ray_o, ray_d, ray_t, t_scalar, image_width, ra))) return rc;
+    if (!(t_stop >= 0.0f) || !std::isfinite(t_stop)) return fail(NEUVV_ERR_RANGE, "t_stop must be >= 0");
+    if (n_rays > 0 && (!rgb || !alpha || !nsamp || !grad_rgb))
+        return fail(NEUVV_ERR_ARG, "rgb / alpha / nsamp / grad_rgb is NULL");
+    if (tree->n_leaves > 0 && (!grad_hh || !grad_wsig)) return fail(NEUVV_ERR_ARG, "grad_hh / grad_wsig is NULL");
+    neuvv::BackwardIO io{rgb, alpha, nsamp, grad_rgb, grad_alpha, grad_hh, grad_wsig, grad_basis};
+    return hip_status(neuvv::launch_render_bwd(tree->K, tree->C, tree->dtype, tree_args(tree), in, ra, io,
+                                               (hipStream_t)stream),
+                      "render_backward launch");
+    NEUVV_GUARD_END
+}
+
+int neuvv_compose(int32_t L, int64_t n_pix, const float* rgb, const float* alpha, const float* depth,
+                  float* out_rgb, float* out_alpha, float* out_depth, void* stream) {
+    NEUVV_GUARD_BEGIN
+    if (L < 1 || L > 16) return fail(NEUVV_ERR_RANGE, "L = %d outside [1, 16]", L);
+    if (n_pix < 0) return fail(NEUVV_ERR_ARG, "n_pix < 0");
+    if (n_pix > 0 && (!rgb || !alpha || !depth || !out_rgb || !out_alpha)) return fail(NEUVV_ERR_ARG, "NULL buffer");
+    return hip_status(neuvv::launch_compose_fwd(L, n_pix, rgb, alpha, depth, out_rgb, out_alpha, out_depth,
+                                                (hipStream_t)stream),
+                      "compose launch");
+    NEUVV_GUARD_END
+}
+
+int neuvv_compose_backward(int32_t L, int64_t n_pix, const float* rgb, const float* alpha, const float* depth,
+                           const float* grad_out_rgb, const float* grad_out_alpha, float* grad_rgb,
+                           float* grad_alpha, void* stream) {
+    NEUVV_GUARD_BEGIN
+    if (L < 1 || L > 16) return fail(NEUVV_ERR_RANGE, "L = %d outside [1, 16]", L);
+    if (n_pix < 0) return fail(NEUVV_ERR_ARG, "n_pix < 0");
+    if (n_pix > 0 && (!rgb || !alpha || !depth || !grad_out_rgb || !grad_rgb || !grad_alpha))
+        return fail(NEUVV_ERR_ARG, "NULL buffer");
+    return hip_status(neuvv::launch_compose_bwd(L, n_pix, rgb, alpha, depth, grad_out_rgb, grad_out_alpha, grad_rgb,
+                                                grad_alpha, (hipStream_t)stream),
+                      "compose_backward launch");
+    NEUVV_GUARD_END
+}
+
+int neuvv_pinhole_rays(const neuvv_camera* cam, int64_t n, const int32_t* pix, float* ray_o, float* ray_d,
+                       void* stream) {
+    NEUVV_GUARD_BEGIN
+    if (!cam) return fail(NEUVV_ERR_ARG, "camera is NULL");
+    if (cam->width < 1 || cam->height < 1) return fail(NEUVV_ERR_RANGE, "camera size must be positive");
+    if ((int64_t)cam->width * cam->height > INT32_MAX) return fail(NEUVV_ERR_RANGE, "camera too large");
+    if (cam->width > (1 << 23) || cam->height > (1 << 23)) return fail(NEUVV_ERR_RANGE, "camera too large");
+    if (!(cam->fx != 0.0f) || !(cam->fy != 0.0f) || !std::isfinite(cam->fx) || !std::isfinite(cam->fy))
+        return fail(NEUVV_ERR_RANGE, "focal lengths must be finite and non-zero");
+    if (n < 0) return fail(NEUVV_ERR_ARG, "n < 0");
+    if (!pix && n != (int64_t)cam->width * cam->height) return fail(NEUVV_ERR_ARG, "pix NULL requires n = W*H");
+    if (n > 0 && (!ray_o || !ray_d)) return fail(NEUVV_ERR_ARG, "ray_o / ray_d is NULL");
+    const float intr[4] = {cam->fx, cam->fy, cam->cx, cam->cy};
+    return hip_status(neuvv::launch_pinhole(cam->width, cam->height, intr, cam->c2w, n, pix, ray_o, ray_d,
+                                            (hipStream_t)stream),
+                      "pinhole launch");
+    NEUVV_GUARD_END
+}
+
+int neuvv_eval_hh(int32_t K, int64_t n, const float* dirs, const float* gam, float* out, void* stream) {
+    NEUVV_GUARD_BEGIN
+    if (K < 1 || K > 30) return fail(NEUVV_ERR_RANGE, "K = %d outside [1, 30]", K);
+    if (n < 0) return fail(NEUVV_ERR_ARG, "n < 0");
+    if (n > 0 && (!dirs || !gam || !out)) return fail(NEUVV_ERR_ARG, "NULL buffer");
+    return hip_status(neuvv::launch_eval_hh(K, n, dirs, gam, out, (hipStream_t)stream), "eval_hh launch");
+    NEUVV_GUARD_END
+}
+
+}  // extern "C"

@@ -1,0 +1,114 @@
+// Host-side octree construction over a list of occupied leaf cells.
+//
+// The leaves are sorted by Morton code (bits of i, j, k interleaved, i in the
+// lowest position); a leaf's slot is its rank in that order, so leaves that
+// are close in space are close in the payload arrays. Interior nodes are the
+// distinct Morton prefixes of each level, stored level by level from the
+// root (breadth first) and in Morton order within a level, so the top levels
+// form a prefix of the child table that a kernel can stage in LDS.
+#include <stdint.h>
+
+#include <algorithm>
+#include <numeric>
+#include <string>
+#include <vector>
+
+namespace neuvv {
+
+static inline uint64_t spread3(uint64_t v) {
+    // v has at most 21 bits; move bit b to bit 3b
+    v &= 0x1fffffULL;
+    v = (v | (v << 32)) & 0x1f00000000ffffULL;
+    v = (v | (v << 16)) & 0x1f0000ff0000ffULL;
+    v = (v | (v << 8)) & 0x100f00f00f00f00fULL;
+    v = (v | (v << 4)) & 0x10c30c30c30c30c3ULL;
+    v = (v | (v << 2)) & 0x1249249249249249ULL;
+    return v;
+}
+
+static inline uint64_t morton3(uint32_t i, uint32_t j, uint32_t k) {
+    return spread3(i) | (spread3(j) << 1) | (spread3(k) << 2);
+}
+
+// Returns 0 or a negative neuvv_status; err receives a message.
+int build_voctree_host(int32_t depth, int64_t n, const int32_t* ijk, int32_t* child, int64_t capacity,
+                       int64_t* n_nodes_out, int64_t* slot_of_input, std::string& err) {
+    const int64_t G = int64_t(1) << depth;
+    std::vector<uint64_t> code(n);
+    for (int64_t q = 0; q < n; ++q) {
+        const int32_t i = ijk[3 * q], j = ijk[3 * q + 1], k = ijk[3 * q + 2];
+        if (i < 0 || j < 0 || k < 0 || i >= G || j >= G || k >= G) {
+            err = "leaf " + std::to_string(q) + " has a coordinate outside [0, 2^depth)";
+            return -2;
+        }
+        code[q] = morton3((uint32_t)i, (uint32_t)j, (uint32_t)k);
+    }
+    std::vector<int64_t> order(n);
+    std::iota(order.begin(), order.end(), int64_t(0));
+    std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return code[a] < code[b]; });
+    for (int64_t s = 1; s < n; ++s)
+        if (code[order[s]] == code[order[s - 1]]) {
+            err = "leaf cell listed twice (inputs " + std::to_string(order[s - 1]) + " and " +
+                  std::to_string(order[s]) + ")";
+            return -3;
+        }
+    std::vector<uint64_t> sorted(n);
+    for (int64_t s = 0; s < n; ++s) sorted[s] = code[order[s]];
+
+    // distinct prefixes per level: level l (0 = root) keys = code >> 3 (D - l)
+    std::vector<std::vector<uint64_t>> keys(depth);
+    std::vector<int64_t> offset(depth + 1, 0);
+    for (int l = 0; l < depth; ++l) {
+        const int sh = 3 * (depth - l);
+        std::vector<uint64_t>& kl = keys[l];
+        if (l == 0) {
+            kl.push_back(0);
+        } else {
+            kl.reserve(n ? n : 1);
+            for (int64_t s = 0; s < n; ++s) {
+                const uint64_t key = sorted[s] >> sh;
+                if (kl.empty() || kl.back() != key) kl.push_back(key);
+            }
+        }
+        offset[l + 1] = offset[l] + (int64_t)kl.size();
+    }
+    const int64_t n_nodes = offset[depth];
+    if (n_nodes > INT32_MAX || n > INT32_MAX) {
+        err = "tree too large for 32-bit node and leaf indices";
+        return -2;
+    }
+    *n_nodes_out = n_nodes;
+    if (slot_of_input)
+        for (int64_t s = 0; s < n; ++s) slot_of_input[order[s]] = s;
+    if (!child) return 0;
+    if (capacity < n_nodes) {
+        err = "node_capacity " + std::to_string(capacity) + " < required " + std::to_string(n_nodes);
+        return -4;
+    }
+    std::fill(child, child + n_nodes * 8, -1);
+    // links from level l to level l+1 (keys of level l+1 sorted: parents found by a merge walk)
+    for (int l = 0; l + 1 < depth; ++l) {
+        const std::vector<uint64_t>& up = keys[l];
+        const std::vector<uint64_t>& dn = keys[l + 1];
+        size_t pu = 0;
+        for (size_t q = 0; q < dn.size(); ++q) {
+            const uint64_t parent = dn[q] >> 3;
+            while (up[pu] != parent) ++pu;
+            child[(offset[l] + (int64_t)pu) * 8 + (dn[q] & 7)] = (int32_t)(offset[l + 1] + (int64_t)q);
+        }
+    }
+    // last level: children are leaf slots
+    {
+        const int l = depth - 1;
+        const std::vector<uint64_t>& up = keys[l];
+        size_t pu = 0;
+        for (int64_t s = 0; s < n; ++s) {
+            const uint64_t parent = sorted[s] >> 3;
+            while (up[pu] != parent) ++pu;
+            child[(offset[l] + (int64_t)pu) * 8 + (sorted[s] & 7)] = (int32_t)s;
+        }
+    }
+    return 0;
+}
+
+}  // namespace neuvv

@@ -1,0 +1,52 @@
+// Host-side launchers shared by the C ABI (api.cpp) and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "neuvv_device.h"
+
+namespace neuvv {
+
+struct RenderOut {
+    float* rgb;
+    float* alpha;
+    float* depth;
+    int32_t* nsamp;
+};
+
+struct BackwardIO {
+    const float* rgb;
+    const float* alpha;
+    const int32_t* nsamp;
+    const float* grad_rgb;
+    const float* grad_alpha;
+    float* grad_hh;
+    float* grad_wsig;
+    float* grad_basis;
+};
+
+// Each returns hipSuccess or the launch error. K, C, dtype must be supported
+// (checked by the caller with render_supported()).
+bool render_supported(int K, int C, int dtype);
+hipError_t launch_render_fwd(int K, int C, int dtype, const TreeArgs& tr, const InstArgs& in, const RayArgs& ra,
+                             float t_stop, const RenderOut& out, hipStream_t stream);
+hipError_t launch_render_bwd(int K, int C, int dtype, const TreeArgs& tr, const InstArgs& in, const RayArgs& ra,
+                             const BackwardIO& io, hipStream_t stream);
+hipError_t launch_compose_fwd(int L, int64_t n, const float* rgb, const float* alpha, const float* depth,
+                              float* out_rgb, float* out_alpha, float* out_depth, hipStream_t stream);
+hipError_t launch_compose_bwd(int L, int64_t n, const float* rgb, const float* alpha, const float* depth,
+                              const float* g_rgb, const float* g_alpha, float* grad_rgb, float* grad_alpha,
+                              hipStream_t stream);
+hipError_t launch_pinhole(int W, int H, const float intr[4], const float c2w[12], int64_t n, const int32_t* pix,
+                          float* ray_o, float* ray_d, hipStream_t stream);
+hipError_t launch_eval_hh(int K, int64_t n, const float* dirs, const float* gam, float* out, hipStream_t stream);
+hipError_t launch_pack(int K, int C, int dtype, int64_t n, const float* hh_in, const float* wsig_in,
+                       const int64_t* slot_of_input, void* hh_out, void* wsig_out, hipStream_t stream);
+
+// Device properties used to size persistent grids (cached per device).
+int device_cu_count();
+
+}  // namespace neuvv

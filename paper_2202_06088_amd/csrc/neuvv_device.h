@@ -1,0 +1,407 @@
+// Device-side building blocks of the VOctree renderer (gfx950).
+//
+//  * df:        compensated float32 pairs (hi + lo, about 48 significant bits)
+//               used for all ray geometry, so that segment lengths inside
+//               leaves keep float32 relative accuracy even when the ray
+//               parameter is thousands of leaf units large;
+//  * hh_all:    the first 30 real 4-D hyperspherical harmonics (Sec. 4.1,
+//               Eq. 2-3, Appendix A.2) as closed-form polynomials;
+//  * RaySetup:  instance transform and re-timing of one ray (Eq. 13), clip to
+//               the tree box, per-ray HH basis and density-basis row (Eq. 5, 8);
+//  * walk_next: octree descent to the next occupied leaf along the ray
+//               (Sec. 4.3 "Rendering"), skipping whole empty nodes.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace neuvv {
+
+constexpr int kMaxDepth = 12;
+constexpr int kWave = 64;
+
+// ----------------------------------------------------------------------------
+// compensated float arithmetic (error-free transformations); contraction is
+// switched off inside so that no a*b+c is fused behind the algorithm's back.
+
+struct df {
+    float hi, lo;
+};
+
+__device__ __forceinline__ df df_two_sum(float a, float b) {
+#pragma clang fp contract(off)
+    float s = a + b;
+    float bb = s - a;
+    float e = (a - (s - bb)) + (b - bb);
+    return {s, e};
+}
+__device__ __forceinline__ df df_quick(float a, float b) {
+#pragma clang fp contract(off)
+    float s = a + b;
+    float e = b - (s - a);
+    return {s, e};
+}
+__device__ __forceinline__ df df_two_prod(float a, float b) {
+#pragma clang fp contract(off)
+    float p = a * b;
+    float e = __builtin_fmaf(a, b, -p);
+    return {p, e};
+}
+__device__ __forceinline__ df df_from(float a) { return {a, 0.0f}; }
+__device__ __forceinline__ df df_neg(df a) { return {-a.hi, -a.lo}; }
+__device__ __forceinline__ df df_add(df a, df b) {
+#pragma clang fp contract(off)
+    df s = df_two_sum(a.hi, b.hi);
+    df t = df_two_sum(a.lo, b.lo);
+    float lo = s.lo + t.hi;
+    df u = df_quick(s.hi, lo);
+    lo = t.lo + u.lo;
+    return df_quick(u.hi, lo);
+}
+__device__ __forceinline__ df df_sub(df a, df b) { return df_add(a, df_neg(b)); }
+__device__ __forceinline__ df df_mul(df a, df b) {
+#pragma clang fp contract(off)
+    df p = df_two_prod(a.hi, b.hi);
+    float cross = __builtin_fmaf(a.hi, b.lo, a.lo * b.hi);
+    return df_quick(p.hi, p.lo + cross);
+}
+__device__ __forceinline__ df df_mul_f(df a, float b) {
+#pragma clang fp contract(off)
+    df p = df_two_prod(a.hi, b);
+    return df_quick(p.hi, __builtin_fmaf(a.lo, b, p.lo));
+}
+__device__ __forceinline__ df df_div(df a, df b) {
+#pragma clang fp contract(off)
+    float q1 = a.hi / b.hi;
+    df r = df_sub(a, df_mul_f(b, q1));
+    float q2 = r.hi / b.hi;
+    r = df_sub(r, df_mul_f(b, q2));
+    float q3 = r.hi / b.hi;
+    return df_add(df_quick(q1, q2), df_from(q3));
+}
+__device__ __forceinline__ bool df_lt(df a, df b) { return a.hi < b.hi || (a.hi == b.hi && a.lo < b.lo); }
+__device__ __forceinline__ float df_f(df a) { return a.hi + a.lo; }
+
+// floor of the value hi + lo (|lo| <= ulp(hi)/2).
+__device__ __forceinline__ int df_floor(df a) {
+    float f = floorf(a.hi);
+    if (f == a.hi && a.lo < 0.0f) f -= 1.0f;
+    return (int)f;
+}
+// Index of the half-open unit cell a ray occupies just after passing x along
+// a direction of the given sign: floor(x) moving up (or still), ceil(x)-1 down.
+__device__ __forceinline__ int df_cell(df a, int sign) {
+    if (sign >= 0) return df_floor(a);
+    float c = ceilf(a.hi);
+    if (c == a.hi && a.lo > 0.0f) c += 1.0f;
+    return (int)c - 1;
+}
+
+// ----------------------------------------------------------------------------
+// Real 4-D hyperspherical harmonics H_nlm(d, gamma) = g_nl(gamma) Y_lm(d)
+// with g_nl = A_nl sin^l(gamma) C^{l+1}_{n-l}(cos gamma), A_nl =
+// (2l)!! sqrt(2 (n+1) (n-l)! / (pi (n+l+1)!)), and Y_lm the orthonormal real
+// spherical harmonic of the unit direction d = (x, y, z), polar axis z, no
+// Condon-Shortley phase (cos m phi for m > 0, sin |m| phi for m < 0). Order:
+// n = 0.., l = 0..n, m = -l..l. Constants are the closed forms evaluated.
+__device__ __forceinline__ void hh_all(float x, float y, float z, float gam, float (&h)[30]) {
+    float s, c;
+    sincosf(gam, &s, &c);
+    const float c2 = c * c, s2 = s * s;
+    // radial factors g_nl
+    const float g00 = 0.7978845608028654f;                       // sqrt(2/pi)
+    const float g10 = 1.5957691216057308f * c;                   // 2 sqrt(2/pi) cos
+    const float g11 = 0.9213177319235613f * s;                   // 2 sqrt(2/(3pi)) sin
+    const float g20 = 0.7978845608028654f * (4.0f * c2 - 1.0f);  // sqrt(2/pi) U_2
+    const float g21 = 2.256758334191025f * s * c;                // (1/sqrt(pi)) sin * 4 cos
+    const float g22 = 1.009253008808064f * s2;                   // 8/sqrt(20 pi) sin^2
+    const float g30 = 0.7978845608028654f * c * (8.0f * c2 - 4.0f);  // sqrt(2/pi) U_3
+    const float g31 = 0.41202581549140227f * s * (12.0f * c2 - 2.0f); // 2 sqrt(2/(15pi)) sin C^2_2
+    const float g32 = 2.854598585844434f * c * s2;               // 8/sqrt(90 pi) sin^2 * 6 cos
+    const float g33 = 1.0789368501515768f * s2 * s;              // 48/sqrt(630 pi) sin^3
+    // real spherical harmonics up to degree 3
+    const float x2 = x * x, y2 = y * y, z2 = z * z;
+    const float Y00 = 0.28209479177387814f;
+    const float k1 = 0.4886025119029199f;
+    const float Y1n1 = k1 * y, Y10 = k1 * z, Y11 = k1 * x;
+    const float k2 = 1.0925484305920792f;
+    const float Y2n2 = k2 * x * y, Y2n1 = k2 * y * z, Y20 = 0.31539156525252005f * (3.0f * z2 - 1.0f);
+    const float Y21 = k2 * x * z, Y22 = 0.5462742152960396f * (x2 - y2);
+    const float k33 = 0.5900435899266435f, k31 = 0.4570457994644658f;
+    const float Y3n3 = k33 * y * (3.0f * x2 - y2), Y3n2 = 2.890611442640554f * x * y * z;
+    const float Y3n1 = k31 * y * (5.0f * z2 - 1.0f), Y30 = 0.3731763325901154f * z * (5.0f * z2 - 3.0f);
+    const float Y31 = k31 * x * (5.0f * z2 - 1.0f), Y32 = 1.445305721320277f * z * (x2 - y2);
+    const float Y33 = k33 * x * (x2 - 3.0f * y2);
+    h[0] = g00 * Y00;
+    h[1] = g10 * Y00;
+    h[2] = g11 * Y1n1; h[3] = g11 * Y10; h[4] = g11 * Y11;
+    h[5] = g20 * Y00;
+    h[6] = g21 * Y1n1; h[7] = g21 * Y10; h[8] = g21 * Y11;
+    h[9] = g22 * Y2n2; h[10] = g22 * Y2n1; h[11] = g22 * Y20; h[12] = g22 * Y21; h[13] = g22 * Y22;
+    h[14] = g30 * Y00;
+    h[15] = g31 * Y1n1; h[16] = g31 * Y10; h[17] = g31 * Y11;
+    h[18] = g32 * Y2n2; h[19] = g32 * Y2n1; h[20] = g32 * Y20; h[21] = g32 * Y21; h[22] = g32 * Y22;
+    h[23] = g33 * Y3n3; h[24] = g33 * Y3n2; h[25] = g33 * Y3n1; h[26] = g33 * Y30;
+    h[27] = g33 * Y31; h[28] = g33 * Y32; h[29] = g33 * Y33;
+}
+
+// ----------------------------------------------------------------------------
+// kernel-side descriptions of the tree, instance and rays
+
+struct TreeArgs {
+    const int32_t* child;
+    const void* hh;
+    const void* wsig;
+    const float* basis;
+    const float* gamma;
+    int64_t n_nodes;
+    int64_t n_leaves;
+    int32_t depth;
+    int32_t T;
+};
+
+struct InstArgs {
+    float rot[9];
+    float trans[3];
+    float scale;
+    float time_offset;
+    int32_t wrap;
+    int32_t identity;
+};
+
+struct RayArgs {
+    const float* o;
+    const float* d;
+    const float* t;      // nullptr: t_scalar for every ray
+    float t_scalar;
+    int32_t img_w;       // > 0: rays form a row-major image of this width
+    int32_t tiles_x;
+    int64_t n;
+    int64_t n_slots;     // work slots (64 per 8x8 tile when img_w > 0, else n)
+};
+
+// Work slot -> ray index, -1 when the slot is padding of a ragged tile.
+__device__ __forceinline__ int64_t slot_to_ray(const RayArgs& ra, int64_t slot) {
+    if (ra.img_w <= 0) return slot < ra.n ? slot : -1;
+    int64_t tile = slot >> 6;
+    int within = (int)(slot & 63);
+    int64_t ty = tile / ra.tiles_x, tx = tile - ty * ra.tiles_x;
+    int64_t px = tx * 8 + (within & 7), py = ty * 8 + (within >> 3);
+    if (px >= ra.img_w) return -1;
+    int64_t r = py * ra.img_w + px;
+    return r < ra.n ? r : -1;
+}
+
+// Per-ray constants: local ray x_l(u) = O + u D with the world parameter u,
+// reciprocal direction, box interval [u_in, u_out), frame interpolation.
+struct RaySetup {
+    df O[3], D[3], inv[3];
+    int sgn[3];
+    df u_in, u_out;
+    float len_local;   // |D|: leaf units per unit of u
+    float len_world;   // |d|: world distance per unit of u
+    float dir[3];      // unit local direction
+    int i0, i1;
+    float f;
+    bool hit;
+};
+
+// Re-timing (Eq. 13): tau = t + offset, wrapped into [0, T) or clamped into
+// [0, T-1]; frames i0 = floor(tau), i1 = min(i0 + 1, T - 1), weight f = tau - i0
+// (0 on the held last frame). tau is kept compensated so f is accurate.
+__device__ __forceinline__ void time_setup(const TreeArgs& tr, const InstArgs& in, float t, int& i0_out,
+                                           int& i1_out, float& f_out) {
+    const int T = tr.T;
+    const float Tf = (float)T;
+    df tau = df_two_sum(t, in.time_offset);
+    if (in.wrap) {
+        float k = floorf(tau.hi / Tf);
+        tau = df_sub(tau, df_two_prod(k, Tf));
+        if (df_lt(tau, df_from(0.0f))) tau = df_add(tau, df_from(Tf));
+        if (!df_lt(tau, df_from(Tf))) tau = df_sub(tau, df_from(Tf));
+        if (df_lt(tau, df_from(0.0f))) tau = df_from(0.0f);
+    } else {
+        if (df_lt(tau, df_from(0.0f))) tau = df_from(0.0f);
+        if (df_lt(df_from(Tf - 1.0f), tau)) tau = df_from(Tf - 1.0f);
+    }
+    int i0 = df_floor(tau);
+    i0 = i0 < 0 ? 0 : (i0 > T - 1 ? T - 1 : i0);
+    float f = df_f(df_sub(tau, df_from((float)i0)));
+    if (i0 == T - 1) f = 0.0f;
+    i0_out = i0;
+    i1_out = i0 + 1 < T ? i0 + 1 : T - 1;
+    f_out = f;
+}
+
+__device__ __forceinline__ void ray_setup(const TreeArgs& tr, const InstArgs& in, const float o[3],
+                                          const float d[3], float t, RaySetup& rs) {
+    const float G = (float)(1 << tr.depth);
+    if (in.identity) {
+        for (int a = 0; a < 3; ++a) { rs.O[a] = df_from(o[a]); rs.D[a] = df_from(d[a]); }
+    } else {
+        df diff[3];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) diff[b] = df_two_sum(o[b], -in.trans[b]);
+        df s = df_from(in.scale);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            df ao = df_mul_f(diff[0], in.rot[a]);
+            ao = df_add(ao, df_mul_f(diff[1], in.rot[3 + a]));
+            ao = df_add(ao, df_mul_f(diff[2], in.rot[6 + a]));
+            df ad = df_two_prod(d[0], in.rot[a]);
+            ad = df_add(ad, df_two_prod(d[1], in.rot[3 + a]));
+            ad = df_add(ad, df_two_prod(d[2], in.rot[6 + a]));
+            rs.O[a] = df_div(ao, s);
+            rs.D[a] = df_div(ad, s);
+        }
+    }
+    float dl2 = 0.0f, dw2 = 0.0f;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        float v = df_f(rs.D[a]);
+        dl2 += v * v;
+        dw2 += d[a] * d[a];
+    }
+    rs.len_local = sqrtf(dl2);
+    rs.len_world = sqrtf(dw2);
+    bool hit = rs.len_local > 0.0f;
+    float inv_len = hit ? 1.0f / rs.len_local : 0.0f;
+    for (int a = 0; a < 3; ++a) rs.dir[a] = df_f(rs.D[a]) * inv_len;
+    if (!hit) rs.dir[2] = 1.0f;
+    // clip to [0, G]^3
+    df u_in = df_from(0.0f), u_out = df_from(0.0f);
+    bool have_out = false;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        rs.sgn[a] = rs.D[a].hi > 0.0f ? 1 : (rs.D[a].hi < 0.0f ? -1 : 0);
+        if (rs.sgn[a] == 0) {
+            if (df_lt(rs.O[a], df_from(0.0f)) || !df_lt(rs.O[a], df_from(G))) hit = false;
+            rs.inv[a] = df_from(0.0f);
+            continue;
+        }
+        rs.inv[a] = df_div(df_from(1.0f), rs.D[a]);
+        df t0 = df_mul(df_sub(df_from(0.0f), rs.O[a]), rs.inv[a]);
+        df t1 = df_mul(df_sub(df_from(G), rs.O[a]), rs.inv[a]);
+        df lo = rs.sgn[a] > 0 ? t0 : t1, hi = rs.sgn[a] > 0 ? t1 : t0;
+        if (df_lt(u_in, lo)) u_in = lo;
+        if (!have_out || df_lt(hi, u_out)) { u_out = hi; have_out = true; }
+    }
+    if (!have_out || !df_lt(u_in, u_out)) hit = false;
+    rs.u_in = u_in;
+    rs.u_out = u_out;
+    rs.hit = hit;
+    time_setup(tr, in, t, rs.i0, rs.i1, rs.f);
+}
+
+// ----------------------------------------------------------------------------
+// octree walk
+
+struct Walk {
+    df u;          // current ray parameter
+    int cell[3];   // leaf-level cell containing the ray just after u
+    int lvl;       // path[0..lvl] holds the ancestors of cell
+    int steps;
+    bool done;
+};
+
+__device__ __forceinline__ void walk_begin(const TreeArgs& tr, const RaySetup& rs, Walk& w) {
+    const int Gm1 = (1 << tr.depth) - 1;
+    w.u = rs.u_in;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        df p = df_add(rs.O[a], df_mul(rs.u_in, rs.D[a]));
+        int c = df_cell(p, rs.sgn[a]);
+        w.cell[a] = c < 0 ? 0 : (c > Gm1 ? Gm1 : c);
+    }
+    w.lvl = 0;
+    w.steps = 0;
+    w.done = !rs.hit;
+}
+
+// Advances to the next occupied leaf segment of positive length. Returns its
+// slot and writes delta (leaf units) and umid (ray parameter of the segment
+// midpoint); returns -1 when the ray has left the box. path points at this
+// lane's column of a [kMaxDepth][stride] LDS array.
+__device__ __forceinline__ int walk_next(const TreeArgs& tr, const int* __restrict__ s_child, int n_lds,
+                                         int* path, int stride, const RaySetup& rs, Walk& w, float& delta,
+                                         float& umid) {
+    const int Dp = tr.depth;
+    const int G = 1 << Dp;
+    const int max_steps = 3 * G + 16;
+    while (!w.done) {
+        if (++w.steps > max_steps) { w.done = true; break; }
+        // descend from the deepest valid ancestor
+        int lvl = w.lvl;
+        int node = lvl == 0 ? 0 : path[lvl * stride];
+        int leaf = -1;
+        int sh;
+        for (;;) {
+            sh = Dp - 1 - lvl;
+            int oct = ((w.cell[0] >> sh) & 1) | (((w.cell[1] >> sh) & 1) << 1) | (((w.cell[2] >> sh) & 1) << 2);
+            int ch = node < n_lds ? s_child[node * 8 + oct] : tr.child[(int64_t)node * 8 + oct];
+            if (ch < 0) break;                  // empty cube of edge 2^sh
+            if (sh == 0) { leaf = ch; break; }  // occupied leaf
+            ++lvl;
+            node = ch;
+            path[lvl * stride] = ch;
+        }
+        const int S = 1 << sh;
+        int corner[3];
+        df ue = df_from(0.0f);
+        int am = -1;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            corner[a] = w.cell[a] & ~(S - 1);
+            if (rs.sgn[a] != 0) {
+                const float plane = (float)(corner[a] + (rs.sgn[a] > 0 ? S : 0));
+                const df ua = df_mul(df_sub(df_from(plane), rs.O[a]), rs.inv[a]);
+                if (am < 0 || df_lt(ua, ue)) { ue = ua; am = a; }
+            }
+        }
+        const bool last = !df_lt(ue, rs.u_out);
+        if (last) ue = rs.u_out;
+        bool produced = false;
+        if (leaf >= 0 && df_lt(w.u, ue)) {
+            delta = df_f(df_sub(ue, w.u)) * rs.len_local;
+            umid = 0.5f * (df_f(w.u) + df_f(ue));
+            produced = delta > 0.0f;
+        }
+        if (last) {
+            w.done = true;
+        } else {
+            if (df_lt(w.u, ue)) w.u = ue;
+            int nc[3];
+            bool out = false;
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                int c;
+                if (b == am) {
+                    c = rs.sgn[b] > 0 ? corner[b] + S : corner[b] - 1;
+                    out = c < 0 || c >= G;
+                } else if (rs.sgn[b] == 0) {
+                    c = w.cell[b];
+                } else {
+                    const df p = df_add(rs.O[b], df_mul(w.u, rs.D[b]));
+                    c = df_cell(p, rs.sgn[b]);
+                    c = c < corner[b] ? corner[b] : (c > corner[b] + S - 1 ? corner[b] + S - 1 : c);
+                }
+                nc[b] = c;
+            }
+            if (out) {
+                w.done = true;
+            } else {
+                const unsigned x = (unsigned)((w.cell[0] ^ nc[0]) | (w.cell[1] ^ nc[1]) | (w.cell[2] ^ nc[2]));
+                const int hb = 31 - __builtin_clz(x);     // x != 0: the exit axis changed
+                const int common = Dp - 1 - hb;
+                w.lvl = common < lvl ? common : lvl;
+                w.cell[0] = nc[0];
+                w.cell[1] = nc[1];
+                w.cell[2] = nc[2];
+            }
+        }
+        if (produced) return leaf;
+    }
+    return -1;
+}
+
+}  // namespace neuvv

@@ -1,0 +1,448 @@
+// VOctree volume rendering on gfx950: forward (Sec. 4.3 "Rendering", Eq. 5,
+// 8, 10, 11) and adjoint (Sec. 4.3 "Optimization").
+//
+// Work distribution: persistent wavefronts. Rays are grouped in chunks of 64
+// work slots (an 8x8 pixel tile when the rays form an image); wavefront w of
+// the grid owns chunks w, w + n_waves, w + 2 n_waves, ... as one stream of
+// slots. A lane whose ray has finished is refilled from that stream: the
+// wavefront takes a ballot of the idle lanes, hands the next slots to them in
+// lane order with mbcnt, and advances its (wave-uniform) stream cursor by the
+// popcount. Blocks are renumbered so that consecutive chunks land on the
+// same XCD (hardware places block b on XCD b % 8), keeping a tile band's
+// leaves in one L2.
+//
+// Per lane: walk_next() descends the octree to the next occupied leaf
+// (top nodes from LDS, the rest from HBM/L2), the leaf's 16-byte-vector
+// structure-of-arrays payload is gathered, colour and density evaluated in
+// float32 and composited. The per-sample HH contraction is a 3x16 times 16
+// matrix-vector product with a different matrix per sample, so it stays on
+// the vector ALUs; the kernel is bound by memory traffic and latency.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+
+#include "launch.h"
+#include "neuvv_device.h"
+
+namespace neuvv {
+
+constexpr int kBlock = 256;
+constexpr int kLdsNodes = 512;
+constexpr int kRefillMin = 16;
+
+template <int DT>
+struct StoreTraits;
+template <>
+struct StoreTraits<0> { static constexpr int V = 4; };
+template <>
+struct StoreTraits<1> { static constexpr int V = 8; };
+template <>
+struct StoreTraits<2> { static constexpr int V = 8; };
+
+template <int DT>
+__device__ __forceinline__ void unpack16(const uint4& v, float (&out)[StoreTraits<DT>::V]) {
+    if constexpr (DT == 0) {
+        out[0] = __uint_as_float(v.x);
+        out[1] = __uint_as_float(v.y);
+        out[2] = __uint_as_float(v.z);
+        out[3] = __uint_as_float(v.w);
+    } else {
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            uint16_t lo = (uint16_t)(w[i] & 0xffffu), hi = (uint16_t)(w[i] >> 16);
+            if constexpr (DT == 1) {
+                out[2 * i] = (float)__builtin_bit_cast(_Float16, lo);
+                out[2 * i + 1] = (float)__builtin_bit_cast(_Float16, hi);
+            } else {
+                out[2 * i] = __uint_as_float((uint32_t)lo << 16);
+                out[2 * i + 1] = __uint_as_float((uint32_t)hi << 16);
+            }
+        }
+    }
+}
+
+// Gathers R values of leaf `slot` from a [ceil(R/V)][N][V] array.
+template <int DT, int R>
+__device__ __forceinline__ void load_leaf(const void* base, int64_t N, int64_t slot, float (&out)[R]) {
+    constexpr int V = StoreTraits<DT>::V;
+    constexpr int NG = (R + V - 1) / V;
+    const uint4* p = reinterpret_cast<const uint4*>(base) + slot;
+    uint4 raw[NG];
+#pragma unroll
+    for (int g = 0; g < NG; ++g) raw[g] = p[(int64_t)g * N];
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+        float tmp[V];
+        unpack16<DT>(raw[g], tmp);
+#pragma unroll
+        for (int e = 0; e < V; ++e)
+            if (g * V + e < R) out[g * V + e] = tmp[e];
+    }
+}
+
+__device__ __forceinline__ float softplus_f(float x) { return fmaxf(x, 0.0f) + log1pf(expf(-fabsf(x))); }
+__device__ __forceinline__ float sigmoid_f(float x) { return 1.0f / (1.0f + expf(-x)); }
+
+__device__ __forceinline__ int lane_rank(uint64_t mask) {
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// Stages the first min(n_nodes, kLdsNodes) octree nodes (the top levels,
+// stored first) in LDS and computes this wavefront's place in the grid.
+struct WaveSched {
+    int64_t gw, n_waves, stream_len;
+};
+
+__device__ __forceinline__ WaveSched wave_schedule(const RayArgs& ra) {
+    const int nb = gridDim.x, b = blockIdx.x;
+    const int per = nb / 8, rem = nb % 8, x = b % 8, k = b / 8;
+    const int logical = (x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per) + k;
+    constexpr int wpb = kBlock / kWave;
+    WaveSched s;
+    s.gw = (int64_t)logical * wpb + (threadIdx.x >> 6);
+    s.n_waves = (int64_t)nb * wpb;
+    const int64_t n_chunks = (ra.n_slots + 63) >> 6;
+    const int64_t mine = s.gw < n_chunks ? (n_chunks - 1 - s.gw) / s.n_waves + 1 : 0;
+    s.stream_len = mine * 64;
+    return s;
+}
+
+__device__ __forceinline__ int stage_top_nodes(const TreeArgs& tr, int* s_child) {
+    const int n_lds = (int)(tr.n_nodes < kLdsNodes ? tr.n_nodes : kLdsNodes);
+    for (int i = threadIdx.x; i < n_lds * 8; i += kBlock) s_child[i] = tr.child[i];
+    __syncthreads();
+    return n_lds;
+}
+
+template <int K, int C>
+__device__ __forceinline__ void ray_basis(const TreeArgs& tr, const RaySetup& rs, float (&h)[K], float (&b)[C]) {
+    float hall[30];
+    const float gam = (1.0f - rs.f) * tr.gamma[rs.i0] + rs.f * tr.gamma[rs.i1];
+    hh_all(rs.dir[0], rs.dir[1], rs.dir[2], gam, hall);
+#pragma unroll
+    for (int k = 0; k < K; ++k) h[k] = hall[k];
+    const float* b0 = tr.basis + (int64_t)rs.i0 * C;
+    const float* b1 = tr.basis + (int64_t)rs.i1 * C;
+#pragma unroll
+    for (int c = 0; c < C; ++c) b[c] = (1.0f - rs.f) * b0[c] + rs.f * b1[c];
+}
+
+// ----------------------------------------------------------------------------
+// forward
+
+template <int K, int C, int DT>
+__global__ __launch_bounds__(kBlock) void render_fwd_kernel(TreeArgs tr, InstArgs in, RayArgs ra, float t_stop,
+                                                            RenderOut out) {
+    __shared__ int s_child[kLdsNodes * 8];
+    __shared__ int s_path[kMaxDepth * kBlock];
+    const int n_lds = stage_top_nodes(tr, s_child);
+    int* path = s_path + threadIdx.x;
+    const WaveSched ws = wave_schedule(ra);
+
+    bool alive = false;
+    int64_t ray = -1;
+    RaySetup rs;
+    Walk w;
+    float h[K], bv[C];
+    float Tr = 1.0f, acc0 = 0.0f, acc1 = 0.0f, acc2 = 0.0f, wsum = 0.0f, dsum = 0.0f;
+    int ns = 0;
+    int64_t p_next = 0;
+
+    for (;;) {
+        const uint64_t idle = __ballot(!alive);
+        const int n_idle = __popcll(idle);
+        const bool more = p_next < ws.stream_len;
+        if (more && (n_idle >= kRefillMin || n_idle == kWave)) {
+            if (!alive) {
+                const int64_t pos = p_next + lane_rank(idle);
+                if (pos < ws.stream_len) {
+                    const int64_t slot = (ws.gw + (pos >> 6) * ws.n_waves) * 64 + (pos & 63);
+                    ray = slot_to_ray(ra, slot);
+                    if (ray >= 0) {
+                        const float o[3] = {ra.o[3 * ray], ra.o[3 * ray + 1], ra.o[3 * ray + 2]};
+                        const float d[3] = {ra.d[3 * ray], ra.d[3 * ray + 1], ra.d[3 * ray + 2]};
+                        const float t = ra.t ? ra.t[ray] : ra.t_scalar;
+                        ray_setup(tr, in, o, d, t, rs);
+                        Tr = 1.0f; acc0 = acc1 = acc2 = 0.0f; wsum = dsum = 0.0f; ns = 0;
+                        if (rs.hit) {
+                            ray_basis<K, C>(tr, rs, h, bv);
+                            walk_begin(tr, rs, w);
+                            alive = true;
+                        } else {
+                            out.rgb[3 * ray] = 0.0f; out.rgb[3 * ray + 1] = 0.0f; out.rgb[3 * ray + 2] = 0.0f;
+                            out.alpha[ray] = 0.0f;
+                            if (out.depth) out.depth[ray] = INFINITY;
+                            out.nsamp[ray] = 0;
+                        }
+                    }
+                }
+            }
+            p_next += n_idle;
+            continue;
+        }
+        if (n_idle == kWave) break;
+        if (alive) {
+            float delta, umid;
+            const int leaf = walk_next(tr, s_child, n_lds, path, kBlock, rs, w, delta, umid);
+            bool finish = leaf < 0;
+            if (!finish) {
+                float wv[3 * K], sv[C];
+                load_leaf<DT, 3 * K>(tr.hh, tr.n_leaves, leaf, wv);
+                load_leaf<DT, C>(tr.wsig, tr.n_leaves, leaf, sv);
+                float x = 0.0f;
+#pragma unroll
+                for (int c = 0; c < C; ++c) x = fmaf(sv[c], bv[c], x);
+                float z0 = 0.0f, z1 = 0.0f, z2 = 0.0f;
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    z0 = fmaf(wv[k], h[k], z0);
+                    z1 = fmaf(wv[K + k], h[k], z1);
+                    z2 = fmaf(wv[2 * K + k], h[k], z2);
+                }
+                const float sig = softplus_f(x);
+                const float od = sig * delta;
+                const float a = -expm1f(-od);
+                const float wt = Tr * a;
+                acc0 = fmaf(wt, sigmoid_f(z0), acc0);
+                acc1 = fmaf(wt, sigmoid_f(z1), acc1);
+                acc2 = fmaf(wt, sigmoid_f(z2), acc2);
+                wsum += wt;
+                dsum = fmaf(wt, umid * rs.len_world, dsum);
+                Tr *= expf(-od);
+                ++ns;
+                finish = t_stop > 0.0f && Tr < t_stop;
+            }
+            if (finish) {
+                out.rgb[3 * ray] = acc0; out.rgb[3 * ray + 1] = acc1; out.rgb[3 * ray + 2] = acc2;
+                out.alpha[ray] = 1.0f - Tr;
+                if (out.depth) out.depth[ray] = wsum > 0.0f ? dsum / wsum : INFINITY;
+                out.nsamp[ray] = ns;
+                alive = false;
+            }
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------
+// adjoint
+
+template <int K, int C, int DT>
+__global__ __launch_bounds__(kBlock) void render_bwd_kernel(TreeArgs tr, InstArgs in, RayArgs ra, BackwardIO io) {
+    __shared__ int s_child[kLdsNodes * 8];
+    __shared__ int s_path[kMaxDepth * kBlock];
+    __shared__ float s_gb[C];
+    if (threadIdx.x < C) s_gb[threadIdx.x] = 0.0f;   // made visible by the barrier in stage_top_nodes
+    const int n_lds = stage_top_nodes(tr, s_child);
+    int* path = s_path + threadIdx.x;
+    const WaveSched ws = wave_schedule(ra);
+    const int64_t N = tr.n_leaves;
+    const bool per_ray_t = ra.t != nullptr;
+
+    bool alive = false;
+    int64_t ray = -1;
+    RaySetup rs;
+    Walk w;
+    float h[K], bv[C], gb[C], gb_all[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) gb_all[c] = 0.0f;
+    float Tr = 1.0f, Tfin = 0.0f, p0 = 0.0f, p1 = 0.0f, p2 = 0.0f, F0 = 0.0f, F1 = 0.0f, F2 = 0.0f;
+    float g0 = 0.0f, g1 = 0.0f, g2 = 0.0f, ga = 0.0f;
+    int ns = 0, ns_fwd = 0;
+    int64_t p_next = 0;
+
+    for (;;) {
+        const uint64_t idle = __ballot(!alive);
+        const int n_idle = __popcll(idle);
+        const bool more = p_next < ws.stream_len;
+        if (more && (n_idle >= kRefillMin || n_idle == kWave)) {
+            if (!alive) {
+                const int64_t pos = p_next + lane_rank(idle);
+                if (pos < ws.stream_len) {
+                    const int64_t slot = (ws.gw + (pos >> 6) * ws.n_waves) * 64 + (pos & 63);
+                    ray = slot_to_ray(ra, slot);
+                    if (ray >= 0 && io.nsamp[ray] > 0) {
+                        const float o[3] = {ra.o[3 * ray], ra.o[3 * ray + 1], ra.o[3 * ray + 2]};
+                        const float d[3] = {ra.d[3 * ray], ra.d[3 * ray + 1], ra.d[3 * ray + 2]};
+                        const float t = per_ray_t ? ra.t[ray] : ra.t_scalar;
+                        ray_setup(tr, in, o, d, t, rs);
+                        if (rs.hit) {
+                            ray_basis<K, C>(tr, rs, h, bv);
+                            walk_begin(tr, rs, w);
+                            ns_fwd = io.nsamp[ray];
+                            ns = 0;
+                            Tr = 1.0f;
+                            Tfin = 1.0f - io.alpha[ray];
+                            F0 = io.rgb[3 * ray]; F1 = io.rgb[3 * ray + 1]; F2 = io.rgb[3 * ray + 2];
+                            g0 = io.grad_rgb[3 * ray]; g1 = io.grad_rgb[3 * ray + 1]; g2 = io.grad_rgb[3 * ray + 2];
+                            ga = io.grad_alpha ? io.grad_alpha[ray] : 0.0f;
+                            p0 = p1 = p2 = 0.0f;
+#pragma unroll
+                            for (int c = 0; c < C; ++c) gb[c] = 0.0f;
+                            alive = true;
+                        }
+                    }
+                }
+            }
+            p_next += n_idle;
+            continue;
+        }
+        if (n_idle == kWave) break;
+        if (alive) {
+            float delta, umid;
+            const int leaf = walk_next(tr, s_child, n_lds, path, kBlock, rs, w, delta, umid);
+            bool finish = leaf < 0;
+            if (!finish) {
+                float wv[3 * K], sv[C];
+                load_leaf<DT, 3 * K>(tr.hh, N, leaf, wv);
+                load_leaf<DT, C>(tr.wsig, N, leaf, sv);
+                float x = 0.0f;
+#pragma unroll
+                for (int c = 0; c < C; ++c) x = fmaf(sv[c], bv[c], x);
+                float z0 = 0.0f, z1 = 0.0f, z2 = 0.0f;
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    z0 = fmaf(wv[k], h[k], z0);
+                    z1 = fmaf(wv[K + k], h[k], z1);
+                    z2 = fmaf(wv[2 * K + k], h[k], z2);
+                }
+                const float sig = softplus_f(x);
+                const float od = sig * delta;
+                const float a = -expm1f(-od);
+                const float e = expf(-od);
+                const float wt = Tr * a;
+                const float Tn = Tr * e;
+                const float c0 = sigmoid_f(z0), c1 = sigmoid_f(z1), c2 = sigmoid_f(z2);
+                p0 = fmaf(wt, c0, p0);
+                p1 = fmaf(wt, c1, p1);
+                p2 = fmaf(wt, c2, p2);
+                const float gdotc = g0 * c0 + g1 * c1 + g2 * c2;
+                const float gsuf = g0 * (F0 - p0) + g1 * (F1 - p1) + g2 * (F2 - p2);
+                const float gsig = delta * (Tn * gdotc - gsuf) + ga * delta * Tfin;
+                const float gx = gsig * sigmoid_f(x);
+                const float gz[3] = {g0 * wt * c0 * (1.0f - c0), g1 * wt * c1 * (1.0f - c1),
+                                     g2 * wt * c2 * (1.0f - c2)};
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) {
+#pragma unroll
+                    for (int k = 0; k < K; ++k) {
+                        const int r = ch * K + k;
+                        unsafeAtomicAdd(io.grad_hh + ((int64_t)(r >> 2) * N + leaf) * 4 + (r & 3), gz[ch] * h[k]);
+                    }
+                }
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    unsafeAtomicAdd(io.grad_wsig + ((int64_t)(c >> 2) * N + leaf) * 4 + (c & 3), gx * bv[c]);
+                    gb[c] = fmaf(gx, sv[c], gb[c]);
+                }
+                Tr = Tn;
+                ++ns;
+                finish = ns >= ns_fwd;
+            }
+            if (finish) {
+                if (io.grad_basis) {
+                    if (per_ray_t) {
+#pragma unroll
+                        for (int c = 0; c < C; ++c) {
+                            unsafeAtomicAdd(io.grad_basis + (int64_t)rs.i0 * C + c, (1.0f - rs.f) * gb[c]);
+                            if (rs.f != 0.0f) unsafeAtomicAdd(io.grad_basis + (int64_t)rs.i1 * C + c, rs.f * gb[c]);
+                        }
+                    } else {
+#pragma unroll
+                        for (int c = 0; c < C; ++c) gb_all[c] += gb[c];
+                    }
+                }
+                alive = false;
+            }
+        }
+    }
+    // one shared time for every ray: reduce the basis gradient over the block
+    if (io.grad_basis && !per_ray_t) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            float v = gb_all[c];
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+            if ((threadIdx.x & 63) == 0) atomicAdd(&s_gb[c], v);
+        }
+        __syncthreads();
+        if (threadIdx.x < C) {
+            int i0, i1;
+            float f;
+            time_setup(tr, in, ra.t_scalar, i0, i1, f);
+            const float v = s_gb[threadIdx.x];
+            unsafeAtomicAdd(io.grad_basis + (int64_t)i0 * C + threadIdx.x, (1.0f - f) * v);
+            if (f != 0.0f) unsafeAtomicAdd(io.grad_basis + (int64_t)i1 * C + threadIdx.x, f * v);
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------
+// launchers
+
+bool render_supported(int K, int C, int dtype) { return K == 16 && C == 8 && dtype >= 0 && dtype <= 2; }
+
+int device_cu_count() {
+    static int cached[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (cached[dev] == 0) {
+        int cu = 0;
+        if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cu <= 0) cu = 256;
+        cached[dev] = cu;
+    }
+    return cached[dev];
+}
+
+template <typename KernelT>
+static int grid_for(KernelT kernel, const RayArgs& ra) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0) != hipSuccess || per_cu <= 0)
+        per_cu = 2;
+    const int64_t chunks = (ra.n_slots + 63) / 64;
+    const int64_t want = (chunks + (kBlock / kWave) - 1) / (kBlock / kWave);
+    const int64_t cap = (int64_t)per_cu * device_cu_count();
+    const int64_t g = want < cap ? want : cap;
+    return (int)(g > 0 ? g : 1);
+}
+
+template <int K, int C, int DT>
+static hipError_t fwd_t(const TreeArgs& tr, const InstArgs& in, const RayArgs& ra, float t_stop, const RenderOut& o,
+                        hipStream_t st) {
+    auto kern = render_fwd_kernel<K, C, DT>;
+    const int grid = grid_for(kern, ra);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, st, tr, in, ra, t_stop, o);
+    return hipGetLastError();
+}
+
+template <int K, int C, int DT>
+static hipError_t bwd_t(const TreeArgs& tr, const InstArgs& in, const RayArgs& ra, const BackwardIO& io,
+                        hipStream_t st) {
+    auto kern = render_bwd_kernel<K, C, DT>;
+    const int grid = grid_for(kern, ra);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, st, tr, in, ra, io);
+    return hipGetLastError();
+}
+
+hipError_t launch_render_fwd(int K, int C, int dtype, const TreeArgs& tr, const InstArgs& in, const RayArgs& ra,
+                             float t_stop, const RenderOut& out, hipStream_t stream) {
+    if (ra.n_slots <= 0) return hipSuccess;
+    switch (dtype) {
+        case 0: return fwd_t<16, 8, 0>(tr, in, ra, t_stop, out, stream);
+        case 1: return fwd_t<16, 8, 1>(tr, in, ra, t_stop, out, stream);
+        default: return fwd_t<16, 8, 2>(tr, in, ra, t_stop, out, stream);
+    }
+    (void)K; (void)C;
+}
+
+hipError_t launch_render_bwd(int K, int C, int dtype, const TreeArgs& tr, const InstArgs& in, const RayArgs& ra,
+                             const BackwardIO& io, hipStream_t stream) {
+    if (ra.n_slots <= 0) return hipSuccess;
+    switch (dtype) {
+        case 0: return bwd_t<16, 8, 0>(tr, in, ra, io, stream);
+        case 1: return bwd_t<16, 8, 1>(tr, in, ra, io, stream);
+        default: return bwd_t<16, 8, 2>(tr, in, ra, io, stream);
+    }
+    (void)K; (void)C;
+}
+
+}  // namespace neuvv

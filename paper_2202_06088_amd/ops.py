@@ -1,0 +1,83 @@
+"""Functional front end over the C ABI: allocates the output tensors and
+calls the library. Every computation runs in the HIP kernels."""
+from __future__ import annotations
+
+from typing import Optional, Sequence
+
+import torch
+
+from . import _lib
+from .voctree import VOctree
+
+
+def _dev(x: torch.Tensor):
+    if not x.is_cuda:
+        raise ValueError("device tensors required")
+    return x.device
+
+
+def render(tree: VOctree, ray_o: torch.Tensor, ray_d: torch.Tensor, t=0.0, inst: Optional[_lib.neuvv_instance] = None,
+           t_stop: float = 1e-4, image_width: int = 0, want_depth: bool = True, stream=None, out=None):
+    """Returns (rgb [n,3], alpha [n], depth [n] or None, nsamp [n] int32)."""
+    dev = _dev(ray_o)
+    n = ray_o.shape[0]
+    ray_t = t if isinstance(t, torch.Tensor) else None
+    t_scalar = 0.0 if ray_t is not None else float(t)
+    if out is None:
+        rgb = torch.empty(n, 3, device=dev)
+        alpha = torch.empty(n, device=dev)
+        depth = torch.empty(n, device=dev) if want_depth else None
+        nsamp = torch.empty(n, dtype=torch.int32, device=dev)
+    else:
+        rgb, alpha, depth, nsamp = out
+    _lib.neuvv_render(tree.struct(), inst, n, ray_o, ray_d, ray_t, t_scalar, image_width, t_stop, rgb, alpha,
+                      depth, nsamp, stream)
+    return rgb, alpha, depth, nsamp
+
+
+def render_backward(tree: VOctree, ray_o, ray_d, rgb, alpha, nsamp, grad_rgb, grad_alpha=None, t=0.0,
+                    inst=None, t_stop: float = 1e-4, image_width: int = 0, grads=None, want_basis=True,
+                    stream=None):
+    """Accumulates into (grad_hh, grad_wsig, grad_basis) float32 buffers (fresh zeros if grads is None)."""
+    if grads is None:
+        grads = tree.zero_grads()
+    ghh, gws, gb = grads
+    ray_t = t if isinstance(t, torch.Tensor) else None
+    t_scalar = 0.0 if ray_t is not None else float(t)
+    _lib.neuvv_render_backward(tree.struct(), inst, ray_o.shape[0], ray_o, ray_d, ray_t, t_scalar, image_width,
+                               t_stop, rgb, alpha, nsamp, grad_rgb, grad_alpha, ghh, gws,
+                               gb if want_basis else None, stream)
+    return ghh, gws, gb
+
+
+def compose(rgb: torch.Tensor, alpha: torch.Tensor, depth: torch.Tensor, stream=None):
+    """rgb [L,n,3], alpha [L,n], depth [L,n] -> (rgb [n,3], alpha [n], depth [n])."""
+    L, n = alpha.shape
+    dev = _dev(rgb)
+    o_rgb = torch.empty(n, 3, device=dev)
+    o_a = torch.empty(n, device=dev)
+    o_d = torch.empty(n, device=dev)
+    _lib.neuvv_compose(L, n, rgb, alpha, depth, o_rgb, o_a, o_d, stream)
+    return o_rgb, o_a, o_d
+
+
+def compose_backward(rgb, alpha, depth, grad_out_rgb, grad_out_alpha=None, stream=None):
+    L, n = alpha.shape
+    g_rgb = torch.empty_like(rgb)
+    g_a = torch.empty_like(alpha)
+    _lib.neuvv_compose_backward(L, n, rgb, alpha, depth, grad_out_rgb, grad_out_alpha, g_rgb, g_a, stream)
+    return g_rgb, g_a
+
+
+def pinhole_rays(cam: _lib.neuvv_camera, pix: Optional[torch.Tensor] = None, device="cuda", stream=None):
+    n = cam.width * cam.height if pix is None else pix.shape[0]
+    o = torch.empty(n, 3, device=device)
+    d = torch.empty(n, 3, device=device)
+    _lib.neuvv_pinhole_rays(cam, n, pix, o, d, stream)
+    return o, d
+
+
+def eval_hh(K: int, dirs: torch.Tensor, gam: torch.Tensor, stream=None):
+    out = torch.empty(dirs.shape[0], K, device=dirs.device)
+    _lib.neuvv_eval_hh(K, dirs.shape[0], dirs, gam, out, stream)
+    return out

@@ -1,0 +1,143 @@
+"""GPU parity of the adjoint (Sec. 4.3 "Optimization"): leaf HH coefficients,
+density weights and the shared density basis, against the FP64 oracle's
+gradient (itself pinned by finite differences). Tolerance: max |gpu - ref|
+<= 1e-4 max |ref| per gradient array."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import DEV, announce, cam_struct, config1_camera, inst_pair, oracle_render, rel_err, tdev, upload
+from oracle import core as OC
+from paper_2202_06088_amd import _lib, autograd, ops
+from workloads import make_scene, ring_cameras, scene_for_config
+
+pytestmark = pytest.mark.gpu
+
+
+def run_backward(tree, o, d, t, t_scalar, t_stop, g_rgb, g_alpha, inst=None, image_width=0):
+    tt = tdev(t) if t is not None else t_scalar
+    oo, dd = tdev(o), tdev(d)
+    rgb, alpha, depth, nsamp = ops.render(tree, oo, dd, tt, inst, t_stop, image_width)
+    ghh, gws, gb = ops.render_backward(tree, oo, dd, rgb, alpha, nsamp, tdev(g_rgb),
+                                       None if g_alpha is None else tdev(g_alpha), tt, inst, t_stop, image_width)
+    torch.cuda.synchronize()
+    hh, ws = tree.unpack_f32(ghh, gws)
+    return hh.cpu().numpy(), ws.cpu().numpy(), gb.cpu().numpy(), nsamp.cpu().numpy()
+
+
+def check(gpu, ref, tol=1e-4, label=""):
+    e = [rel_err(gpu[0], ref["grad_hh"]), rel_err(gpu[1], ref["grad_wsig"]), rel_err(gpu[2], ref["grad_basis"])]
+    announce(f"{label} grad rel errors hh={e[0]:.2e} wsig={e[1]:.2e} basis={e[2]:.2e}")
+    assert max(e) <= tol, e
+    assert np.abs(ref["grad_hh"]).max() > 0 and np.abs(ref["grad_basis"]).max() > 0
+
+
+def test_backward_config1_scalar_time():
+    sc = scene_for_config(1)
+    tree = upload(sc)
+    cam = config1_camera(sc)
+    o, d = OC.pinhole_rays(64, 64, cam.intr(), cam.c2w)
+    rng = np.random.default_rng(41)
+    gC = rng.normal(size=(o.shape[0], 3)).astype(np.float32)
+    gA = rng.normal(size=o.shape[0]).astype(np.float32)
+    for t in (4.0, 7.25):
+        announce(f"config-1 backward t={t}")
+        ref = oracle_render(sc, o, d, None, t, 0.0, g_rgb=gC, g_alpha=gA)
+        gpu = run_backward(tree, o, d, None, t, 0.0, gC, gA, image_width=64)
+        check(gpu, ref, label=f"cfg1 t={t}")
+
+
+def test_backward_training_step_per_ray_time():
+    """Reduced training step: 16 seeded cameras, random (camera, pixel) rays, random t,
+    L2 loss against a target render of a second payload draw."""
+    sc = make_scene(6, 12_000, "human", seed=3, T=300)
+    tgt = make_scene(6, 12_000, "human", seed=3, T=300)
+    rng = np.random.default_rng(1003)
+    tgt.hh = rng.normal(0, 0.3, sc.hh.shape).astype(np.float32)
+    cams = ring_cameras(sc, 8, 96, 54, 40.0, 10.0, seed=5) + ring_cameras(sc, 8, 96, 54, 40.0, -20.0, seed=6)
+    n = 4096
+    ci = rng.integers(0, 16, n)
+    pi = rng.integers(0, 96 * 54, n).astype(np.int32)
+    o = np.zeros((n, 3), np.float32)
+    d = np.zeros((n, 3), np.float32)
+    for c in range(16):
+        m = ci == c
+        oo, dd = OC.pinhole_rays(96, 54, cams[c].intr(), cams[c].c2w, pi[m])
+        o[m], d[m] = oo, dd
+    t = rng.uniform(0, 300, n).astype(np.float32)
+    announce("training-step backward, per-ray t")
+    target = oracle_render(tgt, o, d, t, 0.0, 0.0)["rgb"]
+    fwd = oracle_render(sc, o, d, t, 0.0, 0.0)
+    gC = 2.0 * (fwd["rgb"] - target)                 # d/dC of sum ||C - C*||^2 (Eq. 12)
+    ref = oracle_render(sc, o, d, t, 0.0, 0.0, g_rgb=gC)
+    gpu = run_backward(upload(sc), o, d, t, 0.0, 0.0, gC.astype(np.float32), None)
+    check(gpu, ref, label="train")
+
+
+def test_backward_with_early_stop_and_16bit():
+    sc = scene_for_config(1)
+    cam = config1_camera(sc)
+    o, d = OC.pinhole_rays(64, 64, cam.intr(), cam.c2w)
+    rng = np.random.default_rng(43)
+    gC = rng.normal(size=(o.shape[0], 3)).astype(np.float32)
+    fwd = oracle_render(sc, o, d, None, 2.0, 1e-4)
+    gC[fwd["margin"][:, 1] < 1e-3] = 0.0             # rays whose stop decision is within rounding
+    for dtype in (_lib.F32, _lib.F16, _lib.BF16):
+        announce(f"backward with t_stop=1e-4, storage {dtype}")
+        ref = oracle_render(sc, o, d, None, 2.0, 1e-4, dtype=dtype, g_rgb=gC)
+        gpu = run_backward(upload(sc, dtype), o, d, None, 2.0, 1e-4, gC, None)
+        check(gpu, ref, label=f"stop dtype={dtype}")
+
+
+def test_backward_instance():
+    sc = make_scene(5, 4000, "human", seed=21, T=40)
+    G = sc.G
+    th = -0.6
+    R = np.array([[math.cos(th), -math.sin(th), 0], [math.sin(th), math.cos(th), 0], [0, 0, 1]], np.float32)
+    oi, gi = inst_pair(R, np.array([3.0, 4.0, -1.0], np.float32), 0.75, 12.5, True)
+    rng = np.random.default_rng(44)
+    centre = 0.75 * (R.astype(np.float64) @ np.full(3, G / 2.0)) + np.array([3.0, 4.0, -1.0])
+    v = rng.normal(size=(3000, 3))
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    o = (centre + 2.0 * G * v).astype(np.float32)
+    d = (centre + rng.uniform(-0.4, 0.4, (3000, 3)) * G - o).astype(np.float32)
+    gC = rng.normal(size=(3000, 3)).astype(np.float32)
+    gA = rng.normal(size=3000).astype(np.float32)
+    announce("instance backward")
+    ref = oracle_render(sc, o, d, None, 30.0, 0.0, inst=oi, g_rgb=gC, g_alpha=gA)
+    gpu = run_backward(upload(sc), o, d, None, 30.0, 0.0, gC, gA, inst=gi)
+    check(gpu, ref, label="instance")
+
+
+def test_autograd_function_matches_direct_calls():
+    sc = scene_for_config(1)
+    tree = upload(sc)
+    cam = config1_camera(sc)
+    o, d = ops.pinhole_rays(cam_struct(cam))
+    tree.hh.requires_grad_(True)
+    tree.wsig.requires_grad_(True)
+    tree.basis.requires_grad_(True)
+    announce("autograd RenderFn")
+    rgb, alpha, depth, nsamp = autograd.render(tree, o, d, 5.0, None, 0.0, 64)
+    target = torch.rand_like(rgb)
+    loss = ((rgb - target) ** 2).sum() + alpha.sum()
+    loss.backward()
+    g_rgb = (2 * (rgb - target)).detach().contiguous()
+    with torch.no_grad():
+        ghh, gws, gb = ops.render_backward(tree, o, d, rgb.detach(), alpha.detach(), nsamp, g_rgb,
+                                           torch.ones_like(alpha), 5.0, None, 0.0, 64)
+    torch.cuda.synchronize()
+    assert rel_err(tree.hh.grad.cpu().numpy(), ghh.cpu().numpy()) < 1e-5
+    assert rel_err(tree.wsig.grad.cpu().numpy(), gws.cpu().numpy()) < 1e-5
+    assert rel_err(tree.basis.grad.cpu().numpy(), gb.cpu().numpy()) < 1e-5
+    # ComposeFn against the direct calls
+    P = torch.rand(3, 500, 3, device=DEV, requires_grad=True)
+    A = torch.rand(3, 500, device=DEV, requires_grad=True)
+    D = torch.rand(3, 500, device=DEV)
+    orgb, oa, od = autograd.compose(P, A, D)
+    (orgb.sum() * 2 + oa.sum()).backward()
+    gp, ga = ops.compose_backward(P.detach(), A.detach(), D, torch.full((500, 3), 2.0, device=DEV),
+                                  torch.ones(500, device=DEV))
+    assert torch.allclose(P.grad, gp) and torch.allclose(A.grad, ga)

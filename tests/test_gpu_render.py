@@ -1,0 +1,206 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Tolerances: FP32 forward max|gpu - oracle| <= 1e-5 max|oracle| (rgb, alpha,
+depth), sample counts identical except where the oracle reports an
+ambiguous stop or a sub-1e-5 segment; gradients <= 1e-4 relative to the
+largest entry; 16-bit storage compared on the rounded payload to the same
+1e-5, and against the unrounded payload to 2e-3 max-abs for FP16.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import (DEV, announce, cam_struct, compare, config1_camera, gpu_render, inst_pair, oracle_render,
+                      rel_err, round_storage, tdev, upload)
+from oracle import core as OC
+from oracle.hh import hh_basis
+from paper_2202_06088_amd import _lib, ops
+from workloads import make_scene, random_rays, scene_for_config, special_rays
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    return scene_for_config(1)
+
+
+@pytest.fixture(scope="module")
+def cfg1_tree(cfg1):
+    return upload(cfg1)
+
+
+def test_eval_hh_matches_oracle():
+    announce("eval_hh K=30, 4096 random directions")
+    rng = np.random.default_rng(0)
+    d = rng.normal(size=(4096, 3)).astype(np.float32)
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    g = rng.uniform(0, math.pi, 4096).astype(np.float32)
+    out = ops.eval_hh(30, tdev(d), tdev(g)).cpu().numpy()
+    ref = hh_basis(30, d.astype(np.float64), g.astype(np.float64))
+    assert np.abs(out - ref).max() < 2e-6
+    out16 = ops.eval_hh(16, tdev(d), tdev(g)).cpu().numpy()
+    assert np.array_equal(out16, out[:, :16])
+
+
+def test_pinhole_matches_oracle():
+    from workloads import orbit_camera
+    for (W, H) in ((64, 64), (67, 45), (1920, 1080)):
+        cam = orbit_camera((300.0, 250.0, 200.0), 1400.0, 0.9, 0.17, W, H, 40.0)
+        announce(f"pinhole {W}x{H}")
+        o, d = ops.pinhole_rays(cam_struct(cam))
+        ro, rd = OC.pinhole_rays(W, H, cam.intr(), cam.c2w)
+        o, d = o.cpu().numpy(), d.cpu().numpy()
+        assert np.array_equal(o, ro)
+        diff = d.view(np.int32).astype(np.int64) - rd.view(np.int32).astype(np.int64)
+        assert np.abs(diff).max() <= 1
+        assert (diff != 0).sum() <= max(1, 1e-6 * diff.size), int((diff != 0).sum())
+    pix = torch.tensor([0, 5, 1919, 1920 * 1079 + 7], dtype=torch.int32, device=DEV)
+    o2, d2 = ops.pinhole_rays(cam_struct(cam), pix)
+    assert np.array_equal(d2.cpu().numpy(), d[pix.cpu().numpy()])
+
+
+@pytest.mark.parametrize("t_stop", [0.0, 1e-4])
+def test_render_config1_fp32(cfg1, cfg1_tree, t_stop):
+    """Tiny VOctree: depth 6, ~20k leaves, 64x64 pinhole view, one seeded frame."""
+    cam = config1_camera(cfg1)
+    t = float(np.random.default_rng(12).integers(0, cfg1.T))
+    announce(f"config-1 render t_stop={t_stop} t={t}")
+    o, d = OC.pinhole_rays(64, 64, cam.intr(), cam.c2w)
+    go, gd = ops.pinhole_rays(cam_struct(cam))
+    assert np.array_equal(go.cpu().numpy(), o) and np.array_equal(gd.cpu().numpy(), d)
+    ref = oracle_render(cfg1, o, d, None, t, t_stop)
+    # rays as a row-major 64-wide image (8x8 tiles per wavefront) and as a flat list
+    for iw in (64, 0):
+        rgb, alpha, depth, nsamp = ops.render(cfg1_tree, go, gd, t, None, t_stop, iw)
+        torch.cuda.synchronize()
+        gpu = dict(rgb=rgb.cpu().numpy().astype(np.float64), alpha=alpha.cpu().numpy().astype(np.float64),
+                   depth=depth.cpu().numpy().astype(np.float64), nsamp=nsamp.cpu().numpy())
+        st = compare(gpu, ref, label=f"cfg1 iw={iw}")
+        assert st["hit"] > 500
+
+
+@pytest.mark.parametrize("depth,n_leaves,seed", [(2, 30, 0), (4, 1500, 1), (6, 30000, 2)])
+def test_render_random_and_special_rays(depth, n_leaves, seed):
+    sc = make_scene(depth, n_leaves, "random", seed=seed, T=7)
+    tree = upload(sc)
+    rng = np.random.default_rng(100 + seed)
+    o1, d1 = random_rays(sc.G, 3000, rng, inside_frac=0.2)
+    o2, d2 = special_rays(sc.G)
+    o = np.concatenate([o1, o2])
+    d = np.concatenate([d1, d2])
+    t = rng.uniform(0, sc.T, o.shape[0]).astype(np.float32)
+    for t_stop in (0.0, 1e-2):
+        announce(f"random rays depth={depth} t_stop={t_stop}")
+        ref = oracle_render(sc, o, d, t, 0.0, t_stop)
+        gpu = gpu_render(tree, o, d, t, 0.0, t_stop)
+        compare(gpu, ref, label=f"random d={depth}")
+
+
+def test_render_edge_cases():
+    # empty tree: every ray misses
+    sc = make_scene(4, 100, "random", seed=3, T=5)
+    o, d = random_rays(16, 500, np.random.default_rng(1))
+    empty = type(sc)(4, np.zeros((0, 3), np.int32), np.zeros((0, 3, 16), np.float32), np.zeros((0, 8), np.float32),
+                     sc.basis, sc.gamma)
+    announce("edge: empty tree")
+    g = gpu_render(upload(empty), o, d, None, 1.0)
+    assert np.all(g["rgb"] == 0) and np.all(g["alpha"] == 0) and np.all(g["nsamp"] == 0)
+    assert np.all(np.isinf(g["depth"]))
+    # zero rays
+    announce("edge: zero rays")
+    tree = upload(sc)
+    z = torch.zeros(0, 3, device=DEV)
+    out = ops.render(tree, z, z, 0.0)
+    assert out[0].shape == (0, 3)
+    # ragged image: 67 x 45 rays with the 8x8 tile mapping
+    announce("edge: ragged 67x45 image tiles")
+    rng = np.random.default_rng(5)
+    o, d = random_rays(16, 67 * 45, rng)
+    ref = oracle_render(sc, o, d, None, 2.0, 1e-4)
+    gpu = gpu_render(tree, o, d, None, 2.0, 1e-4, image_width=67)
+    compare(gpu, ref, label="ragged")
+    # non-multiple of the width: the last row is partial
+    gpu = gpu_render(tree, o[:67 * 44 + 13], d[:67 * 44 + 13], None, 2.0, 1e-4, image_width=67)
+    for k in ("rgb", "alpha", "nsamp"):
+        assert np.array_equal(gpu[k], gpu_render(tree, o, d, None, 2.0, 1e-4)[k][:67 * 44 + 13])
+    # depth 1 and depth 12 (maximum) trees
+    for depth, n in ((1, 5), (12, 400)):
+        announce(f"edge: depth {depth}")
+        s2 = make_scene(depth, n, "random", seed=7, T=3) if depth > 1 else None
+        if s2 is None:
+            ijk = np.array([[0, 0, 0], [1, 0, 0], [1, 1, 1], [0, 1, 1], [0, 0, 1]], np.int32)
+            r = np.random.default_rng(9)
+            s2 = type(sc)(1, ijk, r.normal(0, 0.3, (5, 3, 16)).astype(np.float32),
+                          r.normal(size=(5, 8)).astype(np.float32), sc.basis, sc.gamma)
+        o, d = random_rays(s2.G, 2000, np.random.default_rng(depth))
+        ref = oracle_render(s2, o, d, None, 1.5, 1e-4)
+        gpu = gpu_render(upload(s2), o, d, None, 1.5, 1e-4)
+        compare(gpu, ref, label=f"depth{depth}")
+
+
+@pytest.mark.parametrize("dtype", [_lib.F16, _lib.BF16])
+def test_render_16bit_storage(cfg1, dtype):
+    cam = config1_camera(cfg1)
+    o, d = OC.pinhole_rays(64, 64, cam.intr(), cam.c2w)
+    tree = upload(cfg1, dtype)
+    announce(f"16-bit storage dtype={dtype}")
+    gpu = gpu_render(tree, o, d, None, 3.0, 1e-4)
+    ref_r = oracle_render(cfg1, o, d, None, 3.0, 1e-4, dtype=dtype)
+    compare(gpu, ref_r, label=f"dtype{dtype} vs rounded payload")
+    ref = oracle_render(cfg1, o, d, None, 3.0, 1e-4)
+    err = np.abs(gpu["rgb"] - ref["rgb"]).max()
+    mse = np.mean((gpu["rgb"] - ref["rgb"]) ** 2)
+    psnr = 10 * math.log10(1.0 / mse) if mse > 0 else math.inf
+    announce(f"dtype {dtype}: max-abs {err:.3e}, PSNR {psnr:.1f} dB vs FP64 on unrounded payload")
+    if dtype == _lib.F16:
+        assert err <= 2e-3
+    assert psnr > 40
+
+
+def test_instances_match_oracle():
+    sc = make_scene(5, 4000, "human", seed=21, T=40)
+    tree = upload(sc)
+    rng = np.random.default_rng(22)
+    G = sc.G
+    th = 1.1
+    R = np.array([[math.cos(th), -math.sin(th), 0], [math.sin(th), math.cos(th), 0], [0, 0, 1]], np.float32)
+    s = 1.7
+    trans = np.array([10.0, -20.0, 3.0], np.float32)
+    centre = s * (R.astype(np.float64) @ np.full(3, G / 2.0)) + trans
+    v = rng.normal(size=(2500, 3))
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    o = (centre + 2.2 * s * G * v).astype(np.float32)
+    tgt = centre + rng.uniform(-0.5, 0.5, (2500, 3)) * s * G
+    d = (tgt - o).astype(np.float32)
+    for off, wrap, t in ((0.0, False, 5.5), (33.25, True, 20.0), (-7.5, True, 3.0), (50.0, False, 1.0)):
+        oi, gi = inst_pair(R, trans, s, off, wrap)
+        announce(f"instance off={off} wrap={wrap} t={t}")
+        ref = oracle_render(sc, o, d, None, t, 1e-4, inst=oi)
+        gpu = gpu_render(tree, o, d, None, t, 1e-4, inst=gi)
+        st = compare(gpu, ref, label="instance")
+        assert st["hit"] > 200
+
+
+def test_compose_matches_oracle():
+    rng = np.random.default_rng(31)
+    for L, n in ((1, 100), (2, 5000), (4, 100_003), (16, 2000)):
+        announce(f"compose L={L} n={n}")
+        P = rng.uniform(0, 0.6, (L, n, 3)).astype(np.float32)
+        A = rng.uniform(0, 1, (L, n)).astype(np.float32)
+        D = rng.uniform(0, 10, (L, n)).astype(np.float32)
+        D[:, : n // 10] = np.round(D[:, : n // 10])          # many exact ties
+        D[rng.uniform(size=(L, n)) < 0.1] = np.inf
+        gP = rng.normal(size=(n, 3)).astype(np.float32)
+        gA = rng.normal(size=n).astype(np.float32)
+        o_rgb, o_a, o_d = ops.compose(tdev(P), tdev(A), tdev(D))
+        r_rgb, r_a, r_d = OC.compose(P, A, D)
+        assert rel_err(o_rgb.cpu().numpy(), r_rgb) < 1e-6
+        assert np.abs(o_a.cpu().numpy() - r_a).max() < 1e-6
+        assert np.array_equal(o_d.cpu().numpy(), r_d.astype(np.float32))
+        g_rgb, g_a = ops.compose_backward(tdev(P), tdev(A), tdev(D), tdev(gP), tdev(gA))
+        q_rgb, q_a = OC.compose_grad(P, A, D, gP, gA)
+        assert rel_err(g_rgb.cpu().numpy(), q_rgb) < 1e-5
+        assert rel_err(g_a.cpu().numpy(), q_a) < 1e-5
