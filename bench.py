@@ -72,7 +72,12 @@ def main():
     ap.add_argument("--dtype", choices=["f32", "f16", "bf16"], default="f32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a 1 GiB device copy (counter calibration for profiles)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}). "
               "Rays are independent, so N GPUs would each render a share of the ring; run with --gpus 1.",
@@ -178,43 +183,69 @@ def main():
 
 
 def cpu_leg(sc, cams, t_frame, t_stop, rgb_gpu, g_rgb, grads, tree, budget_s):
-    """FP64 oracle (as written, untuned) on a strided sample of camera 0's rays, forward +
+    """FP64 oracle (as written, untuned) on a strided sample of the ring's rays, forward +
     gradient, on the host cores; also the GPU's error against it on those rays."""
     from oracle import core as OC
     W, H = 1920, 1080
-    cam = cams[0]
+    n_cam = W * H
+    n_all = 8 * n_cam
     threads = OC.default_threads()
     OC.build(force=False)
 
     def run(stride, offset=0):
-        pix = np.arange(offset, W * H, stride, dtype=np.int32)
-        o, d = OC.pinhole_rays(W, H, cam.intr(), cam.c2w, pix)
-        g = g_rgb[:W * H][pix.astype(np.int64)].cpu().numpy().astype(np.float64)
+        g_idx = np.arange(offset, n_all, stride, dtype=np.int64)
+        cam_of = g_idx // n_cam
+        o = np.zeros((g_idx.size, 3), np.float32)
+        d = np.zeros((g_idx.size, 3), np.float32)
+        for c in range(8):
+            m = cam_of == c
+            if m.any():
+                o[m], d[m] = OC.pinhole_rays(W, H, cams[c].intr(), cams[c].c2w, (g_idx[m] % n_cam).astype(np.int32))
+        g = g_rgb[torch_index(g_idx, g_rgb.device)].cpu().numpy().astype(np.float64)
         t1 = time.perf_counter()
         ref = OC.render(sc.depth, sc.leaf_ijk, sc.hh, sc.wsig, sc.basis, sc.gamma, o, d, None, t_frame, t_stop,
                         g_rgb=g, threads=threads)
-        return pix, ref, time.perf_counter() - t1
+        return g_idx, ref, time.perf_counter() - t1
 
-    log(f"cpu baseline pilot ({threads} threads)")
-    pix, ref, dt = run(997)
-    rate = len(pix) / max(dt, 1e-6)
-    stride = max(1, int(W * H / max(rate * budget_s, 1)))
-    log(f"pilot {len(pix)} rays in {dt:.2f}s; sample stride {stride}")
-    pix, ref, dt = run(stride, 1)
-    gpu = rgb_gpu[:W * H][pix.astype(np.int64)].cpu().numpy().astype(np.float64)
+    log(f"cpu baseline pilots ({threads} threads)")
+    n_a, _, t_a = run(n_all // 64)          # fixed cost (hash set of the leaves, thread start)
+    n_b, _, t_b = run(257)
+    rate = max((len(n_b) - len(n_a)) / max(t_b - t_a, 1e-3), 1.0)
+    stride = max(1, int(n_all / max(rate * budget_s, 1.0)))
+    log(f"pilot rate {rate / 1e6:.3f} Mrays/s; sample stride {stride}")
+    g_idx, ref, dt = run(stride, 1)
+    gpu = rgb_gpu[torch_index(g_idx, rgb_gpu.device)].cpu().numpy().astype(np.float64)
     ok = ref["margin"][:, 1] >= 1e-4
     err = np.abs(gpu - ref["rgb"])[ok]
     mse = float(np.mean(err ** 2)) if err.size else 0.0
     psnr = 10 * math.log10(1.0 / mse) if mse > 0 else float("inf")
-    log(f"oracle {len(pix)} rays fwd+grad in {dt:.2f}s; GPU max-abs {err.max(initial=0):.3e} PSNR {psnr:.1f} dB")
+    log(f"oracle {len(g_idx)} rays fwd+grad in {dt:.2f}s; GPU max-abs {err.max(initial=0):.3e} PSNR {psnr:.1f} dB")
     return {
-        "cpu_baseline": {"value": round(len(pix) / dt / 1e6, 5), "unit": "Mrays/s", "cores": threads,
+        "cpu_baseline": {"value": round(len(g_idx) / dt / 1e6, 5), "unit": "Mrays/s", "cores": threads,
                          "kind": "oracle",
-                         "sample": f"every {stride}th pixel of camera 0 ({len(pix)} rays), FP64 forward + gradient"},
+                         "sample": f"every {stride}th ray of the 8-camera ring ({len(g_idx)} rays), "
+                                   "FP64 forward + gradient"},
         "psnr_vs_fp64_db": None if math.isinf(psnr) else round(psnr, 2),
         "maxabs_vs_fp64": float(f"{err.max(initial=0):.3e}"),
         "fp64_compare_rays": int(ok.sum()),
     }
+
+
+def torch_index(idx, device):
+    import torch
+    return torch.from_numpy(idx).to(device)
+
+
+def calibrate_copy(nbytes=1 << 30):
+    """A plain device-to-device copy of known size, for scaling HBM byte counters."""
+    import torch
+    a = torch.ones(nbytes // 4, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"copied {nbytes} bytes 3 times")
 
 
 if __name__ == "__main__":

@@ -49,8 +49,8 @@ typedef enum { NEUVV_F32 = 0, NEUVV_F16 = 1, NEUVV_BF16 = 2 } neuvv_dtype;
 /*
  * Leaf payload layout ("16-byte-vector structure of arrays").
  * A leaf has R_hh = 3K colour coefficients, value r = ch*K + k for colour
- * channel ch and HH function k (Eq. 5), and R_sig = C density weights
- * (Eq. 8). Let V = 16 / sizeof(element) (4 for float32, 8 for 16-bit). The
+ * channel ch and HH function k (Eq. 4), and R_sig = C density weights
+ * (Eq. 5). Let V = 16 / sizeof(element) (4 for float32, 8 for 16-bit). The
  * values of all leaves are stored as
  *     hh  [ceil(R_hh / V)][n_leaves][V]
  *     wsig[ceil(R_sig / V)][n_leaves][V]
@@ -73,8 +73,8 @@ typedef struct {
     const void* hh;       /* colour coefficients, layout above */
     const void* wsig;     /* density weights, layout above */
     int32_t T;            /* frames of the temporal tables */
-    const float* basis;   /* [T][C] density basis, row t = frame t (Eq. 8: A transposed) */
-    const float* gamma;   /* [T] hyperangle per frame, in [0, pi] (Eq. 5's gamma(t)) */
+    const float* basis;   /* [T][C] density basis, row t = frame t (Eq. 5: A transposed) */
+    const float* gamma;   /* [T] hyperangle per frame, in [0, pi] (Eq. 4's gamma(t)) */
 } neuvv_tree;
 
 /* Placement and re-timing of one tree instance (Eq. 13). A world point x is
@@ -150,7 +150,7 @@ int neuvv_pack_leaves(int32_t K, int32_t C, int32_t dtype, int64_t n_leaves, con
 
 /*
  * neuvv_render - volume rendering of a VOctree along n rays (Sec. 4.3
- * "Rendering", Eq. 5, 8, 10, 11).
+ * "Rendering", Eq. 4, 5, 8, 9).
  *
  * For ray r with world origin o, direction d (need not be unit) and time t:
  * the tree-local ray is x_l(u) = R^T (o + u d - trans) / scale, u >= 0; the
@@ -176,8 +176,8 @@ int neuvv_pack_leaves(int32_t K, int32_t C, int32_t dtype, int64_t n_leaves, con
  *                 each wavefront then takes 8x8 pixel tiles (coherence hint,
  *                 results are identical).
  * t_stop          early-termination threshold on transmittance, >= 0.
- * rgb             device [n][3] premultiplied colour (Eq. 10).
- * alpha           device [n] 1 - T_final = sum of weights (Eq. 11).
+ * rgb             device [n][3] premultiplied colour (Eq. 8).
+ * alpha           device [n] 1 - T_final = sum of weights (Eq. 9).
  * depth           device [n] or NULL: sum(w * s_mid) / sum(w), s_mid the world
  *                 distance |d| u of the segment midpoint; +inf if sum(w) = 0.
  * nsamp           device [n] int32 samples composited (needed by backward).
@@ -252,7 +252,7 @@ int neuvv_pinhole_rays(const neuvv_camera* cam, int64_t n, const int32_t* pix, f
 /*
  * neuvv_eval_hh - the first K real HH (K in {1..30}) at unit directions
  * dirs device [n][3] and hyperangles gam device [n] into out device [n][K]
- * (the per-ray basis of Eq. 5; exposed for testing).
+ * (the per-ray basis of Eq. 4; exposed for testing).
  * Errors: ARG, RANGE, HIP.
  */
 int neuvv_eval_hh(int32_t K, int64_t n, const float* dirs, const float* gam, float* out, void* stream);

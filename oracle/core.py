@@ -4,7 +4,7 @@ TEST INFRASTRUCTURE ONLY: used by tests/, ``__graft_entry__.smoke()`` and the
 ``cpu_baseline`` leg of ``bench.py``; the product never imports it.
 
 * ``render`` / ``render_grad``: the FP64 C renderer in ``render.c`` (Sec. 4.3,
-  Eq. 5, 8, 10, 11, 13) through ctypes.
+  Eq. 4, 5, 8, 9, 13) through ctypes.
 * ``pinhole_rays``: FP64 pinhole rays rounded once to float.
 * ``compose`` / ``compose_grad``: depth-aware alpha blending (Alg. 1) in numpy,
   read as a per-pixel depth sort followed by premultiplied "over"

@@ -6,7 +6,7 @@
  * It shares no code with the GPU path.
  *
  * What it computes, per ray, in double precision (Sec. 4.3 "Rendering",
- * Eq. 5, 8, 10, 11, 13):
+ * Eq. 4, 5, 8, 9, 13):
  *   1. instance transform (Eq. 13): local point x_l = R^T (x - trans) / s for
  *      every point of the world ray x(u) = o + u d, so the local ray is
  *      o_l + u d_l with o_l = R^T (o - trans)/s, d_l = R^T d / s and the same
@@ -17,16 +17,16 @@
  *      half-open cells [i,i+1), each occupied cell looked up in a hash set
  *      of the leaf coordinates. Segments of zero length are not samples;
  *   3. per ray, the basis h = first K real HH at the unit local view
- *      direction and gamma = lerp of the hyperangle table at tau (Eq. 2-5),
- *      and b = lerp of the density basis rows at tau (Eq. 8);
+ *      direction and gamma = lerp of the hyperangle table at tau (Eq. 2-4),
+ *      and b = lerp of the density basis rows at tau (Eq. 5);
  *   4. per occupied segment, in order of increasing u:
- *        sigma = softplus(sum_c wsig_c b_c)          (Eq. 8, softplus reading)
- *        c_ch  = sigmoid(sum_k hh_ch,k h_k)            (Eq. 5 + sigmoid)
+ *        sigma = softplus(sum_c wsig_c b_c)          (Eq. 5, softplus reading)
+ *        c_ch  = sigmoid(sum_k hh_ch,k h_k)            (Eq. 4 + sigmoid)
  *        delta = segment length in leaf units
  *        alpha_i = 1 - exp(-sigma delta), w = T alpha_i, T *= exp(-sigma delta)
  *        C += w c, A += w, D += w * (world distance of the segment midpoint)
- *      stopping after the first sample that leaves T < t_stop (Eq. 10);
- *   5. outputs: premultiplied colour C, alpha A = sum of weights (Eq. 11),
+ *      stopping after the first sample that leaves T < t_stop (Eq. 8);
+ *   5. outputs: premultiplied colour C, alpha A = sum of weights (Eq. 9),
  *      depth D / A (+inf when A = 0), the sample count and the final
  *      transmittance exp(-sum sigma delta) recomputed from the optical depth.
  *   6. optionally the gradient of L = <g_C, C> + g_A * A with respect to the

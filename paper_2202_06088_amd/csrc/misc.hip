@@ -2,7 +2,7 @@
 //  * compose_fwd / compose_bwd: depth-aware alpha blending of L layers
 //    (Alg. 1), read as a per-pixel depth sort then premultiplied "over";
 //  * pinhole: camera rays, compensated arithmetic rounded once;
-//  * eval_hh: the per-ray HH basis on its own (Eq. 2-5), a test hook;
+//  * eval_hh: the per-ray HH basis on its own (Eq. 2-4), a test hook;
 //  * pack: leaf coefficients into the 16-byte-vector structure-of-arrays
 //    storage layout, with round-to-nearest-even for 16-bit storage.
 // All are memory-bound streaming kernels: one thread per pixel / ray / leaf,

@@ -7,7 +7,7 @@
 //  * hh_all:    the first 30 real 4-D hyperspherical harmonics (Sec. 4.1,
 //               Eq. 2-3, Appendix A.2) as closed-form polynomials;
 //  * RaySetup:  instance transform and re-timing of one ray (Eq. 13), clip to
-//               the tree box, per-ray HH basis and density-basis row (Eq. 5, 8);
+//               the tree box, per-ray HH basis and density-basis row (Eq. 4, 5);
 //  * walk_next: octree descent to the next occupied leaf along the ray
 //               (Sec. 4.3 "Rendering"), skipping whole empty nodes.
 #pragma once

@@ -1,5 +1,5 @@
-// VOctree volume rendering on gfx950: forward (Sec. 4.3 "Rendering", Eq. 5,
-// 8, 10, 11) and adjoint (Sec. 4.3 "Optimization").
+// VOctree volume rendering on gfx950: forward (Sec. 4.3 "Rendering", Eq. 4,
+// 5, 8, 9) and adjoint (Sec. 4.3 "Optimization").
 //
 // Work distribution: persistent wavefronts. Rays are grouped in chunks of 64
 // work slots (an 8x8 pixel tile when the rays form an image); wavefront w of

@@ -3,7 +3,7 @@
 * ``segments``: every crossing of the ray with every integer plane of the
   grid, sorted; each interval between consecutive crossings is classified by
   its midpoint against a dense occupancy grid. No DDA, no hashing.
-* ``render``: Eq. 10 written literally, T_i = exp(-sum_{j<i} sigma_j delta_j),
+* ``render``: Eq. 8 written literally, T_i = exp(-sum_{j<i} sigma_j delta_j),
   over those segments, with the early stop after the first sample whose
   following transmittance is below t_stop.
 """

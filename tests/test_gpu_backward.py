@@ -70,7 +70,7 @@ def test_backward_training_step_per_ray_time():
     announce("training-step backward, per-ray t")
     target = oracle_render(tgt, o, d, t, 0.0, 0.0)["rgb"]
     fwd = oracle_render(sc, o, d, t, 0.0, 0.0)
-    gC = 2.0 * (fwd["rgb"] - target)                 # d/dC of sum ||C - C*||^2 (Eq. 12)
+    gC = 2.0 * (fwd["rgb"] - target)                 # d/dC of sum ||C - C*||^2 (Eq. 10)
     ref = oracle_render(sc, o, d, t, 0.0, 0.0, g_rgb=gC)
     gpu = run_backward(upload(sc), o, d, t, 0.0, 0.0, gC.astype(np.float32), None)
     check(gpu, ref, label="train")

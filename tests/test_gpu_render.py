@@ -127,15 +127,26 @@ def test_render_edge_cases():
     for k in ("rgb", "alpha", "nsamp"):
         assert np.array_equal(gpu[k], gpu_render(tree, o, d, None, 2.0, 1e-4)[k][:67 * 44 + 13])
     # depth 1 and depth 12 (maximum) trees
-    for depth, n in ((1, 5), (12, 400)):
+    r = np.random.default_rng(9)
+    ijk1 = np.array([[0, 0, 0], [1, 0, 0], [1, 1, 1], [0, 1, 1], [0, 0, 1]], np.int32)
+    # depth 12: a dense 12^3 cluster near the centre plus 300 cells scattered over the 4096^3 grid
+    cl = np.stack(np.meshgrid(*[np.arange(2040, 2052)] * 3, indexing="ij"), -1).reshape(-1, 3)
+    sc_ = r.integers(0, 4096, (300, 3))
+    ijk12 = np.unique(np.concatenate([cl, sc_]), axis=0).astype(np.int32)
+    for depth, ijk in ((1, ijk1), (12, ijk12)):
         announce(f"edge: depth {depth}")
-        s2 = make_scene(depth, n, "random", seed=7, T=3) if depth > 1 else None
-        if s2 is None:
-            ijk = np.array([[0, 0, 0], [1, 0, 0], [1, 1, 1], [0, 1, 1], [0, 0, 1]], np.int32)
-            r = np.random.default_rng(9)
-            s2 = type(sc)(1, ijk, r.normal(0, 0.3, (5, 3, 16)).astype(np.float32),
-                          r.normal(size=(5, 8)).astype(np.float32), sc.basis, sc.gamma)
-        o, d = random_rays(s2.G, 2000, np.random.default_rng(depth))
+        n = ijk.shape[0]
+        s2 = type(sc)(depth, ijk, r.normal(0, 0.3, (n, 3, 16)).astype(np.float32),
+                      r.normal(size=(n, 8)).astype(np.float32), sc.basis, sc.gamma)
+        if depth == 12:
+            v = r.normal(size=(2000, 3))
+            v /= np.linalg.norm(v, axis=1, keepdims=True)
+            o = (2046.0 + 40.0 * v).astype(np.float32)
+            d = (2046.0 + r.uniform(-8, 8, (2000, 3)) - o).astype(np.float32)
+            o2, d2 = random_rays(s2.G, 500, r)
+            o, d = np.concatenate([o, o2]), np.concatenate([d, d2])
+        else:
+            o, d = random_rays(s2.G, 2000, np.random.default_rng(depth))
         ref = oracle_render(s2, o, d, None, 1.5, 1e-4)
         gpu = gpu_render(upload(s2), o, d, None, 1.5, 1e-4)
         compare(gpu, ref, label=f"depth{depth}")

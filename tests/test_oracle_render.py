@@ -1,7 +1,7 @@
-"""Pins for the FP64 oracle renderer (Sec. 4.3 "Rendering", Eq. 8, 10, 11, 13).
+"""Pins for the FP64 oracle renderer (Sec. 4.3 "Rendering", Eq. 4, 5, 8, 9, 13).
 
 The oracle is checked against: a brute-force plane-crossing renderer that
-writes Eq. 10 literally (tiny trees, tests/bruteforce.py), the closed form of
+writes Eq. 8 literally (tiny trees, tests/bruteforce.py), the closed form of
 a single voxel, the telescoping identity sum(w) + T_final = 1, the merge of two
 equal-colour voxels into one of summed optical depth, the miss case, integer
 times selecting basis rows, central finite differences for the gradient, and

@@ -171,7 +171,9 @@ def occupancy_from_ellipsoids(depth: int, ells: List[Ellipsoid], factor: float =
 
 
 def _fit_occupancy(depth: int, ells: List[Ellipsoid], target: int, tol: float = 0.02) -> Tuple[np.ndarray, float]:
-    f = 1.0
+    # start from the radius factor at which the summed ellipsoid volumes equal the target
+    vol = sum(4.0 / 3.0 * math.pi * float(np.prod(e.radii)) for e in ells)
+    f = min(1.0, (target / max(vol, 1e-30)) ** (1.0 / 3.0))
     ijk = occupancy_from_ellipsoids(depth, ells, f)
     for _ in range(8):
         n = ijk.shape[0]
