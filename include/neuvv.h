@@ -57,8 +57,15 @@ typedef enum { NEUVV_F32 = 0, NEUVV_F16 = 1, NEUVV_BF16 = 2 } neuvv_dtype;
  * i.e. value r of leaf slot s lives at element (r / V) * n_leaves * V + s * V
  * + r % V; padding values (r >= R) are zero. A wavefront whose lanes visit
  * neighbouring leaf slots reads one contiguous run of 16-byte vectors per
- * vector index. Gradients use the same layout with float32 (V = 4).
+ * vector index.
  * neuvv_payload_words() gives the sizes; neuvv_pack_leaves() fills them.
+ *
+ * Leaf gradient layout ("rows"). Gradients are float32 and leaf-major:
+ *     grad_leaf[n_leaves][ROW],  ROW = neuvv_grad_row_elems(K, C) = 3K + C rounded up to 64,
+ * row s holding d/d hh of slot s at r = ch*K + k (r < 3K), d/d wsig at 3K + c,
+ * and zeros after 3K + C. The adjoint adds one sample's whole row with a
+ * single wavefront-wide atomic instruction, which the L2 serves as a couple
+ * of line operations.
  */
 
 /* A built tree on the device. All pointers are device pointers. */
@@ -73,6 +80,9 @@ typedef struct {
     const void* hh;       /* colour coefficients, layout above */
     const void* wsig;     /* density weights, layout above */
     int32_t T;            /* frames of the temporal tables */
+    int32_t box[6];       /* occupied-cell bounds from neuvv_build_voctree (lo x,y,z; hi x,y,z
+                             exclusive): rays are clipped to this box instead of the whole grid.
+                             All zero = the whole grid [0, 2^D)^3. */
     const float* basis;   /* [T][C] density basis, row t = frame t (Eq. 5: A transposed) */
     const float* gamma;   /* [T] hyperangle per frame, in [0, pi] (Eq. 4's gamma(t)) */
 } neuvv_tree;
@@ -118,11 +128,14 @@ typedef struct {
  * n_nodes_out     host output, the number of nodes (always written on OK).
  * slot_of_input   host [n_leaves] int64 output or NULL: the leaf slot
  *                 (rank in Morton order) of input cell i.
+ * box_out         host [6] int32 output or NULL: bounds of the occupied cells,
+ *                 lo (inclusive) x, y, z then hi (exclusive) x, y, z; all zero
+ *                 when there are no leaves. Goes into neuvv_tree.box.
  * Errors: ARG (null leaf_ijk with n_leaves > 0, null n_nodes_out), RANGE
  * (depth, coordinates), DUPLICATE, CAPACITY (node_capacity < n_nodes).
  */
 int neuvv_build_voctree(int32_t depth, int64_t n_leaves, const int32_t* leaf_ijk, int32_t* child,
-                        int64_t node_capacity, int64_t* n_nodes_out, int64_t* slot_of_input);
+                        int64_t node_capacity, int64_t* n_nodes_out, int64_t* slot_of_input, int32_t* box_out);
 
 /*
  * neuvv_payload_words - element counts of the payload arrays for n_leaves
@@ -131,6 +144,12 @@ int neuvv_build_voctree(int32_t depth, int64_t n_leaves, const int32_t* leaf_ijk
  */
 int neuvv_payload_words(int32_t K, int32_t C, int32_t dtype, int64_t n_leaves, int64_t* hh_elems,
                         int64_t* wsig_elems);
+
+/*
+ * neuvv_grad_row_elems - floats per leaf gradient row for K and C (3K + C
+ * rounded up to 64), or NEUVV_ERR_RANGE. Host only.
+ */
+int neuvv_grad_row_elems(int32_t K, int32_t C);
 
 /*
  * neuvv_pack_leaves - convert leaf coefficients given per input leaf into
@@ -198,8 +217,8 @@ int neuvv_render(const neuvv_tree* tree, const neuvv_instance* inst, int64_t n_r
  * Arguments as neuvv_render, plus
  * rgb, alpha, nsamp  device forward outputs for the same rays and inputs.
  * grad_rgb        device [n][3]; grad_alpha device [n] or NULL (zero).
- * grad_hh         device float32, hh layout with V = 4, accumulated (+=).
- * grad_wsig       device float32, wsig layout with V = 4, accumulated.
+ * grad_leaf       device float32 [n_leaves][ROW] leaf gradient rows (layout
+ *                 above), accumulated (+=).
  * grad_basis      device [T][C] float32 accumulated, or NULL to skip.
  * The gradient with respect to the gamma table is not computed.
  * Errors: ARG, RANGE, UNSUPPORTED, HIP.
@@ -208,7 +227,7 @@ int neuvv_render_backward(const neuvv_tree* tree, const neuvv_instance* inst, in
                           const float* ray_o, const float* ray_d, const float* ray_t, float t_scalar,
                           int32_t image_width, float t_stop, const float* rgb, const float* alpha,
                           const int32_t* nsamp, const float* grad_rgb, const float* grad_alpha,
-                          float* grad_hh, float* grad_wsig, float* grad_basis, void* stream);
+                          float* grad_leaf, float* grad_basis, void* stream);
 
 /*
  * neuvv_compose - depth-aware alpha blending of L rendered layers (Alg. 1),

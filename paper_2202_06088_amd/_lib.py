@@ -26,7 +26,8 @@ class neuvv_tree(ctypes.Structure):
     _fields_ = [("depth", ctypes.c_int32), ("K", ctypes.c_int32), ("C", ctypes.c_int32),
                 ("dtype", ctypes.c_int32), ("n_nodes", ctypes.c_int64), ("n_leaves", ctypes.c_int64),
                 ("child", ctypes.c_void_p), ("hh", ctypes.c_void_p), ("wsig", ctypes.c_void_p),
-                ("T", ctypes.c_int32), ("basis", ctypes.c_void_p), ("gamma", ctypes.c_void_p)]
+                ("T", ctypes.c_int32), ("box", ctypes.c_int32 * 6), ("basis", ctypes.c_void_p),
+                ("gamma", ctypes.c_void_p)]
 
 
 class neuvv_instance(ctypes.Structure):
@@ -46,13 +47,14 @@ _I64 = ctypes.c_int64
 _F = ctypes.c_float
 
 _SIGNATURES = {
-    "neuvv_build_voctree": [_I32, _I64, _P, _P, _I64, _P, _P],
+    "neuvv_build_voctree": [_I32, _I64, _P, _P, _I64, _P, _P, _P],
     "neuvv_payload_words": [_I32, _I32, _I32, _I64, _P, _P],
     "neuvv_pack_leaves": [_I32, _I32, _I32, _I64, _P, _P, _P, _P, _P, _P],
     "neuvv_render": [ctypes.POINTER(neuvv_tree), ctypes.POINTER(neuvv_instance), _I64, _P, _P, _P, _F, _I32, _F,
                      _P, _P, _P, _P, _P],
     "neuvv_render_backward": [ctypes.POINTER(neuvv_tree), ctypes.POINTER(neuvv_instance), _I64, _P, _P, _P, _F,
-                              _I32, _F, _P, _P, _P, _P, _P, _P, _P, _P, _P],
+                              _I32, _F, _P, _P, _P, _P, _P, _P, _P, _P],
+    "neuvv_grad_row_elems": [_I32, _I32],
     "neuvv_compose": [_I32, _I64, _P, _P, _P, _P, _P, _P, _P],
     "neuvv_compose_backward": [_I32, _I64, _P, _P, _P, _P, _P, _P, _P, _P],
     "neuvv_pinhole_rays": [ctypes.POINTER(neuvv_camera), _I64, _P, _P, _P, _P],
@@ -119,15 +121,18 @@ def neuvv_last_error() -> str:
     return load().neuvv_last_error().decode(errors="replace")
 
 
-def neuvv_build_voctree(depth: int, leaf_ijk, child=None, node_capacity: int = 0, slot_of_input=None) -> int:
+def neuvv_build_voctree(depth: int, leaf_ijk, child=None, node_capacity: int = 0, slot_of_input=None,
+                        box_out=None) -> int:
     """leaf_ijk: host int32 numpy [N,3]; child: host int32 numpy [cap,8] or None;
-    slot_of_input: host int64 numpy [N] or None. Returns n_nodes."""
+    slot_of_input: host int64 numpy [N] or None; box_out: host int32 numpy [6] or None.
+    Returns n_nodes."""
     n_nodes = ctypes.c_int64(0)
     n = 0 if leaf_ijk is None else int(leaf_ijk.shape[0])
     rc = load().neuvv_build_voctree(
         depth, n, None if leaf_ijk is None else leaf_ijk.ctypes.data,
         None if child is None else child.ctypes.data, int(node_capacity), ctypes.addressof(n_nodes),
-        None if slot_of_input is None else slot_of_input.ctypes.data)
+        None if slot_of_input is None else slot_of_input.ctypes.data,
+        None if box_out is None else box_out.ctypes.data)
     _check("neuvv_build_voctree", rc)
     return int(n_nodes.value)
 
@@ -157,11 +162,18 @@ def neuvv_render(tree: neuvv_tree, inst, n_rays, ray_o, ray_d, ray_t, t_scalar, 
 
 
 def neuvv_render_backward(tree: neuvv_tree, inst, n_rays, ray_o, ray_d, ray_t, t_scalar, image_width, t_stop,
-                          rgb, alpha, nsamp, grad_rgb, grad_alpha, grad_hh, grad_wsig, grad_basis, stream=None):
+                          rgb, alpha, nsamp, grad_rgb, grad_alpha, grad_leaf, grad_basis, stream=None):
     _check("neuvv_render_backward", load().neuvv_render_backward(
         ctypes.byref(tree), _inst_ptr(inst), int(n_rays), _ptr(ray_o), _ptr(ray_d), _ptr(ray_t), float(t_scalar),
         int(image_width), float(t_stop), _ptr(rgb), _ptr(alpha), _ptr(nsamp), _ptr(grad_rgb), _ptr(grad_alpha),
-        _ptr(grad_hh), _ptr(grad_wsig), _ptr(grad_basis), _stream(stream)))
+        _ptr(grad_leaf), _ptr(grad_basis), _stream(stream)))
+
+
+def neuvv_grad_row_elems(K: int, C: int) -> int:
+    rc = load().neuvv_grad_row_elems(int(K), int(C))
+    if rc < 0:
+        _check("neuvv_grad_row_elems", rc)
+    return rc
 
 
 def neuvv_compose(L, n_pix, rgb, alpha, depth, out_rgb, out_alpha, out_depth, stream=None):

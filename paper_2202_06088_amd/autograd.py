@@ -36,9 +36,10 @@ class RenderFn(torch.autograd.Function):
         if g_rgb is None:
             g_rgb = torch.zeros_like(rgb)
         t_arg = t if t is not None else ctx.t_scalar
-        ghh, gws, gb = ops.render_backward(ctx.tree, ray_o, ray_d, rgb, alpha, nsamp, g_rgb.contiguous(),
-                                           None if g_alpha is None else g_alpha.contiguous(), t_arg, ctx.inst,
-                                           ctx.t_stop, ctx.image_width, want_basis=ctx.needs_input_grad[2])
+        gl, gb = ops.render_backward(ctx.tree, ray_o, ray_d, rgb, alpha, nsamp, g_rgb.contiguous(),
+                                     None if g_alpha is None else g_alpha.contiguous(), t_arg, ctx.inst,
+                                     ctx.t_stop, ctx.image_width, want_basis=ctx.needs_input_grad[2])
+        ghh, gws = ctx.tree.rows_to_payload_f32(gl)
         return ghh, gws, (gb if ctx.needs_input_grad[2] else None), None, None, None, None, None, None, None
 
 

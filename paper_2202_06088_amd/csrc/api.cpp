@@ -14,7 +14,7 @@
 
 namespace neuvv {
 int build_voctree_host(int32_t depth, int64_t n, const int32_t* ijk, int32_t* child, int64_t capacity,
-                       int64_t* n_nodes_out, int64_t* slot_of_input, std::string& err);
+                       int64_t* n_nodes_out, int64_t* slot_of_input, int32_t* box_out, std::string& err);
 }
 
 namespace {
@@ -47,6 +47,11 @@ int check_tree(const neuvv_tree* t) {
         return fail(NEUVV_ERR_RANGE, "n_leaves %lld", (long long)t->n_leaves);
     if (t->T < 1) return fail(NEUVV_ERR_RANGE, "T = %d must be >= 1", t->T);
     if (!t->child || !t->basis || !t->gamma) return fail(NEUVV_ERR_ARG, "tree child/basis/gamma pointer is NULL");
+    const bool box_unset = !(t->box[0] | t->box[1] | t->box[2] | t->box[3] | t->box[4] | t->box[5]);
+    if (!box_unset)
+        for (int a = 0; a < 3; ++a)
+            if (t->box[a] < 0 || t->box[a] >= t->box[3 + a] || t->box[3 + a] > (1 << t->depth))
+                return fail(NEUVV_ERR_RANGE, "tree box must satisfy 0 <= lo < hi <= 2^depth on every axis");
     if (t->n_leaves > 0 && (!t->hh || !t->wsig)) return fail(NEUVV_ERR_ARG, "tree payload pointer is NULL");
     return NEUVV_OK;
 }
@@ -112,6 +117,11 @@ neuvv::TreeArgs tree_args(const neuvv_tree* t) {
     a.n_leaves = t->n_leaves;
     a.depth = t->depth;
     a.T = t->T;
+    const bool box_unset = !(t->box[0] | t->box[1] | t->box[2] | t->box[3] | t->box[4] | t->box[5]);
+    for (int i = 0; i < 3; ++i) {
+        a.box_lo[i] = box_unset ? 0 : t->box[i];
+        a.box_hi[i] = box_unset ? (1 << t->depth) : t->box[3 + i];
+    }
     return a;
 }
 
@@ -134,7 +144,7 @@ int neuvv_version(void) { return 100; }
 const char* neuvv_last_error(void) { return g_err.c_str(); }
 
 int neuvv_build_voctree(int32_t depth, int64_t n_leaves, const int32_t* leaf_ijk, int32_t* child,
-                        int64_t node_capacity, int64_t* n_nodes_out, int64_t* slot_of_input) {
+                        int64_t node_capacity, int64_t* n_nodes_out, int64_t* slot_of_input, int32_t* box_out) {
     NEUVV_GUARD_BEGIN
     if (depth < 1 || depth > neuvv::kMaxDepth) return fail(NEUVV_ERR_RANGE, "depth %d outside [1, 12]", depth);
     if (n_leaves < 0) return fail(NEUVV_ERR_ARG, "n_leaves < 0");
@@ -142,7 +152,7 @@ int neuvv_build_voctree(int32_t depth, int64_t n_leaves, const int32_t* leaf_ijk
     if (!n_nodes_out) return fail(NEUVV_ERR_ARG, "n_nodes_out is NULL");
     std::string err;
     const int rc = neuvv::build_voctree_host(depth, n_leaves, leaf_ijk, child, node_capacity, n_nodes_out,
-                                             slot_of_input, err);
+                                             slot_of_input, box_out, err);
     if (rc != 0) return fail(rc, "%s", err.c_str());
     return NEUVV_OK;
     NEUVV_GUARD_END
@@ -157,6 +167,11 @@ int neuvv_payload_words(int32_t K, int32_t C, int32_t dtype, int64_t n_leaves, i
     *hh_elems = (int64_t)((3 * K + V - 1) / V) * n_leaves * V;
     *wsig_elems = (int64_t)((C + V - 1) / V) * n_leaves * V;
     return NEUVV_OK;
+}
+
+int neuvv_grad_row_elems(int32_t K, int32_t C) {
+    if (K < 1 || K > 30 || C < 1 || C > 64) return fail(NEUVV_ERR_RANGE, "K in [1,30] and C in [1,64] required");
+    return neuvv::grad_row_elems(K, C);
 }
 
 int neuvv_pack_leaves(int32_t K, int32_t C, int32_t dtype, int64_t n_leaves, const float* hh_in,
@@ -195,8 +210,8 @@ int neuvv_render(const neuvv_tree* tree, const neuvv_instance* inst, int64_t n_r
 int neuvv_render_backward(const neuvv_tree* tree, const neuvv_instance* inst, int64_t n_rays,
                           const float* ray_o, const float* ray_d, const float* ray_t, float t_scalar,
                           int32_t image_width, float t_stop, const float* rgb, const float* alpha,
-                          const int32_t* nsamp, const float* grad_rgb, const float* grad_alpha, float* grad_hh,
-                          float* grad_wsig, float* grad_basis, void* stream) {
+                          const int32_t* nsamp, const float* grad_rgb, const float* grad_alpha, float* grad_leaf,
+                          float* grad_basis, void* stream) {
     NEUVV_GUARD_BEGIN
     int rc = check_tree(tree);
     if (rc) return rc;
@@ -207,8 +222,8 @@ int neuvv_render_backward(const neuvv_tree* tree, const neuvv_instance* inst, in
     if (!(t_stop >= 0.0f) || !std::isfinite(t_stop)) return fail(NEUVV_ERR_RANGE, "t_stop must be >= 0");
     if (n_rays > 0 && (!rgb || !alpha || !nsamp || !grad_rgb))
         return fail(NEUVV_ERR_ARG, "rgb / alpha / nsamp / grad_rgb is NULL");
-    if (tree->n_leaves > 0 && (!grad_hh || !grad_wsig)) return fail(NEUVV_ERR_ARG, "grad_hh / grad_wsig is NULL");
-    neuvv::BackwardIO io{rgb, alpha, nsamp, grad_rgb, grad_alpha, grad_hh, grad_wsig, grad_basis};
+    if (tree->n_leaves > 0 && !grad_leaf) return fail(NEUVV_ERR_ARG, "grad_leaf is NULL");
+    neuvv::BackwardIO io{rgb, alpha, nsamp, grad_rgb, grad_alpha, grad_leaf, grad_basis};
     return hip_status(neuvv::launch_render_bwd(tree->K, tree->C, tree->dtype, tree_args(tree), in, ra, io,
                                                (hipStream_t)stream),
                       "render_backward launch");

@@ -32,9 +32,10 @@ static inline uint64_t morton3(uint32_t i, uint32_t j, uint32_t k) {
 
 // Returns 0 or a negative neuvv_status; err receives a message.
 int build_voctree_host(int32_t depth, int64_t n, const int32_t* ijk, int32_t* child, int64_t capacity,
-                       int64_t* n_nodes_out, int64_t* slot_of_input, std::string& err) {
+                       int64_t* n_nodes_out, int64_t* slot_of_input, int32_t* box_out, std::string& err) {
     const int64_t G = int64_t(1) << depth;
     std::vector<uint64_t> code(n);
+    int32_t box[6] = {0, 0, 0, 0, 0, 0};
     for (int64_t q = 0; q < n; ++q) {
         const int32_t i = ijk[3 * q], j = ijk[3 * q + 1], k = ijk[3 * q + 2];
         if (i < 0 || j < 0 || k < 0 || i >= G || j >= G || k >= G) {
@@ -42,6 +43,11 @@ int build_voctree_host(int32_t depth, int64_t n, const int32_t* ijk, int32_t* ch
             return -2;
         }
         code[q] = morton3((uint32_t)i, (uint32_t)j, (uint32_t)k);
+        const int32_t c[3] = {i, j, k};
+        for (int a = 0; a < 3; ++a) {
+            if (q == 0 || c[a] < box[a]) box[a] = c[a];
+            if (q == 0 || c[a] + 1 > box[3 + a]) box[3 + a] = c[a] + 1;
+        }
     }
     std::vector<int64_t> order(n);
     std::iota(order.begin(), order.end(), int64_t(0));
@@ -78,6 +84,8 @@ int build_voctree_host(int32_t depth, int64_t n, const int32_t* ijk, int32_t* ch
         return -2;
     }
     *n_nodes_out = n_nodes;
+    if (box_out)
+        for (int a = 0; a < 6; ++a) box_out[a] = box[a];
     if (slot_of_input)
         for (int64_t s = 0; s < n; ++s) slot_of_input[order[s]] = s;
     if (!child) return 0;

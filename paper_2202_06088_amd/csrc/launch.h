@@ -23,14 +23,15 @@ struct BackwardIO {
     const int32_t* nsamp;
     const float* grad_rgb;
     const float* grad_alpha;
-    float* grad_hh;
-    float* grad_wsig;
+    float* grad_leaf;    // [n_leaves][grad_row_elems(K, C)]
     float* grad_basis;
 };
 
 // Each returns hipSuccess or the launch error. K, C, dtype must be supported
 // (checked by the caller with render_supported()).
 bool render_supported(int K, int C, int dtype);
+// Floats per row of the leaf-major gradient array: 3K + C rounded up to 64.
+int grad_row_elems(int K, int C);
 hipError_t launch_render_fwd(int K, int C, int dtype, const TreeArgs& tr, const InstArgs& in, const RayArgs& ra,
                              float t_stop, const RenderOut& out, hipStream_t stream);
 hipError_t launch_render_bwd(int K, int C, int dtype, const TreeArgs& tr, const InstArgs& in, const RayArgs& ra,

@@ -158,6 +158,8 @@ struct TreeArgs {
     int64_t n_leaves;
     int32_t depth;
     int32_t T;
+    int32_t box_lo[3];   // occupied-cell bounds: rays are clipped to [lo, hi)
+    int32_t box_hi[3];
 };
 
 struct InstArgs {
@@ -233,10 +235,12 @@ __device__ __forceinline__ void time_setup(const TreeArgs& tr, const InstArgs& i
     f_out = f;
 }
 
+// IDENT: the instance is the identity (known at compile time), so the local
+// ray is the world ray and the low parts of O and D are constant zeros.
+template <bool IDENT>
 __device__ __forceinline__ void ray_setup(const TreeArgs& tr, const InstArgs& in, const float o[3],
                                           const float d[3], float t, RaySetup& rs) {
-    const float G = (float)(1 << tr.depth);
-    if (in.identity) {
+    if constexpr (IDENT) {
         for (int a = 0; a < 3; ++a) { rs.O[a] = df_from(o[a]); rs.D[a] = df_from(d[a]); }
     } else {
         df diff[3];
@@ -268,20 +272,21 @@ __device__ __forceinline__ void ray_setup(const TreeArgs& tr, const InstArgs& in
     float inv_len = hit ? 1.0f / rs.len_local : 0.0f;
     for (int a = 0; a < 3; ++a) rs.dir[a] = df_f(rs.D[a]) * inv_len;
     if (!hit) rs.dir[2] = 1.0f;
-    // clip to [0, G]^3
+    // clip to the occupied-cell box [lo, hi) (no occupied cell lies outside it)
     df u_in = df_from(0.0f), u_out = df_from(0.0f);
     bool have_out = false;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         rs.sgn[a] = rs.D[a].hi > 0.0f ? 1 : (rs.D[a].hi < 0.0f ? -1 : 0);
+        const float lo_p = (float)tr.box_lo[a], hi_p = (float)tr.box_hi[a];
         if (rs.sgn[a] == 0) {
-            if (df_lt(rs.O[a], df_from(0.0f)) || !df_lt(rs.O[a], df_from(G))) hit = false;
+            if (df_lt(rs.O[a], df_from(lo_p)) || !df_lt(rs.O[a], df_from(hi_p))) hit = false;
             rs.inv[a] = df_from(0.0f);
             continue;
         }
         rs.inv[a] = df_div(df_from(1.0f), rs.D[a]);
-        df t0 = df_mul(df_sub(df_from(0.0f), rs.O[a]), rs.inv[a]);
-        df t1 = df_mul(df_sub(df_from(G), rs.O[a]), rs.inv[a]);
+        df t0 = df_mul(df_sub(df_from(lo_p), rs.O[a]), rs.inv[a]);
+        df t1 = df_mul(df_sub(df_from(hi_p), rs.O[a]), rs.inv[a]);
         df lo = rs.sgn[a] > 0 ? t0 : t1, hi = rs.sgn[a] > 0 ? t1 : t0;
         if (df_lt(u_in, lo)) u_in = lo;
         if (!have_out || df_lt(hi, u_out)) { u_out = hi; have_out = true; }
@@ -305,13 +310,12 @@ struct Walk {
 };
 
 __device__ __forceinline__ void walk_begin(const TreeArgs& tr, const RaySetup& rs, Walk& w) {
-    const int Gm1 = (1 << tr.depth) - 1;
     w.u = rs.u_in;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         df p = df_add(rs.O[a], df_mul(rs.u_in, rs.D[a]));
         int c = df_cell(p, rs.sgn[a]);
-        w.cell[a] = c < 0 ? 0 : (c > Gm1 ? Gm1 : c);
+        w.cell[a] = c < tr.box_lo[a] ? tr.box_lo[a] : (c > tr.box_hi[a] - 1 ? tr.box_hi[a] - 1 : c);
     }
     w.lvl = 0;
     w.steps = 0;

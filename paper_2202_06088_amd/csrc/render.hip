@@ -131,8 +131,8 @@ __device__ __forceinline__ void ray_basis(const TreeArgs& tr, const RaySetup& rs
 // ----------------------------------------------------------------------------
 // forward
 
-template <int K, int C, int DT>
-__global__ __launch_bounds__(kBlock) void render_fwd_kernel(TreeArgs tr, InstArgs in, RayArgs ra, float t_stop,
+template <int K, int C, int DT, bool IDENT>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) void render_fwd_kernel(TreeArgs tr, InstArgs in, RayArgs ra, float t_stop,
                                                             RenderOut out) {
     __shared__ int s_child[kLdsNodes * 8];
     __shared__ int s_path[kMaxDepth * kBlock];
@@ -163,7 +163,7 @@ __global__ __launch_bounds__(kBlock) void render_fwd_kernel(TreeArgs tr, InstArg
                         const float o[3] = {ra.o[3 * ray], ra.o[3 * ray + 1], ra.o[3 * ray + 2]};
                         const float d[3] = {ra.d[3 * ray], ra.d[3 * ray + 1], ra.d[3 * ray + 2]};
                         const float t = ra.t ? ra.t[ray] : ra.t_scalar;
-                        ray_setup(tr, in, o, d, t, rs);
+                        ray_setup<IDENT>(tr, in, o, d, t, rs);
                         Tr = 1.0f; acc0 = acc1 = acc2 = 0.0f; wsum = dsum = 0.0f; ns = 0;
                         if (rs.hit) {
                             ray_basis<K, C>(tr, rs, h, bv);
@@ -226,11 +226,29 @@ __global__ __launch_bounds__(kBlock) void render_fwd_kernel(TreeArgs tr, InstArg
 
 // ----------------------------------------------------------------------------
 // adjoint
+//
+// Scatter of the leaf gradients, transposed: a sample's 3K + C gradient values
+// form one row of the leaf-major gradient array, and the whole wavefront adds
+// that row with one atomic instruction (lane c = component c). An atomic whose
+// lanes fall in one 256-byte row is handled as a couple of L2 line
+// operations, where one whose lanes hit 64 different leaves costs 64; the
+// per-ray basis h and density row b every lane needs for this are kept in LDS.
 
-template <int K, int C, int DT>
-__global__ __launch_bounds__(kBlock) void render_bwd_kernel(TreeArgs tr, InstArgs in, RayArgs ra, BackwardIO io) {
+template <int K, int C>
+__host__ __device__ constexpr int grad_row() { return ((3 * K + C + 63) / 64) * 64; }
+
+__device__ __forceinline__ float readlane_f(float v, int lane) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
+template <int K, int C, int DT, bool IDENT>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) void render_bwd_kernel(
+    TreeArgs tr, InstArgs in, RayArgs ra, BackwardIO io) {
+    constexpr int ROW = grad_row<K, C>();
     __shared__ int s_child[kLdsNodes * 8];
     __shared__ int s_path[kMaxDepth * kBlock];
+    __shared__ float s_h[kBlock * K];
+    __shared__ float s_b[kBlock * C];
     __shared__ float s_gb[C];
     if (threadIdx.x < C) s_gb[threadIdx.x] = 0.0f;   // made visible by the barrier in stage_top_nodes
     const int n_lds = stage_top_nodes(tr, s_child);
@@ -238,14 +256,18 @@ __global__ __launch_bounds__(kBlock) void render_bwd_kernel(TreeArgs tr, InstArg
     const WaveSched ws = wave_schedule(ra);
     const int64_t N = tr.n_leaves;
     const bool per_ray_t = ra.t != nullptr;
+    const int lane = threadIdx.x & 63;
+    const int wbase = threadIdx.x - lane;
 
     bool alive = false;
     int64_t ray = -1;
     RaySetup rs;
     Walk w;
-    float h[K], bv[C], gb[C], gb_all[C];
+    // basis-row gradient: per ray when rays carry their own time, else one running
+    // sum over all rays of the lane (they share the frames and the weight f)
+    float gb[C];
 #pragma unroll
-    for (int c = 0; c < C; ++c) gb_all[c] = 0.0f;
+    for (int c = 0; c < C; ++c) gb[c] = 0.0f;
     float Tr = 1.0f, Tfin = 0.0f, p0 = 0.0f, p1 = 0.0f, p2 = 0.0f, F0 = 0.0f, F1 = 0.0f, F2 = 0.0f;
     float g0 = 0.0f, g1 = 0.0f, g2 = 0.0f, ga = 0.0f;
     int ns = 0, ns_fwd = 0;
@@ -265,9 +287,16 @@ __global__ __launch_bounds__(kBlock) void render_bwd_kernel(TreeArgs tr, InstArg
                         const float o[3] = {ra.o[3 * ray], ra.o[3 * ray + 1], ra.o[3 * ray + 2]};
                         const float d[3] = {ra.d[3 * ray], ra.d[3 * ray + 1], ra.d[3 * ray + 2]};
                         const float t = per_ray_t ? ra.t[ray] : ra.t_scalar;
-                        ray_setup(tr, in, o, d, t, rs);
+                        ray_setup<IDENT>(tr, in, o, d, t, rs);
                         if (rs.hit) {
-                            ray_basis<K, C>(tr, rs, h, bv);
+                            {
+                                float h[K], bv[C];
+                                ray_basis<K, C>(tr, rs, h, bv);
+#pragma unroll
+                                for (int k = 0; k < K; ++k) s_h[threadIdx.x * K + k] = h[k];
+#pragma unroll
+                                for (int c = 0; c < C; ++c) s_b[threadIdx.x * C + c] = bv[c];
+                            }
                             walk_begin(tr, rs, w);
                             ns_fwd = io.nsamp[ray];
                             ns = 0;
@@ -277,8 +306,10 @@ __global__ __launch_bounds__(kBlock) void render_bwd_kernel(TreeArgs tr, InstArg
                             g0 = io.grad_rgb[3 * ray]; g1 = io.grad_rgb[3 * ray + 1]; g2 = io.grad_rgb[3 * ray + 2];
                             ga = io.grad_alpha ? io.grad_alpha[ray] : 0.0f;
                             p0 = p1 = p2 = 0.0f;
+                            if (per_ray_t) {
 #pragma unroll
-                            for (int c = 0; c < C; ++c) gb[c] = 0.0f;
+                                for (int c = 0; c < C; ++c) gb[c] = 0.0f;
+                            }
                             alive = true;
                         }
                     }
@@ -288,23 +319,29 @@ __global__ __launch_bounds__(kBlock) void render_bwd_kernel(TreeArgs tr, InstArg
             continue;
         }
         if (n_idle == kWave) break;
+        bool has = false;
+        int leaf = -1;
+        float gz0 = 0.0f, gz1 = 0.0f, gz2 = 0.0f, gx = 0.0f;
         if (alive) {
             float delta, umid;
-            const int leaf = walk_next(tr, s_child, n_lds, path, kBlock, rs, w, delta, umid);
+            leaf = walk_next(tr, s_child, n_lds, path, kBlock, rs, w, delta, umid);
             bool finish = leaf < 0;
             if (!finish) {
                 float wv[3 * K], sv[C];
                 load_leaf<DT, 3 * K>(tr.hh, N, leaf, wv);
                 load_leaf<DT, C>(tr.wsig, N, leaf, sv);
+                const float* hl = s_h + threadIdx.x * K;
+                const float* bl = s_b + threadIdx.x * C;
                 float x = 0.0f;
 #pragma unroll
-                for (int c = 0; c < C; ++c) x = fmaf(sv[c], bv[c], x);
+                for (int c = 0; c < C; ++c) x = fmaf(sv[c], bl[c], x);
                 float z0 = 0.0f, z1 = 0.0f, z2 = 0.0f;
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
-                    z0 = fmaf(wv[k], h[k], z0);
-                    z1 = fmaf(wv[K + k], h[k], z1);
-                    z2 = fmaf(wv[2 * K + k], h[k], z2);
+                    const float hk = hl[k];
+                    z0 = fmaf(wv[k], hk, z0);
+                    z1 = fmaf(wv[K + k], hk, z1);
+                    z2 = fmaf(wv[2 * K + k], hk, z2);
                 }
                 const float sig = softplus_f(x);
                 const float od = sig * delta;
@@ -318,41 +355,50 @@ __global__ __launch_bounds__(kBlock) void render_bwd_kernel(TreeArgs tr, InstArg
                 p2 = fmaf(wt, c2, p2);
                 const float gdotc = g0 * c0 + g1 * c1 + g2 * c2;
                 const float gsuf = g0 * (F0 - p0) + g1 * (F1 - p1) + g2 * (F2 - p2);
+                // dL/dsigma = delta (T_{k+1} <g, c_k> - <g, rgb - rgb_<=k>) + g_a delta T_final
                 const float gsig = delta * (Tn * gdotc - gsuf) + ga * delta * Tfin;
-                const float gx = gsig * sigmoid_f(x);
-                const float gz[3] = {g0 * wt * c0 * (1.0f - c0), g1 * wt * c1 * (1.0f - c1),
-                                     g2 * wt * c2 * (1.0f - c2)};
+                gx = gsig * sigmoid_f(x);
+                gz0 = g0 * wt * c0 * (1.0f - c0);
+                gz1 = g1 * wt * c1 * (1.0f - c1);
+                gz2 = g2 * wt * c2 * (1.0f - c2);
 #pragma unroll
-                for (int ch = 0; ch < 3; ++ch) {
-#pragma unroll
-                    for (int k = 0; k < K; ++k) {
-                        const int r = ch * K + k;
-                        unsafeAtomicAdd(io.grad_hh + ((int64_t)(r >> 2) * N + leaf) * 4 + (r & 3), gz[ch] * h[k]);
-                    }
-                }
-#pragma unroll
-                for (int c = 0; c < C; ++c) {
-                    unsafeAtomicAdd(io.grad_wsig + ((int64_t)(c >> 2) * N + leaf) * 4 + (c & 3), gx * bv[c]);
-                    gb[c] = fmaf(gx, sv[c], gb[c]);
-                }
+                for (int c = 0; c < C; ++c) gb[c] = fmaf(gx, sv[c], gb[c]);
+                has = true;
                 Tr = Tn;
                 ++ns;
                 finish = ns >= ns_fwd;
             }
             if (finish) {
-                if (io.grad_basis) {
-                    if (per_ray_t) {
+                if (io.grad_basis && per_ray_t) {
 #pragma unroll
-                        for (int c = 0; c < C; ++c) {
-                            unsafeAtomicAdd(io.grad_basis + (int64_t)rs.i0 * C + c, (1.0f - rs.f) * gb[c]);
-                            if (rs.f != 0.0f) unsafeAtomicAdd(io.grad_basis + (int64_t)rs.i1 * C + c, rs.f * gb[c]);
-                        }
-                    } else {
-#pragma unroll
-                        for (int c = 0; c < C; ++c) gb_all[c] += gb[c];
+                    for (int c = 0; c < C; ++c) {
+                        unsafeAtomicAdd(io.grad_basis + (int64_t)rs.i0 * C + c, (1.0f - rs.f) * gb[c]);
+                        if (rs.f != 0.0f) unsafeAtomicAdd(io.grad_basis + (int64_t)rs.i1 * C + c, rs.f * gb[c]);
                     }
                 }
                 alive = false;
+            }
+        }
+        // every lane of the wavefront adds one component of each produced row
+        uint64_t m = __ballot(has);
+        __builtin_amdgcn_wave_barrier();
+        while (m) {
+            const int src = __builtin_ctzll(m);
+            m &= m - 1;
+            const int L = __builtin_amdgcn_readlane(leaf, src);
+            const float a0 = readlane_f(gz0, src), a1 = readlane_f(gz1, src), a2 = readlane_f(gz2, src);
+            const float ax = readlane_f(gx, src);
+            float* row = io.grad_leaf + (int64_t)L * ROW;
+#pragma unroll
+            for (int c0 = 0; c0 < 3 * K + C; c0 += kWave) {
+                const int c = c0 + lane;
+                if (c < 3 * K) {
+                    const int ch = c / K;
+                    const float gzc = ch == 0 ? a0 : (ch == 1 ? a1 : a2);
+                    unsafeAtomicAdd(row + c, gzc * s_h[(wbase + src) * K + (c - ch * K)]);
+                } else if (c < 3 * K + C) {
+                    unsafeAtomicAdd(row + c, ax * s_b[(wbase + src) * C + (c - 3 * K)]);
+                }
             }
         }
     }
@@ -360,7 +406,7 @@ __global__ __launch_bounds__(kBlock) void render_bwd_kernel(TreeArgs tr, InstArg
     if (io.grad_basis && !per_ray_t) {
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-            float v = gb_all[c];
+            float v = gb[c];
             for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
             if ((threadIdx.x & 63) == 0) atomicAdd(&s_gb[c], v);
         }
@@ -380,6 +426,8 @@ __global__ __launch_bounds__(kBlock) void render_bwd_kernel(TreeArgs tr, InstArg
 // launchers
 
 bool render_supported(int K, int C, int dtype) { return K == 16 && C == 8 && dtype >= 0 && dtype <= 2; }
+
+int grad_row_elems(int K, int C) { return ((3 * K + C + 63) / 64) * 64; }
 
 int device_cu_count() {
     static int cached[64] = {0};
@@ -408,41 +456,51 @@ static int grid_for(KernelT kernel, const RayArgs& ra) {
 template <int K, int C, int DT>
 static hipError_t fwd_t(const TreeArgs& tr, const InstArgs& in, const RayArgs& ra, float t_stop, const RenderOut& o,
                         hipStream_t st) {
-    auto kern = render_fwd_kernel<K, C, DT>;
-    const int grid = grid_for(kern, ra);
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, st, tr, in, ra, t_stop, o);
+    if (in.identity) {
+        auto kern = render_fwd_kernel<K, C, DT, true>;
+        hipLaunchKernelGGL(kern, dim3(grid_for(kern, ra)), dim3(kBlock), 0, st, tr, in, ra, t_stop, o);
+    } else {
+        auto kern = render_fwd_kernel<K, C, DT, false>;
+        hipLaunchKernelGGL(kern, dim3(grid_for(kern, ra)), dim3(kBlock), 0, st, tr, in, ra, t_stop, o);
+    }
     return hipGetLastError();
 }
 
 template <int K, int C, int DT>
 static hipError_t bwd_t(const TreeArgs& tr, const InstArgs& in, const RayArgs& ra, const BackwardIO& io,
                         hipStream_t st) {
-    auto kern = render_bwd_kernel<K, C, DT>;
-    const int grid = grid_for(kern, ra);
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, st, tr, in, ra, io);
+    if (in.identity) {
+        auto kern = render_bwd_kernel<K, C, DT, true>;
+        hipLaunchKernelGGL(kern, dim3(grid_for(kern, ra)), dim3(kBlock), 0, st, tr, in, ra, io);
+    } else {
+        auto kern = render_bwd_kernel<K, C, DT, false>;
+        hipLaunchKernelGGL(kern, dim3(grid_for(kern, ra)), dim3(kBlock), 0, st, tr, in, ra, io);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_render_fwd(int K, int C, int dtype, const TreeArgs& tr, const InstArgs& in, const RayArgs& ra,
                              float t_stop, const RenderOut& out, hipStream_t stream) {
+    (void)K;
+    (void)C;
     if (ra.n_slots <= 0) return hipSuccess;
     switch (dtype) {
         case 0: return fwd_t<16, 8, 0>(tr, in, ra, t_stop, out, stream);
         case 1: return fwd_t<16, 8, 1>(tr, in, ra, t_stop, out, stream);
         default: return fwd_t<16, 8, 2>(tr, in, ra, t_stop, out, stream);
     }
-    (void)K; (void)C;
 }
 
 hipError_t launch_render_bwd(int K, int C, int dtype, const TreeArgs& tr, const InstArgs& in, const RayArgs& ra,
                              const BackwardIO& io, hipStream_t stream) {
+    (void)K;
+    (void)C;
     if (ra.n_slots <= 0) return hipSuccess;
     switch (dtype) {
         case 0: return bwd_t<16, 8, 0>(tr, in, ra, io, stream);
         case 1: return bwd_t<16, 8, 1>(tr, in, ra, io, stream);
         default: return bwd_t<16, 8, 2>(tr, in, ra, io, stream);
     }
-    (void)K; (void)C;
 }
 
 }  // namespace neuvv

@@ -38,16 +38,16 @@ def render(tree: VOctree, ray_o: torch.Tensor, ray_d: torch.Tensor, t=0.0, inst:
 def render_backward(tree: VOctree, ray_o, ray_d, rgb, alpha, nsamp, grad_rgb, grad_alpha=None, t=0.0,
                     inst=None, t_stop: float = 1e-4, image_width: int = 0, grads=None, want_basis=True,
                     stream=None):
-    """Accumulates into (grad_hh, grad_wsig, grad_basis) float32 buffers (fresh zeros if grads is None)."""
+    """Accumulates into (grad_leaf [N, ROW], grad_basis [T, C]) float32 buffers (fresh zeros if grads is None)."""
     if grads is None:
         grads = tree.zero_grads()
-    ghh, gws, gb = grads
+    gl, gb = grads
     ray_t = t if isinstance(t, torch.Tensor) else None
     t_scalar = 0.0 if ray_t is not None else float(t)
     _lib.neuvv_render_backward(tree.struct(), inst, ray_o.shape[0], ray_o, ray_d, ray_t, t_scalar, image_width,
-                               t_stop, rgb, alpha, nsamp, grad_rgb, grad_alpha, ghh, gws,
-                               gb if want_basis else None, stream)
-    return ghh, gws, gb
+                               t_stop, rgb, alpha, nsamp, grad_rgb, grad_alpha, gl, gb if want_basis else None,
+                               stream)
+    return gl, gb
 
 
 def compose(rgb: torch.Tensor, alpha: torch.Tensor, depth: torch.Tensor, stream=None):

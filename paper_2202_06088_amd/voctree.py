@@ -14,14 +14,15 @@ from . import _lib
 _TORCH_DTYPE = {_lib.F32: torch.float32, _lib.F16: torch.float16, _lib.BF16: torch.bfloat16}
 
 
-def build_child_table(depth: int, leaf_ijk: np.ndarray):
-    """Host octree over the leaf cells: (child [n_nodes,8] int32, slot_of_input [N] int64)."""
+def build_child_table(depth: int, leaf_ijk: np.ndarray, with_box: bool = False):
+    """Host octree over the leaf cells: (child [n_nodes,8] int32, slot_of_input [N] int64[, box [6]])."""
     ijk = np.ascontiguousarray(leaf_ijk, dtype=np.int32).reshape(-1, 3)
     n_nodes = _lib.neuvv_build_voctree(depth, ijk)
     child = np.empty((n_nodes, 8), np.int32)
     slots = np.empty(ijk.shape[0], np.int64)
-    _lib.neuvv_build_voctree(depth, ijk, child, n_nodes, slots)
-    return child, slots
+    box = np.zeros(6, np.int32)
+    _lib.neuvv_build_voctree(depth, ijk, child, n_nodes, slots, box)
+    return (child, slots, box) if with_box else (child, slots)
 
 
 @dataclass
@@ -38,12 +39,13 @@ class VOctree:
     basis: torch.Tensor          # [T, C] float32
     gamma: torch.Tensor          # [T] float32
     slot_of_input: torch.Tensor  # [N] int64, device
+    box: tuple = (0, 0, 0, 0, 0, 0)  # occupied-cell bounds (lo xyz, hi xyz exclusive)
 
     @classmethod
     def build(cls, depth: int, leaf_ijk, hh, wsig, basis, gamma, dtype: int = _lib.F32,
               device: str = "cuda", stream=None) -> "VOctree":
         """leaf_ijk [N,3]; hh [N,3,K] and wsig [N,C] float32 per input leaf; basis [T,C]; gamma [T]."""
-        child, slots = build_child_table(depth, leaf_ijk)
+        child, slots, box = build_child_table(depth, leaf_ijk, with_box=True)
         hh = np.ascontiguousarray(hh, np.float32)
         wsig = np.ascontiguousarray(wsig, np.float32)
         N, _, K = hh.shape
@@ -53,7 +55,7 @@ class VOctree:
                 torch.from_numpy(child).to(dev), None, None,
                 torch.from_numpy(np.ascontiguousarray(basis, np.float32)).to(dev),
                 torch.from_numpy(np.ascontiguousarray(gamma, np.float32)).to(dev),
-                torch.from_numpy(slots).to(dev))
+                torch.from_numpy(slots).to(dev), tuple(int(v) for v in box))
         t.set_payload(torch.from_numpy(hh).to(dev), torch.from_numpy(wsig).to(dev), stream=stream)
         return t
 
@@ -77,20 +79,35 @@ class VOctree:
         s.n_nodes, s.n_leaves = int(self.child.shape[0]), self.n_leaves
         s.child, s.hh, s.wsig = self.child.data_ptr(), self.hh.data_ptr(), self.wsig.data_ptr()
         s.T, s.basis, s.gamma = self.T, self.basis.data_ptr(), self.gamma.data_ptr()
+        for i in range(6):
+            s.box[i] = self.box[i]
         return s
 
+    @property
+    def grad_row(self) -> int:
+        return _lib.neuvv_grad_row_elems(self.K, self.C)
+
     def zero_grads(self):
-        """Float32 gradient buffers in the float32 payload layout, and [T,C] for the basis."""
-        a, b = self.payload_elems(_lib.F32)
+        """Zeroed float32 gradient buffers: leaf rows [N, ROW] and the basis [T, C]."""
         dev = self.child.device
-        return (torch.zeros(a, dtype=torch.float32, device=dev), torch.zeros(b, dtype=torch.float32, device=dev),
+        return (torch.zeros(self.n_leaves, self.grad_row, dtype=torch.float32, device=dev),
                 torch.zeros(self.T, self.C, dtype=torch.float32, device=dev))
 
-    def unpack_f32(self, packed_hh: torch.Tensor, packed_wsig: torch.Tensor):
-        """Float32 packed arrays -> per input leaf [N,3,K] and [N,C] (layout permutation only)."""
+    def unpack_grad(self, grad_leaf: torch.Tensor):
+        """Leaf gradient rows (slot order) -> per input leaf d/dhh [N,3,K] and d/dwsig [N,C]."""
+        K, C = self.K, self.C
+        rows = grad_leaf.view(self.n_leaves, self.grad_row)[self.slot_of_input]
+        return rows[:, :3 * K].reshape(-1, 3, K), rows[:, 3 * K:3 * K + C]
+
+    def rows_to_payload_f32(self, grad_leaf: torch.Tensor):
+        """Leaf gradient rows -> the float32 payload layout of hh and wsig (a transpose of
+        layout only), for an element-wise optimizer step on float32 payload tensors."""
         N, K, C = self.n_leaves, self.K, self.C
-        gh = -(-3 * K // 4)
-        gw = -(-C // 4)
-        hh = packed_hh.view(gh, N, 4).permute(1, 0, 2).reshape(N, gh * 4)[:, :3 * K].reshape(N, 3, K)
-        ws = packed_wsig.view(gw, N, 4).permute(1, 0, 2).reshape(N, gw * 4)[:, :C]
-        return hh[self.slot_of_input], ws[self.slot_of_input]
+        rows = grad_leaf.view(N, self.grad_row)
+        gh, gw = -(-3 * K // 4), -(-C // 4)
+        hh = torch.zeros(N, gh * 4, device=rows.device)
+        hh[:, :3 * K] = rows[:, :3 * K]
+        ws = torch.zeros(N, gw * 4, device=rows.device)
+        ws[:, :C] = rows[:, 3 * K:3 * K + C]
+        return (hh.view(N, gh, 4).permute(1, 0, 2).reshape(-1).contiguous(),
+                ws.view(N, gw, 4).permute(1, 0, 2).reshape(-1).contiguous())

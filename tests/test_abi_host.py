@@ -83,16 +83,18 @@ def test_build_matches_reference(lib, depth, n, seed):
     G = 1 << depth
     flat = rng.choice(G ** 3, size=min(n, G ** 3), replace=False)
     ijk = np.stack([flat % G, (flat // G) % G, flat // (G * G)], -1).astype(np.int32)
-    child, slots = build_child_table(depth, ijk)
+    child, slots, box = build_child_table(depth, ijk, with_box=True)
     ref_child, ref_slots = reference_tree(depth, ijk)
     assert np.array_equal(child, ref_child)
     assert np.array_equal(slots, ref_slots)
+    assert np.array_equal(box[:3], ijk.min(0)) and np.array_equal(box[3:], ijk.max(0) + 1)
 
 
 def test_build_empty_and_errors(lib):
     from paper_2202_06088_amd.voctree import build_child_table
-    child, slots = build_child_table(4, np.zeros((0, 3), np.int32))
+    child, slots, box = build_child_table(4, np.zeros((0, 3), np.int32), with_box=True)
     assert child.shape == (1, 8) and np.all(child == -1) and slots.shape == (0,)
+    assert np.all(box == 0)
     ijk = np.array([[0, 0, 0], [1, 2, 3], [0, 0, 0]], np.int32)
     with pytest.raises(_lib.NeuvvError) as e:
         _lib.neuvv_build_voctree(3, ijk)
@@ -122,6 +124,12 @@ def test_argument_errors_without_launch(lib):
     t.K, t.depth = 16, 13
     assert lib.neuvv_render(ctypes.byref(t), None, 0, None, None, None, 0.0, 0, 0.0, None, None, None, None,
                             None) == -2
+    t.K, t.depth, t.child, t.basis, t.gamma = 16, 3, 8, 8, 8    # non-NULL placeholders, never dereferenced
+    for bad in ((0, 0, 0, 9, 1, 1), (2, 0, 0, 2, 1, 1), (-1, 0, 0, 1, 1, 1)):
+        for i in range(6):
+            t.box[i] = bad[i]
+        assert lib.neuvv_render(ctypes.byref(t), None, 0, None, None, None, 0.0, 0, 0.0, None, None, None, None,
+                                None) == -2
     t.depth, t.dtype = 9, 7
     assert lib.neuvv_render_backward(ctypes.byref(t), None, 0, None, None, None, 0.0, 0, 0.0, None, None, None,
                                      None, None, None, None, None, None) == -1

@@ -20,10 +20,12 @@ def run_backward(tree, o, d, t, t_scalar, t_stop, g_rgb, g_alpha, inst=None, ima
     tt = tdev(t) if t is not None else t_scalar
     oo, dd = tdev(o), tdev(d)
     rgb, alpha, depth, nsamp = ops.render(tree, oo, dd, tt, inst, t_stop, image_width)
-    ghh, gws, gb = ops.render_backward(tree, oo, dd, rgb, alpha, nsamp, tdev(g_rgb),
-                                       None if g_alpha is None else tdev(g_alpha), tt, inst, t_stop, image_width)
+    gl, gb = ops.render_backward(tree, oo, dd, rgb, alpha, nsamp, tdev(g_rgb),
+                                 None if g_alpha is None else tdev(g_alpha), tt, inst, t_stop, image_width)
     torch.cuda.synchronize()
-    hh, ws = tree.unpack_f32(ghh, gws)
+    hh, ws = tree.unpack_grad(gl)
+    pad = gl[:, 3 * tree.K + tree.C:]
+    assert pad.numel() == 0 or float(pad.abs().max()) == 0.0, "row padding must stay zero"
     return hh.cpu().numpy(), ws.cpu().numpy(), gb.cpu().numpy(), nsamp.cpu().numpy()
 
 
@@ -126,8 +128,14 @@ def test_autograd_function_matches_direct_calls():
     loss.backward()
     g_rgb = (2 * (rgb - target)).detach().contiguous()
     with torch.no_grad():
-        ghh, gws, gb = ops.render_backward(tree, o, d, rgb.detach(), alpha.detach(), nsamp, g_rgb,
-                                           torch.ones_like(alpha), 5.0, None, 0.0, 64)
+        gl, gb = ops.render_backward(tree, o, d, rgb.detach(), alpha.detach(), nsamp, g_rgb,
+                                     torch.ones_like(alpha), 5.0, None, 0.0, 64)
+        ghh, gws = tree.rows_to_payload_f32(gl)
+        # the payload-layout gradient is the same numbers as the rows, per input leaf
+        a_hh, a_ws = tree.unpack_grad(gl)
+        N = tree.n_leaves
+        soa = ghh.view(12, N, 4).permute(1, 0, 2).reshape(N, 48)[tree.slot_of_input].view(N, 3, 16)
+        assert torch.equal(soa, a_hh)
     torch.cuda.synchronize()
     assert rel_err(tree.hh.grad.cpu().numpy(), ghh.cpu().numpy()) < 1e-5
     assert rel_err(tree.wsig.grad.cpu().numpy(), gws.cpu().numpy()) < 1e-5

@@ -77,9 +77,9 @@ def test_full_ring_forward_and_adjoint_sampled(ring):
     g_rgb[sidx] = tdev(gC)
     g_alpha[sidx] = tdev(gA)
     announce("full size: adjoint")
-    ghh, gws, gb = ops.render_backward(tree, o, d, rgb, alpha, nsamp, g_rgb, g_alpha, t, None, 1e-4, W)
+    gl, gb = ops.render_backward(tree, o, d, rgb, alpha, nsamp, g_rgb, g_alpha, t, None, 1e-4, W)
     torch.cuda.synchronize()
-    hh, ws = tree.unpack_f32(ghh, gws)
+    hh, ws = tree.unpack_grad(gl)
     e = [rel_err(hh.cpu().numpy(), ref["grad_hh"]), rel_err(ws.cpu().numpy(), ref["grad_wsig"]),
          rel_err(gb.cpu().numpy(), ref["grad_basis"])]
     announce(f"full size adjoint rel errors {e}")
