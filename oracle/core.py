@@ -45,7 +45,7 @@ def _load():
         P = ctypes.c_void_p
         lib.oracle_render.restype = ctypes.c_int
         lib.oracle_render.argtypes = [ctypes.c_int, ctypes.c_int64, P, ctypes.c_int, ctypes.c_int, P, P,
-                                      ctypes.c_int, P, P, P, ctypes.c_int64, P, P, P,
+                                      ctypes.c_int, P, P, ctypes.c_int, P, P, P, P, P, ctypes.c_int64, P, P, P,
                                       ctypes.c_double, ctypes.c_double, P, P,
                                       P, P, P, P, P, P, P, P, P, ctypes.c_int]
         lib.oracle_pinhole_rays.restype = None
@@ -101,15 +101,18 @@ class Instance:
 
 def render(depth: int, leaf_ijk, hh, wsig, basis, gamma, ray_o, ray_d, ray_t=None, t_scalar=0.0,
            t_stop=1e-4, inst: Optional[Instance] = None, g_rgb=None, g_alpha=None,
-           want_grad_basis=True, threads: Optional[int] = None):
+           want_grad_basis=True, threads: Optional[int] = None, wgam=None, basis_g=None):
     """FP64 render of float32 rays through a tree given by its leaf cells.
 
     leaf_ijk [N,3] int; hh [N,3,K]; wsig [N,C]; basis [T,C]; gamma [T] (all as
     the exact values the product stores: pass dtype-rounded arrays for 16-bit
-    storage). Returns a dict with rgb [n,3], alpha, depth, nsamp, tfinal,
-    margin [n,2] (smallest sampled segment length, smallest relative distance
-    of T to t_stop at a stop test) and, if g_rgb is given, grad_hh [N,3,K],
-    grad_wsig [N,C], grad_basis [T,C] of <g_rgb, rgb> + <g_alpha, alpha>.
+    storage). With wgam [N,Cg] and basis_g [T,Cg] the hyperangle is per point,
+    gamma = pi sigmoid(sum_c wgam_c basis_g_c(t)) (Eq. 6), and gamma is unused.
+    Returns a dict with rgb [n,3], alpha, depth, nsamp, tfinal, margin [n,2]
+    (smallest sampled segment length, smallest relative distance of T to t_stop
+    at a stop test) and, if g_rgb is given, grad_hh [N,3,K], grad_wsig [N,C],
+    grad_basis [T,C] (and grad_wgam [N,Cg], grad_basis_g [T,Cg]) of
+    <g_rgb, rgb> + <g_alpha, alpha>.
     """
     lib = _load()
     leaf_ijk = _c(leaf_ijk, np.int32).reshape(-1, 3)
@@ -126,6 +129,12 @@ def render(depth: int, leaf_ijk, hh, wsig, basis, gamma, ray_o, ray_d, ray_t=Non
     n = ray_o.shape[0]
     ray_t = None if ray_t is None else _c(ray_t, np.float32).reshape(-1)
     ip = None if inst is None else inst.packed()
+    Cg = 0
+    if wgam is not None:
+        wgam = _c(wgam, np.float64)
+        basis_g = _c(basis_g, np.float64)
+        Cg = wgam.shape[1]
+        assert wgam.shape[0] == N and basis_g.shape == (T, Cg)
     out = dict(rgb=np.zeros((n, 3)), alpha=np.zeros(n), depth=np.zeros(n),
                nsamp=np.zeros(n, np.int32), tfinal=np.zeros(n), margin=np.zeros((n, 2)))
     gr = ga = None
@@ -135,7 +144,11 @@ def render(depth: int, leaf_ijk, hh, wsig, basis, gamma, ray_o, ray_d, ray_t=Non
         out["grad_hh"] = np.zeros((N, 3, K))
         out["grad_wsig"] = np.zeros((N, C))
         out["grad_basis"] = np.zeros((T, C)) if want_grad_basis else None
+        if wgam is not None:
+            out["grad_wgam"] = np.zeros((N, Cg))
+            out["grad_basis_g"] = np.zeros((T, Cg)) if want_grad_basis else None
     rc = lib.oracle_render(depth, N, _p(leaf_ijk), K, C, _p(hh), _p(wsig), T, _p(basis), _p(gamma),
+                           Cg, _p(wgam), _p(basis_g), _p(out.get("grad_wgam")), _p(out.get("grad_basis_g")),
                            _p(ip), n, _p(ray_o), _p(ray_d), _p(ray_t), float(t_scalar), float(t_stop),
                            _p(gr), _p(ga), _p(out["rgb"]), _p(out["alpha"]), _p(out["depth"]),
                            _p(out["nsamp"]), _p(out["tfinal"]), _p(out["margin"]),

@@ -93,6 +93,30 @@ static void hh_basis(int K, const double d[3], double gam, double* h) {
         }
 }
 
+/* Direction factors Y_k and the (n, l) of each of the first K functions. */
+static void hh_dir_factors(int K, const double d[3], double* Y, int* nk, int* lk) {
+    int k = 0;
+    for (int n = 0; k < K; ++n)
+        for (int l = 0; l <= n && k < K; ++l)
+            for (int m = -l; m <= l && k < K; ++m) {
+                Y[k] = real_sh(l, m, d[0], d[1], d[2]);
+                nk[k] = n; lk[k] = l; ++k;
+            }
+}
+
+/* g_nl(gamma) = A_nl sin^l(g) C^{l+1}_{n-l}(cos g) and its derivative in gamma, using
+   d/dx C^lam_k(x) = 2 lam C^{lam+1}_{k-1}(x). */
+static void hh_radial(int n, int l, double gam, double* g, double* dg) {
+    double A = dfact(2 * l) * sqrt(2.0 * (n + 1) * fact(n - l) / (M_PI * fact(n + l + 1)));
+    double s = sin(gam), c = cos(gam);
+    double C0 = gegenbauer(n - l, l + 1.0, c);
+    double C1 = n - l >= 1 ? 2.0 * (l + 1.0) * gegenbauer(n - l - 1, l + 2.0, c) : 0.0;
+    double sl = pow(s, l);
+    *g = A * sl * C0;
+    double dsl = l >= 1 ? l * pow(s, l - 1) * c : 0.0;
+    *dg = A * (dsl * C0 - sl * s * C1);
+}
+
 void oracle_hh_basis(int K, int64_t n, const double* dirs, const double* gam, double* out) {
     for (int64_t i = 0; i < n; ++i) hh_basis(K, dirs + 3 * i, gam[i], out + i * K);
 }
@@ -141,7 +165,7 @@ static int64_t hs_find(const hashset* h, int64_t i, int64_t j, int64_t k) {
 static double softplus(double x) { return (x > 0 ? x : 0.0) + log1p(exp(-fabs(x))); }
 static double sigmoid(double x) { return 1.0 / (1.0 + exp(-x)); }
 
-typedef struct { int64_t leaf; double delta, smid, x, sig, z[3], c[3], Tin, alpha; } sample_t;
+typedef struct { int64_t leaf; double delta, smid, x, sig, z[3], c[3], Tin, alpha, yg, gam; } sample_t;
 
 /* Time re-mapping (Eq. 13): tau = t + off; wrap into [0,T) or clamp into [0,T-1];
    i0 = floor(tau), f = tau - i0, i1 = min(i0+1, T-1); the last frame is held on [T-1,T). */
@@ -161,6 +185,8 @@ static void time_lerp(double t, double off, int wrap, int T, int* i0, int* i1, d
 int oracle_render(int depth, int64_t n_leaves, const int32_t* leaf_ijk,
                   int K, int C, const double* hh /*[N][3][K]*/, const double* wsig /*[N][C]*/,
                   int T, const double* basis /*[T][C]*/, const double* gamma /*[T]*/,
+                  int Cg, const double* wgam /* NULL or [N][Cg] */, const double* basis_g /* [T][Cg] */,
+                  double* grad_wgam /* NULL or [N][Cg] */, double* grad_basis_g /* NULL or [T][Cg] */,
                   const double* inst /* NULL or rot[9] row-major, trans[3], scale, time_offset, wrap */,
                   int64_t n_rays, const float* ray_o, const float* ray_d, const float* ray_t,
                   double t_scalar, double t_stop,
@@ -169,6 +195,7 @@ int oracle_render(int depth, int64_t n_leaves, const int32_t* leaf_ijk,
                   double* margin /* NULL or [n][2]: min sampled delta, min |T - t_stop|/t_stop */,
                   double* grad_hh, double* grad_wsig, double* grad_basis, int n_threads) {
     if (depth < 1 || depth > 20 || K < 1 || K > 64 || C < 1 || C > 64 || T < 1) return -3;
+    if (wgam && (Cg < 1 || Cg > 64 || !basis_g)) return -3;
     hashset hs;
     int rc = hs_build(&hs, n_leaves, leaf_ijk);
     if (rc) { free(hs.keys); free(hs.vals); return rc; }
@@ -212,6 +239,13 @@ int oracle_render(int depth, int64_t n_leaves, const int32_t* leaf_ijk,
             for (int c = 0; c < C; ++c) b[c] = (1.0 - f) * basis[i0 * C + c] + f * basis[i1 * C + c];
             double gam = (1.0 - f) * gamma[i0] + f * gamma[i1];
             hh_basis(K, dirn, gam, h);
+            /* per-point hyperangle (Eq. 6): gamma = pi sigmoid(sum_c wgam_c bg_c), h per sample */
+            double bg[64], Yd[64];
+            int nk[64], lk[64];
+            if (wgam) {
+                for (int c = 0; c < Cg; ++c) bg[c] = (1.0 - f) * basis_g[i0 * Cg + c] + f * basis_g[i1 * Cg + c];
+                hh_dir_factors(K, dirn, Yd, nk, lk);
+            }
 
             /* clip to the box [0,G]^3 */
             double u_in = 0.0, u_out = INFINITY;
@@ -257,9 +291,23 @@ int oracle_render(int depth, int64_t n_leaves, const int32_t* leaf_ijk,
                             double x = 0.0;
                             for (int c = 0; c < C; ++c) x += wsig[q * C + c] * b[c];
                             s->x = x; s->sig = softplus(x);
+                            double hs[64];
+                            const double* hk = h;
+                            if (wgam) {
+                                double y = 0.0;
+                                for (int c = 0; c < Cg; ++c) y += wgam[q * Cg + c] * bg[c];
+                                s->yg = y;
+                                s->gam = M_PI * sigmoid(y);
+                                for (int k = 0; k < K; ++k) {
+                                    double g, dg;
+                                    hh_radial(nk[k], lk[k], s->gam, &g, &dg);
+                                    hs[k] = g * Yd[k];
+                                }
+                                hk = hs;
+                            }
                             for (int ch = 0; ch < 3; ++ch) {
                                 double z = 0.0;
-                                for (int k = 0; k < K; ++k) z += hh[(q * 3 + ch) * K + k] * h[k];
+                                for (int k = 0; k < K; ++k) z += hh[(q * 3 + ch) * K + k] * hk[k];
                                 s->z[ch] = z; s->c[ch] = sigmoid(z);
                             }
                             double e = exp(-s->sig * s->delta);
@@ -296,8 +344,9 @@ int oracle_render(int depth, int64_t n_leaves, const int32_t* leaf_ijk,
             if (want_grad && ns > 0) {
                 double gC[3] = {g_rgb[3 * r], g_rgb[3 * r + 1], g_rgb[3 * r + 2]};
                 double gA = g_alpha ? g_alpha[r] : 0.0;
-                double Tfin = Tr, prefix[3] = {0, 0, 0}, gb[64];
+                double Tfin = Tr, prefix[3] = {0, 0, 0}, gb[64], gbg[64];
                 for (int c = 0; c < C; ++c) gb[c] = 0.0;
+                if (wgam) for (int c = 0; c < Cg; ++c) gbg[c] = 0.0;
                 for (int k = 0; k < ns; ++k) {
                     const sample_t* s = &S[k];
                     double w = s->Tin * s->alpha, Tnext = s->Tin * (1.0 - s->alpha);
@@ -310,11 +359,35 @@ int oracle_render(int depth, int64_t n_leaves, const int32_t* leaf_ijk,
                     /* dC/dsigma_k = delta_k (T_{k+1} c_k - sum_{i>k} w_i c_i); dA/dsigma_k = delta_k T_final */
                     double gsig = s->delta * (Tnext * gdotc - gdotsuf) + gA * s->delta * Tfin;
                     double gx = gsig * sigmoid(s->x);
+                    double hs[64], dhs[64];
+                    const double* hk = h;
+                    if (wgam) {
+                        for (int k = 0; k < K; ++k) {
+                            double g, dg;
+                            hh_radial(nk[k], lk[k], s->gam, &g, &dg);
+                            hs[k] = g * Yd[k];
+                            dhs[k] = dg * Yd[k];
+                        }
+                        hk = hs;
+                    }
+                    double ggam = 0.0;   /* dL/dgamma of this sample */
                     for (int ch = 0; ch < 3; ++ch) {
                         double gz = gC[ch] * w * s->c[ch] * (1.0 - s->c[ch]);
                         for (int kk = 0; kk < K; ++kk) {
 #pragma omp atomic
-                            grad_hh[(s->leaf * 3 + ch) * K + kk] += gz * h[kk];
+                            grad_hh[(s->leaf * 3 + ch) * K + kk] += gz * hk[kk];
+                            if (wgam) ggam += gz * hh[(s->leaf * 3 + ch) * K + kk] * dhs[kk];
+                        }
+                    }
+                    if (wgam) {
+                        double sg = sigmoid(s->yg);
+                        double gy = ggam * M_PI * sg * (1.0 - sg);
+                        for (int c = 0; c < Cg; ++c) {
+                            if (grad_wgam) {
+#pragma omp atomic
+                                grad_wgam[s->leaf * Cg + c] += gy * bg[c];
+                            }
+                            gbg[c] += gy * wgam[s->leaf * Cg + c];
                         }
                     }
                     for (int c = 0; c < C; ++c) {
@@ -329,6 +402,13 @@ int oracle_render(int depth, int64_t n_leaves, const int32_t* leaf_ijk,
                         grad_basis[i0 * C + c] += (1.0 - f) * gb[c];
 #pragma omp atomic
                         grad_basis[i1 * C + c] += f * gb[c];
+                    }
+                if (wgam && grad_basis_g)
+                    for (int c = 0; c < Cg; ++c) {
+#pragma omp atomic
+                        grad_basis_g[i0 * Cg + c] += (1.0 - f) * gbg[c];
+#pragma omp atomic
+                        grad_basis_g[i1 * Cg + c] += f * gbg[c];
                     }
             }
         }

@@ -79,6 +79,13 @@ __device__ __forceinline__ df df_div(df a, df b) {
     float q3 = r.hi / b.hi;
     return df_add(df_quick(q1, q2), df_from(q3));
 }
+// 1/d: hardware reciprocal refined by one compensated Newton step (~46 bits).
+__device__ __forceinline__ df df_rcp(df d) {
+#pragma clang fp contract(off)
+    const float r = __builtin_amdgcn_rcpf(d.hi);
+    const float e = __builtin_fmaf(-d.hi, r, 1.0f) - d.lo * r;
+    return df_quick(r, r * e);
+}
 __device__ __forceinline__ bool df_lt(df a, df b) { return a.hi < b.hi || (a.hi == b.hi && a.lo < b.lo); }
 __device__ __forceinline__ float df_f(df a) { return a.hi + a.lo; }
 
@@ -240,7 +247,45 @@ __device__ __forceinline__ void time_setup(const TreeArgs& tr, const InstArgs& i
 template <bool IDENT>
 __device__ __forceinline__ void ray_setup(const TreeArgs& tr, const InstArgs& in, const float o[3],
                                           const float d[3], float t, RaySetup& rs) {
+    // Coarse reject in plain float against the box grown by one leaf on every
+    // side: float rounding of the clip is far below that margin for any local
+    // coordinate below ~1e5, so a ray rejected here misses the exact box.
+    {
+        float of[3], dfl[3];
+        if constexpr (IDENT) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) { of[a] = o[a]; dfl[a] = d[a]; }
+        } else {
+            const float is = 1.0f / in.scale;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                of[a] = ((o[0] - in.trans[0]) * in.rot[a] + (o[1] - in.trans[1]) * in.rot[3 + a] +
+                         (o[2] - in.trans[2]) * in.rot[6 + a]) * is;
+                dfl[a] = (d[0] * in.rot[a] + d[1] * in.rot[3 + a] + d[2] * in.rot[6 + a]) * is;
+            }
+        }
+        float tn = 0.0f, tf = INFINITY;
+        bool pass = true, small = true;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            small = small && fabsf(of[a]) < 1.0e5f;
+            const float lo = (float)tr.box_lo[a] - 1.0f, hi = (float)tr.box_hi[a] + 1.0f;
+            if (dfl[a] == 0.0f) {
+                pass = pass && of[a] >= lo && of[a] < hi;
+            } else {
+                const float iv = 1.0f / dfl[a];
+                const float t0 = (lo - of[a]) * iv, t1 = (hi - of[a]) * iv;
+                tn = fmaxf(tn, fminf(t0, t1));
+                tf = fminf(tf, fmaxf(t0, t1));
+            }
+        }
+        if (small && !(pass && tn < tf)) {
+            rs.hit = false;
+            return;
+        }
+    }
     if constexpr (IDENT) {
+#pragma unroll
         for (int a = 0; a < 3; ++a) { rs.O[a] = df_from(o[a]); rs.D[a] = df_from(d[a]); }
     } else {
         df diff[3];
@@ -259,32 +304,37 @@ __device__ __forceinline__ void ray_setup(const TreeArgs& tr, const InstArgs& in
             rs.D[a] = df_div(ad, s);
         }
     }
-    float dl2 = 0.0f, dw2 = 0.0f;
+    float dl2 = 0.0f, dw2 = 0.0f, dmax = 0.0f;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         float v = df_f(rs.D[a]);
         dl2 += v * v;
         dw2 += d[a] * d[a];
+        dmax = fmaxf(dmax, fabsf(v));
     }
     rs.len_local = sqrtf(dl2);
     rs.len_world = sqrtf(dw2);
     bool hit = rs.len_local > 0.0f;
     float inv_len = hit ? 1.0f / rs.len_local : 0.0f;
+#pragma unroll
     for (int a = 0; a < 3; ++a) rs.dir[a] = df_f(rs.D[a]) * inv_len;
     if (!hit) rs.dir[2] = 1.0f;
-    // clip to the occupied-cell box [lo, hi) (no occupied cell lies outside it)
+    // clip to the occupied-cell box [lo, hi) (no occupied cell lies outside it).
+    // Direction components below 1e-20 of the largest are treated as zero: their
+    // plane crossings lie beyond any representable ray parameter.
     df u_in = df_from(0.0f), u_out = df_from(0.0f);
     bool have_out = false;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        rs.sgn[a] = rs.D[a].hi > 0.0f ? 1 : (rs.D[a].hi < 0.0f ? -1 : 0);
+        const bool zero = fabsf(rs.D[a].hi) <= 1.0e-20f * dmax;
+        rs.sgn[a] = zero ? 0 : (rs.D[a].hi > 0.0f ? 1 : -1);
         const float lo_p = (float)tr.box_lo[a], hi_p = (float)tr.box_hi[a];
         if (rs.sgn[a] == 0) {
             if (df_lt(rs.O[a], df_from(lo_p)) || !df_lt(rs.O[a], df_from(hi_p))) hit = false;
             rs.inv[a] = df_from(0.0f);
             continue;
         }
-        rs.inv[a] = df_div(df_from(1.0f), rs.D[a]);
+        rs.inv[a] = df_rcp(rs.D[a]);
         df t0 = df_mul(df_sub(df_from(lo_p), rs.O[a]), rs.inv[a]);
         df t1 = df_mul(df_sub(df_from(hi_p), rs.O[a]), rs.inv[a]);
         df lo = rs.sgn[a] > 0 ? t0 : t1, hi = rs.sgn[a] > 0 ? t1 : t0;
@@ -302,15 +352,16 @@ __device__ __forceinline__ void ray_setup(const TreeArgs& tr, const InstArgs& in
 // octree walk
 
 struct Walk {
-    df u;          // current ray parameter
-    int cell[3];   // leaf-level cell containing the ray just after u
-    int lvl;       // path[0..lvl] holds the ancestors of cell
+    int cell[3];     // leaf-level cell containing the ray just after the entry point
+    int lvl;         // path[0..lvl] holds the ancestors of cell
     int steps;
+    int entry_axis;  // the entry point is the crossing of plane entry_plane on this axis; -1: u_in
+    int entry_plane;
+    float u_est;     // float estimate of the entry parameter
     bool done;
 };
 
 __device__ __forceinline__ void walk_begin(const TreeArgs& tr, const RaySetup& rs, Walk& w) {
-    w.u = rs.u_in;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         df p = df_add(rs.O[a], df_mul(rs.u_in, rs.D[a]));
@@ -319,19 +370,52 @@ __device__ __forceinline__ void walk_begin(const TreeArgs& tr, const RaySetup& r
     }
     w.lvl = 0;
     w.steps = 0;
+    w.entry_axis = -1;
+    w.entry_plane = 0;
+    w.u_est = df_f(rs.u_in);
     w.done = !rs.hit;
+}
+
+// v[i] for a runtime i in [0, 3) without indexing a local array (which would
+// place it in scratch memory).
+#define NEUVV_SEL3(v, i) ((i) == 0 ? +(v)[0] : ((i) == 1 ? +(v)[1] : +(v)[2]))
+
+// Exact (compensated) parameter at which the ray crosses the plane x_a = p.
+__device__ __forceinline__ df crossing(const RaySetup& rs, int a, int p) {
+    // branches over constant members (no address arithmetic), so rs stays in registers
+    float oh, ol, ih, il;
+    if (a == 0) {
+        oh = rs.O[0].hi; ol = rs.O[0].lo; ih = rs.inv[0].hi; il = rs.inv[0].lo;
+    } else if (a == 1) {
+        oh = rs.O[1].hi; ol = rs.O[1].lo; ih = rs.inv[1].hi; il = rs.inv[1].lo;
+    } else {
+        oh = rs.O[2].hi; ol = rs.O[2].lo; ih = rs.inv[2].hi; il = rs.inv[2].lo;
+    }
+    return df_mul(df_sub(df_from((float)p), df{oh, ol}), df{ih, il});
+}
+
+__device__ __forceinline__ df entry_param(const RaySetup& rs, const Walk& w) {
+    return w.entry_axis < 0 ? rs.u_in : crossing(rs, w.entry_axis, w.entry_plane);
 }
 
 // Advances to the next occupied leaf segment of positive length. Returns its
 // slot and writes delta (leaf units) and umid (ray parameter of the segment
 // midpoint); returns -1 when the ray has left the box. path points at this
 // lane's column of a [kMaxDepth][stride] LDS array.
+//
+// Every decision of the walk (which face a node is left through, which cell
+// the ray enters, whether it leaves the box) is taken on float estimates
+// whose rounding error is bounded; only when an estimate falls within that
+// bound of the decision threshold is it redone in compensated arithmetic.
+// Segment lengths of leaves always come from compensated entry and exit
+// parameters. The sequence of cells is therefore that of the exact walk.
 __device__ __forceinline__ int walk_next(const TreeArgs& tr, const int* __restrict__ s_child, int n_lds,
                                          int* path, int stride, const RaySetup& rs, Walk& w, float& delta,
                                          float& umid) {
     const int Dp = tr.depth;
     const int G = 1 << Dp;
     const int max_steps = 3 * G + 16;
+    constexpr float kRel = 1.0e-6f;   // bound on the relative error of a float estimate (~16 ulp)
     while (!w.done) {
         if (++w.steps > max_steps) { w.done = true; break; }
         // descend from the deepest valid ancestor
@@ -350,30 +434,78 @@ __device__ __forceinline__ int walk_next(const TreeArgs& tr, const int* __restri
             path[lvl * stride] = ch;
         }
         const int S = 1 << sh;
-        int corner[3];
-        df ue = df_from(0.0f);
-        int am = -1;
+        int corner[3], plane[3];
+        float est[3], tol[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             corner[a] = w.cell[a] & ~(S - 1);
-            if (rs.sgn[a] != 0) {
-                const float plane = (float)(corner[a] + (rs.sgn[a] > 0 ? S : 0));
-                const df ua = df_mul(df_sub(df_from(plane), rs.O[a]), rs.inv[a]);
-                if (am < 0 || df_lt(ua, ue)) { ue = ua; am = a; }
+            plane[a] = corner[a] + (rs.sgn[a] > 0 ? S : 0);
+            if (rs.sgn[a] == 0) {
+                est[a] = INFINITY;
+                tol[a] = 0.0f;
+            } else {
+                const float of = rs.O[a].hi, iv = rs.inv[a].hi;
+                est[a] = ((float)plane[a] - of) * iv;
+                tol[a] = kRel * (fabsf((float)plane[a]) + fabsf(of)) * fabsf(iv) + 1.0e-30f;
             }
         }
-        const bool last = !df_lt(ue, rs.u_out);
-        if (last) ue = rs.u_out;
+        // exit face: smallest estimate, resolved exactly when another is within the bounds
+        int am = 0;
+        {
+            float e = est[0];
+            if (est[1] < e) { am = 1; e = est[1]; }
+            if (est[2] < e) am = 2;
+        }
+        const float e_am = NEUVV_SEL3(est, am), t_am = NEUVV_SEL3(tol, am);
+        bool exact_ue = false;
+        df ue;
+        {
+            bool near = false;
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                if (a != am && rs.sgn[a] != 0 && est[a] - e_am <= tol[a] + t_am) near = true;
+            if (near) {
+                int best = -1;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    if (rs.sgn[a] == 0 || est[a] - e_am > tol[a] + t_am) continue;
+                    const df ua = crossing(rs, a, plane[a]);
+                    if (best < 0 || df_lt(ua, ue)) { ue = ua; best = a; }
+                }
+                am = best;
+                exact_ue = true;
+            }
+        }
+        float ue_est = exact_ue ? df_f(ue) : e_am;
+        const float ue_tol = exact_ue ? 0.0f : t_am;
+        // leaving the box?
+        const float uo = df_f(rs.u_out);
+        bool last;
+        if (ue_est - ue_tol > uo + kRel * fabsf(uo)) {
+            last = true;
+        } else if (ue_est + ue_tol < uo - kRel * fabsf(uo)) {
+            last = false;
+        } else {
+            if (!exact_ue) { ue = crossing(rs, am, NEUVV_SEL3(plane, am)); exact_ue = true; }
+            last = !df_lt(ue, rs.u_out);
+        }
         bool produced = false;
-        if (leaf >= 0 && df_lt(w.u, ue)) {
-            delta = df_f(df_sub(ue, w.u)) * rs.len_local;
-            umid = 0.5f * (df_f(w.u) + df_f(ue));
-            produced = delta > 0.0f;
+        if (leaf >= 0) {
+            df ux;
+            if (last) ux = rs.u_out;
+            else if (exact_ue) ux = ue;
+            else ux = crossing(rs, am, NEUVV_SEL3(plane, am));
+            const df u0 = entry_param(rs, w);
+            if (df_lt(u0, ux)) {
+                delta = df_f(df_sub(ux, u0)) * rs.len_local;
+                umid = 0.5f * (df_f(u0) + df_f(ux));
+                produced = delta > 0.0f;
+            }
+            if (!exact_ue && !last) { ue = ux; exact_ue = true; }
         }
         if (last) {
             w.done = true;
         } else {
-            if (df_lt(w.u, ue)) w.u = ue;
             int nc[3];
             bool out = false;
 #pragma unroll
@@ -385,8 +517,17 @@ __device__ __forceinline__ int walk_next(const TreeArgs& tr, const int* __restri
                 } else if (rs.sgn[b] == 0) {
                     c = w.cell[b];
                 } else {
-                    const df p = df_add(rs.O[b], df_mul(w.u, rs.D[b]));
-                    c = df_cell(p, rs.sgn[b]);
+                    const float of = rs.O[b].hi, dfb = rs.D[b].hi;
+                    const float pf = __builtin_fmaf(ue_est, dfb, of);
+                    const float err = ue_tol * fabsf(dfb) + kRel * (fabsf(of) + fabsf(ue_est * dfb)) + 1.0e-30f;
+                    const float r = rintf(pf);
+                    if (fabsf(pf - r) > err) {
+                        c = rs.sgn[b] > 0 ? (int)floorf(pf) : (int)ceilf(pf) - 1;
+                    } else {
+                        if (!exact_ue) { ue = crossing(rs, am, NEUVV_SEL3(plane, am)); exact_ue = true; }
+                        const df p = df_add(rs.O[b], df_mul(ue, rs.D[b]));
+                        c = df_cell(p, rs.sgn[b]);
+                    }
                     c = c < corner[b] ? corner[b] : (c > corner[b] + S - 1 ? corner[b] + S - 1 : c);
                 }
                 nc[b] = c;
@@ -401,6 +542,9 @@ __device__ __forceinline__ int walk_next(const TreeArgs& tr, const int* __restri
                 w.cell[0] = nc[0];
                 w.cell[1] = nc[1];
                 w.cell[2] = nc[2];
+                w.entry_axis = am;
+                w.entry_plane = NEUVV_SEL3(plane, am);
+                w.u_est = ue_est;
             }
         }
         if (produced) return leaf;

@@ -53,8 +53,9 @@ def sigmoid(x):
     return 1.0 / (1.0 + math.exp(-x))
 
 
-def render(depth, leaf_ijk, hh, wsig, basis, gamma, o, d, t, t_stop):
-    """Single identity-instance ray, t an exact frame index or fraction in [0, T-1]."""
+def render(depth, leaf_ijk, hh, wsig, basis, gamma, o, d, t, t_stop, wgam=None, basis_g=None):
+    """Single identity-instance ray, t an exact frame index or fraction in [0, T-1].
+    With wgam/basis_g the hyperangle of each sample is pi * sigmoid(wgam . basis_g(t)) (Eq. 6)."""
     G = 1 << depth
     occ = np.zeros((G, G, G), bool)
     idx = -np.ones((G, G, G), np.int64)
@@ -77,8 +78,13 @@ def render(depth, leaf_ijk, hh, wsig, basis, gamma, o, d, t, t_stop):
     sig_del = []
     cols = []
     mids = []
+    if wgam is not None:
+        bg = (1 - f) * basis_g[i0].astype(np.float64) + f * basis_g[i1].astype(np.float64)
     for (i, j, k, u0, u1) in segs:
         q = idx[i, j, k]
+        if wgam is not None:
+            gq = math.pi * sigmoid(float(np.dot(wgam[q].astype(np.float64), bg)))
+            h = hh_basis(K, d / n, gq)
         sig = softplus(float(np.dot(wsig[q].astype(np.float64), b)))
         c = np.array([sigmoid(float(np.dot(hh[q, ch].astype(np.float64), h))) for ch in range(3)])
         sig_del.append(sig * (u1 - u0) * n)

@@ -259,3 +259,77 @@ def test_pinhole_rays(oracle_lib):
     pix = np.array([0, 5, 64 * 47 + 63, 1000], np.int32)
     o2, d2 = oracle_lib.pinhole_rays(cam.width, cam.height, cam.intr(), cam.c2w, pix)
     assert np.array_equal(d2, d[pix]) and np.array_equal(o2, o[pix])
+
+
+# ---------------------------------------------------------------------------
+# per-point hyperangle (Eq. 6): gamma = pi * sigmoid(sum_c wgam_c B_c(t))
+
+def test_per_point_hyperangle_reduces_to_global_table(oracle_lib):
+    sc = make_scene(5, 3000, "random", seed=13, T=10)
+    o, d = random_rays(sc.G, 300, np.random.default_rng(14))
+    wg = np.ones((sc.n_leaves, 1), np.float32)
+    g = sc.gamma.astype(np.float64) / math.pi
+    bg = np.log(g / (1 - g)).astype(np.float32)[:, None]     # logit: sigmoid(bg) * pi = gamma
+    for t in (0.0, 3.0, 9.0):
+        a = oracle_lib.render(5, sc.leaf_ijk, sc.hh, sc.wsig, sc.basis, sc.gamma, o, d, None, t, 1e-4)
+        b = oracle_lib.render(5, sc.leaf_ijk, sc.hh, sc.wsig, sc.basis, sc.gamma * 0 + 0.123, o, d, None, t, 1e-4,
+                              wgam=wg, basis_g=bg)
+        # basis_g holds float32 logits: gamma agrees to float32 rounding of the logit
+        assert np.abs(a["rgb"] - b["rgb"]).max() < 1e-6
+        assert np.abs(a["alpha"] - b["alpha"]).max() < 1e-14
+
+
+@pytest.mark.parametrize("t_stop,seed", [(0.0, 21), (0.05, 22)])
+def test_per_point_hyperangle_matches_bruteforce(oracle_lib, t_stop, seed):
+    ijk, hh, wsig, basis, gamma = tiny_scene(3, seed=seed)
+    rng = np.random.default_rng(seed + 1)
+    wg = rng.normal(0, 1, (ijk.shape[0], 4)).astype(np.float32)
+    bg = rng.normal(0, 1, (basis.shape[0], 4)).astype(np.float32)
+    o1, d1 = random_rays(8, 40, rng, inside_frac=0.25)
+    o2, d2 = special_rays(8)
+    o = np.concatenate([o1, o2])
+    d = np.concatenate([d1, d2])
+    res = oracle_lib.render(3, ijk, hh, wsig, basis, gamma, o, d, None, 3.0, t_stop, wgam=wg, basis_g=bg)
+    for r in range(o.shape[0]):
+        C, A, D, ns = BF.render(3, ijk, hh, wsig, basis, gamma, o[r].astype(np.float64), d[r].astype(np.float64),
+                                3.0, t_stop, wgam=wg, basis_g=bg)
+        assert np.allclose(res["rgb"][r], C, rtol=0, atol=1e-12), r
+        assert abs(res["alpha"][r] - A) < 1e-12 and res["nsamp"][r] == ns, r
+
+
+def test_per_point_hyperangle_gradient_finite_differences(oracle_lib):
+    ijk, hh, wsig, basis, gamma = tiny_scene(3, n_leaves=60, seed=31, T=5)
+    rng = np.random.default_rng(32)
+    hh = hh.astype(np.float64)
+    wg = rng.normal(0, 1, (60, 3))
+    bg = rng.normal(0, 1, (5, 3))
+    o, d = random_rays(8, 30, rng)
+    t = rng.uniform(0, 4, 30).astype(np.float32)
+    gC = rng.normal(size=(30, 3))
+    gA = rng.normal(size=30)
+
+    def run(hh_, wg_, bg_):
+        r = oracle_lib.render(3, ijk, hh_, wsig, basis, gamma, o, d, t, 0.0, 0.0, g_rgb=gC, g_alpha=gA,
+                              wgam=wg_, basis_g=bg_)
+        return float((r["rgb"] * gC).sum() + (r["alpha"] * gA).sum()), r
+
+    L0, res = run(hh, wg, bg)
+    eps = 1e-6
+    touched = np.unique(np.nonzero(np.abs(res["grad_wgam"]).sum(1))[0])
+    assert touched.size > 5
+    for q in touched[:6]:
+        for c in range(3):
+            a = wg.copy(); a[q, c] += eps
+            b = wg.copy(); b[q, c] -= eps
+            fd = (run(hh, a, bg)[0] - run(hh, b, bg)[0]) / (2 * eps)
+            assert abs(fd - res["grad_wgam"][q, c]) < 1e-7 * max(1, abs(fd))
+        a = hh.copy(); a[q, 1, 7] += eps
+        b = hh.copy(); b[q, 1, 7] -= eps
+        fd = (run(a, wg, bg)[0] - run(b, wg, bg)[0]) / (2 * eps)
+        assert abs(fd - res["grad_hh"][q, 1, 7]) < 1e-7 * max(1, abs(fd))
+    for i in range(5):
+        for c in range(3):
+            a = bg.copy(); a[i, c] += eps
+            b = bg.copy(); b[i, c] -= eps
+            fd = (run(hh, wg, a)[0] - run(hh, wg, b)[0]) / (2 * eps)
+            assert abs(fd - res["grad_basis_g"][i, c]) < 1e-7 * max(1, abs(fd))
