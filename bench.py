@@ -70,6 +70,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--dtype", choices=["f32", "f16", "bf16"], default="f32")
+    ap.add_argument("--layout", choices=["soa", "rows"], default="soa",
+                    help="leaf payload layout: 16-byte-vector SoA or leaf-major rows")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -97,7 +99,8 @@ def main():
     t_frame = float(np.random.default_rng(2002).uniform(0, sc.T))
     log(f"scene: {sc.n_leaves} leaves, T={sc.T}, t={t_frame:.3f} ({time.time() - t0:.1f}s)")
     dev = "cuda"
-    tree = VOctree.build(sc.depth, sc.leaf_ijk, sc.hh, sc.wsig, sc.basis, sc.gamma, dt, dev)
+    layout = _lib.LAYOUT_VEC_SOA if args.layout == "soa" else _lib.LAYOUT_LEAF_ROWS
+    tree = VOctree.build(sc.depth, sc.leaf_ijk, sc.hh, sc.wsig, sc.basis, sc.gamma, dt, dev, layout=layout)
     W, H = 1920, 1080
     n_cam = W * H
     n = 8 * n_cam
@@ -171,7 +174,7 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
         "config": {"workload": workload, "depth": sc.depth, "leaves": sc.n_leaves, "K": sc.K, "C": sc.C,
                    "T": sc.T, "rays_per_step": n, "image": "8 x 1920x1080", "t_stop": t_stop,
-                   "step": "render fwd + adjoint"},
+                   "step": "render fwd + adjoint", "layout": args.layout},
         "fwd_mrays_s": round(n / (fwd_ms * 1e-3) / 1e6, 2),
         "samples_per_step": total_samples, "hit_rays": hit,
         "roofline": roof, "roofline_other_kernel": roof_other,
@@ -223,8 +226,8 @@ def cpu_leg(sc, cams, t_frame, t_stop, rgb_gpu, g_rgb, grads, tree, budget_s):
     return {
         "cpu_baseline": {"value": round(len(g_idx) / dt / 1e6, 5), "unit": "Mrays/s", "cores": threads,
                          "kind": "oracle",
-                         "sample": f"every {stride}th ray of the 8-camera ring ({len(g_idx)} rays), "
-                                   "FP64 forward + gradient"},
+                         "sample": (f"every {stride}th ray of" if stride > 1 else "all rays of") +
+                                   f" the 8-camera ring ({len(g_idx)} rays), FP64 forward + gradient"},
         "psnr_vs_fp64_db": None if math.isinf(psnr) else round(psnr, 2),
         "maxabs_vs_fp64": float(f"{err.max(initial=0):.3e}"),
         "fp64_compare_rays": int(ok.sum()),

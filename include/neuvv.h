@@ -42,6 +42,9 @@ typedef enum {
     NEUVV_ERR_HIP = -6          /* a HIP launch or runtime error */
 } neuvv_status;
 
+/* Arrangement of the leaf payload arrays (see "Leaf payload layout"). */
+typedef enum { NEUVV_LAYOUT_VEC_SOA = 0, NEUVV_LAYOUT_LEAF_ROWS = 1 } neuvv_layout;
+
 /* Storage type of the leaf coefficients. Evaluation and compositing are
    always float32; 16-bit storage is converted with round-to-nearest-even. */
 typedef enum { NEUVV_F32 = 0, NEUVV_F16 = 1, NEUVV_BF16 = 2 } neuvv_dtype;
@@ -83,6 +86,7 @@ typedef struct {
     int32_t box[6];       /* occupied-cell bounds from neuvv_build_voctree (lo x,y,z; hi x,y,z
                              exclusive): rays are clipped to this box instead of the whole grid.
                              All zero = the whole grid [0, 2^D)^3. */
+    int32_t layout;       /* neuvv_layout of hh and wsig */
     const float* basis;   /* [T][C] density basis, row t = frame t (Eq. 5: A transposed) */
     const float* gamma;   /* [T] hyperangle per frame, in [0, pi] (Eq. 4's gamma(t)) */
 } neuvv_tree;
@@ -161,9 +165,10 @@ int neuvv_grad_row_elems(int32_t K, int32_t C);
  *                 when the inputs are already in slot order.
  * hh_out, wsig_out device outputs of neuvv_payload_words() elements; the
  *                 padding elements are written with zero.
- * Errors: ARG, UNSUPPORTED (dtype).
+ * layout          neuvv_layout of the outputs.
+ * Errors: ARG, UNSUPPORTED (dtype, layout).
  */
-int neuvv_pack_leaves(int32_t K, int32_t C, int32_t dtype, int64_t n_leaves, const float* hh_in,
+int neuvv_pack_leaves(int32_t K, int32_t C, int32_t dtype, int32_t layout, int64_t n_leaves, const float* hh_in,
                       const float* wsig_in, const int64_t* slot_of_input, void* hh_out, void* wsig_out,
                       void* stream);
 

@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(HERE, "libneuvv.so")
 
 NEUVV_OK = 0
 F32, F16, BF16 = 0, 1, 2
+LAYOUT_VEC_SOA, LAYOUT_LEAF_ROWS = 0, 1
 
 
 class NeuvvError(RuntimeError):
@@ -26,8 +27,8 @@ class neuvv_tree(ctypes.Structure):
     _fields_ = [("depth", ctypes.c_int32), ("K", ctypes.c_int32), ("C", ctypes.c_int32),
                 ("dtype", ctypes.c_int32), ("n_nodes", ctypes.c_int64), ("n_leaves", ctypes.c_int64),
                 ("child", ctypes.c_void_p), ("hh", ctypes.c_void_p), ("wsig", ctypes.c_void_p),
-                ("T", ctypes.c_int32), ("box", ctypes.c_int32 * 6), ("basis", ctypes.c_void_p),
-                ("gamma", ctypes.c_void_p)]
+                ("T", ctypes.c_int32), ("box", ctypes.c_int32 * 6), ("layout", ctypes.c_int32),
+                ("basis", ctypes.c_void_p), ("gamma", ctypes.c_void_p)]
 
 
 class neuvv_instance(ctypes.Structure):
@@ -49,7 +50,7 @@ _F = ctypes.c_float
 _SIGNATURES = {
     "neuvv_build_voctree": [_I32, _I64, _P, _P, _I64, _P, _P, _P],
     "neuvv_payload_words": [_I32, _I32, _I32, _I64, _P, _P],
-    "neuvv_pack_leaves": [_I32, _I32, _I32, _I64, _P, _P, _P, _P, _P, _P],
+    "neuvv_pack_leaves": [_I32, _I32, _I32, _I32, _I64, _P, _P, _P, _P, _P, _P],
     "neuvv_render": [ctypes.POINTER(neuvv_tree), ctypes.POINTER(neuvv_instance), _I64, _P, _P, _P, _F, _I32, _F,
                      _P, _P, _P, _P, _P],
     "neuvv_render_backward": [ctypes.POINTER(neuvv_tree), ctypes.POINTER(neuvv_instance), _I64, _P, _P, _P, _F,
@@ -144,8 +145,9 @@ def neuvv_payload_words(K: int, C: int, dtype: int, n_leaves: int):
     return int(a.value), int(b.value)
 
 
-def neuvv_pack_leaves(K, C, dtype, n_leaves, hh_in, wsig_in, slot_of_input, hh_out, wsig_out, stream=None):
-    _check("neuvv_pack_leaves", load().neuvv_pack_leaves(K, C, dtype, n_leaves, _ptr(hh_in), _ptr(wsig_in),
+def neuvv_pack_leaves(K, C, dtype, layout, n_leaves, hh_in, wsig_in, slot_of_input, hh_out, wsig_out,
+                      stream=None):
+    _check("neuvv_pack_leaves", load().neuvv_pack_leaves(K, C, dtype, layout, n_leaves, _ptr(hh_in), _ptr(wsig_in),
                                                          _ptr(slot_of_input), _ptr(hh_out), _ptr(wsig_out),
                                                          _stream(stream)))
 

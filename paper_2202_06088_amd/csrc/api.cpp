@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 
 #include <cmath>
 #include <exception>
@@ -20,6 +21,17 @@ int build_voctree_host(int32_t depth, int64_t n, const int32_t* ijk, int32_t* ch
 namespace {
 
 thread_local std::string g_err;
+
+// Idle lanes that trigger a wavefront refill in the render kernels: 16 unless
+// NEUVV_REFILL_MIN (1..64) is set in the environment (a tuning knob).
+int refill_min() {
+    static int v = [] {
+        const char* e = getenv("NEUVV_REFILL_MIN");
+        int x = e ? atoi(e) : 16;
+        return x >= 1 && x <= 64 ? x : 16;
+    }();
+    return v;
+}
 
 int fail(int code, const char* fmt, ...) {
     char buf[512];
@@ -40,6 +52,7 @@ int check_tree(const neuvv_tree* t) {
     if (!t) return fail(NEUVV_ERR_ARG, "tree is NULL");
     if (t->depth < 1 || t->depth > neuvv::kMaxDepth) return fail(NEUVV_ERR_RANGE, "depth %d outside [1, 12]", t->depth);
     if (t->dtype < 0 || t->dtype > 2) return fail(NEUVV_ERR_ARG, "unknown dtype %d", t->dtype);
+    if (t->layout < 0 || t->layout > 1) return fail(NEUVV_ERR_ARG, "unknown layout %d", t->layout);
     if (!neuvv::render_supported(t->K, t->C, t->dtype))
         return fail(NEUVV_ERR_UNSUPPORTED, "no kernel compiled for K=%d C=%d (have K=16, C=8)", t->K, t->C);
     if (t->n_nodes < 1 || t->n_nodes > INT32_MAX) return fail(NEUVV_ERR_RANGE, "n_nodes %lld", (long long)t->n_nodes);
@@ -95,6 +108,7 @@ int make_rays(int64_t n, const float* o, const float* d, const float* t, float t
     ra.t_scalar = t_scalar;
     ra.n = n;
     ra.img_w = image_width;
+    ra.refill_min = refill_min();
     if (image_width > 0) {
         const int64_t rows = (n + image_width - 1) / image_width;
         ra.tiles_x = (image_width + 7) / 8;
@@ -122,6 +136,7 @@ neuvv::TreeArgs tree_args(const neuvv_tree* t) {
         a.box_lo[i] = box_unset ? 0 : t->box[i];
         a.box_hi[i] = box_unset ? (1 << t->depth) : t->box[3 + i];
     }
+    a.layout = t->layout;
     return a;
 }
 
@@ -174,15 +189,16 @@ int neuvv_grad_row_elems(int32_t K, int32_t C) {
     return neuvv::grad_row_elems(K, C);
 }
 
-int neuvv_pack_leaves(int32_t K, int32_t C, int32_t dtype, int64_t n_leaves, const float* hh_in,
+int neuvv_pack_leaves(int32_t K, int32_t C, int32_t dtype, int32_t layout, int64_t n_leaves, const float* hh_in,
                       const float* wsig_in, const int64_t* slot_of_input, void* hh_out, void* wsig_out,
                       void* stream) {
     NEUVV_GUARD_BEGIN
     if (K < 1 || K > 30 || C < 1 || C > 64) return fail(NEUVV_ERR_RANGE, "K in [1,30] and C in [1,64] required");
     if (dtype < 0 || dtype > 2) return fail(NEUVV_ERR_UNSUPPORTED, "unknown dtype %d", dtype);
+    if (layout < 0 || layout > 1) return fail(NEUVV_ERR_UNSUPPORTED, "unknown layout %d", layout);
     if (n_leaves < 0) return fail(NEUVV_ERR_ARG, "n_leaves < 0");
     if (n_leaves > 0 && (!hh_in || !wsig_in || !hh_out || !wsig_out)) return fail(NEUVV_ERR_ARG, "NULL buffer");
-    return hip_status(neuvv::launch_pack(K, C, dtype, n_leaves, hh_in, wsig_in, slot_of_input, hh_out, wsig_out,
+    return hip_status(neuvv::launch_pack(K, C, dtype, layout, n_leaves, hh_in, wsig_in, slot_of_input, hh_out, wsig_out,
                                          (hipStream_t)stream),
                       "pack_leaves launch");
     NEUVV_GUARD_END

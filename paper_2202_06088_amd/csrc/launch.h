@@ -44,7 +44,7 @@ hipError_t launch_compose_bwd(int L, int64_t n, const float* rgb, const float* a
 hipError_t launch_pinhole(int W, int H, const float intr[4], const float c2w[12], int64_t n, const int32_t* pix,
                           float* ray_o, float* ray_d, hipStream_t stream);
 hipError_t launch_eval_hh(int K, int64_t n, const float* dirs, const float* gam, float* out, hipStream_t stream);
-hipError_t launch_pack(int K, int C, int dtype, int64_t n, const float* hh_in, const float* wsig_in,
+hipError_t launch_pack(int K, int C, int dtype, int layout, int64_t n, const float* hh_in, const float* wsig_in,
                        const int64_t* slot_of_input, void* hh_out, void* wsig_out, hipStream_t stream);
 
 // Device properties used to size persistent grids (cached per device).

@@ -277,7 +277,8 @@ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float x) {
 // One thread per (leaf, vector): reads the V values of the vector, converts
 // and writes 16 bytes.
 template <int DT>
-__global__ __launch_bounds__(kEwBlock) void pack_kernel(int R, int NG, int64_t n, const float* __restrict__ in,
+__global__ __launch_bounds__(kEwBlock) void pack_kernel(int R, int NG, int layout, int64_t n,
+                                                        const float* __restrict__ in,
                                                         const int64_t* __restrict__ slot_of_input,
                                                         uint4* __restrict__ out) {
     constexpr int V = DT == 0 ? 4 : 8;
@@ -306,33 +307,34 @@ __global__ __launch_bounds__(kEwBlock) void pack_kernel(int R, int NG, int64_t n
             }
             w.x = q[0]; w.y = q[1]; w.z = q[2]; w.w = q[3];
         }
-        out[(int64_t)g * n + s] = w;
+        out[layout ? s * NG + g : (int64_t)g * n + s] = w;
     }
 }
 
 template <int DT>
-static hipError_t pack_t(int R, int64_t n, const float* in, const int64_t* slots, void* out, hipStream_t st) {
+static hipError_t pack_t(int R, int layout, int64_t n, const float* in, const int64_t* slots, void* out,
+                         hipStream_t st) {
     constexpr int V = DT == 0 ? 4 : 8;
     const int NG = (R + V - 1) / V;
-    hipLaunchKernelGGL(pack_kernel<DT>, dim3(ew_grid(n * NG)), dim3(kEwBlock), 0, st, R, NG, n, in, slots,
+    hipLaunchKernelGGL(pack_kernel<DT>, dim3(ew_grid(n * NG)), dim3(kEwBlock), 0, st, R, NG, layout, n, in, slots,
                        reinterpret_cast<uint4*>(out));
     return hipGetLastError();
 }
 
-hipError_t launch_pack(int K, int C, int dtype, int64_t n, const float* hh_in, const float* wsig_in,
+hipError_t launch_pack(int K, int C, int dtype, int layout, int64_t n, const float* hh_in, const float* wsig_in,
                        const int64_t* slot_of_input, void* hh_out, void* wsig_out, hipStream_t stream) {
     if (n <= 0) return hipSuccess;
     hipError_t e;
     switch (dtype) {
         case 0:
-            e = pack_t<0>(3 * K, n, hh_in, slot_of_input, hh_out, stream);
-            return e != hipSuccess ? e : pack_t<0>(C, n, wsig_in, slot_of_input, wsig_out, stream);
+            e = pack_t<0>(3 * K, layout, n, hh_in, slot_of_input, hh_out, stream);
+            return e != hipSuccess ? e : pack_t<0>(C, layout, n, wsig_in, slot_of_input, wsig_out, stream);
         case 1:
-            e = pack_t<1>(3 * K, n, hh_in, slot_of_input, hh_out, stream);
-            return e != hipSuccess ? e : pack_t<1>(C, n, wsig_in, slot_of_input, wsig_out, stream);
+            e = pack_t<1>(3 * K, layout, n, hh_in, slot_of_input, hh_out, stream);
+            return e != hipSuccess ? e : pack_t<1>(C, layout, n, wsig_in, slot_of_input, wsig_out, stream);
         default:
-            e = pack_t<2>(3 * K, n, hh_in, slot_of_input, hh_out, stream);
-            return e != hipSuccess ? e : pack_t<2>(C, n, wsig_in, slot_of_input, wsig_out, stream);
+            e = pack_t<2>(3 * K, layout, n, hh_in, slot_of_input, hh_out, stream);
+            return e != hipSuccess ? e : pack_t<2>(C, layout, n, wsig_in, slot_of_input, wsig_out, stream);
     }
 }
 

@@ -167,6 +167,7 @@ struct TreeArgs {
     int32_t T;
     int32_t box_lo[3];   // occupied-cell bounds: rays are clipped to [lo, hi)
     int32_t box_hi[3];
+    int32_t layout;      // 0: vectors structure-of-arrays, 1: leaf-major rows of vectors
 };
 
 struct InstArgs {
@@ -187,6 +188,7 @@ struct RayArgs {
     int32_t tiles_x;
     int64_t n;
     int64_t n_slots;     // work slots (64 per 8x8 tile when img_w > 0, else n)
+    int32_t refill_min;  // idle lanes that trigger a refill of the wavefront
 };
 
 // Work slot -> ray index, -1 when the slot is padding of a ragged tile.

@@ -28,7 +28,6 @@ namespace neuvv {
 
 constexpr int kBlock = 256;
 constexpr int kLdsNodes = 512;
-constexpr int kRefillMin = 16;
 
 template <int DT>
 struct StoreTraits;
@@ -62,15 +61,18 @@ __device__ __forceinline__ void unpack16(const uint4& v, float (&out)[StoreTrait
     }
 }
 
-// Gathers R values of leaf `slot` from a [ceil(R/V)][N][V] array.
+// Gathers R values of leaf `slot` from a [ceil(R/V)][N][V] array (layout 0) or
+// a [N][ceil(R/V)][V] array (layout 1).
 template <int DT, int R>
-__device__ __forceinline__ void load_leaf(const void* base, int64_t N, int64_t slot, float (&out)[R]) {
+__device__ __forceinline__ void load_leaf(const void* base, int64_t N, int64_t slot, int layout,
+                                          float (&out)[R]) {
     constexpr int V = StoreTraits<DT>::V;
     constexpr int NG = (R + V - 1) / V;
-    const uint4* p = reinterpret_cast<const uint4*>(base) + slot;
+    const int64_t stride = layout ? 1 : N;
+    const uint4* p = reinterpret_cast<const uint4*>(base) + (layout ? slot * NG : slot);
     uint4 raw[NG];
 #pragma unroll
-    for (int g = 0; g < NG; ++g) raw[g] = p[(int64_t)g * N];
+    for (int g = 0; g < NG; ++g) raw[g] = p[(int64_t)g * stride];
 #pragma unroll
     for (int g = 0; g < NG; ++g) {
         float tmp[V];
@@ -153,7 +155,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
         const uint64_t idle = __ballot(!alive);
         const int n_idle = __popcll(idle);
         const bool more = p_next < ws.stream_len;
-        if (more && (n_idle >= kRefillMin || n_idle == kWave)) {
+        if (more && (n_idle >= ra.refill_min || n_idle == kWave)) {
             if (!alive) {
                 const int64_t pos = p_next + lane_rank(idle);
                 if (pos < ws.stream_len) {
@@ -188,8 +190,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
             bool finish = leaf < 0;
             if (!finish) {
                 float wv[3 * K], sv[C];
-                load_leaf<DT, 3 * K>(tr.hh, tr.n_leaves, leaf, wv);
-                load_leaf<DT, C>(tr.wsig, tr.n_leaves, leaf, sv);
+                load_leaf<DT, 3 * K>(tr.hh, tr.n_leaves, leaf, tr.layout, wv);
+                load_leaf<DT, C>(tr.wsig, tr.n_leaves, leaf, tr.layout, sv);
                 float x = 0.0f;
 #pragma unroll
                 for (int c = 0; c < C; ++c) x = fmaf(sv[c], bv[c], x);
@@ -277,7 +279,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
         const uint64_t idle = __ballot(!alive);
         const int n_idle = __popcll(idle);
         const bool more = p_next < ws.stream_len;
-        if (more && (n_idle >= kRefillMin || n_idle == kWave)) {
+        if (more && (n_idle >= ra.refill_min || n_idle == kWave)) {
             if (!alive) {
                 const int64_t pos = p_next + lane_rank(idle);
                 if (pos < ws.stream_len) {
@@ -328,8 +330,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
             bool finish = leaf < 0;
             if (!finish) {
                 float wv[3 * K], sv[C];
-                load_leaf<DT, 3 * K>(tr.hh, N, leaf, wv);
-                load_leaf<DT, C>(tr.wsig, N, leaf, sv);
+                load_leaf<DT, 3 * K>(tr.hh, N, leaf, tr.layout, wv);
+                load_leaf<DT, C>(tr.wsig, N, leaf, tr.layout, sv);
                 const float* hl = s_h + threadIdx.x * K;
                 const float* bl = s_b + threadIdx.x * C;
                 float x = 0.0f;

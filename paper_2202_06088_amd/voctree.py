@@ -40,10 +40,11 @@ class VOctree:
     gamma: torch.Tensor          # [T] float32
     slot_of_input: torch.Tensor  # [N] int64, device
     box: tuple = (0, 0, 0, 0, 0, 0)  # occupied-cell bounds (lo xyz, hi xyz exclusive)
+    layout: int = _lib.LAYOUT_VEC_SOA
 
     @classmethod
     def build(cls, depth: int, leaf_ijk, hh, wsig, basis, gamma, dtype: int = _lib.F32,
-              device: str = "cuda", stream=None) -> "VOctree":
+              device: str = "cuda", stream=None, layout: int = _lib.LAYOUT_VEC_SOA) -> "VOctree":
         """leaf_ijk [N,3]; hh [N,3,K] and wsig [N,C] float32 per input leaf; basis [T,C]; gamma [T]."""
         child, slots, box = build_child_table(depth, leaf_ijk, with_box=True)
         hh = np.ascontiguousarray(hh, np.float32)
@@ -55,7 +56,7 @@ class VOctree:
                 torch.from_numpy(child).to(dev), None, None,
                 torch.from_numpy(np.ascontiguousarray(basis, np.float32)).to(dev),
                 torch.from_numpy(np.ascontiguousarray(gamma, np.float32)).to(dev),
-                torch.from_numpy(slots).to(dev), tuple(int(v) for v in box))
+                torch.from_numpy(slots).to(dev), tuple(int(v) for v in box), layout)
         t.set_payload(torch.from_numpy(hh).to(dev), torch.from_numpy(wsig).to(dev), stream=stream)
         return t
 
@@ -70,7 +71,7 @@ class VOctree:
         if self.hh is None or self.hh.numel() != a:
             self.hh = torch.empty(a, dtype=td, device=dev)
             self.wsig = torch.empty(b, dtype=td, device=dev)
-        _lib.neuvv_pack_leaves(self.K, self.C, self.dtype, self.n_leaves, hh_in.contiguous().float(),
+        _lib.neuvv_pack_leaves(self.K, self.C, self.dtype, self.layout, self.n_leaves, hh_in.contiguous().float(),
                                wsig_in.contiguous().float(), self.slot_of_input, self.hh, self.wsig, stream)
 
     def struct(self) -> _lib.neuvv_tree:
@@ -81,6 +82,7 @@ class VOctree:
         s.T, s.basis, s.gamma = self.T, self.basis.data_ptr(), self.gamma.data_ptr()
         for i in range(6):
             s.box[i] = self.box[i]
+        s.layout = self.layout
         return s
 
     @property
@@ -100,8 +102,8 @@ class VOctree:
         return rows[:, :3 * K].reshape(-1, 3, K), rows[:, 3 * K:3 * K + C]
 
     def rows_to_payload_f32(self, grad_leaf: torch.Tensor):
-        """Leaf gradient rows -> the float32 payload layout of hh and wsig (a transpose of
-        layout only), for an element-wise optimizer step on float32 payload tensors."""
+        """Leaf gradient rows -> the float32 payload layout of hh and wsig (a rearrangement
+        only), for an element-wise optimizer step on float32 payload tensors."""
         N, K, C = self.n_leaves, self.K, self.C
         rows = grad_leaf.view(N, self.grad_row)
         gh, gw = -(-3 * K // 4), -(-C // 4)
@@ -109,5 +111,7 @@ class VOctree:
         hh[:, :3 * K] = rows[:, :3 * K]
         ws = torch.zeros(N, gw * 4, device=rows.device)
         ws[:, :C] = rows[:, 3 * K:3 * K + C]
+        if self.layout == _lib.LAYOUT_LEAF_ROWS:
+            return hh.reshape(-1).contiguous(), ws.reshape(-1).contiguous()
         return (hh.view(N, gh, 4).permute(1, 0, 2).reshape(-1).contiguous(),
                 ws.view(N, gw, 4).permute(1, 0, 2).reshape(-1).contiguous())

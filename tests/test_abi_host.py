@@ -130,6 +130,12 @@ def test_argument_errors_without_launch(lib):
             t.box[i] = bad[i]
         assert lib.neuvv_render(ctypes.byref(t), None, 0, None, None, None, 0.0, 0, 0.0, None, None, None, None,
                                 None) == -2
+    t.layout = 3
+    for i in range(6):
+        t.box[i] = 0
+    assert lib.neuvv_render(ctypes.byref(t), None, 0, None, None, None, 0.0, 0, 0.0, None, None, None, None,
+                            None) == -1
+    t.layout = 0
     t.depth, t.dtype = 9, 7
     assert lib.neuvv_render_backward(ctypes.byref(t), None, 0, None, None, None, 0.0, 0, 0.0, None, None, None,
                                      None, None, None, None, None, None) == -1
@@ -139,7 +145,8 @@ def test_argument_errors_without_launch(lib):
     assert lib.neuvv_eval_hh(31, 1, None, None, None, None) == -2
     cam = _lib.make_camera(0, 10, 1.0, 1.0, 0.0, 0.0, np.zeros(12))
     assert lib.neuvv_pinhole_rays(ctypes.byref(cam), 0, None, None, None, None) == -2
-    assert lib.neuvv_pack_leaves(16, 8, 5, 1, None, None, None, None, None, None) == -5
+    assert lib.neuvv_pack_leaves(16, 8, 5, 0, 1, None, None, None, None, None, None) == -5
+    assert lib.neuvv_pack_leaves(16, 8, 0, 7, 1, None, None, None, None, None, None) == -5
     a, b = _lib.neuvv_payload_words(16, 8, _lib.F32, 10)
     assert (a, b) == (12 * 10 * 4, 2 * 10 * 4)
     a, b = _lib.neuvv_payload_words(16, 8, _lib.F16, 10)

@@ -215,3 +215,24 @@ def test_compose_matches_oracle():
         q_rgb, q_a = OC.compose_grad(P, A, D, gP, gA)
         assert rel_err(g_rgb.cpu().numpy(), q_rgb) < 1e-5
         assert rel_err(g_a.cpu().numpy(), q_a) < 1e-5
+
+
+@pytest.mark.parametrize("dtype", [_lib.F32, _lib.F16, _lib.BF16])
+def test_leaf_rows_layout_same_results(cfg1, dtype):
+    """The leaf-major payload layout loads the same values: forward outputs are bitwise
+    equal to the vector-SoA layout, adjoints equal up to the order of atomic additions."""
+    from paper_2202_06088_amd.voctree import VOctree
+    cam = config1_camera(cfg1)
+    o, d = ops.pinhole_rays(cam_struct(cam))
+    trees = [VOctree.build(cfg1.depth, cfg1.leaf_ijk, cfg1.hh, cfg1.wsig, cfg1.basis, cfg1.gamma, dtype, DEV,
+                           layout=lay) for lay in (_lib.LAYOUT_VEC_SOA, _lib.LAYOUT_LEAF_ROWS)]
+    announce(f"leaf-rows layout, dtype {dtype}")
+    outs = [ops.render(tr, o, d, 6.0, None, 1e-4, 64) for tr in trees]
+    for a, b in zip(outs[0], outs[1]):
+        assert torch.equal(a, b)
+    g = torch.randn_like(outs[0][0])
+    grads = [ops.render_backward(tr, o, d, out[0], out[1], out[3], g, None, 6.0, None, 1e-4, 64)
+             for tr, out in zip(trees, outs)]
+    torch.cuda.synchronize()
+    assert rel_err(grads[1][0].cpu().numpy(), grads[0][0].cpu().numpy()) < 1e-6
+    assert rel_err(grads[1][1].cpu().numpy(), grads[0][1].cpu().numpy()) < 1e-6
