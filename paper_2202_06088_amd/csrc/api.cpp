@@ -22,13 +22,13 @@ namespace {
 
 thread_local std::string g_err;
 
-// Idle lanes that trigger a wavefront refill in the render kernels: 16 unless
+// Idle lanes that trigger a wavefront refill in the render kernels: 32 unless
 // NEUVV_REFILL_MIN (1..64) is set in the environment (a tuning knob).
 int refill_min() {
     static int v = [] {
         const char* e = getenv("NEUVV_REFILL_MIN");
-        int x = e ? atoi(e) : 16;
-        return x >= 1 && x <= 64 ? x : 16;
+        int x = e ? atoi(e) : 32;
+        return x >= 1 && x <= 64 ? x : 32;
     }();
     return v;
 }

@@ -246,46 +246,48 @@ __device__ __forceinline__ void time_setup(const TreeArgs& tr, const InstArgs& i
 
 // IDENT: the instance is the identity (known at compile time), so the local
 // ray is the world ray and the low parts of O and D are constant zeros.
+// Coarse reject in plain float against the occupied box grown by one leaf on
+// every side: float rounding of the clip is far below that margin for any
+// local coordinate below ~1e5, so a ray rejected here misses the exact box.
+// Returns false only for such rays.
+template <bool IDENT>
+__device__ __forceinline__ bool ray_may_hit(const TreeArgs& tr, const InstArgs& in, const float o[3],
+                                            const float d[3]) {
+    float of[3], dfl[3];
+    if constexpr (IDENT) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) { of[a] = o[a]; dfl[a] = d[a]; }
+    } else {
+        const float is = 1.0f / in.scale;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            of[a] = ((o[0] - in.trans[0]) * in.rot[a] + (o[1] - in.trans[1]) * in.rot[3 + a] +
+                     (o[2] - in.trans[2]) * in.rot[6 + a]) * is;
+            dfl[a] = (d[0] * in.rot[a] + d[1] * in.rot[3 + a] + d[2] * in.rot[6 + a]) * is;
+        }
+    }
+    float tn = 0.0f, tf = INFINITY;
+    bool pass = true, small = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        small = small && fabsf(of[a]) < 1.0e5f;
+        const float lo = (float)tr.box_lo[a] - 1.0f, hi = (float)tr.box_hi[a] + 1.0f;
+        if (dfl[a] == 0.0f) {
+            pass = pass && of[a] >= lo && of[a] < hi;
+        } else {
+            const float iv = 1.0f / dfl[a];
+            const float t0 = (lo - of[a]) * iv, t1 = (hi - of[a]) * iv;
+            tn = fmaxf(tn, fminf(t0, t1));
+            tf = fminf(tf, fmaxf(t0, t1));
+        }
+    }
+    return !small || (pass && tn < tf);
+}
+
+// Exact per-ray setup (compensated geometry); call for rays ray_may_hit accepts.
 template <bool IDENT>
 __device__ __forceinline__ void ray_setup(const TreeArgs& tr, const InstArgs& in, const float o[3],
                                           const float d[3], float t, RaySetup& rs) {
-    // Coarse reject in plain float against the box grown by one leaf on every
-    // side: float rounding of the clip is far below that margin for any local
-    // coordinate below ~1e5, so a ray rejected here misses the exact box.
-    {
-        float of[3], dfl[3];
-        if constexpr (IDENT) {
-#pragma unroll
-            for (int a = 0; a < 3; ++a) { of[a] = o[a]; dfl[a] = d[a]; }
-        } else {
-            const float is = 1.0f / in.scale;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                of[a] = ((o[0] - in.trans[0]) * in.rot[a] + (o[1] - in.trans[1]) * in.rot[3 + a] +
-                         (o[2] - in.trans[2]) * in.rot[6 + a]) * is;
-                dfl[a] = (d[0] * in.rot[a] + d[1] * in.rot[3 + a] + d[2] * in.rot[6 + a]) * is;
-            }
-        }
-        float tn = 0.0f, tf = INFINITY;
-        bool pass = true, small = true;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            small = small && fabsf(of[a]) < 1.0e5f;
-            const float lo = (float)tr.box_lo[a] - 1.0f, hi = (float)tr.box_hi[a] + 1.0f;
-            if (dfl[a] == 0.0f) {
-                pass = pass && of[a] >= lo && of[a] < hi;
-            } else {
-                const float iv = 1.0f / dfl[a];
-                const float t0 = (lo - of[a]) * iv, t1 = (hi - of[a]) * iv;
-                tn = fmaxf(tn, fminf(t0, t1));
-                tf = fminf(tf, fmaxf(t0, t1));
-            }
-        }
-        if (small && !(pass && tn < tf)) {
-            rs.hit = false;
-            return;
-        }
-    }
     if constexpr (IDENT) {
 #pragma unroll
         for (int a = 0; a < 3; ++a) { rs.O[a] = df_from(o[a]); rs.D[a] = df_from(d[a]); }

@@ -133,6 +133,15 @@ __device__ __forceinline__ void ray_basis(const TreeArgs& tr, const RaySetup& rs
 // ----------------------------------------------------------------------------
 // forward
 
+__device__ __forceinline__ void write_miss(const RenderOut& out, int64_t ray) {
+    out.rgb[3 * ray] = 0.0f;
+    out.rgb[3 * ray + 1] = 0.0f;
+    out.rgb[3 * ray + 2] = 0.0f;
+    out.alpha[ray] = 0.0f;
+    if (out.depth) out.depth[ray] = INFINITY;
+    out.nsamp[ray] = 0;
+}
+
 template <int K, int C, int DT, bool IDENT>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) void render_fwd_kernel(TreeArgs tr, InstArgs in, RayArgs ra, float t_stop,
                                                             RenderOut out) {
@@ -156,31 +165,42 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
         const int n_idle = __popcll(idle);
         const bool more = p_next < ws.stream_len;
         if (more && (n_idle >= ra.refill_min || n_idle == kWave)) {
-            if (!alive) {
-                const int64_t pos = p_next + lane_rank(idle);
-                if (pos < ws.stream_len) {
-                    const int64_t slot = (ws.gw + (pos >> 6) * ws.n_waves) * 64 + (pos & 63);
-                    ray = slot_to_ray(ra, slot);
-                    if (ray >= 0) {
-                        const float o[3] = {ra.o[3 * ray], ra.o[3 * ray + 1], ra.o[3 * ray + 2]};
-                        const float d[3] = {ra.d[3 * ray], ra.d[3 * ray + 1], ra.d[3 * ray + 2]};
-                        const float t = ra.t ? ra.t[ray] : ra.t_scalar;
-                        ray_setup<IDENT>(tr, in, o, d, t, rs);
-                        Tr = 1.0f; acc0 = acc1 = acc2 = 0.0f; wsum = dsum = 0.0f; ns = 0;
-                        if (rs.hit) {
-                            ray_basis<K, C>(tr, rs, h, bv);
-                            walk_begin(tr, rs, w);
-                            alive = true;
-                        } else {
-                            out.rgb[3 * ray] = 0.0f; out.rgb[3 * ray + 1] = 0.0f; out.rgb[3 * ray + 2] = 0.0f;
-                            out.alpha[ray] = 0.0f;
-                            if (out.depth) out.depth[ray] = INFINITY;
-                            out.nsamp[ray] = 0;
+            // Acquisition: idle lanes take the next slots of the stream; rays the
+            // plain-float test rejects get their miss outputs at once and the lane
+            // takes another slot, while at least refill_min lanes are idle. Then
+            // the compensated setup runs once for all accepted rays together.
+            bool cand = false;
+            float o[3], d[3], t = 0.0f;
+            for (;;) {
+                const uint64_t need = __ballot(!alive && !cand);
+                if (__popcll(need) < ra.refill_min || p_next >= ws.stream_len) break;
+                if (!alive && !cand) {
+                    const int64_t pos = p_next + lane_rank(need);
+                    if (pos < ws.stream_len) {
+                        const int64_t slot = (ws.gw + (pos >> 6) * ws.n_waves) * 64 + (pos & 63);
+                        ray = slot_to_ray(ra, slot);
+                        if (ray >= 0) {
+                            o[0] = ra.o[3 * ray]; o[1] = ra.o[3 * ray + 1]; o[2] = ra.o[3 * ray + 2];
+                            d[0] = ra.d[3 * ray]; d[1] = ra.d[3 * ray + 1]; d[2] = ra.d[3 * ray + 2];
+                            t = ra.t ? ra.t[ray] : ra.t_scalar;
+                            cand = ray_may_hit<IDENT>(tr, in, o, d);
+                            if (!cand) write_miss(out, ray);
                         }
                     }
                 }
+                p_next += __popcll(need);
             }
-            p_next += n_idle;
+            if (cand) {
+                ray_setup<IDENT>(tr, in, o, d, t, rs);
+                Tr = 1.0f; acc0 = acc1 = acc2 = 0.0f; wsum = dsum = 0.0f; ns = 0;
+                if (rs.hit) {
+                    ray_basis<K, C>(tr, rs, h, bv);
+                    walk_begin(tr, rs, w);
+                    alive = true;
+                } else {
+                    write_miss(out, ray);
+                }
+            }
             continue;
         }
         if (n_idle == kWave) break;
@@ -280,44 +300,53 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
         const int n_idle = __popcll(idle);
         const bool more = p_next < ws.stream_len;
         if (more && (n_idle >= ra.refill_min || n_idle == kWave)) {
-            if (!alive) {
-                const int64_t pos = p_next + lane_rank(idle);
-                if (pos < ws.stream_len) {
-                    const int64_t slot = (ws.gw + (pos >> 6) * ws.n_waves) * 64 + (pos & 63);
-                    ray = slot_to_ray(ra, slot);
-                    if (ray >= 0 && io.nsamp[ray] > 0) {
-                        const float o[3] = {ra.o[3 * ray], ra.o[3 * ray + 1], ra.o[3 * ray + 2]};
-                        const float d[3] = {ra.d[3 * ray], ra.d[3 * ray + 1], ra.d[3 * ray + 2]};
-                        const float t = per_ray_t ? ra.t[ray] : ra.t_scalar;
-                        ray_setup<IDENT>(tr, in, o, d, t, rs);
-                        if (rs.hit) {
-                            {
-                                float h[K], bv[C];
-                                ray_basis<K, C>(tr, rs, h, bv);
-#pragma unroll
-                                for (int k = 0; k < K; ++k) s_h[threadIdx.x * K + k] = h[k];
-#pragma unroll
-                                for (int c = 0; c < C; ++c) s_b[threadIdx.x * C + c] = bv[c];
-                            }
-                            walk_begin(tr, rs, w);
-                            ns_fwd = io.nsamp[ray];
-                            ns = 0;
-                            Tr = 1.0f;
-                            Tfin = 1.0f - io.alpha[ray];
-                            F0 = io.rgb[3 * ray]; F1 = io.rgb[3 * ray + 1]; F2 = io.rgb[3 * ray + 2];
-                            g0 = io.grad_rgb[3 * ray]; g1 = io.grad_rgb[3 * ray + 1]; g2 = io.grad_rgb[3 * ray + 2];
-                            ga = io.grad_alpha ? io.grad_alpha[ray] : 0.0f;
-                            p0 = p1 = p2 = 0.0f;
-                            if (per_ray_t) {
-#pragma unroll
-                                for (int c = 0; c < C; ++c) gb[c] = 0.0f;
-                            }
-                            alive = true;
-                        }
+            // Acquisition: idle lanes take the next slots while at least refill_min
+            // lanes are idle; rays that composited no sample carry no gradient and
+            // are passed over. The setup then runs once for all taken rays together.
+            bool cand = false;
+            for (;;) {
+                const uint64_t need = __ballot(!alive && !cand);
+                if (__popcll(need) < ra.refill_min || p_next >= ws.stream_len) break;
+                if (!alive && !cand) {
+                    const int64_t pos = p_next + lane_rank(need);
+                    if (pos < ws.stream_len) {
+                        const int64_t slot = (ws.gw + (pos >> 6) * ws.n_waves) * 64 + (pos & 63);
+                        ray = slot_to_ray(ra, slot);
+                        cand = ray >= 0 && io.nsamp[ray] > 0;
                     }
                 }
+                p_next += __popcll(need);
             }
-            p_next += n_idle;
+            if (cand) {
+                const float o[3] = {ra.o[3 * ray], ra.o[3 * ray + 1], ra.o[3 * ray + 2]};
+                const float d[3] = {ra.d[3 * ray], ra.d[3 * ray + 1], ra.d[3 * ray + 2]};
+                const float t = per_ray_t ? ra.t[ray] : ra.t_scalar;
+                ray_setup<IDENT>(tr, in, o, d, t, rs);
+                if (rs.hit) {
+                    {
+                        float h[K], bv[C];
+                        ray_basis<K, C>(tr, rs, h, bv);
+#pragma unroll
+                        for (int k = 0; k < K; ++k) s_h[threadIdx.x * K + k] = h[k];
+#pragma unroll
+                        for (int c = 0; c < C; ++c) s_b[threadIdx.x * C + c] = bv[c];
+                    }
+                    walk_begin(tr, rs, w);
+                    ns_fwd = io.nsamp[ray];
+                    ns = 0;
+                    Tr = 1.0f;
+                    Tfin = 1.0f - io.alpha[ray];
+                    F0 = io.rgb[3 * ray]; F1 = io.rgb[3 * ray + 1]; F2 = io.rgb[3 * ray + 2];
+                    g0 = io.grad_rgb[3 * ray]; g1 = io.grad_rgb[3 * ray + 1]; g2 = io.grad_rgb[3 * ray + 2];
+                    ga = io.grad_alpha ? io.grad_alpha[ray] : 0.0f;
+                    p0 = p1 = p2 = 0.0f;
+                    if (per_ray_t) {
+#pragma unroll
+                        for (int c = 0; c < C; ++c) gb[c] = 0.0f;
+                    }
+                    alive = true;
+                }
+            }
             continue;
         }
         if (n_idle == kWave) break;
