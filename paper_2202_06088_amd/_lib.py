@@ -74,6 +74,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     if not os.path.exists(path):
         raise ImportError(f"{path} is not built; run `python -m paper_2202_06088_amd.build` "
                           "(the HIP library is required, there is no CPU fallback)")
+    # torch ships its own HIP runtime; importing it first makes the library bind
+    # to that copy (same soname) instead of loading a second runtime beside it,
+    # which would see no device.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     for name, args in _SIGNATURES.items():
         fn = getattr(lib, name)
