@@ -77,9 +77,9 @@ typedef struct {
     int32_t K;            /* HH functions per colour channel (compiled: 16) */
     int32_t C;            /* density basis size (compiled: 8) */
     int32_t dtype;        /* neuvv_dtype of hh and wsig */
-    int64_t n_nodes;      /* rows of child */
+    int64_t n_nodes;      /* rows of nodes */
     int64_t n_leaves;     /* leaf slots */
-    const int32_t* child; /* [n_nodes][8] from neuvv_build_voctree */
+    const int32_t* nodes; /* [n_nodes][4] from neuvv_build_voctree, 16-byte aligned */
     const void* hh;       /* colour coefficients, layout above */
     const void* wsig;     /* density weights, layout above */
     int32_t T;            /* frames of the temporal tables */
@@ -122,13 +122,24 @@ typedef struct {
  * depth           D in [1, 12].
  * n_leaves        number of cells, >= 0.
  * leaf_ijk        host [n_leaves][3] int32, each in [0, 2^D); no duplicates.
- * child           host [node_capacity][8] int32 output, or NULL to only count.
- *                 Node 0 is the root; nodes are stored level by level from
- *                 the root (breadth first), Morton order within a level.
- *                 child[n][o] for octant o = (i&1) | (j&1)<<1 | (k&1)<<2 of
- *                 the cell bits at that level: -1 for an empty octant, else
- *                 the child node index, or at the last level the leaf slot.
- * node_capacity   rows available in child (ignored when child is NULL).
+ * nodes           host [node_capacity][4] int32 output, or NULL to only count.
+ *                 The octree is stored two levels per node. There are
+ *                 L = ceil(D/2) node levels; a node of level w is a cube of
+ *                 edge 2^e_w split into child cells of edge 2^(e_w - b_w),
+ *                 with b_0 = 1 for odd D (else 2), b_w = 2 for w > 0,
+ *                 e_0 = D and e_(w+1) = e_w - b_w; the children of the last
+ *                 level are the leaves. Child cell (x, y, z) (coordinates
+ *                 local to the node, in [0, 2^b_w)) is bit q = x0 | y0<<1 |
+ *                 z0<<2 | x1<<3 | y1<<4 | z1<<5 (xk = bit k of x).
+ *                 Row r: words 0 and 1 = low and high half of the 64-bit
+ *                 occupancy mask (bit q set: child cell q holds a leaf);
+ *                 word 2 = index of the first occupied child, a node row
+ *                 (levels w < L-1) or a leaf slot (last level); occupied
+ *                 children follow consecutively in bit order, so child q is
+ *                 word2 + popcount(mask & (2^q - 1)); word 3 = 0. Row 0 is
+ *                 the root; rows are stored level by level from the root,
+ *                 Morton order within a level.
+ * node_capacity   rows available in nodes (ignored when nodes is NULL).
  * n_nodes_out     host output, the number of nodes (always written on OK).
  * slot_of_input   host [n_leaves] int64 output or NULL: the leaf slot
  *                 (rank in Morton order) of input cell i.
@@ -138,7 +149,7 @@ typedef struct {
  * Errors: ARG (null leaf_ijk with n_leaves > 0, null n_nodes_out), RANGE
  * (depth, coordinates), DUPLICATE, CAPACITY (node_capacity < n_nodes).
  */
-int neuvv_build_voctree(int32_t depth, int64_t n_leaves, const int32_t* leaf_ijk, int32_t* child,
+int neuvv_build_voctree(int32_t depth, int64_t n_leaves, const int32_t* leaf_ijk, int32_t* nodes,
                         int64_t node_capacity, int64_t* n_nodes_out, int64_t* slot_of_input, int32_t* box_out);
 
 /*

@@ -26,7 +26,7 @@ class NeuvvError(RuntimeError):
 class neuvv_tree(ctypes.Structure):
     _fields_ = [("depth", ctypes.c_int32), ("K", ctypes.c_int32), ("C", ctypes.c_int32),
                 ("dtype", ctypes.c_int32), ("n_nodes", ctypes.c_int64), ("n_leaves", ctypes.c_int64),
-                ("child", ctypes.c_void_p), ("hh", ctypes.c_void_p), ("wsig", ctypes.c_void_p),
+                ("nodes", ctypes.c_void_p), ("hh", ctypes.c_void_p), ("wsig", ctypes.c_void_p),
                 ("T", ctypes.c_int32), ("box", ctypes.c_int32 * 6), ("layout", ctypes.c_int32),
                 ("basis", ctypes.c_void_p), ("gamma", ctypes.c_void_p)]
 
@@ -126,16 +126,16 @@ def neuvv_last_error() -> str:
     return load().neuvv_last_error().decode(errors="replace")
 
 
-def neuvv_build_voctree(depth: int, leaf_ijk, child=None, node_capacity: int = 0, slot_of_input=None,
+def neuvv_build_voctree(depth: int, leaf_ijk, nodes=None, node_capacity: int = 0, slot_of_input=None,
                         box_out=None) -> int:
-    """leaf_ijk: host int32 numpy [N,3]; child: host int32 numpy [cap,8] or None;
+    """leaf_ijk: host int32 numpy [N,3]; nodes: host int32 numpy [cap,4] or None;
     slot_of_input: host int64 numpy [N] or None; box_out: host int32 numpy [6] or None.
     Returns n_nodes."""
     n_nodes = ctypes.c_int64(0)
     n = 0 if leaf_ijk is None else int(leaf_ijk.shape[0])
     rc = load().neuvv_build_voctree(
         depth, n, None if leaf_ijk is None else leaf_ijk.ctypes.data,
-        None if child is None else child.ctypes.data, int(node_capacity), ctypes.addressof(n_nodes),
+        None if nodes is None else nodes.ctypes.data, int(node_capacity), ctypes.addressof(n_nodes),
         None if slot_of_input is None else slot_of_input.ctypes.data,
         None if box_out is None else box_out.ctypes.data)
     _check("neuvv_build_voctree", rc)

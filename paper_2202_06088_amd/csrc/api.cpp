@@ -14,7 +14,7 @@
 #include "launch.h"
 
 namespace neuvv {
-int build_voctree_host(int32_t depth, int64_t n, const int32_t* ijk, int32_t* child, int64_t capacity,
+int build_voctree_host(int32_t depth, int64_t n, const int32_t* ijk, int32_t* nodes, int64_t capacity,
                        int64_t* n_nodes_out, int64_t* slot_of_input, int32_t* box_out, std::string& err);
 }
 
@@ -59,7 +59,8 @@ int check_tree(const neuvv_tree* t) {
     if (t->n_leaves < 0 || t->n_leaves > INT32_MAX)
         return fail(NEUVV_ERR_RANGE, "n_leaves %lld", (long long)t->n_leaves);
     if (t->T < 1) return fail(NEUVV_ERR_RANGE, "T = %d must be >= 1", t->T);
-    if (!t->child || !t->basis || !t->gamma) return fail(NEUVV_ERR_ARG, "tree child/basis/gamma pointer is NULL");
+    if (!t->nodes || !t->basis || !t->gamma) return fail(NEUVV_ERR_ARG, "tree nodes/basis/gamma pointer is NULL");
+    if (reinterpret_cast<uintptr_t>(t->nodes) % 16 != 0) return fail(NEUVV_ERR_ARG, "tree nodes must be 16-byte aligned");
     const bool box_unset = !(t->box[0] | t->box[1] | t->box[2] | t->box[3] | t->box[4] | t->box[5]);
     if (!box_unset)
         for (int a = 0; a < 3; ++a)
@@ -122,7 +123,7 @@ int make_rays(int64_t n, const float* o, const float* d, const float* t, float t
 
 neuvv::TreeArgs tree_args(const neuvv_tree* t) {
     neuvv::TreeArgs a;
-    a.child = t->child;
+    a.nodes = reinterpret_cast<const int4*>(t->nodes);
     a.hh = t->hh;
     a.wsig = t->wsig;
     a.basis = t->basis;
@@ -154,11 +155,11 @@ neuvv::TreeArgs tree_args(const neuvv_tree* t) {
 
 extern "C" {
 
-int neuvv_version(void) { return 100; }
+int neuvv_version(void) { return 200; }
 
 const char* neuvv_last_error(void) { return g_err.c_str(); }
 
-int neuvv_build_voctree(int32_t depth, int64_t n_leaves, const int32_t* leaf_ijk, int32_t* child,
+int neuvv_build_voctree(int32_t depth, int64_t n_leaves, const int32_t* leaf_ijk, int32_t* nodes,
                         int64_t node_capacity, int64_t* n_nodes_out, int64_t* slot_of_input, int32_t* box_out) {
     NEUVV_GUARD_BEGIN
     if (depth < 1 || depth > neuvv::kMaxDepth) return fail(NEUVV_ERR_RANGE, "depth %d outside [1, 12]", depth);
@@ -166,7 +167,7 @@ int neuvv_build_voctree(int32_t depth, int64_t n_leaves, const int32_t* leaf_ijk
     if (n_leaves > 0 && !leaf_ijk) return fail(NEUVV_ERR_ARG, "leaf_ijk is NULL");
     if (!n_nodes_out) return fail(NEUVV_ERR_ARG, "n_nodes_out is NULL");
     std::string err;
-    const int rc = neuvv::build_voctree_host(depth, n_leaves, leaf_ijk, child, node_capacity, n_nodes_out,
+    const int rc = neuvv::build_voctree_host(depth, n_leaves, leaf_ijk, nodes, node_capacity, n_nodes_out,
                                              slot_of_input, box_out, err);
     if (rc != 0) return fail(rc, "%s", err.c_str());
     return NEUVV_OK;

@@ -9,7 +9,10 @@
 //  * RaySetup:  instance transform and re-timing of one ray (Eq. 13), clip to
 //               the tree box, per-ray HH basis and density-basis row (Eq. 4, 5);
 //  * walk_next: octree descent to the next occupied leaf along the ray
-//               (Sec. 4.3 "Rendering"), skipping whole empty nodes.
+//               (Sec. 4.3 "Rendering"), skipping whole empty octree nodes;
+//               the octree is stored two levels per node (64-bit occupancy
+//               mask + base index), and the node of the current 4^3 brick of
+//               leaves is kept in registers.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -18,6 +21,7 @@
 namespace neuvv {
 
 constexpr int kMaxDepth = 12;
+constexpr int kMaxLevels = (kMaxDepth + 1) / 2;   // node levels (two octree levels each)
 constexpr int kWave = 64;
 
 // ----------------------------------------------------------------------------
@@ -156,7 +160,7 @@ __device__ __forceinline__ void hh_all(float x, float y, float z, float gam, flo
 // kernel-side descriptions of the tree, instance and rays
 
 struct TreeArgs {
-    const int32_t* child;
+    const int4* nodes;   // [n_nodes] {mask lo, mask hi, first child, 0}
     const void* hh;
     const void* wsig;
     const float* basis;
@@ -357,13 +361,27 @@ __device__ __forceinline__ void ray_setup(const TreeArgs& tr, const InstArgs& in
 
 struct Walk {
     int cell[3];     // leaf-level cell containing the ray just after the entry point
-    int lvl;         // path[0..lvl] holds the ancestors of cell
+    int lvl;         // node level of the deepest ancestor of cell known in path[]
     int steps;
     int entry_axis;  // the entry point is the crossing of plane entry_plane on this axis; -1: u_in
     int entry_plane;
     float u_est;     // float estimate of the entry parameter
     bool done;
+    int brick;       // row of the last-level node held below, -1: none
+    uint32_t bm_lo, bm_hi;
+    int bbase;
 };
+
+// Node levels of a depth-D tree: L = ceil(D/2); level w is a cube of edge
+// 2^node_edge(D, w) split into child cells of edge 2^(node_edge - node_bits).
+__device__ __forceinline__ int node_bits(int D, int w) { return (w == 0 && (D & 1)) ? 1 : 2; }
+__device__ __forceinline__ int node_edge(int D, int w) { return w == 0 ? D : D - (D & 1 ? 1 : 2) - 2 * (w - 1); }
+// Deepest node level whose node still contains two cells whose coordinates
+// first differ in bit hb.
+__device__ __forceinline__ int common_level(int D, int hb) {
+    const int top = (D & 1) ? 1 : 2;
+    return D - top > hb ? ((D - top - hb - 1) >> 1) + 1 : 0;
+}
 
 __device__ __forceinline__ void walk_begin(const TreeArgs& tr, const RaySetup& rs, Walk& w) {
 #pragma unroll
@@ -378,6 +396,9 @@ __device__ __forceinline__ void walk_begin(const TreeArgs& tr, const RaySetup& r
     w.entry_plane = 0;
     w.u_est = df_f(rs.u_in);
     w.done = !rs.hit;
+    w.brick = -1;
+    w.bm_lo = w.bm_hi = 0u;
+    w.bbase = 0;
 }
 
 // v[i] for a runtime i in [0, 3) without indexing a local array (which would
@@ -405,7 +426,8 @@ __device__ __forceinline__ df entry_param(const RaySetup& rs, const Walk& w) {
 // Advances to the next occupied leaf segment of positive length. Returns its
 // slot and writes delta (leaf units) and umid (ray parameter of the segment
 // midpoint); returns -1 when the ray has left the box. path points at this
-// lane's column of a [kMaxDepth][stride] LDS array.
+// lane's column of a [kMaxLevels][stride] LDS array of node rows; s_nodes
+// holds the first n_lds rows of the node table.
 //
 // Every decision of the walk (which face a node is left through, which cell
 // the ray enters, whether it leaves the box) is taken on float estimates
@@ -413,29 +435,49 @@ __device__ __forceinline__ df entry_param(const RaySetup& rs, const Walk& w) {
 // bound of the decision threshold is it redone in compensated arithmetic.
 // Segment lengths of leaves always come from compensated entry and exit
 // parameters. The sequence of cells is therefore that of the exact walk.
-__device__ __forceinline__ int walk_next(const TreeArgs& tr, const int* __restrict__ s_child, int n_lds,
+__device__ __forceinline__ int walk_next(const TreeArgs& tr, const int4* __restrict__ s_nodes, int n_lds,
                                          int* path, int stride, const RaySetup& rs, Walk& w, float& delta,
                                          float& umid) {
     const int Dp = tr.depth;
     const int G = 1 << Dp;
+    const int last = (Dp + 1) / 2 - 1;   // last node level
     const int max_steps = 3 * G + 16;
     constexpr float kRel = 1.0e-6f;   // bound on the relative error of a float estimate (~16 ulp)
     while (!w.done) {
         if (++w.steps > max_steps) { w.done = true; break; }
-        // descend from the deepest valid ancestor
+        // descend from the deepest valid ancestor; sh = log2 of the edge of the
+        // empty octree node or leaf reached
         int lvl = w.lvl;
         int node = lvl == 0 ? 0 : path[lvl * stride];
         int leaf = -1;
         int sh;
         for (;;) {
-            sh = Dp - 1 - lvl;
-            int oct = ((w.cell[0] >> sh) & 1) | (((w.cell[1] >> sh) & 1) << 1) | (((w.cell[2] >> sh) & 1) << 2);
-            int ch = node < n_lds ? s_child[node * 8 + oct] : tr.child[(int64_t)node * 8 + oct];
-            if (ch < 0) break;                  // empty cube of edge 2^sh
-            if (sh == 0) { leaf = ch; break; }  // occupied leaf
+            uint32_t mlo, mhi;
+            int base;
+            if (lvl == last && node == w.brick) {
+                mlo = w.bm_lo; mhi = w.bm_hi; base = w.bbase;
+            } else {
+                const int4 v = node < n_lds ? s_nodes[node] : tr.nodes[node];
+                mlo = (uint32_t)v.x; mhi = (uint32_t)v.y; base = v.z;
+                if (lvl == last) { w.brick = node; w.bm_lo = mlo; w.bm_hi = mhi; w.bbase = base; }
+            }
+            const int bits = node_bits(Dp, lvl);
+            const int cs = node_edge(Dp, lvl) - bits;   // log2 child edge
+            const int x = w.cell[0] >> cs, y = w.cell[1] >> cs, z = w.cell[2] >> cs;
+            int q = (x & 1) | ((y & 1) << 1) | ((z & 1) << 2);
+            if (bits == 2) q |= ((x & 2) << 2) | ((y & 2) << 3) | ((z & 2) << 4);
+            const uint64_t m = ((uint64_t)mhi << 32) | mlo;
+            if (!((m >> q) & 1ull)) {
+                // empty child cell; the octree node one level up (its 2^3 group,
+                // one byte of the mask) may be empty as a whole
+                sh = (bits == 2 && ((m >> (q & 56)) & 0xffull) == 0ull) ? cs + 1 : cs;
+                break;
+            }
+            const int idx = base + (int)__builtin_popcountll(m & ((1ull << q) - 1ull));
+            if (lvl == last) { leaf = idx; sh = 0; break; }   // occupied leaf
             ++lvl;
-            node = ch;
-            path[lvl * stride] = ch;
+            node = idx;
+            path[lvl * stride] = idx;
         }
         const int S = 1 << sh;
         int corner[3], plane[3];
@@ -541,7 +583,7 @@ __device__ __forceinline__ int walk_next(const TreeArgs& tr, const int* __restri
             } else {
                 const unsigned x = (unsigned)((w.cell[0] ^ nc[0]) | (w.cell[1] ^ nc[1]) | (w.cell[2] ^ nc[2]));
                 const int hb = 31 - __builtin_clz(x);     // x != 0: the exit axis changed
-                const int common = Dp - 1 - hb;
+                const int common = common_level(Dp, hb);
                 w.lvl = common < lvl ? common : lvl;
                 w.cell[0] = nc[0];
                 w.cell[1] = nc[1];

@@ -12,7 +12,8 @@
 // leaves in one L2.
 //
 // Per lane: walk_next() descends the octree to the next occupied leaf
-// (top nodes from LDS, the rest from HBM/L2), the leaf's 16-byte-vector
+// (top node rows from LDS, the rest from L2/HBM, the current brick's node in
+// registers), the leaf's 16-byte-vector
 // structure-of-arrays payload is gathered, colour and density evaluated in
 // float32 and composited. The per-sample HH contraction is a 3x16 times 16
 // matrix-vector product with a different matrix per sample, so it stays on
@@ -27,7 +28,9 @@
 namespace neuvv {
 
 constexpr int kBlock = 256;
-constexpr int kLdsNodes = 512;
+// node rows (16 B each) staged in LDS: the top levels of the tree
+constexpr int kLdsNodesFwd = 2048;
+constexpr int kLdsNodesBwd = 1024;
 
 template <int DT>
 struct StoreTraits;
@@ -90,8 +93,8 @@ __device__ __forceinline__ int lane_rank(uint64_t mask) {
     return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
-// Stages the first min(n_nodes, kLdsNodes) octree nodes (the top levels,
-// stored first) in LDS and computes this wavefront's place in the grid.
+// This wavefront's place in the grid: its global index, the number of
+// wavefronts, and the length of its stream of slots.
 struct WaveSched {
     int64_t gw, n_waves, stream_len;
 };
@@ -110,9 +113,12 @@ __device__ __forceinline__ WaveSched wave_schedule(const RayArgs& ra) {
     return s;
 }
 
-__device__ __forceinline__ int stage_top_nodes(const TreeArgs& tr, int* s_child) {
-    const int n_lds = (int)(tr.n_nodes < kLdsNodes ? tr.n_nodes : kLdsNodes);
-    for (int i = threadIdx.x; i < n_lds * 8; i += kBlock) s_child[i] = tr.child[i];
+// Stages the first min(n_nodes, CAP) node rows (the top levels, stored
+// first) in LDS; returns their number.
+template <int CAP>
+__device__ __forceinline__ int stage_top_nodes(const TreeArgs& tr, int4* s_nodes) {
+    const int n_lds = (int)(tr.n_nodes < CAP ? tr.n_nodes : CAP);
+    for (int i = threadIdx.x; i < n_lds; i += kBlock) s_nodes[i] = tr.nodes[i];
     __syncthreads();
     return n_lds;
 }
@@ -145,9 +151,9 @@ __device__ __forceinline__ void write_miss(const RenderOut& out, int64_t ray) {
 template <int K, int C, int DT, bool IDENT>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) void render_fwd_kernel(TreeArgs tr, InstArgs in, RayArgs ra, float t_stop,
                                                             RenderOut out) {
-    __shared__ int s_child[kLdsNodes * 8];
-    __shared__ int s_path[kMaxDepth * kBlock];
-    const int n_lds = stage_top_nodes(tr, s_child);
+    __shared__ int4 s_nodes[kLdsNodesFwd];
+    __shared__ int s_path[kMaxLevels * kBlock];
+    const int n_lds = stage_top_nodes<kLdsNodesFwd>(tr, s_nodes);
     int* path = s_path + threadIdx.x;
     const WaveSched ws = wave_schedule(ra);
 
@@ -206,7 +212,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
         if (n_idle == kWave) break;
         if (alive) {
             float delta, umid;
-            const int leaf = walk_next(tr, s_child, n_lds, path, kBlock, rs, w, delta, umid);
+            const int leaf = walk_next(tr, s_nodes, n_lds, path, kBlock, rs, w, delta, umid);
             bool finish = leaf < 0;
             if (!finish) {
                 float wv[3 * K], sv[C];
@@ -267,13 +273,13 @@ template <int K, int C, int DT, bool IDENT>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) void render_bwd_kernel(
     TreeArgs tr, InstArgs in, RayArgs ra, BackwardIO io) {
     constexpr int ROW = grad_row<K, C>();
-    __shared__ int s_child[kLdsNodes * 8];
-    __shared__ int s_path[kMaxDepth * kBlock];
+    __shared__ int4 s_nodes[kLdsNodesBwd];
+    __shared__ int s_path[kMaxLevels * kBlock];
     __shared__ float s_h[kBlock * K];
     __shared__ float s_b[kBlock * C];
     __shared__ float s_gb[C];
     if (threadIdx.x < C) s_gb[threadIdx.x] = 0.0f;   // made visible by the barrier in stage_top_nodes
-    const int n_lds = stage_top_nodes(tr, s_child);
+    const int n_lds = stage_top_nodes<kLdsNodesBwd>(tr, s_nodes);
     int* path = s_path + threadIdx.x;
     const WaveSched ws = wave_schedule(ra);
     const int64_t N = tr.n_leaves;
@@ -355,7 +361,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
         float gz0 = 0.0f, gz1 = 0.0f, gz2 = 0.0f, gx = 0.0f;
         if (alive) {
             float delta, umid;
-            leaf = walk_next(tr, s_child, n_lds, path, kBlock, rs, w, delta, umid);
+            leaf = walk_next(tr, s_nodes, n_lds, path, kBlock, rs, w, delta, umid);
             bool finish = leaf < 0;
             if (!finish) {
                 float wv[3 * K], sv[C];

@@ -14,15 +14,16 @@ from . import _lib
 _TORCH_DTYPE = {_lib.F32: torch.float32, _lib.F16: torch.float16, _lib.BF16: torch.bfloat16}
 
 
-def build_child_table(depth: int, leaf_ijk: np.ndarray, with_box: bool = False):
-    """Host octree over the leaf cells: (child [n_nodes,8] int32, slot_of_input [N] int64[, box [6]])."""
+def build_node_table(depth: int, leaf_ijk: np.ndarray, with_box: bool = False):
+    """Host octree over the leaf cells, two levels per node row:
+    (nodes [n_nodes,4] int32, slot_of_input [N] int64[, box [6]])."""
     ijk = np.ascontiguousarray(leaf_ijk, dtype=np.int32).reshape(-1, 3)
     n_nodes = _lib.neuvv_build_voctree(depth, ijk)
-    child = np.empty((n_nodes, 8), np.int32)
+    nodes = np.empty((n_nodes, 4), np.int32)
     slots = np.empty(ijk.shape[0], np.int64)
     box = np.zeros(6, np.int32)
-    _lib.neuvv_build_voctree(depth, ijk, child, n_nodes, slots, box)
-    return (child, slots, box) if with_box else (child, slots)
+    _lib.neuvv_build_voctree(depth, ijk, nodes, n_nodes, slots, box)
+    return (nodes, slots, box) if with_box else (nodes, slots)
 
 
 @dataclass
@@ -33,7 +34,7 @@ class VOctree:
     T: int
     dtype: int
     n_leaves: int
-    child: torch.Tensor          # [n_nodes, 8] int32
+    nodes: torch.Tensor          # [n_nodes, 4] int32 node rows (mask lo, mask hi, first child, 0)
     hh: torch.Tensor             # packed colour coefficients (storage dtype)
     wsig: torch.Tensor           # packed density weights (storage dtype)
     basis: torch.Tensor          # [T, C] float32
@@ -46,14 +47,14 @@ class VOctree:
     def build(cls, depth: int, leaf_ijk, hh, wsig, basis, gamma, dtype: int = _lib.F32,
               device: str = "cuda", stream=None, layout: int = _lib.LAYOUT_VEC_SOA) -> "VOctree":
         """leaf_ijk [N,3]; hh [N,3,K] and wsig [N,C] float32 per input leaf; basis [T,C]; gamma [T]."""
-        child, slots, box = build_child_table(depth, leaf_ijk, with_box=True)
+        nodes, slots, box = build_node_table(depth, leaf_ijk, with_box=True)
         hh = np.ascontiguousarray(hh, np.float32)
         wsig = np.ascontiguousarray(wsig, np.float32)
         N, _, K = hh.shape
         C = wsig.shape[1]
         dev = torch.device(device)
         t = cls(depth, K, C, int(np.asarray(basis).shape[0]), dtype, N,
-                torch.from_numpy(child).to(dev), None, None,
+                torch.from_numpy(nodes).to(dev), None, None,
                 torch.from_numpy(np.ascontiguousarray(basis, np.float32)).to(dev),
                 torch.from_numpy(np.ascontiguousarray(gamma, np.float32)).to(dev),
                 torch.from_numpy(slots).to(dev), tuple(int(v) for v in box), layout)
@@ -67,7 +68,7 @@ class VOctree:
         """(Re)packs float32 coefficients given per input leaf ([N,3,K], [N,C], device)."""
         a, b = self.payload_elems()
         td = _TORCH_DTYPE[self.dtype]
-        dev = self.child.device
+        dev = self.nodes.device
         if self.hh is None or self.hh.numel() != a:
             self.hh = torch.empty(a, dtype=td, device=dev)
             self.wsig = torch.empty(b, dtype=td, device=dev)
@@ -77,8 +78,8 @@ class VOctree:
     def struct(self) -> _lib.neuvv_tree:
         s = _lib.neuvv_tree()
         s.depth, s.K, s.C, s.dtype = self.depth, self.K, self.C, self.dtype
-        s.n_nodes, s.n_leaves = int(self.child.shape[0]), self.n_leaves
-        s.child, s.hh, s.wsig = self.child.data_ptr(), self.hh.data_ptr(), self.wsig.data_ptr()
+        s.n_nodes, s.n_leaves = int(self.nodes.shape[0]), self.n_leaves
+        s.nodes, s.hh, s.wsig = self.nodes.data_ptr(), self.hh.data_ptr(), self.wsig.data_ptr()
         s.T, s.basis, s.gamma = self.T, self.basis.data_ptr(), self.gamma.data_ptr()
         for i in range(6):
             s.box[i] = self.box[i]
@@ -91,7 +92,7 @@ class VOctree:
 
     def zero_grads(self):
         """Zeroed float32 gradient buffers: leaf rows [N, ROW] and the basis [T, C]."""
-        dev = self.child.device
+        dev = self.nodes.device
         return (torch.zeros(self.n_leaves, self.grad_row, dtype=torch.float32, device=dev),
                 torch.zeros(self.T, self.C, dtype=torch.float32, device=dev))
 
