@@ -11,7 +11,12 @@
  * Conventions shared by every call
  *   - Pointers named "device" are HIP device pointers owned by the caller;
  *     pointers named "host" are host memory owned by the caller. The library
- *     keeps no pointer after a call returns and allocates no device memory.
+ *     keeps no pointer after a call returns. The only device memory it
+ *     allocates is the 1 KiB of work-queue counters that neuvv_render and
+ *     neuvv_render_backward take per call from the stream-ordered allocator
+ *     (hipMallocAsync on the call's stream, released with hipFreeAsync after
+ *     the kernel); each call has its own, so calls on different streams do
+ *     not interfere.
  *   - "stream" is a hipStream_t (NULL = the null stream). GPU work is queued
  *     on it asynchronously; the caller synchronises. Argument errors are
  *     detected on the host before anything is queued.

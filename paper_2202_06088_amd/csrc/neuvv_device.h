@@ -193,6 +193,7 @@ struct RayArgs {
     int64_t n;
     int64_t n_slots;     // work slots (64 per 8x8 tile when img_w > 0, else n)
     int32_t refill_min;  // idle lanes that trigger a refill of the wavefront
+    unsigned long long* queue;   // work-queue counters of the launch (set by the launcher)
 };
 
 // Work slot -> ray index, -1 when the slot is padding of a ragged tile.

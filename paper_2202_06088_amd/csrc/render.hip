@@ -1,15 +1,18 @@
 // VOctree volume rendering on gfx950: forward (Sec. 4.3 "Rendering", Eq. 4,
 // 5, 8, 9) and adjoint (Sec. 4.3 "Optimization").
 //
-// Work distribution: persistent wavefronts. Rays are grouped in chunks of 64
-// work slots (an 8x8 pixel tile when the rays form an image); wavefront w of
-// the grid owns chunks w, w + n_waves, w + 2 n_waves, ... as one stream of
-// slots. A lane whose ray has finished is refilled from that stream: the
-// wavefront takes a ballot of the idle lanes, hands the next slots to them in
-// lane order with mbcnt, and advances its (wave-uniform) stream cursor by the
-// popcount. Blocks are renumbered so that consecutive chunks land on the
-// same XCD (hardware places block b on XCD b % 8), keeping a tile band's
-// leaves in one L2.
+// Work distribution: persistent wavefronts fed from work queues. Rays are
+// grouped in chunks of 64 work slots (an 8x8 pixel tile when the rays form an
+// image). The chunk range is cut into one contiguous part per XCD (hardware
+// places block b on XCD b % 8), so that neighbouring tiles, which hit the
+// same leaves, share an L2; each part has an atomic counter. A wavefront
+// takes chunks one at a time from its own XCD's counter, then from the other
+// parts in turn once its own is drained, so no wavefront idles while work is
+// left anywhere (the cost of a tile varies by orders of magnitude between
+// sky and subject). A lane whose ray has finished is refilled from the
+// current chunk: the wavefront takes a ballot of the idle lanes, hands the
+// next slots to them in lane order with mbcnt, and advances its
+// (wave-uniform) cursor by the popcount.
 //
 // Per lane: walk_next() descends the octree to the next occupied leaf
 // (top node rows from LDS, the rest from L2/HBM, the current brick's node in
@@ -93,24 +96,43 @@ __device__ __forceinline__ int lane_rank(uint64_t mask) {
     return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
-// This wavefront's place in the grid: its global index, the number of
-// wavefronts, and the length of its stream of slots.
-struct WaveSched {
-    int64_t gw, n_waves, stream_len;
+// Dynamic chunk distribution: kQueues counters, 128 bytes apart, one per XCD.
+constexpr int kQueues = 8;
+constexpr int kQueueStride = 16;
+
+struct ChunkCursor {
+    int home;       // this block's XCD
+    int tried;      // queues drained so far (wave-uniform)
+    int64_t chunk;  // current chunk
+    int pos;        // slots of it handed out; 64 = take a new chunk
 };
 
-__device__ __forceinline__ WaveSched wave_schedule(const RayArgs& ra) {
-    const int nb = gridDim.x, b = blockIdx.x;
-    const int per = nb / 8, rem = nb % 8, x = b % 8, k = b / 8;
-    const int logical = (x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per) + k;
-    constexpr int wpb = kBlock / kWave;
-    WaveSched s;
-    s.gw = (int64_t)logical * wpb + (threadIdx.x >> 6);
-    s.n_waves = (int64_t)nb * wpb;
+__device__ __forceinline__ ChunkCursor chunk_cursor() {
+    ChunkCursor c;
+    c.home = (int)(blockIdx.x & (kQueues - 1));
+    c.tried = 0;
+    c.chunk = -1;
+    c.pos = kWave;
+    return c;
+}
+
+// Next chunk for the (converged) wavefront, or -1 when every queue is drained.
+// One lane takes the ticket; the result is wave-uniform.
+__device__ __forceinline__ int64_t next_chunk(const RayArgs& ra, ChunkCursor& cc) {
     const int64_t n_chunks = (ra.n_slots + 63) >> 6;
-    const int64_t mine = s.gw < n_chunks ? (n_chunks - 1 - s.gw) / s.n_waves + 1 : 0;
-    s.stream_len = mine * 64;
-    return s;
+    const int leader = __builtin_ctzll(__ballot(1));
+    while (cc.tried < kQueues) {
+        const int x = (cc.home + cc.tried) & (kQueues - 1);
+        const int64_t lo = n_chunks * x / kQueues, hi = n_chunks * (x + 1) / kQueues;
+        unsigned long long t = 0;
+        if ((int)(threadIdx.x & 63) == leader) t = atomicAdd(ra.queue + x * kQueueStride, 1ull);
+        const uint32_t t_lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)t);
+        const uint32_t t_hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(t >> 32));
+        const int64_t k = lo + (int64_t)(((uint64_t)t_hi << 32) | t_lo);
+        if (k < hi) return k;
+        ++cc.tried;
+    }
+    return -1;
 }
 
 // Stages the first min(n_nodes, CAP) node rows (the top levels, stored
@@ -155,7 +177,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
     __shared__ int s_path[kMaxLevels * kBlock];
     const int n_lds = stage_top_nodes<kLdsNodesFwd>(tr, s_nodes);
     int* path = s_path + threadIdx.x;
-    const WaveSched ws = wave_schedule(ra);
+    ChunkCursor cc = chunk_cursor();
+    bool more = true;   // wave-uniform: chunks may be left
 
     bool alive = false;
     int64_t ray = -1;
@@ -164,27 +187,31 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
     float h[K], bv[C];
     float Tr = 1.0f, acc0 = 0.0f, acc1 = 0.0f, acc2 = 0.0f, wsum = 0.0f, dsum = 0.0f;
     int ns = 0;
-    int64_t p_next = 0;
 
     for (;;) {
         const uint64_t idle = __ballot(!alive);
         const int n_idle = __popcll(idle);
-        const bool more = p_next < ws.stream_len;
         if (more && (n_idle >= ra.refill_min || n_idle == kWave)) {
-            // Acquisition: idle lanes take the next slots of the stream; rays the
-            // plain-float test rejects get their miss outputs at once and the lane
-            // takes another slot, while at least refill_min lanes are idle. Then
-            // the compensated setup runs once for all accepted rays together.
+            // Acquisition: idle lanes take the next slots; rays the plain-float
+            // test rejects get their miss outputs at once and the lane takes
+            // another slot, while at least refill_min lanes are idle. Then the
+            // compensated setup runs once for all accepted rays together.
             bool cand = false;
             float o[3], d[3], t = 0.0f;
             for (;;) {
                 const uint64_t need = __ballot(!alive && !cand);
-                if (__popcll(need) < ra.refill_min || p_next >= ws.stream_len) break;
+                const int n_need = __popcll(need);
+                if (n_need < ra.refill_min) break;
+                if (cc.pos == kWave) {
+                    cc.chunk = next_chunk(ra, cc);
+                    cc.pos = 0;
+                    if (cc.chunk < 0) { more = false; break; }
+                }
+                const int take = n_need < kWave - cc.pos ? n_need : kWave - cc.pos;
                 if (!alive && !cand) {
-                    const int64_t pos = p_next + lane_rank(need);
-                    if (pos < ws.stream_len) {
-                        const int64_t slot = (ws.gw + (pos >> 6) * ws.n_waves) * 64 + (pos & 63);
-                        ray = slot_to_ray(ra, slot);
+                    const int r = lane_rank(need);
+                    if (r < take) {
+                        ray = slot_to_ray(ra, cc.chunk * 64 + cc.pos + r);
                         if (ray >= 0) {
                             o[0] = ra.o[3 * ray]; o[1] = ra.o[3 * ray + 1]; o[2] = ra.o[3 * ray + 2];
                             d[0] = ra.d[3 * ray]; d[1] = ra.d[3 * ray + 1]; d[2] = ra.d[3 * ray + 2];
@@ -194,7 +221,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
                         }
                     }
                 }
-                p_next += __popcll(need);
+                cc.pos += take;
             }
             if (cand) {
                 ray_setup<IDENT>(tr, in, o, d, t, rs);
@@ -281,7 +308,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
     if (threadIdx.x < C) s_gb[threadIdx.x] = 0.0f;   // made visible by the barrier in stage_top_nodes
     const int n_lds = stage_top_nodes<kLdsNodesBwd>(tr, s_nodes);
     int* path = s_path + threadIdx.x;
-    const WaveSched ws = wave_schedule(ra);
+    ChunkCursor cc = chunk_cursor();
+    bool more = true;   // wave-uniform: chunks may be left
     const int64_t N = tr.n_leaves;
     const bool per_ray_t = ra.t != nullptr;
     const int lane = threadIdx.x & 63;
@@ -299,12 +327,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
     float Tr = 1.0f, Tfin = 0.0f, p0 = 0.0f, p1 = 0.0f, p2 = 0.0f, F0 = 0.0f, F1 = 0.0f, F2 = 0.0f;
     float g0 = 0.0f, g1 = 0.0f, g2 = 0.0f, ga = 0.0f;
     int ns = 0, ns_fwd = 0;
-    int64_t p_next = 0;
 
     for (;;) {
         const uint64_t idle = __ballot(!alive);
         const int n_idle = __popcll(idle);
-        const bool more = p_next < ws.stream_len;
         if (more && (n_idle >= ra.refill_min || n_idle == kWave)) {
             // Acquisition: idle lanes take the next slots while at least refill_min
             // lanes are idle; rays that composited no sample carry no gradient and
@@ -312,16 +338,22 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
             bool cand = false;
             for (;;) {
                 const uint64_t need = __ballot(!alive && !cand);
-                if (__popcll(need) < ra.refill_min || p_next >= ws.stream_len) break;
+                const int n_need = __popcll(need);
+                if (n_need < ra.refill_min) break;
+                if (cc.pos == kWave) {
+                    cc.chunk = next_chunk(ra, cc);
+                    cc.pos = 0;
+                    if (cc.chunk < 0) { more = false; break; }
+                }
+                const int take = n_need < kWave - cc.pos ? n_need : kWave - cc.pos;
                 if (!alive && !cand) {
-                    const int64_t pos = p_next + lane_rank(need);
-                    if (pos < ws.stream_len) {
-                        const int64_t slot = (ws.gw + (pos >> 6) * ws.n_waves) * 64 + (pos & 63);
-                        ray = slot_to_ray(ra, slot);
+                    const int r = lane_rank(need);
+                    if (r < take) {
+                        ray = slot_to_ray(ra, cc.chunk * 64 + cc.pos + r);
                         cand = ray >= 0 && io.nsamp[ray] > 0;
                     }
                 }
-                p_next += __popcll(need);
+                cc.pos += take;
             }
             if (cand) {
                 const float o[3] = {ra.o[3 * ray], ra.o[3 * ray + 1], ra.o[3 * ray + 2]};
@@ -490,6 +522,25 @@ static int grid_for(KernelT kernel, const RayArgs& ra) {
     return (int)(g > 0 ? g : 1);
 }
 
+// Work-queue counters of one launch: 1 KiB of stream-ordered scratch, zeroed
+// by a one-block kernel (no memset node, so the sequence may be captured in a
+// graph) and freed after the render kernel in stream order.
+__global__ void zero_queue_kernel(unsigned long long* q) { q[threadIdx.x] = 0ull; }
+
+template <typename Launch>
+static hipError_t with_queue(const RayArgs& ra_in, hipStream_t st, Launch&& launch) {
+    RayArgs ra = ra_in;
+    void* q = nullptr;
+    hipError_t e = hipMallocAsync(&q, kQueues * kQueueStride * sizeof(unsigned long long), st);
+    if (e != hipSuccess) return e;
+    ra.queue = static_cast<unsigned long long*>(q);
+    hipLaunchKernelGGL(zero_queue_kernel, dim3(1), dim3(kQueues * kQueueStride), 0, st, ra.queue);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = launch(ra);
+    const hipError_t f = hipFreeAsync(q, st);
+    return e != hipSuccess ? e : f;
+}
+
 template <int K, int C, int DT>
 static hipError_t fwd_t(const TreeArgs& tr, const InstArgs& in, const RayArgs& ra, float t_stop, const RenderOut& o,
                         hipStream_t st) {
@@ -522,9 +573,9 @@ hipError_t launch_render_fwd(int K, int C, int dtype, const TreeArgs& tr, const 
     (void)C;
     if (ra.n_slots <= 0) return hipSuccess;
     switch (dtype) {
-        case 0: return fwd_t<16, 8, 0>(tr, in, ra, t_stop, out, stream);
-        case 1: return fwd_t<16, 8, 1>(tr, in, ra, t_stop, out, stream);
-        default: return fwd_t<16, 8, 2>(tr, in, ra, t_stop, out, stream);
+        case 0: return with_queue(ra, stream, [&](const RayArgs& r) { return fwd_t<16, 8, 0>(tr, in, r, t_stop, out, stream); });
+        case 1: return with_queue(ra, stream, [&](const RayArgs& r) { return fwd_t<16, 8, 1>(tr, in, r, t_stop, out, stream); });
+        default: return with_queue(ra, stream, [&](const RayArgs& r) { return fwd_t<16, 8, 2>(tr, in, r, t_stop, out, stream); });
     }
 }
 
@@ -534,9 +585,9 @@ hipError_t launch_render_bwd(int K, int C, int dtype, const TreeArgs& tr, const 
     (void)C;
     if (ra.n_slots <= 0) return hipSuccess;
     switch (dtype) {
-        case 0: return bwd_t<16, 8, 0>(tr, in, ra, io, stream);
-        case 1: return bwd_t<16, 8, 1>(tr, in, ra, io, stream);
-        default: return bwd_t<16, 8, 2>(tr, in, ra, io, stream);
+        case 0: return with_queue(ra, stream, [&](const RayArgs& r) { return bwd_t<16, 8, 0>(tr, in, r, io, stream); });
+        case 1: return with_queue(ra, stream, [&](const RayArgs& r) { return bwd_t<16, 8, 1>(tr, in, r, io, stream); });
+        default: return with_queue(ra, stream, [&](const RayArgs& r) { return bwd_t<16, 8, 2>(tr, in, r, io, stream); });
     }
 }
 
