@@ -51,7 +51,7 @@ def kernel_source_hash() -> str:
 
 def measured_traffic(kernel: str, workload: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it was
-    taken on the current kernel source; else None."""
+    taken on the current kernel source; else None. kernel = "<name>/<layout>/<dtype>"."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as fh:
@@ -161,12 +161,12 @@ def main():
     achieved = dbytes / (dms * 1e-3) / 1e9
     workload = "forward_ring_d9_2M_8x1080p"
     roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(dom, workload),
+            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(f"{dom}/{args.layout}/{args.dtype}", workload),
             "algorithmic_bytes_per_launch": dbytes, "launch_ms": round(dms, 4)}
     other = [k for k in kern if k != dom][0]
     roof_other = {"kernel": other, "achieved": round(kern[other][1] / (kern[other][0] * 1e-3) / 1e9, 1),
                   "launch_ms": round(kern[other][0], 4), "algorithmic_bytes_per_launch": kern[other][1],
-                  "traffic": measured_traffic(other, workload)}
+                  "traffic": measured_traffic(f"{other}/{args.layout}/{args.dtype}", workload)}
 
     result = {
         "metric": METRIC, "value": round(n / (ms_step * 1e-3) / 1e6, 2), "unit": "Mrays/s", "n_gpus": 1,
