@@ -70,7 +70,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--dtype", choices=["f32", "f16", "bf16"], default="f32")
-    ap.add_argument("--layout", choices=["soa", "rows"], default="soa",
+    ap.add_argument("--layout", choices=["soa", "rows"], default="rows",
                     help="leaf payload layout: 16-byte-vector SoA or leaf-major rows")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)

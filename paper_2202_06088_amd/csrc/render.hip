@@ -103,22 +103,24 @@ constexpr int kQueueStride = 16;
 struct ChunkCursor {
     int home;       // this block's XCD
     int tried;      // queues drained so far (wave-uniform)
-    int64_t chunk;  // current chunk
-    int pos;        // slots of it handed out; 64 = take a new chunk
+    int pos;        // slots of the current chunk handed out; 64 = take a new chunk
+    int px0;        // x of the tile's first pixel (images)
+    int64_t base;   // ray index of the chunk's first slot
 };
 
 __device__ __forceinline__ ChunkCursor chunk_cursor() {
     ChunkCursor c;
     c.home = (int)(blockIdx.x & (kQueues - 1));
     c.tried = 0;
-    c.chunk = -1;
     c.pos = kWave;
+    c.px0 = 0;
+    c.base = 0;
     return c;
 }
 
-// Next chunk for the (converged) wavefront, or -1 when every queue is drained.
-// One lane takes the ticket; the result is wave-uniform.
-__device__ __forceinline__ int64_t next_chunk(const RayArgs& ra, ChunkCursor& cc) {
+// Moves the (converged) wavefront to its next chunk; false when every queue
+// is drained. One lane takes the ticket; the result is wave-uniform.
+__device__ __forceinline__ bool next_chunk(const RayArgs& ra, ChunkCursor& cc) {
     const int64_t n_chunks = (ra.n_slots + 63) >> 6;
     const int leader = __builtin_ctzll(__ballot(1));
     while (cc.tried < kQueues) {
@@ -129,10 +131,32 @@ __device__ __forceinline__ int64_t next_chunk(const RayArgs& ra, ChunkCursor& cc
         const uint32_t t_lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)t);
         const uint32_t t_hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(t >> 32));
         const int64_t k = lo + (int64_t)(((uint64_t)t_hi << 32) | t_lo);
-        if (k < hi) return k;
+        if (k < hi) {
+            cc.pos = 0;
+            if (ra.img_w > 0) {
+                const int64_t ty = k / ra.tiles_x, tx = k - ty * ra.tiles_x;
+                cc.px0 = (int)(tx * 8);
+                cc.base = ty * 8 * (int64_t)ra.img_w + cc.px0;
+            } else {
+                cc.base = k * 64;
+            }
+            return true;
+        }
         ++cc.tried;
     }
-    return -1;
+    return false;
+}
+
+// Ray index of slot `within` (0..63) of the current chunk, -1 for padding.
+__device__ __forceinline__ int64_t chunk_ray(const RayArgs& ra, const ChunkCursor& cc, int within) {
+    int64_t r;
+    if (ra.img_w > 0) {
+        if (cc.px0 + (within & 7) >= ra.img_w) return -1;
+        r = cc.base + (int64_t)(within >> 3) * ra.img_w + (within & 7);
+    } else {
+        r = cc.base + within;
+    }
+    return r < ra.n ? r : -1;
 }
 
 // Stages the first min(n_nodes, CAP) node rows (the top levels, stored
@@ -202,16 +226,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
                 const uint64_t need = __ballot(!alive && !cand);
                 const int n_need = __popcll(need);
                 if (n_need < ra.refill_min) break;
-                if (cc.pos == kWave) {
-                    cc.chunk = next_chunk(ra, cc);
-                    cc.pos = 0;
-                    if (cc.chunk < 0) { more = false; break; }
+                if (cc.pos == kWave && !next_chunk(ra, cc)) {
+                    more = false;
+                    break;
                 }
                 const int take = n_need < kWave - cc.pos ? n_need : kWave - cc.pos;
                 if (!alive && !cand) {
                     const int r = lane_rank(need);
                     if (r < take) {
-                        ray = slot_to_ray(ra, cc.chunk * 64 + cc.pos + r);
+                        ray = chunk_ray(ra, cc, cc.pos + r);
                         if (ray >= 0) {
                             o[0] = ra.o[3 * ray]; o[1] = ra.o[3 * ray + 1]; o[2] = ra.o[3 * ray + 2];
                             d[0] = ra.d[3 * ray]; d[1] = ra.d[3 * ray + 1]; d[2] = ra.d[3 * ray + 2];
@@ -340,16 +363,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
                 const uint64_t need = __ballot(!alive && !cand);
                 const int n_need = __popcll(need);
                 if (n_need < ra.refill_min) break;
-                if (cc.pos == kWave) {
-                    cc.chunk = next_chunk(ra, cc);
-                    cc.pos = 0;
-                    if (cc.chunk < 0) { more = false; break; }
+                if (cc.pos == kWave && !next_chunk(ra, cc)) {
+                    more = false;
+                    break;
                 }
                 const int take = n_need < kWave - cc.pos ? n_need : kWave - cc.pos;
                 if (!alive && !cand) {
                     const int r = lane_rank(need);
                     if (r < take) {
-                        ray = slot_to_ray(ra, cc.chunk * 64 + cc.pos + r);
+                        ray = chunk_ray(ra, cc, cc.pos + r);
                         cand = ray >= 0 && io.nsamp[ray] > 0;
                     }
                 }

@@ -41,11 +41,11 @@ class VOctree:
     gamma: torch.Tensor          # [T] float32
     slot_of_input: torch.Tensor  # [N] int64, device
     box: tuple = (0, 0, 0, 0, 0, 0)  # occupied-cell bounds (lo xyz, hi xyz exclusive)
-    layout: int = _lib.LAYOUT_VEC_SOA
+    layout: int = _lib.LAYOUT_LEAF_ROWS
 
     @classmethod
     def build(cls, depth: int, leaf_ijk, hh, wsig, basis, gamma, dtype: int = _lib.F32,
-              device: str = "cuda", stream=None, layout: int = _lib.LAYOUT_VEC_SOA) -> "VOctree":
+              device: str = "cuda", stream=None, layout: int = _lib.LAYOUT_LEAF_ROWS) -> "VOctree":
         """leaf_ijk [N,3]; hh [N,3,K] and wsig [N,C] float32 per input leaf; basis [T,C]; gamma [T]."""
         nodes, slots, box = build_node_table(depth, leaf_ijk, with_box=True)
         hh = np.ascontiguousarray(hh, np.float32)

@@ -25,8 +25,9 @@ def tdev(a, dtype=torch.float32):
     return torch.from_numpy(np.ascontiguousarray(a)).to(DEV, dtype)
 
 
-def upload(scene, dtype=_lib.F32) -> VOctree:
-    return VOctree.build(scene.depth, scene.leaf_ijk, scene.hh, scene.wsig, scene.basis, scene.gamma, dtype)
+def upload(scene, dtype=_lib.F32, layout=_lib.LAYOUT_LEAF_ROWS) -> VOctree:
+    return VOctree.build(scene.depth, scene.leaf_ijk, scene.hh, scene.wsig, scene.basis, scene.gamma, dtype,
+                         layout=layout)
 
 
 def round_storage(x: np.ndarray, dtype: int) -> np.ndarray:

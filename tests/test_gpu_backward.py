@@ -36,16 +36,17 @@ def check(gpu, ref, tol=1e-4, label=""):
     assert np.abs(ref["grad_hh"]).max() > 0 and np.abs(ref["grad_basis"]).max() > 0
 
 
-def test_backward_config1_scalar_time():
+@pytest.mark.parametrize("layout", [_lib.LAYOUT_LEAF_ROWS, _lib.LAYOUT_VEC_SOA])
+def test_backward_config1_scalar_time(layout):
     sc = scene_for_config(1)
-    tree = upload(sc)
+    tree = upload(sc, layout=layout)
     cam = config1_camera(sc)
     o, d = OC.pinhole_rays(64, 64, cam.intr(), cam.c2w)
     rng = np.random.default_rng(41)
     gC = rng.normal(size=(o.shape[0], 3)).astype(np.float32)
     gA = rng.normal(size=o.shape[0]).astype(np.float32)
     for t in (4.0, 7.25):
-        announce(f"config-1 backward t={t}")
+        announce(f"config-1 backward t={t} layout={layout}")
         ref = oracle_render(sc, o, d, None, t, 0.0, g_rgb=gC, g_alpha=gA)
         gpu = run_backward(tree, o, d, None, t, 0.0, gC, gA, image_width=64)
         check(gpu, ref, label=f"cfg1 t={t}")
@@ -113,15 +114,16 @@ def test_backward_instance():
     check(gpu, ref, label="instance")
 
 
-def test_autograd_function_matches_direct_calls():
+@pytest.mark.parametrize("layout", [_lib.LAYOUT_LEAF_ROWS, _lib.LAYOUT_VEC_SOA])
+def test_autograd_function_matches_direct_calls(layout):
     sc = scene_for_config(1)
-    tree = upload(sc)
+    tree = upload(sc, layout=layout)
     cam = config1_camera(sc)
     o, d = ops.pinhole_rays(cam_struct(cam))
     tree.hh.requires_grad_(True)
     tree.wsig.requires_grad_(True)
     tree.basis.requires_grad_(True)
-    announce("autograd RenderFn")
+    announce(f"autograd RenderFn layout={layout}")
     rgb, alpha, depth, nsamp = autograd.render(tree, o, d, 5.0, None, 0.0, 64)
     target = torch.rand_like(rgb)
     loss = ((rgb - target) ** 2).sum() + alpha.sum()
@@ -134,8 +136,11 @@ def test_autograd_function_matches_direct_calls():
         # the payload-layout gradient is the same numbers as the rows, per input leaf
         a_hh, a_ws = tree.unpack_grad(gl)
         N = tree.n_leaves
-        soa = ghh.view(12, N, 4).permute(1, 0, 2).reshape(N, 48)[tree.slot_of_input].view(N, 3, 16)
-        assert torch.equal(soa, a_hh)
+        if layout == _lib.LAYOUT_VEC_SOA:     # [48/4][N][4]
+            per_slot = ghh.view(12, N, 4).permute(1, 0, 2).reshape(N, 48)
+        else:                                 # [N][48/4][4]
+            per_slot = ghh.view(N, 48)
+        assert torch.equal(per_slot[tree.slot_of_input].view(N, 3, 16), a_hh)
     torch.cuda.synchronize()
     assert rel_err(tree.hh.grad.cpu().numpy(), ghh.cpu().numpy()) < 1e-5
     assert rel_err(tree.wsig.grad.cpu().numpy(), gws.cpu().numpy()) < 1e-5
