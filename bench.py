@@ -126,7 +126,7 @@ def main():
 
     def bwd():
         _lib.neuvv_render_backward(tree.struct(), None, n, ray_o, ray_d, None, t_frame, W, t_stop, rgb, alpha, nsamp,
-                                   g_rgb, None, grads[0], grads[1], stream)
+                                   g_rgb, None, grads[0], grads[1], None, stream)
 
     log(f"warmup {args.warmup} steps")
     for _ in range(args.warmup):

@@ -43,7 +43,7 @@ typedef enum {
     NEUVV_ERR_RANGE = -2,       /* a value outside its documented range */
     NEUVV_ERR_DUPLICATE = -3,   /* the same leaf cell listed twice */
     NEUVV_ERR_CAPACITY = -4,    /* an output buffer smaller than required */
-    NEUVV_ERR_UNSUPPORTED = -5, /* K, C or dtype without a compiled kernel */
+    NEUVV_ERR_UNSUPPORTED = -5, /* K, C, Cg or dtype without a compiled kernel */
     NEUVV_ERR_HIP = -6          /* a HIP launch or runtime error */
 } neuvv_status;
 
@@ -55,32 +55,34 @@ typedef enum { NEUVV_LAYOUT_VEC_SOA = 0, NEUVV_LAYOUT_LEAF_ROWS = 1 } neuvv_layo
 typedef enum { NEUVV_F32 = 0, NEUVV_F16 = 1, NEUVV_BF16 = 2 } neuvv_dtype;
 
 /*
- * Leaf payload layout ("16-byte-vector structure of arrays").
- * A leaf has R_hh = 3K colour coefficients, value r = ch*K + k for colour
- * channel ch and HH function k (Eq. 4), and R_sig = C density weights
- * (Eq. 5). Let V = 16 / sizeof(element) (4 for float32, 8 for 16-bit). The
- * values of all leaves are stored as
- *     hh  [ceil(R_hh / V)][n_leaves][V]
- *     wsig[ceil(R_sig / V)][n_leaves][V]
- * i.e. value r of leaf slot s lives at element (r / V) * n_leaves * V + s * V
- * + r % V; padding values (r >= R) are zero. A wavefront whose lanes visit
- * neighbouring leaf slots reads one contiguous run of 16-byte vectors per
- * vector index.
- * neuvv_payload_words() gives the sizes; neuvv_pack_leaves() fills them.
+ * Leaf payload layout. A leaf has R_hh = 3K colour coefficients, value
+ * r = ch*K + k for colour channel ch and HH function k (Eq. 4), R_sig = C
+ * density weights (Eq. 5) and, in the per-point hyperangle form, R_gam = Cg
+ * hyperangle weights (Eq. 6). Each array is stored in 16-byte vectors of
+ * V = 16 / sizeof(element) values (4 for float32, 8 for 16-bit), padding
+ * values (r >= R) zero, leaves in slot (Morton) order, in one of two layouts:
+ *   NEUVV_LAYOUT_LEAF_ROWS: a[n_leaves][ceil(R / V)][V]: value r of slot s at
+ *     element s * ceil(R / V) * V + r; one leaf's values are contiguous (the
+ *     renderer gathers one whole leaf per lane and sample).
+ *   NEUVV_LAYOUT_VEC_SOA: a[ceil(R / V)][n_leaves][V]: value r of slot s at
+ *     element (r / V) * n_leaves * V + s * V + r % V.
+ * neuvv_payload_words() gives the sizes (the wgam array has the size of a
+ * wsig array with C = Cg); neuvv_pack_leaves() and neuvv_pack_rows() fill
+ * them.
  *
  * Leaf gradient layout ("rows"). Gradients are float32 and leaf-major:
- *     grad_leaf[n_leaves][ROW],  ROW = neuvv_grad_row_elems(K, C) = 3K + C rounded up to 64,
+ *     grad_leaf[n_leaves][ROW],  ROW = neuvv_grad_row_elems(K, C, Cg) = 3K + C + Cg rounded up to 64,
  * row s holding d/d hh of slot s at r = ch*K + k (r < 3K), d/d wsig at 3K + c,
- * and zeros after 3K + C. The adjoint adds one sample's whole row with a
- * single wavefront-wide atomic instruction, which the L2 serves as a couple
- * of line operations.
+ * d/d wgam at 3K + C + c, and zeros after 3K + C + Cg. The adjoint adds one
+ * sample's row with wavefront-wide atomic instructions (one per 64 values),
+ * each of which the L2 serves as a couple of line operations.
  */
 
 /* A built tree on the device. All pointers are device pointers. */
 typedef struct {
     int32_t depth;        /* D in [1, 12]: leaf grid [0, 2^D)^3 in tree-local units */
-    int32_t K;            /* HH functions per colour channel (compiled: 16) */
-    int32_t C;            /* density basis size (compiled: 8) */
+    int32_t K;            /* HH functions per colour channel (compiled: 16, or 14 with Cg = 31) */
+    int32_t C;            /* density basis size (compiled: 8, or 31 with Cg = 31) */
     int32_t dtype;        /* neuvv_dtype of hh and wsig */
     int64_t n_nodes;      /* rows of nodes */
     int64_t n_leaves;     /* leaf slots */
@@ -93,7 +95,13 @@ typedef struct {
                              All zero = the whole grid [0, 2^D)^3. */
     int32_t layout;       /* neuvv_layout of hh and wsig */
     const float* basis;   /* [T][C] density basis, row t = frame t (Eq. 5: A transposed) */
-    const float* gamma;   /* [T] hyperangle per frame, in [0, pi] (Eq. 4's gamma(t)) */
+    const float* gamma;   /* [T] hyperangle per frame, in [0, pi] (Eq. 4's gamma(t)); used when
+                             Cg = 0, may be NULL otherwise */
+    int32_t Cg;           /* 0: one hyperangle per frame (gamma). 31 (with K = 14, C = 31): the
+                             per-point hyperangle of Eq. 6, gamma = pi sigmoid(sum_c wgam_c Bg_c(t)),
+                             the paper's 104-value leaf */
+    const void* wgam;     /* hyperangle weights, storage dtype and layout of wsig (Cg > 0) */
+    const float* basis_g; /* [T][Cg] hyperangle basis (Cg > 0) */
 } neuvv_tree;
 
 /* Placement and re-timing of one tree instance (Eq. 13). A world point x is
@@ -166,10 +174,10 @@ int neuvv_payload_words(int32_t K, int32_t C, int32_t dtype, int64_t n_leaves, i
                         int64_t* wsig_elems);
 
 /*
- * neuvv_grad_row_elems - floats per leaf gradient row for K and C (3K + C
- * rounded up to 64), or NEUVV_ERR_RANGE. Host only.
+ * neuvv_grad_row_elems - floats per leaf gradient row for K, C and Cg
+ * (3K + C + Cg rounded up to 64), or NEUVV_ERR_RANGE. Host only.
  */
-int neuvv_grad_row_elems(int32_t K, int32_t C);
+int neuvv_grad_row_elems(int32_t K, int32_t C, int32_t Cg);
 
 /*
  * neuvv_pack_leaves - convert leaf coefficients given per input leaf into
@@ -189,6 +197,19 @@ int neuvv_pack_leaves(int32_t K, int32_t C, int32_t dtype, int32_t layout, int64
                       void* stream);
 
 /*
+ * neuvv_pack_rows - convert one per-leaf array of R float32 values (e.g. the
+ * Cg hyperangle weights of Eq. 6) into the payload layout above, in slot
+ * order and the storage dtype (round to nearest even for 16-bit).
+ * R               values per leaf, [1, 256].
+ * in              device [n_leaves][R] float32, input leaf order.
+ * slot_of_input   device [n_leaves] int64, or NULL (inputs in slot order).
+ * out             device output of ceil(R/V) * n_leaves * V elements.
+ * Errors: ARG, RANGE (R), UNSUPPORTED (dtype, layout), HIP.
+ */
+int neuvv_pack_rows(int32_t R, int32_t dtype, int32_t layout, int64_t n_leaves, const float* in,
+                    const int64_t* slot_of_input, void* out, void* stream);
+
+/*
  * neuvv_render - volume rendering of a VOctree along n rays (Sec. 4.3
  * "Rendering", Eq. 4, 5, 8, 9).
  *
@@ -205,7 +226,9 @@ int neuvv_pack_leaves(int32_t K, int32_t C, int32_t dtype, int32_t layout, int64
  *     a = 1 - exp(-sigma delta), w = T a, rgb += w c, T *= exp(-sigma delta),
  * stopping after the first sample that leaves T < t_stop (t_stop = 0 never
  * stops early). The K = 16 HH functions are n <= 2 (14) then (3,0,0), (3,1,-1)
- * in the order n, l, m.
+ * in the order n, l, m. With the per-point hyperangle (Cg > 0) gamma is
+ * evaluated per sample, gamma = pi sigmoid(sum_c wgam_c bg_c) with bg the
+ * hyperangle basis at tau, and h = the first K = 14 HH at (direction, gamma).
  *
  * tree            device tree (pointer to a host struct).
  * inst            host struct or NULL (identity).
@@ -241,14 +264,18 @@ int neuvv_render(const neuvv_tree* tree, const neuvv_instance* inst, int64_t n_r
  * grad_leaf       device float32 [n_leaves][ROW] leaf gradient rows (layout
  *                 above), accumulated (+=).
  * grad_basis      device [T][C] float32 accumulated, or NULL to skip.
- * The gradient with respect to the gamma table is not computed.
+ * grad_basis_g    device [T][Cg] float32 accumulated, or NULL to skip
+ *                 (ignored when Cg = 0). With Cg > 0 the chain rule also runs
+ *                 through gamma: dL/dgamma_k = sum_ch dL/dz_k,ch sum_j hh_ch,j
+ *                 dh_j/dgamma, dL/dy_k = pi sigmoid'(y_k) dL/dgamma_k.
+ * The gradient with respect to the gamma table (Cg = 0) is not computed.
  * Errors: ARG, RANGE, UNSUPPORTED, HIP.
  */
 int neuvv_render_backward(const neuvv_tree* tree, const neuvv_instance* inst, int64_t n_rays,
                           const float* ray_o, const float* ray_d, const float* ray_t, float t_scalar,
                           int32_t image_width, float t_stop, const float* rgb, const float* alpha,
                           const int32_t* nsamp, const float* grad_rgb, const float* grad_alpha,
-                          float* grad_leaf, float* grad_basis, void* stream);
+                          float* grad_leaf, float* grad_basis, float* grad_basis_g, void* stream);
 
 /*
  * neuvv_compose - depth-aware alpha blending of L rendered layers (Alg. 1),

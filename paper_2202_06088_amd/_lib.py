@@ -28,7 +28,8 @@ class neuvv_tree(ctypes.Structure):
                 ("dtype", ctypes.c_int32), ("n_nodes", ctypes.c_int64), ("n_leaves", ctypes.c_int64),
                 ("nodes", ctypes.c_void_p), ("hh", ctypes.c_void_p), ("wsig", ctypes.c_void_p),
                 ("T", ctypes.c_int32), ("box", ctypes.c_int32 * 6), ("layout", ctypes.c_int32),
-                ("basis", ctypes.c_void_p), ("gamma", ctypes.c_void_p)]
+                ("basis", ctypes.c_void_p), ("gamma", ctypes.c_void_p), ("Cg", ctypes.c_int32),
+                ("wgam", ctypes.c_void_p), ("basis_g", ctypes.c_void_p)]
 
 
 class neuvv_instance(ctypes.Structure):
@@ -54,8 +55,9 @@ _SIGNATURES = {
     "neuvv_render": [ctypes.POINTER(neuvv_tree), ctypes.POINTER(neuvv_instance), _I64, _P, _P, _P, _F, _I32, _F,
                      _P, _P, _P, _P, _P],
     "neuvv_render_backward": [ctypes.POINTER(neuvv_tree), ctypes.POINTER(neuvv_instance), _I64, _P, _P, _P, _F,
-                              _I32, _F, _P, _P, _P, _P, _P, _P, _P, _P],
-    "neuvv_grad_row_elems": [_I32, _I32],
+                              _I32, _F, _P, _P, _P, _P, _P, _P, _P, _P, _P],
+    "neuvv_grad_row_elems": [_I32, _I32, _I32],
+    "neuvv_pack_rows": [_I32, _I32, _I32, _I64, _P, _P, _P, _P],
     "neuvv_compose": [_I32, _I64, _P, _P, _P, _P, _P, _P, _P],
     "neuvv_compose_backward": [_I32, _I64, _P, _P, _P, _P, _P, _P, _P, _P],
     "neuvv_pinhole_rays": [ctypes.POINTER(neuvv_camera), _I64, _P, _P, _P, _P],
@@ -156,6 +158,11 @@ def neuvv_pack_leaves(K, C, dtype, layout, n_leaves, hh_in, wsig_in, slot_of_inp
                                                          _stream(stream)))
 
 
+def neuvv_pack_rows(R, dtype, layout, n_leaves, rows_in, slot_of_input, out, stream=None):
+    _check("neuvv_pack_rows", load().neuvv_pack_rows(int(R), int(dtype), int(layout), int(n_leaves), _ptr(rows_in),
+                                                     _ptr(slot_of_input), _ptr(out), _stream(stream)))
+
+
 def _inst_ptr(inst: Optional[neuvv_instance]):
     return None if inst is None else ctypes.byref(inst)
 
@@ -168,15 +175,16 @@ def neuvv_render(tree: neuvv_tree, inst, n_rays, ray_o, ray_d, ray_t, t_scalar, 
 
 
 def neuvv_render_backward(tree: neuvv_tree, inst, n_rays, ray_o, ray_d, ray_t, t_scalar, image_width, t_stop,
-                          rgb, alpha, nsamp, grad_rgb, grad_alpha, grad_leaf, grad_basis, stream=None):
+                          rgb, alpha, nsamp, grad_rgb, grad_alpha, grad_leaf, grad_basis, grad_basis_g=None,
+                          stream=None):
     _check("neuvv_render_backward", load().neuvv_render_backward(
         ctypes.byref(tree), _inst_ptr(inst), int(n_rays), _ptr(ray_o), _ptr(ray_d), _ptr(ray_t), float(t_scalar),
         int(image_width), float(t_stop), _ptr(rgb), _ptr(alpha), _ptr(nsamp), _ptr(grad_rgb), _ptr(grad_alpha),
-        _ptr(grad_leaf), _ptr(grad_basis), _stream(stream)))
+        _ptr(grad_leaf), _ptr(grad_basis), _ptr(grad_basis_g), _stream(stream)))
 
 
-def neuvv_grad_row_elems(K: int, C: int) -> int:
-    rc = load().neuvv_grad_row_elems(int(K), int(C))
+def neuvv_grad_row_elems(K: int, C: int, Cg: int = 0) -> int:
+    rc = load().neuvv_grad_row_elems(int(K), int(C), int(Cg))
     if rc < 0:
         _check("neuvv_grad_row_elems", rc)
     return rc

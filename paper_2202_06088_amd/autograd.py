@@ -10,19 +10,22 @@ from .voctree import VOctree
 
 
 class RenderFn(torch.autograd.Function):
-    """rgb, alpha, depth, nsamp = RenderFn.apply(hh, wsig, basis, tree, ray_o, ray_d, t, inst, t_stop, image_width)
+    """rgb, alpha, depth, nsamp = RenderFn.apply(hh, wsig, basis, wgam, basis_g, tree, ray_o, ray_d, t, inst,
+    t_stop, image_width)
 
-    hh, wsig, basis must be the float32 tensors the tree renders from
-    (tree.hh, tree.wsig, tree.basis): their gradients come back in the same
-    packed layout, ready for an element-wise optimizer step."""
+    hh, wsig, basis (and wgam, basis_g for a tree with per-point hyperangle weights, else
+    None) must be the float32 tensors the tree renders from: their gradients come back in the
+    same packed layout, ready for an element-wise optimizer step."""
 
     @staticmethod
-    def forward(ctx, hh, wsig, basis, tree: VOctree, ray_o, ray_d, t, inst, t_stop, image_width):
+    def forward(ctx, hh, wsig, basis, wgam, basis_g, tree: VOctree, ray_o, ray_d, t, inst, t_stop, image_width):
         if tree.dtype != _lib.F32:
             raise ValueError("autograd needs float32 leaf storage; call ops.render_backward for 16-bit trees")
-        if hh.data_ptr() != tree.hh.data_ptr() or wsig.data_ptr() != tree.wsig.data_ptr() \
-                or basis.data_ptr() != tree.basis.data_ptr():
-            raise ValueError("hh / wsig / basis must be the tree's own tensors")
+        own = [(hh, tree.hh), (wsig, tree.wsig), (basis, tree.basis)]
+        if tree.Cg > 0:
+            own += [(wgam, tree.wgam), (basis_g, tree.basis_g)]
+        if any(a is None or a.data_ptr() != b.data_ptr() for a, b in own):
+            raise ValueError("the payload and basis tensors must be the tree's own")
         rgb, alpha, depth, nsamp = ops.render(tree, ray_o, ray_d, t, inst, t_stop, image_width)
         ctx.tree, ctx.inst, ctx.t_stop, ctx.image_width = tree, inst, t_stop, image_width
         ctx.t_scalar = None if isinstance(t, torch.Tensor) else float(t)
@@ -36,11 +39,19 @@ class RenderFn(torch.autograd.Function):
         if g_rgb is None:
             g_rgb = torch.zeros_like(rgb)
         t_arg = t if t is not None else ctx.t_scalar
-        gl, gb = ops.render_backward(ctx.tree, ray_o, ray_d, rgb, alpha, nsamp, g_rgb.contiguous(),
-                                     None if g_alpha is None else g_alpha.contiguous(), t_arg, ctx.inst,
-                                     ctx.t_stop, ctx.image_width, want_basis=ctx.needs_input_grad[2])
-        ghh, gws = ctx.tree.rows_to_payload_f32(gl)
-        return ghh, gws, (gb if ctx.needs_input_grad[2] else None), None, None, None, None, None, None, None
+        tree = ctx.tree
+        want_basis = ctx.needs_input_grad[2] or (tree.Cg > 0 and ctx.needs_input_grad[4])
+        out = ops.render_backward(tree, ray_o, ray_d, rgb, alpha, nsamp, g_rgb.contiguous(),
+                                  None if g_alpha is None else g_alpha.contiguous(), t_arg, ctx.inst,
+                                  ctx.t_stop, ctx.image_width, want_basis=want_basis)
+        parts = tree.rows_to_payload_f32(out[0])
+        g_basis = out[1] if ctx.needs_input_grad[2] else None
+        if tree.Cg > 0:
+            g_wgam = parts[2]
+            g_basis_g = out[2] if ctx.needs_input_grad[4] else None
+        else:
+            g_wgam = g_basis_g = None
+        return (parts[0], parts[1], g_basis, g_wgam, g_basis_g) + (None,) * 7
 
 
 class ComposeFn(torch.autograd.Function):
@@ -65,7 +76,8 @@ class ComposeFn(torch.autograd.Function):
 
 
 def render(tree: VOctree, ray_o, ray_d, t=0.0, inst=None, t_stop=1e-4, image_width=0):
-    return RenderFn.apply(tree.hh, tree.wsig, tree.basis, tree, ray_o, ray_d, t, inst, t_stop, image_width)
+    return RenderFn.apply(tree.hh, tree.wsig, tree.basis, tree.wgam, tree.basis_g, tree, ray_o, ray_d, t, inst,
+                          t_stop, image_width)
 
 
 def compose(rgb, alpha, depth):

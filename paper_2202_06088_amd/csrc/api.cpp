@@ -53,20 +53,25 @@ int check_tree(const neuvv_tree* t) {
     if (t->depth < 1 || t->depth > neuvv::kMaxDepth) return fail(NEUVV_ERR_RANGE, "depth %d outside [1, 12]", t->depth);
     if (t->dtype < 0 || t->dtype > 2) return fail(NEUVV_ERR_ARG, "unknown dtype %d", t->dtype);
     if (t->layout < 0 || t->layout > 1) return fail(NEUVV_ERR_ARG, "unknown layout %d", t->layout);
-    if (!neuvv::render_supported(t->K, t->C, t->dtype))
-        return fail(NEUVV_ERR_UNSUPPORTED, "no kernel compiled for K=%d C=%d (have K=16, C=8)", t->K, t->C);
+    if (!neuvv::render_supported(t->K, t->C, t->Cg, t->dtype))
+        return fail(NEUVV_ERR_UNSUPPORTED,
+                    "no kernel compiled for K=%d C=%d Cg=%d (have K=16 C=8 Cg=0 and K=14 C=31 Cg=31)", t->K, t->C,
+                    t->Cg);
     if (t->n_nodes < 1 || t->n_nodes > INT32_MAX) return fail(NEUVV_ERR_RANGE, "n_nodes %lld", (long long)t->n_nodes);
     if (t->n_leaves < 0 || t->n_leaves > INT32_MAX)
         return fail(NEUVV_ERR_RANGE, "n_leaves %lld", (long long)t->n_leaves);
     if (t->T < 1) return fail(NEUVV_ERR_RANGE, "T = %d must be >= 1", t->T);
-    if (!t->nodes || !t->basis || !t->gamma) return fail(NEUVV_ERR_ARG, "tree nodes/basis/gamma pointer is NULL");
+    if (!t->nodes || !t->basis) return fail(NEUVV_ERR_ARG, "tree nodes/basis pointer is NULL");
+    if (t->Cg == 0 && !t->gamma) return fail(NEUVV_ERR_ARG, "tree gamma pointer is NULL");
+    if (t->Cg > 0 && !t->basis_g) return fail(NEUVV_ERR_ARG, "tree basis_g pointer is NULL");
     if (reinterpret_cast<uintptr_t>(t->nodes) % 16 != 0) return fail(NEUVV_ERR_ARG, "tree nodes must be 16-byte aligned");
     const bool box_unset = !(t->box[0] | t->box[1] | t->box[2] | t->box[3] | t->box[4] | t->box[5]);
     if (!box_unset)
         for (int a = 0; a < 3; ++a)
             if (t->box[a] < 0 || t->box[a] >= t->box[3 + a] || t->box[3 + a] > (1 << t->depth))
                 return fail(NEUVV_ERR_RANGE, "tree box must satisfy 0 <= lo < hi <= 2^depth on every axis");
-    if (t->n_leaves > 0 && (!t->hh || !t->wsig)) return fail(NEUVV_ERR_ARG, "tree payload pointer is NULL");
+    if (t->n_leaves > 0 && (!t->hh || !t->wsig || (t->Cg > 0 && !t->wgam)))
+        return fail(NEUVV_ERR_ARG, "tree payload pointer is NULL");
     return NEUVV_OK;
 }
 
@@ -129,6 +134,9 @@ neuvv::TreeArgs tree_args(const neuvv_tree* t) {
     a.wsig = t->wsig;
     a.basis = t->basis;
     a.gamma = t->gamma;
+    a.Cg = t->Cg;
+    a.wgam = t->wgam;
+    a.basis_g = t->basis_g;
     a.n_nodes = t->n_nodes;
     a.n_leaves = t->n_leaves;
     a.depth = t->depth;
@@ -186,9 +194,23 @@ int neuvv_payload_words(int32_t K, int32_t C, int32_t dtype, int64_t n_leaves, i
     return NEUVV_OK;
 }
 
-int neuvv_grad_row_elems(int32_t K, int32_t C) {
-    if (K < 1 || K > 30 || C < 1 || C > 64) return fail(NEUVV_ERR_RANGE, "K in [1,30] and C in [1,64] required");
-    return neuvv::grad_row_elems(K, C);
+int neuvv_grad_row_elems(int32_t K, int32_t C, int32_t Cg) {
+    if (K < 1 || K > 30 || C < 1 || C > 64 || Cg < 0 || Cg > 64)
+        return fail(NEUVV_ERR_RANGE, "K in [1,30], C in [1,64] and Cg in [0,64] required");
+    return neuvv::grad_row_elems(K, C, Cg);
+}
+
+int neuvv_pack_rows(int32_t R, int32_t dtype, int32_t layout, int64_t n_leaves, const float* in,
+                    const int64_t* slot_of_input, void* out, void* stream) {
+    NEUVV_GUARD_BEGIN
+    if (R < 1 || R > 256) return fail(NEUVV_ERR_RANGE, "R in [1,256] required");
+    if (dtype < 0 || dtype > 2) return fail(NEUVV_ERR_UNSUPPORTED, "unknown dtype %d", dtype);
+    if (layout < 0 || layout > 1) return fail(NEUVV_ERR_UNSUPPORTED, "unknown layout %d", layout);
+    if (n_leaves < 0) return fail(NEUVV_ERR_ARG, "n_leaves < 0");
+    if (n_leaves > 0 && (!in || !out)) return fail(NEUVV_ERR_ARG, "NULL buffer");
+    return hip_status(neuvv::launch_pack_rows(R, dtype, layout, n_leaves, in, slot_of_input, out, (hipStream_t)stream),
+                      "pack_rows launch");
+    NEUVV_GUARD_END
 }
 
 int neuvv_pack_leaves(int32_t K, int32_t C, int32_t dtype, int32_t layout, int64_t n_leaves, const float* hh_in,
@@ -219,9 +241,12 @@ int neuvv_render(const neuvv_tree* tree, const neuvv_instance* inst, int64_t n_r
     if (!(t_stop >= 0.0f) || !std::isfinite(t_stop)) return fail(NEUVV_ERR_RANGE, "t_stop must be >= 0");
     if (n_rays > 0 && (!rgb || !alpha || !nsamp)) return fail(NEUVV_ERR_ARG, "rgb / alpha / nsamp is NULL");
     neuvv::RenderOut out{rgb, alpha, depth, nsamp};
-    return hip_status(neuvv::launch_render_fwd(tree->K, tree->C, tree->dtype, tree_args(tree), in, ra, t_stop, out,
-                                               (hipStream_t)stream),
-                      "render launch");
+    const hipError_t e = tree->Cg > 0
+                             ? neuvv::launch_render_pp_fwd(tree->dtype, tree_args(tree), in, ra, t_stop, out,
+                                                           (hipStream_t)stream)
+                             : neuvv::launch_render_fwd(tree->K, tree->C, tree->dtype, tree_args(tree), in, ra,
+                                                        t_stop, out, (hipStream_t)stream);
+    return hip_status(e, "render launch");
     NEUVV_GUARD_END
 }
 
@@ -229,7 +254,7 @@ int neuvv_render_backward(const neuvv_tree* tree, const neuvv_instance* inst, in
                           const float* ray_o, const float* ray_d, const float* ray_t, float t_scalar,
                           int32_t image_width, float t_stop, const float* rgb, const float* alpha,
                           const int32_t* nsamp, const float* grad_rgb, const float* grad_alpha, float* grad_leaf,
-                          float* grad_basis, void* stream) {
+                          float* grad_basis, float* grad_basis_g, void* stream) {
     NEUVV_GUARD_BEGIN
     int rc = check_tree(tree);
     if (rc) return rc;
@@ -241,10 +266,14 @@ int neuvv_render_backward(const neuvv_tree* tree, const neuvv_instance* inst, in
     if (n_rays > 0 && (!rgb || !alpha || !nsamp || !grad_rgb))
         return fail(NEUVV_ERR_ARG, "rgb / alpha / nsamp / grad_rgb is NULL");
     if (tree->n_leaves > 0 && !grad_leaf) return fail(NEUVV_ERR_ARG, "grad_leaf is NULL");
-    neuvv::BackwardIO io{rgb, alpha, nsamp, grad_rgb, grad_alpha, grad_leaf, grad_basis};
-    return hip_status(neuvv::launch_render_bwd(tree->K, tree->C, tree->dtype, tree_args(tree), in, ra, io,
-                                               (hipStream_t)stream),
-                      "render_backward launch");
+    neuvv::BackwardIO io{rgb, alpha, nsamp, grad_rgb, grad_alpha, grad_leaf, grad_basis,
+                         tree->Cg > 0 ? grad_basis_g : nullptr};
+    const hipError_t e = tree->Cg > 0
+                             ? neuvv::launch_render_pp_bwd(tree->dtype, tree_args(tree), in, ra, io,
+                                                           (hipStream_t)stream)
+                             : neuvv::launch_render_bwd(tree->K, tree->C, tree->dtype, tree_args(tree), in, ra, io,
+                                                        (hipStream_t)stream);
+    return hip_status(e, "render_backward launch");
     NEUVV_GUARD_END
 }
 

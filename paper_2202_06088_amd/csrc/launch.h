@@ -23,19 +23,25 @@ struct BackwardIO {
     const int32_t* nsamp;
     const float* grad_rgb;
     const float* grad_alpha;
-    float* grad_leaf;    // [n_leaves][grad_row_elems(K, C)]
+    float* grad_leaf;    // [n_leaves][grad_row_elems(K, C, Cg)]
     float* grad_basis;
+    float* grad_basis_g;   // per-point hyperangle basis gradient (Cg > 0), or nullptr
 };
 
 // Each returns hipSuccess or the launch error. K, C, dtype must be supported
 // (checked by the caller with render_supported()).
-bool render_supported(int K, int C, int dtype);
-// Floats per row of the leaf-major gradient array: 3K + C rounded up to 64.
-int grad_row_elems(int K, int C);
+bool render_supported(int K, int C, int Cg, int dtype);
+// Floats per row of the leaf-major gradient array: 3K + C + Cg rounded up to 64.
+int grad_row_elems(int K, int C, int Cg);
 hipError_t launch_render_fwd(int K, int C, int dtype, const TreeArgs& tr, const InstArgs& in, const RayArgs& ra,
                              float t_stop, const RenderOut& out, hipStream_t stream);
 hipError_t launch_render_bwd(int K, int C, int dtype, const TreeArgs& tr, const InstArgs& in, const RayArgs& ra,
                              const BackwardIO& io, hipStream_t stream);
+// Per-point hyperangle form (K = 14, C = 31, Cg = 31).
+hipError_t launch_render_pp_fwd(int dtype, const TreeArgs& tr, const InstArgs& in, const RayArgs& ra, float t_stop,
+                                const RenderOut& out, hipStream_t stream);
+hipError_t launch_render_pp_bwd(int dtype, const TreeArgs& tr, const InstArgs& in, const RayArgs& ra,
+                                const BackwardIO& io, hipStream_t stream);
 hipError_t launch_compose_fwd(int L, int64_t n, const float* rgb, const float* alpha, const float* depth,
                               float* out_rgb, float* out_alpha, float* out_depth, hipStream_t stream);
 hipError_t launch_compose_bwd(int L, int64_t n, const float* rgb, const float* alpha, const float* depth,
@@ -44,6 +50,8 @@ hipError_t launch_compose_bwd(int L, int64_t n, const float* rgb, const float* a
 hipError_t launch_pinhole(int W, int H, const float intr[4], const float c2w[12], int64_t n, const int32_t* pix,
                           float* ray_o, float* ray_d, hipStream_t stream);
 hipError_t launch_eval_hh(int K, int64_t n, const float* dirs, const float* gam, float* out, hipStream_t stream);
+hipError_t launch_pack_rows(int R, int dtype, int layout, int64_t n, const float* in, const int64_t* slot_of_input,
+                            void* out, hipStream_t stream);
 hipError_t launch_pack(int K, int C, int dtype, int layout, int64_t n, const float* hh_in, const float* wsig_in,
                        const int64_t* slot_of_input, void* hh_out, void* wsig_out, hipStream_t stream);
 

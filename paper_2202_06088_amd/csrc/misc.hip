@@ -321,6 +321,16 @@ static hipError_t pack_t(int R, int layout, int64_t n, const float* in, const in
     return hipGetLastError();
 }
 
+hipError_t launch_pack_rows(int R, int dtype, int layout, int64_t n, const float* in, const int64_t* slot_of_input,
+                            void* out, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    switch (dtype) {
+        case 0: return pack_t<0>(R, layout, n, in, slot_of_input, out, stream);
+        case 1: return pack_t<1>(R, layout, n, in, slot_of_input, out, stream);
+        default: return pack_t<2>(R, layout, n, in, slot_of_input, out, stream);
+    }
+}
+
 hipError_t launch_pack(int K, int C, int dtype, int layout, int64_t n, const float* hh_in, const float* wsig_in,
                        const int64_t* slot_of_input, void* hh_out, void* wsig_out, hipStream_t stream) {
     if (n <= 0) return hipSuccess;

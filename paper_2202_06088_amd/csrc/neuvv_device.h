@@ -156,6 +156,39 @@ __device__ __forceinline__ void hh_all(float x, float y, float z, float gam, flo
     h[27] = g33 * Y31; h[28] = g33 * Y32; h[29] = g33 * Y33;
 }
 
+// Per-point hyperangle form (Eq. 6), first 14 functions (all n <= 2): the
+// direction factors are per ray, the radial factors per sample.
+// Y = (Y1-1, Y10, Y11, Y2-2, Y2-1, Y20, Y21, Y22) of the unit direction; Y00 is
+// the constant 1 / (2 sqrt(pi)).
+constexpr float kY00 = 0.28209479177387814f;
+__device__ __forceinline__ void sh_deg2(float x, float y, float z, float (&Y)[8]) {
+    const float k1 = 0.4886025119029199f, k2 = 1.0925484305920792f;
+    Y[0] = k1 * y; Y[1] = k1 * z; Y[2] = k1 * x;
+    Y[3] = k2 * x * y; Y[4] = k2 * y * z; Y[5] = 0.31539156525252005f * (3.0f * z * z - 1.0f);
+    Y[6] = k2 * x * z; Y[7] = 0.5462742152960396f * (x * x - y * y);
+}
+// g = (g00, g10, g11, g20, g21, g22)(gamma) and their derivatives in gamma,
+// from s = sin(gamma), c = cos(gamma); same closed forms as hh_all.
+__device__ __forceinline__ void radial_n2(float s, float c, float (&g)[6], float (&dg)[6]) {
+    const float a0 = 0.7978845608028654f, a1 = 1.5957691216057308f, b1 = 0.9213177319235613f;
+    const float d1 = 2.256758334191025f, e2 = 1.009253008808064f;
+    g[0] = a0;                         dg[0] = 0.0f;
+    g[1] = a1 * c;                     dg[1] = -a1 * s;
+    g[2] = b1 * s;                     dg[2] = b1 * c;
+    g[3] = a0 * (4.0f * c * c - 1.0f); dg[3] = -8.0f * a0 * c * s;
+    g[4] = d1 * s * c;                 dg[4] = d1 * (c * c - s * s);
+    g[5] = e2 * s * s;                 dg[5] = 2.0f * e2 * s * c;
+}
+// h_k = g_{n(k) l(k)} Y_{l(k) m(k)} in the canonical order of the first 14.
+__device__ __forceinline__ void hh14(const float (&g)[6], const float (&Y)[8], float (&h)[14]) {
+    h[0] = g[0] * kY00;
+    h[1] = g[1] * kY00;
+    h[2] = g[2] * Y[0]; h[3] = g[2] * Y[1]; h[4] = g[2] * Y[2];
+    h[5] = g[3] * kY00;
+    h[6] = g[4] * Y[0]; h[7] = g[4] * Y[1]; h[8] = g[4] * Y[2];
+    h[9] = g[5] * Y[3]; h[10] = g[5] * Y[4]; h[11] = g[5] * Y[5]; h[12] = g[5] * Y[6]; h[13] = g[5] * Y[7];
+}
+
 // ----------------------------------------------------------------------------
 // kernel-side descriptions of the tree, instance and rays
 
@@ -172,6 +205,9 @@ struct TreeArgs {
     int32_t box_lo[3];   // occupied-cell bounds: rays are clipped to [lo, hi)
     int32_t box_hi[3];
     int32_t layout;      // 0: vectors structure-of-arrays, 1: leaf-major rows of vectors
+    int32_t Cg;          // per-point hyperangle weights per leaf (0: the global table gamma)
+    const void* wgam;    // [N] rows of Cg weights, storage dtype and layout of wsig
+    const float* basis_g;   // [T][Cg] hyperangle basis
 };
 
 struct InstArgs {

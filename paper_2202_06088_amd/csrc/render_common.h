@@ -1,0 +1,195 @@
+// Building blocks shared by the render kernels (render.hip, render_pp.hip):
+// payload gathers, work queues, LDS staging of the top node rows, launch
+// sizing. Device code for gfx950.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+
+#include "launch.h"
+#include "neuvv_device.h"
+
+namespace neuvv {
+
+constexpr int kBlock = 256;
+
+template <int DT>
+struct StoreTraits;
+template <>
+struct StoreTraits<0> { static constexpr int V = 4; };
+template <>
+struct StoreTraits<1> { static constexpr int V = 8; };
+template <>
+struct StoreTraits<2> { static constexpr int V = 8; };
+
+template <int DT>
+__device__ __forceinline__ void unpack16(const uint4& v, float (&out)[StoreTraits<DT>::V]) {
+    if constexpr (DT == 0) {
+        out[0] = __uint_as_float(v.x);
+        out[1] = __uint_as_float(v.y);
+        out[2] = __uint_as_float(v.z);
+        out[3] = __uint_as_float(v.w);
+    } else {
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            uint16_t lo = (uint16_t)(w[i] & 0xffffu), hi = (uint16_t)(w[i] >> 16);
+            if constexpr (DT == 1) {
+                out[2 * i] = (float)__builtin_bit_cast(_Float16, lo);
+                out[2 * i + 1] = (float)__builtin_bit_cast(_Float16, hi);
+            } else {
+                out[2 * i] = __uint_as_float((uint32_t)lo << 16);
+                out[2 * i + 1] = __uint_as_float((uint32_t)hi << 16);
+            }
+        }
+    }
+}
+
+// Gathers R values of leaf `slot` from a [ceil(R/V)][N][V] array (layout 0) or
+// a [N][ceil(R/V)][V] array (layout 1).
+template <int DT, int R>
+__device__ __forceinline__ void load_leaf(const void* base, int64_t N, int64_t slot, int layout,
+                                          float (&out)[R]) {
+    constexpr int V = StoreTraits<DT>::V;
+    constexpr int NG = (R + V - 1) / V;
+    const int64_t stride = layout ? 1 : N;
+    const uint4* p = reinterpret_cast<const uint4*>(base) + (layout ? slot * NG : slot);
+    uint4 raw[NG];
+#pragma unroll
+    for (int g = 0; g < NG; ++g) raw[g] = p[(int64_t)g * stride];
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+        float tmp[V];
+        unpack16<DT>(raw[g], tmp);
+#pragma unroll
+        for (int e = 0; e < V; ++e)
+            if (g * V + e < R) out[g * V + e] = tmp[e];
+    }
+}
+
+__device__ __forceinline__ float softplus_f(float x) { return fmaxf(x, 0.0f) + log1pf(expf(-fabsf(x))); }
+__device__ __forceinline__ float sigmoid_f(float x) { return 1.0f / (1.0f + expf(-x)); }
+
+__device__ __forceinline__ int lane_rank(uint64_t mask) {
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// Dynamic chunk distribution: kQueues counters, 128 bytes apart, one per XCD.
+constexpr int kQueues = 8;
+constexpr int kQueueStride = 16;
+
+struct ChunkCursor {
+    int home;       // this block's XCD
+    int tried;      // queues drained so far (wave-uniform)
+    int pos;        // slots of the current chunk handed out; 64 = take a new chunk
+    int px0;        // x of the tile's first pixel (images)
+    int64_t base;   // ray index of the chunk's first slot
+};
+
+__device__ __forceinline__ ChunkCursor chunk_cursor() {
+    ChunkCursor c;
+    c.home = (int)(blockIdx.x & (kQueues - 1));
+    c.tried = 0;
+    c.pos = kWave;
+    c.px0 = 0;
+    c.base = 0;
+    return c;
+}
+
+// Moves the (converged) wavefront to its next chunk; false when every queue
+// is drained. One lane takes the ticket; the result is wave-uniform.
+__device__ __forceinline__ bool next_chunk(const RayArgs& ra, ChunkCursor& cc) {
+    const int64_t n_chunks = (ra.n_slots + 63) >> 6;
+    const int leader = __builtin_ctzll(__ballot(1));
+    while (cc.tried < kQueues) {
+        const int x = (cc.home + cc.tried) & (kQueues - 1);
+        const int64_t lo = n_chunks * x / kQueues, hi = n_chunks * (x + 1) / kQueues;
+        unsigned long long t = 0;
+        if ((int)(threadIdx.x & 63) == leader) t = atomicAdd(ra.queue + x * kQueueStride, 1ull);
+        const uint32_t t_lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)t);
+        const uint32_t t_hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(t >> 32));
+        const int64_t k = lo + (int64_t)(((uint64_t)t_hi << 32) | t_lo);
+        if (k < hi) {
+            cc.pos = 0;
+            if (ra.img_w > 0) {
+                const int64_t ty = k / ra.tiles_x, tx = k - ty * ra.tiles_x;
+                cc.px0 = (int)(tx * 8);
+                cc.base = ty * 8 * (int64_t)ra.img_w + cc.px0;
+            } else {
+                cc.base = k * 64;
+            }
+            return true;
+        }
+        ++cc.tried;
+    }
+    return false;
+}
+
+// Ray index of slot `within` (0..63) of the current chunk, -1 for padding.
+__device__ __forceinline__ int64_t chunk_ray(const RayArgs& ra, const ChunkCursor& cc, int within) {
+    int64_t r;
+    if (ra.img_w > 0) {
+        if (cc.px0 + (within & 7) >= ra.img_w) return -1;
+        r = cc.base + (int64_t)(within >> 3) * ra.img_w + (within & 7);
+    } else {
+        r = cc.base + within;
+    }
+    return r < ra.n ? r : -1;
+}
+
+// Stages the first min(n_nodes, CAP) node rows (the top levels, stored
+// first) in LDS; returns their number.
+template <int CAP>
+__device__ __forceinline__ int stage_top_nodes(const TreeArgs& tr, int4* s_nodes) {
+    const int n_lds = (int)(tr.n_nodes < CAP ? tr.n_nodes : CAP);
+    for (int i = threadIdx.x; i < n_lds; i += kBlock) s_nodes[i] = tr.nodes[i];
+    __syncthreads();
+    return n_lds;
+}
+
+__device__ __forceinline__ void write_miss(const RenderOut& out, int64_t ray) {
+    out.rgb[3 * ray] = 0.0f;
+    out.rgb[3 * ray + 1] = 0.0f;
+    out.rgb[3 * ray + 2] = 0.0f;
+    out.alpha[ray] = 0.0f;
+    if (out.depth) out.depth[ray] = INFINITY;
+    out.nsamp[ray] = 0;
+}
+
+__device__ __forceinline__ float readlane_f(float v, int lane) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
+template <typename KernelT>
+static int grid_for(KernelT kernel, const RayArgs& ra) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0) != hipSuccess || per_cu <= 0)
+        per_cu = 2;
+    const int64_t chunks = (ra.n_slots + 63) / 64;
+    const int64_t want = (chunks + (kBlock / kWave) - 1) / (kBlock / kWave);
+    const int64_t cap = (int64_t)per_cu * device_cu_count();
+    const int64_t g = want < cap ? want : cap;
+    return (int)(g > 0 ? g : 1);
+}
+
+// Work-queue counters of one launch: 1 KiB of stream-ordered scratch, zeroed
+// by a one-block kernel (no memset node, so the sequence may be captured in a
+// graph) and freed after the render kernel in stream order.
+static __global__ void zero_queue_kernel(unsigned long long* q) { q[threadIdx.x] = 0ull; }
+
+template <typename Launch>
+static hipError_t with_queue(const RayArgs& ra_in, hipStream_t st, Launch&& launch) {
+    RayArgs ra = ra_in;
+    void* q = nullptr;
+    hipError_t e = hipMallocAsync(&q, kQueues * kQueueStride * sizeof(unsigned long long), st);
+    if (e != hipSuccess) return e;
+    ra.queue = static_cast<unsigned long long*>(q);
+    hipLaunchKernelGGL(zero_queue_kernel, dim3(1), dim3(kQueues * kQueueStride), 0, st, ra.queue);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = launch(ra);
+    const hipError_t f = hipFreeAsync(q, st);
+    return e != hipSuccess ? e : f;
+}
+
+}  // namespace neuvv

@@ -1,0 +1,479 @@
+// VOctree rendering with the per-point hyperangle (Sec. 4.2, Eq. 6): every
+// leaf carries Cg weights on a second learned temporal basis, a sample's
+// hyperangle is gamma = pi sigmoid(sum_c wgam_c Bg_c(t)), and its HH basis is
+// g_nl(gamma) Y_lm(d) (Eq. 2-4), with the direction factors Y_lm per ray and
+// the radial factors g_nl per sample. Compiled for the paper's leaf: K = 14
+// HH functions per channel (all n <= 2), C = 31 density weights and Cg = 31
+// hyperangle weights, 104 values in all (Sec. 1, Tables 2-3); forward and
+// adjoint (Sec. 4.3 "Optimization"), whose chain rule gains the hyperangle
+// path dL/dgamma -> dL/dwgam and dL/dBg.
+//
+// Work distribution, traversal and compositing are those of render.hip. The
+// interpolated basis rows are common to all rays when the time is one scalar
+// and are then staged once per block in LDS; with a time per ray they are
+// read per sample from the basis tables, which stay in cache.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+
+#include "launch.h"
+#include "neuvv_device.h"
+#include "render_common.h"
+
+namespace neuvv {
+
+namespace pp {
+constexpr int K = 14;
+constexpr int C = 31;
+constexpr int CG = 31;
+constexpr int ROW = ((3 * K + C + CG + 63) / 64) * 64;   // 128
+constexpr int kLdsNodes = 1024;
+constexpr float kPi = 3.14159265358979323846f;
+}  // namespace pp
+
+// sum_c w[c] * ((1 - f) B[i0][c] + f B[i1][c]); s_row holds that interpolated
+// row when every ray shares it (nullptr otherwise).
+template <int N>
+__device__ __forceinline__ float basis_dot(const float (&w)[N], const float* s_row, const float* B, int i0, int i1,
+                                           float f) {
+    float x = 0.0f;
+    if (s_row) {
+#pragma unroll
+        for (int c = 0; c < N; ++c) x = fmaf(w[c], s_row[c], x);
+    } else {
+        const float* b0 = B + (int64_t)i0 * N;
+        const float* b1 = B + (int64_t)i1 * N;
+#pragma unroll
+        for (int c = 0; c < N; ++c) x = fmaf(w[c], (1.0f - f) * b0[c] + f * b1[c], x);
+    }
+    return x;
+}
+
+// Value e of the R-value row of leaf `slot` (layouts as in load_leaf).
+template <int DT, int R>
+__device__ __forceinline__ float leaf_elem(const void* base, int64_t N, int64_t slot, int e, int layout) {
+    constexpr int V = StoreTraits<DT>::V;
+    constexpr int NG = (R + V - 1) / V;
+    const int g = e / V, r = e - (e / V) * V;
+    const int64_t vec = layout ? slot * NG + g : (int64_t)g * N + slot;
+    if constexpr (DT == 0) {
+        return reinterpret_cast<const float*>(base)[vec * 4 + r];
+    } else {
+        const uint16_t u = reinterpret_cast<const uint16_t*>(base)[vec * 8 + r];
+        if constexpr (DT == 1) return (float)__builtin_bit_cast(_Float16, u);
+        else return __uint_as_float((uint32_t)u << 16);
+    }
+}
+
+// Stages the interpolated basis rows shared by every ray (scalar time) in
+// LDS; the caller's barrier makes them visible.
+__device__ __forceinline__ void stage_common_rows(const TreeArgs& tr, const InstArgs& in, float t, float* s_b,
+                                                  float* s_bg) {
+    using namespace pp;
+    if (threadIdx.x < C + CG) {
+        int i0, i1;
+        float f;
+        time_setup(tr, in, t, i0, i1, f);
+        if (threadIdx.x < C) {
+            const int c = threadIdx.x;
+            s_b[c] = (1.0f - f) * tr.basis[(int64_t)i0 * C + c] + f * tr.basis[(int64_t)i1 * C + c];
+        } else {
+            const int c = threadIdx.x - C;
+            s_bg[c] = (1.0f - f) * tr.basis_g[(int64_t)i0 * CG + c] + f * tr.basis_g[(int64_t)i1 * CG + c];
+        }
+    }
+}
+
+// One sample's per-point quantities: density logit x, hyperangle logit y,
+// radial factors g (and dg / dgamma) and colour logits z.
+template <int DT>
+struct PPSample {
+    float wv[3 * pp::K], sv[pp::C], gv[pp::CG];
+    float x, y, g[6], dg[6], h[pp::K], z0, z1, z2;
+};
+
+template <int DT>
+__device__ __forceinline__ void pp_eval(const TreeArgs& tr, const RaySetup& rs, const float (&Y)[8], const float* s_b,
+                                        const float* s_bg, int leaf, PPSample<DT>& p) {
+    using namespace pp;
+    load_leaf<DT, 3 * K>(tr.hh, tr.n_leaves, leaf, tr.layout, p.wv);
+    load_leaf<DT, C>(tr.wsig, tr.n_leaves, leaf, tr.layout, p.sv);
+    load_leaf<DT, CG>(tr.wgam, tr.n_leaves, leaf, tr.layout, p.gv);
+    p.x = basis_dot<C>(p.sv, s_b, tr.basis, rs.i0, rs.i1, rs.f);
+    p.y = basis_dot<CG>(p.gv, s_bg, tr.basis_g, rs.i0, rs.i1, rs.f);
+    const float gam = kPi * sigmoid_f(p.y);
+    float sn, cs;
+    sincosf(gam, &sn, &cs);
+    radial_n2(sn, cs, p.g, p.dg);
+    hh14(p.g, Y, p.h);
+    p.z0 = p.z1 = p.z2 = 0.0f;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        p.z0 = fmaf(p.wv[k], p.h[k], p.z0);
+        p.z1 = fmaf(p.wv[K + k], p.h[k], p.z1);
+        p.z2 = fmaf(p.wv[2 * K + k], p.h[k], p.z2);
+    }
+}
+
+// ----------------------------------------------------------------------------
+// forward
+
+template <int DT, bool IDENT>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) void render_pp_fwd_kernel(
+    TreeArgs tr, InstArgs in, RayArgs ra, float t_stop, RenderOut out) {
+    using namespace pp;
+    __shared__ int4 s_nodes[kLdsNodes];
+    __shared__ int s_path[kMaxLevels * kBlock];
+    __shared__ float s_brow[C], s_bgrow[CG];
+    const bool common_t = ra.t == nullptr;
+    if (common_t) stage_common_rows(tr, in, ra.t_scalar, s_brow, s_bgrow);
+    const int n_lds = stage_top_nodes<kLdsNodes>(tr, s_nodes);   // its barrier also covers the rows
+    const float* s_b = common_t ? s_brow : nullptr;
+    const float* s_bg = common_t ? s_bgrow : nullptr;
+    int* path = s_path + threadIdx.x;
+    ChunkCursor cc = chunk_cursor();
+    bool more = true;
+
+    bool alive = false;
+    int64_t ray = -1;
+    RaySetup rs;
+    Walk w;
+    float Y[8];
+    float Tr = 1.0f, acc0 = 0.0f, acc1 = 0.0f, acc2 = 0.0f, wsum = 0.0f, dsum = 0.0f;
+    int ns = 0;
+
+    for (;;) {
+        const uint64_t idle = __ballot(!alive);
+        const int n_idle = __popcll(idle);
+        if (more && (n_idle >= ra.refill_min || n_idle == kWave)) {
+            bool cand = false;
+            float o[3], d[3], t = 0.0f;
+            for (;;) {
+                const uint64_t need = __ballot(!alive && !cand);
+                const int n_need = __popcll(need);
+                if (n_need < ra.refill_min) break;
+                if (cc.pos == kWave && !next_chunk(ra, cc)) {
+                    more = false;
+                    break;
+                }
+                const int take = n_need < kWave - cc.pos ? n_need : kWave - cc.pos;
+                if (!alive && !cand) {
+                    const int r = lane_rank(need);
+                    if (r < take) {
+                        ray = chunk_ray(ra, cc, cc.pos + r);
+                        if (ray >= 0) {
+                            o[0] = ra.o[3 * ray]; o[1] = ra.o[3 * ray + 1]; o[2] = ra.o[3 * ray + 2];
+                            d[0] = ra.d[3 * ray]; d[1] = ra.d[3 * ray + 1]; d[2] = ra.d[3 * ray + 2];
+                            t = ra.t ? ra.t[ray] : ra.t_scalar;
+                            cand = ray_may_hit<IDENT>(tr, in, o, d);
+                            if (!cand) write_miss(out, ray);
+                        }
+                    }
+                }
+                cc.pos += take;
+            }
+            if (cand) {
+                ray_setup<IDENT>(tr, in, o, d, t, rs);
+                Tr = 1.0f; acc0 = acc1 = acc2 = 0.0f; wsum = dsum = 0.0f; ns = 0;
+                if (rs.hit) {
+                    sh_deg2(rs.dir[0], rs.dir[1], rs.dir[2], Y);
+                    walk_begin(tr, rs, w);
+                    alive = true;
+                } else {
+                    write_miss(out, ray);
+                }
+            }
+            continue;
+        }
+        if (n_idle == kWave) break;
+        if (alive) {
+            float delta, umid;
+            const int leaf = walk_next(tr, s_nodes, n_lds, path, kBlock, rs, w, delta, umid);
+            bool finish = leaf < 0;
+            if (!finish) {
+                PPSample<DT> p;
+                pp_eval<DT>(tr, rs, Y, s_b, s_bg, leaf, p);
+                const float sig = softplus_f(p.x);
+                const float od = sig * delta;
+                const float a = -expm1f(-od);
+                const float wt = Tr * a;
+                acc0 = fmaf(wt, sigmoid_f(p.z0), acc0);
+                acc1 = fmaf(wt, sigmoid_f(p.z1), acc1);
+                acc2 = fmaf(wt, sigmoid_f(p.z2), acc2);
+                wsum += wt;
+                dsum = fmaf(wt, umid * rs.len_world, dsum);
+                Tr *= expf(-od);
+                ++ns;
+                finish = t_stop > 0.0f && Tr < t_stop;
+            }
+            if (finish) {
+                out.rgb[3 * ray] = acc0; out.rgb[3 * ray + 1] = acc1; out.rgb[3 * ray + 2] = acc2;
+                out.alpha[ray] = 1.0f - Tr;
+                if (out.depth) out.depth[ray] = wsum > 0.0f ? dsum / wsum : INFINITY;
+                out.nsamp[ray] = ns;
+                alive = false;
+            }
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------
+// adjoint
+//
+// A sample's gradient row has 3K + C + CG = 104 values (two 64-lane atomics):
+// lane component c < 42 is d/dhh = gz_ch h_k, 42 <= c < 73 d/dwsig = gx b,
+// 73 <= c < 104 d/dwgam = gy bg, with gy = dL/dgamma * pi sigmoid'(y) and
+// dL/dgamma = sum_ch gz_ch sum_k W_ch,k g'_nl(gamma) Y_k. The sample's h is
+// passed to the other lanes through LDS; the basis gradients are summed by
+// the lanes that own the density and hyperangle components, each reading the
+// source leaf's weight from cache (it was loaded just before).
+
+// Component of lane slot j (0, 1) of the gradient row.
+__device__ __forceinline__ int pp_component(int j, int lane) { return j * kWave + lane; }
+
+template <int DT, bool IDENT>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) void render_pp_bwd_kernel(
+    TreeArgs tr, InstArgs in, RayArgs ra, BackwardIO io) {
+    using namespace pp;
+    __shared__ int4 s_nodes[kLdsNodes];
+    __shared__ int s_path[kMaxLevels * kBlock];
+    __shared__ float s_h[kBlock * K];
+    __shared__ float s_brow[C], s_bgrow[CG];
+    __shared__ float s_acc[2 * kWave];   // block sum of the lanes' basis-gradient components
+    const bool common_t = ra.t == nullptr;
+    if (common_t) stage_common_rows(tr, in, ra.t_scalar, s_brow, s_bgrow);
+    if (threadIdx.x < 2 * kWave) s_acc[threadIdx.x] = 0.0f;
+    const int n_lds = stage_top_nodes<kLdsNodes>(tr, s_nodes);
+    const float* s_b = common_t ? s_brow : nullptr;
+    const float* s_bg = common_t ? s_bgrow : nullptr;
+    int* path = s_path + threadIdx.x;
+    ChunkCursor cc = chunk_cursor();
+    bool more = true;
+    const int64_t N = tr.n_leaves;
+    const int lane = threadIdx.x & 63;
+    const int wbase = threadIdx.x - lane;
+
+    bool alive = false;
+    int64_t ray = -1;
+    RaySetup rs;
+    Walk w;
+    float Y[8];
+    float Tr = 1.0f, Tfin = 0.0f, p0 = 0.0f, p1 = 0.0f, p2 = 0.0f, F0 = 0.0f, F1 = 0.0f, F2 = 0.0f;
+    float g0 = 0.0f, g1 = 0.0f, g2 = 0.0f, ga = 0.0f;
+    int ns = 0, ns_fwd = 0;
+    float bacc[2] = {0.0f, 0.0f};   // this lane's basis-gradient components (scalar time)
+
+    for (;;) {
+        const uint64_t idle = __ballot(!alive);
+        const int n_idle = __popcll(idle);
+        if (more && (n_idle >= ra.refill_min || n_idle == kWave)) {
+            bool cand = false;
+            for (;;) {
+                const uint64_t need = __ballot(!alive && !cand);
+                const int n_need = __popcll(need);
+                if (n_need < ra.refill_min) break;
+                if (cc.pos == kWave && !next_chunk(ra, cc)) {
+                    more = false;
+                    break;
+                }
+                const int take = n_need < kWave - cc.pos ? n_need : kWave - cc.pos;
+                if (!alive && !cand) {
+                    const int r = lane_rank(need);
+                    if (r < take) {
+                        ray = chunk_ray(ra, cc, cc.pos + r);
+                        cand = ray >= 0 && io.nsamp[ray] > 0;
+                    }
+                }
+                cc.pos += take;
+            }
+            if (cand) {
+                const float o[3] = {ra.o[3 * ray], ra.o[3 * ray + 1], ra.o[3 * ray + 2]};
+                const float d[3] = {ra.d[3 * ray], ra.d[3 * ray + 1], ra.d[3 * ray + 2]};
+                const float t = ra.t ? ra.t[ray] : ra.t_scalar;
+                ray_setup<IDENT>(tr, in, o, d, t, rs);
+                if (rs.hit) {
+                    sh_deg2(rs.dir[0], rs.dir[1], rs.dir[2], Y);
+                    walk_begin(tr, rs, w);
+                    ns_fwd = io.nsamp[ray];
+                    ns = 0;
+                    Tr = 1.0f;
+                    Tfin = 1.0f - io.alpha[ray];
+                    F0 = io.rgb[3 * ray]; F1 = io.rgb[3 * ray + 1]; F2 = io.rgb[3 * ray + 2];
+                    g0 = io.grad_rgb[3 * ray]; g1 = io.grad_rgb[3 * ray + 1]; g2 = io.grad_rgb[3 * ray + 2];
+                    ga = io.grad_alpha ? io.grad_alpha[ray] : 0.0f;
+                    p0 = p1 = p2 = 0.0f;
+                    alive = true;
+                }
+            }
+            continue;
+        }
+        if (n_idle == kWave) break;
+        bool has = false;
+        int leaf = -1;
+        float gz0 = 0.0f, gz1 = 0.0f, gz2 = 0.0f, gx = 0.0f, gy = 0.0f;
+        if (alive) {
+            float delta, umid;
+            leaf = walk_next(tr, s_nodes, n_lds, path, kBlock, rs, w, delta, umid);
+            bool finish = leaf < 0;
+            if (!finish) {
+                PPSample<DT> p;
+                pp_eval<DT>(tr, rs, Y, s_b, s_bg, leaf, p);
+                const float sig = softplus_f(p.x);
+                const float od = sig * delta;
+                const float a = -expm1f(-od);
+                const float e = expf(-od);
+                const float wt = Tr * a;
+                const float Tn = Tr * e;
+                const float c0 = sigmoid_f(p.z0), c1 = sigmoid_f(p.z1), c2 = sigmoid_f(p.z2);
+                p0 = fmaf(wt, c0, p0);
+                p1 = fmaf(wt, c1, p1);
+                p2 = fmaf(wt, c2, p2);
+                const float gdotc = g0 * c0 + g1 * c1 + g2 * c2;
+                const float gsuf = g0 * (F0 - p0) + g1 * (F1 - p1) + g2 * (F2 - p2);
+                const float gsig = delta * (Tn * gdotc - gsuf) + ga * delta * Tfin;
+                gx = gsig * sigmoid_f(p.x);
+                gz0 = g0 * wt * c0 * (1.0f - c0);
+                gz1 = g1 * wt * c1 * (1.0f - c1);
+                gz2 = g2 * wt * c2 * (1.0f - c2);
+                // dL/dgamma through every h_k = g_nl(gamma) Y_k
+                float dh[K];
+                hh14(p.dg, Y, dh);
+                float ggam = 0.0f;
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+                    ggam = fmaf(dh[k], gz0 * p.wv[k] + gz1 * p.wv[K + k] + gz2 * p.wv[2 * K + k], ggam);
+                const float sg = sigmoid_f(p.y);
+                gy = ggam * kPi * sg * (1.0f - sg);
+#pragma unroll
+                for (int k = 0; k < K; ++k) s_h[threadIdx.x * K + k] = p.h[k];
+                has = true;
+                Tr = Tn;
+                ++ns;
+                finish = ns >= ns_fwd;
+            }
+            if (finish) alive = false;
+        }
+        uint64_t m = __ballot(has);
+        __builtin_amdgcn_wave_barrier();
+        while (m) {
+            const int src = __builtin_ctzll(m);
+            m &= m - 1;
+            const int L = __builtin_amdgcn_readlane(leaf, src);
+            const float a0 = readlane_f(gz0, src), a1 = readlane_f(gz1, src), a2 = readlane_f(gz2, src);
+            const float ax = readlane_f(gx, src), ay = readlane_f(gy, src);
+            int i0 = 0, i1 = 0;
+            float f = 0.0f;
+            if (!common_t) {
+                i0 = __builtin_amdgcn_readlane(rs.i0, src);
+                i1 = __builtin_amdgcn_readlane(rs.i1, src);
+                f = readlane_f(rs.f, src);
+            }
+            float* row = io.grad_leaf + (int64_t)L * ROW;
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int c = pp_component(j, lane);
+                if (c < 3 * K) {
+                    const int ch = c / K;
+                    const float gzc = ch == 0 ? a0 : (ch == 1 ? a1 : a2);
+                    unsafeAtomicAdd(row + c, gzc * s_h[(wbase + src) * K + (c - ch * K)]);
+                } else if (c < 3 * K + C + CG) {
+                    const bool dens = c < 3 * K + C;
+                    const int e = dens ? c - 3 * K : c - 3 * K - C;
+                    const float gsrc = dens ? ax : ay;
+                    const float* B = dens ? tr.basis : tr.basis_g;
+                    const int R = dens ? C : CG;
+                    const float be = common_t ? (dens ? s_brow[e] : s_bgrow[e])
+                                              : (1.0f - f) * B[(int64_t)i0 * R + e] + f * B[(int64_t)i1 * R + e];
+                    unsafeAtomicAdd(row + c, gsrc * be);
+                    float* gB = dens ? io.grad_basis : io.grad_basis_g;
+                    if (gB) {
+                        const float wl = dens ? leaf_elem<DT, C>(tr.wsig, N, L, e, tr.layout)
+                                              : leaf_elem<DT, CG>(tr.wgam, N, L, e, tr.layout);
+                        const float v = gsrc * wl;
+                        if (common_t) {
+                            bacc[j] += v;
+                        } else {
+                            unsafeAtomicAdd(gB + (int64_t)i0 * R + e, (1.0f - f) * v);
+                            if (f != 0.0f) unsafeAtomicAdd(gB + (int64_t)i1 * R + e, f * v);
+                        }
+                    }
+                }
+            }
+        }
+    }
+    // one shared time: sum the lanes' basis components over the block, then
+    // spread them over the two interpolated rows
+    if (common_t) {
+        atomicAdd(&s_acc[lane], bacc[0]);
+        atomicAdd(&s_acc[kWave + lane], bacc[1]);
+        __syncthreads();
+        if (threadIdx.x < 2 * kWave) {
+            const int c = threadIdx.x;
+            if (c >= 3 * K && c < 3 * K + C + CG) {
+                const bool dens = c < 3 * K + C;
+                const int e = dens ? c - 3 * K : c - 3 * K - C;
+                const int R = dens ? C : CG;
+                float* gB = dens ? io.grad_basis : io.grad_basis_g;
+                if (gB) {
+                    int i0, i1;
+                    float f;
+                    time_setup(tr, in, ra.t_scalar, i0, i1, f);
+                    const float v = s_acc[c];
+                    unsafeAtomicAdd(gB + (int64_t)i0 * R + e, (1.0f - f) * v);
+                    if (f != 0.0f) unsafeAtomicAdd(gB + (int64_t)i1 * R + e, f * v);
+                }
+            }
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------
+// launchers
+
+template <int DT>
+static hipError_t pp_fwd_t(const TreeArgs& tr, const InstArgs& in, const RayArgs& ra, float t_stop,
+                           const RenderOut& o, hipStream_t st) {
+    if (in.identity) {
+        auto kern = render_pp_fwd_kernel<DT, true>;
+        hipLaunchKernelGGL(kern, dim3(grid_for(kern, ra)), dim3(kBlock), 0, st, tr, in, ra, t_stop, o);
+    } else {
+        auto kern = render_pp_fwd_kernel<DT, false>;
+        hipLaunchKernelGGL(kern, dim3(grid_for(kern, ra)), dim3(kBlock), 0, st, tr, in, ra, t_stop, o);
+    }
+    return hipGetLastError();
+}
+
+template <int DT>
+static hipError_t pp_bwd_t(const TreeArgs& tr, const InstArgs& in, const RayArgs& ra, const BackwardIO& io,
+                           hipStream_t st) {
+    if (in.identity) {
+        auto kern = render_pp_bwd_kernel<DT, true>;
+        hipLaunchKernelGGL(kern, dim3(grid_for(kern, ra)), dim3(kBlock), 0, st, tr, in, ra, io);
+    } else {
+        auto kern = render_pp_bwd_kernel<DT, false>;
+        hipLaunchKernelGGL(kern, dim3(grid_for(kern, ra)), dim3(kBlock), 0, st, tr, in, ra, io);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_render_pp_fwd(int dtype, const TreeArgs& tr, const InstArgs& in, const RayArgs& ra, float t_stop,
+                                const RenderOut& out, hipStream_t stream) {
+    if (ra.n_slots <= 0) return hipSuccess;
+    switch (dtype) {
+        case 0: return with_queue(ra, stream, [&](const RayArgs& r) { return pp_fwd_t<0>(tr, in, r, t_stop, out, stream); });
+        case 1: return with_queue(ra, stream, [&](const RayArgs& r) { return pp_fwd_t<1>(tr, in, r, t_stop, out, stream); });
+        default: return with_queue(ra, stream, [&](const RayArgs& r) { return pp_fwd_t<2>(tr, in, r, t_stop, out, stream); });
+    }
+}
+
+hipError_t launch_render_pp_bwd(int dtype, const TreeArgs& tr, const InstArgs& in, const RayArgs& ra,
+                                const BackwardIO& io, hipStream_t stream) {
+    if (ra.n_slots <= 0) return hipSuccess;
+    switch (dtype) {
+        case 0: return with_queue(ra, stream, [&](const RayArgs& r) { return pp_bwd_t<0>(tr, in, r, io, stream); });
+        case 1: return with_queue(ra, stream, [&](const RayArgs& r) { return pp_bwd_t<1>(tr, in, r, io, stream); });
+        default: return with_queue(ra, stream, [&](const RayArgs& r) { return pp_bwd_t<2>(tr, in, r, io, stream); });
+    }
+}
+
+}  // namespace neuvv

@@ -38,16 +38,19 @@ def render(tree: VOctree, ray_o: torch.Tensor, ray_d: torch.Tensor, t=0.0, inst:
 def render_backward(tree: VOctree, ray_o, ray_d, rgb, alpha, nsamp, grad_rgb, grad_alpha=None, t=0.0,
                     inst=None, t_stop: float = 1e-4, image_width: int = 0, grads=None, want_basis=True,
                     stream=None):
-    """Accumulates into (grad_leaf [N, ROW], grad_basis [T, C]) float32 buffers (fresh zeros if grads is None)."""
+    """Accumulates into float32 buffers (fresh zeros if grads is None) and returns them:
+    (grad_leaf [N, ROW], grad_basis [T, C]), plus grad_basis_g [T, Cg] for a tree with
+    per-point hyperangle weights."""
     if grads is None:
         grads = tree.zero_grads()
-    gl, gb = grads
+    gl, gb = grads[0], grads[1]
+    gbg = grads[2] if tree.Cg > 0 else None
     ray_t = t if isinstance(t, torch.Tensor) else None
     t_scalar = 0.0 if ray_t is not None else float(t)
     _lib.neuvv_render_backward(tree.struct(), inst, ray_o.shape[0], ray_o, ray_d, ray_t, t_scalar, image_width,
                                t_stop, rgb, alpha, nsamp, grad_rgb, grad_alpha, gl, gb if want_basis else None,
-                               stream)
-    return gl, gb
+                               gbg if want_basis else None, stream)
+    return (gl, gb, gbg) if tree.Cg > 0 else (gl, gb)
 
 
 def compose(rgb: torch.Tensor, alpha: torch.Tensor, depth: torch.Tensor, stream=None):

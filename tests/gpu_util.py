@@ -27,7 +27,7 @@ def tdev(a, dtype=torch.float32):
 
 def upload(scene, dtype=_lib.F32, layout=_lib.LAYOUT_LEAF_ROWS) -> VOctree:
     return VOctree.build(scene.depth, scene.leaf_ijk, scene.hh, scene.wsig, scene.basis, scene.gamma, dtype,
-                         layout=layout)
+                         layout=layout, wgam=scene.wgam, basis_g=scene.basis_g)
 
 
 def round_storage(x: np.ndarray, dtype: int) -> np.ndarray:
@@ -44,8 +44,10 @@ def round_storage(x: np.ndarray, dtype: int) -> np.ndarray:
 
 def oracle_render(scene, o, d, t=None, t_scalar=0.0, t_stop=1e-4, inst=None, dtype=_lib.F32, g_rgb=None,
                   g_alpha=None):
+    wg = None if scene.wgam is None else round_storage(scene.wgam, dtype)
     return OC.render(scene.depth, scene.leaf_ijk, round_storage(scene.hh, dtype), round_storage(scene.wsig, dtype),
-                     scene.basis, scene.gamma, o, d, t, t_scalar, t_stop, inst, g_rgb, g_alpha)
+                     scene.basis, scene.gamma, o, d, t, t_scalar, t_stop, inst, g_rgb, g_alpha, wgam=wg,
+                     basis_g=scene.basis_g)
 
 
 def gpu_render(tree, o, d, t=None, t_scalar=0.0, t_stop=1e-4, inst=None, image_width=0):

@@ -193,7 +193,22 @@ def test_argument_errors_without_launch(lib):
     t.nodes = 16
     t.depth, t.dtype = 9, 7
     assert lib.neuvv_render_backward(ctypes.byref(t), None, 0, None, None, None, 0.0, 0, 0.0, None, None, None,
-                                     None, None, None, None, None, None) == -1
+                                     None, None, None, None, None, None, None) == -1
+    # per-point hyperangle form: only K = 14, C = 31, Cg = 31 is compiled, and it needs its basis
+    t.depth, t.dtype = 9, 0
+    t.K, t.C, t.Cg = 16, 8, 31
+    assert lib.neuvv_render(ctypes.byref(t), None, 0, None, None, None, 0.0, 0, 0.0, None, None, None, None,
+                            None) == -5
+    t.K, t.C, t.Cg, t.gamma = 14, 31, 31, None
+    assert lib.neuvv_render(ctypes.byref(t), None, 0, None, None, None, 0.0, 0, 0.0, None, None, None, None,
+                            None) == -1
+    assert "basis_g" in _lib.neuvv_last_error()
+    t.basis_g = 8
+    assert lib.neuvv_render(ctypes.byref(t), None, 0, None, None, None, 0.0, 0, 0.0, None, None, None, None,
+                            None) == 0
+    t.Cg = 0
+    assert lib.neuvv_render(ctypes.byref(t), None, 0, None, None, None, 0.0, 0, 0.0, None, None, None, None,
+                            None) == -5
     assert lib.neuvv_compose(0, 10, None, None, None, None, None, None, None) == -2
     assert lib.neuvv_compose(17, 10, None, None, None, None, None, None, None) == -2
     assert lib.neuvv_compose(2, 10, None, None, None, None, None, None, None) == -1
@@ -202,6 +217,13 @@ def test_argument_errors_without_launch(lib):
     assert lib.neuvv_pinhole_rays(ctypes.byref(cam), 0, None, None, None, None) == -2
     assert lib.neuvv_pack_leaves(16, 8, 5, 0, 1, None, None, None, None, None, None) == -5
     assert lib.neuvv_pack_leaves(16, 8, 0, 7, 1, None, None, None, None, None, None) == -5
+    assert lib.neuvv_pack_rows(0, 0, 0, 1, None, None, None, None) == -2
+    assert lib.neuvv_pack_rows(31, 5, 0, 1, None, None, None, None) == -5
+    assert lib.neuvv_pack_rows(31, 0, 1, 1, None, None, None, None) == -1
+    assert lib.neuvv_pack_rows(31, 0, 1, 0, None, None, None, None) == 0
+    assert _lib.neuvv_grad_row_elems(16, 8) == 64
+    assert _lib.neuvv_grad_row_elems(14, 31, 31) == 128
+    assert lib.neuvv_grad_row_elems(14, 31, 65) == -2
     a, b = _lib.neuvv_payload_words(16, 8, _lib.F32, 10)
     assert (a, b) == (12 * 10 * 4, 2 * 10 * 4)
     a, b = _lib.neuvv_payload_words(16, 8, _lib.F16, 10)

@@ -1,0 +1,171 @@
+"""GPU parity of the per-point hyperangle form (Sec. 4.2, Eq. 6) against the
+FP64 oracle: the paper's 104-value leaf (K = 14 HH per channel, C = 31
+density weights, Cg = 31 hyperangle weights on a second basis), forward and
+adjoint, both payload layouts, 16-bit storage, per-ray times and a placed
+instance. The oracle's per-point path is pinned on the CPU (brute force,
+reduction to the global table, finite differences)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import (DEV, announce, cam_struct, compare, config1_camera, gpu_render, inst_pair, oracle_render,
+                      rel_err, tdev, upload)
+from paper_2202_06088_amd import _lib, autograd, ops
+from workloads import make_scene_per_point, random_rays, special_rays
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def scene():
+    announce("per-point scene: depth 6, ~20k leaves, K=14 C=31 Cg=31")
+    return make_scene_per_point(6, 20_000, "random", T=30, seed=31)
+
+
+def pp_backward(tree, o, d, t, t_scalar, t_stop, g_rgb, g_alpha, inst=None, image_width=0):
+    tt = tdev(t) if t is not None else t_scalar
+    oo, dd = tdev(o), tdev(d)
+    rgb, alpha, depth, nsamp = ops.render(tree, oo, dd, tt, inst, t_stop, image_width)
+    gl, gb, gbg = ops.render_backward(tree, oo, dd, rgb, alpha, nsamp, tdev(g_rgb),
+                                      None if g_alpha is None else tdev(g_alpha), tt, inst, t_stop, image_width)
+    torch.cuda.synchronize()
+    hh, ws, wg = tree.unpack_grad(gl)
+    pad = gl[:, 3 * tree.K + tree.C + tree.Cg:]
+    assert pad.numel() == 0 or float(pad.abs().max()) == 0.0, "row padding must stay zero"
+    return [x.cpu().numpy() for x in (hh, ws, wg, gb, gbg)]
+
+
+def check_grads(gpu, ref, tol=1e-4, label=""):
+    names = ["grad_hh", "grad_wsig", "grad_wgam", "grad_basis", "grad_basis_g"]
+    e = [rel_err(g, ref[n]) for g, n in zip(gpu, names)]
+    announce(f"{label} grad rel errors " + " ".join(f"{n}={v:.2e}" for n, v in zip(names, e)))
+    assert max(e) <= tol, e
+    for n in names:
+        assert np.abs(ref[n]).max() > 0, n
+
+
+@pytest.mark.parametrize("layout", [_lib.LAYOUT_LEAF_ROWS, _lib.LAYOUT_VEC_SOA])
+def test_per_point_forward_image(scene, layout):
+    tree = upload(scene, layout=layout)
+    cam = config1_camera(scene)
+    from oracle import core as OC
+    o, d = OC.pinhole_rays(64, 64, cam.intr(), cam.c2w)
+    for t, t_stop in ((0.0, 0.0), (7.25, 0.0), (12.5, 1e-4), (29.0, 1e-4)):
+        announce(f"per-point forward t={t} t_stop={t_stop} layout={layout}")
+        ref = oracle_render(scene, o, d, None, t, t_stop)
+        gpu = gpu_render(tree, o, d, None, t, t_stop, image_width=64)
+        st = compare(gpu, ref, label=f"pp t={t}")
+        assert st["hit"] > 300
+
+
+def test_per_point_forward_random_rays_per_ray_time(scene):
+    tree = upload(scene)
+    rng = np.random.default_rng(32)
+    o1, d1 = random_rays(scene.G, 3000, rng, inside_frac=0.2)
+    o2, d2 = special_rays(scene.G)
+    o, d = np.concatenate([o1, o2]), np.concatenate([d1, d2])
+    t = rng.uniform(0, 30, o.shape[0]).astype(np.float32)
+    announce("per-point forward, random rays, per-ray time")
+    ref = oracle_render(scene, o, d, t, 0.0, 1e-4)
+    gpu = gpu_render(tree, o, d, t, 0.0, 1e-4)
+    compare(gpu, ref, label="pp random")
+
+
+@pytest.mark.parametrize("layout", [_lib.LAYOUT_LEAF_ROWS, _lib.LAYOUT_VEC_SOA])
+def test_per_point_backward_scalar_time(scene, layout):
+    tree = upload(scene, layout=layout)
+    cam = config1_camera(scene)
+    from oracle import core as OC
+    o, d = OC.pinhole_rays(64, 64, cam.intr(), cam.c2w)
+    rng = np.random.default_rng(33)
+    gC = rng.normal(size=(o.shape[0], 3)).astype(np.float32)
+    gA = rng.normal(size=o.shape[0]).astype(np.float32)
+    for t in (4.0, 17.6):
+        announce(f"per-point backward t={t} layout={layout}")
+        ref = oracle_render(scene, o, d, None, t, 0.0, g_rgb=gC, g_alpha=gA)
+        gpu = pp_backward(tree, o, d, None, t, 0.0, gC, gA, image_width=64)
+        check_grads(gpu, ref, label=f"pp t={t}")
+
+
+def test_per_point_backward_per_ray_time_and_early_stop(scene):
+    tree = upload(scene)
+    rng = np.random.default_rng(34)
+    o, d = random_rays(scene.G, 4000, rng, inside_frac=0.2)
+    t = rng.uniform(0, 30, o.shape[0]).astype(np.float32)
+    gC = rng.normal(size=(o.shape[0], 3)).astype(np.float32)
+    fwd = oracle_render(scene, o, d, t, 0.0, 1e-4)
+    gC[fwd["margin"][:, 1] < 1e-3] = 0.0         # rays whose stop decision is within rounding
+    announce("per-point backward, per-ray time, t_stop=1e-4")
+    ref = oracle_render(scene, o, d, t, 0.0, 1e-4, g_rgb=gC)
+    gpu = pp_backward(tree, o, d, t, 0.0, 1e-4, gC, None)
+    check_grads(gpu, ref, label="pp per-ray t")
+
+
+@pytest.mark.parametrize("dtype", [_lib.F16, _lib.BF16])
+def test_per_point_16bit_storage(scene, dtype):
+    tree = upload(scene, dtype)
+    cam = config1_camera(scene)
+    from oracle import core as OC
+    o, d = OC.pinhole_rays(64, 64, cam.intr(), cam.c2w)
+    rng = np.random.default_rng(35)
+    gC = rng.normal(size=(o.shape[0], 3)).astype(np.float32)
+    announce(f"per-point storage {dtype}")
+    ref = oracle_render(scene, o, d, None, 9.0, 0.0, dtype=dtype, g_rgb=gC)
+    gpu = gpu_render(tree, o, d, None, 9.0, 0.0, image_width=64)
+    compare(gpu, ref, label=f"pp dtype={dtype}")
+    g = pp_backward(tree, o, d, None, 9.0, 0.0, gC, None, image_width=64)
+    check_grads(g, ref, label=f"pp dtype={dtype}")
+    # against the unrounded payload: the storage error itself
+    full = oracle_render(scene, o, d, None, 9.0, 0.0)
+    err = float(np.abs(gpu["rgb"] - full["rgb"]).max())
+    mse = float(np.mean((gpu["rgb"] - full["rgb"]) ** 2))
+    announce(f"pp dtype={dtype} vs unrounded: max-abs {err:.2e} PSNR {10 * math.log10(1 / max(mse, 1e-30)):.1f} dB")
+    if dtype == _lib.F16:
+        assert err <= 2e-3
+
+
+def test_per_point_instance(scene):
+    tree = upload(scene)
+    G = scene.G
+    th = 0.7
+    R = np.array([[math.cos(th), -math.sin(th), 0], [math.sin(th), math.cos(th), 0], [0, 0, 1]], np.float32)
+    oi, gi = inst_pair(R, [3.0, -2.0, 1.5], 1.75, 11.5, 1)
+    rng = np.random.default_rng(36)
+    o, d = random_rays(G, 2000, rng, inside_frac=0.1)
+    o = (o @ R.T) * 1.75 + np.array([3.0, -2.0, 1.5], np.float32)
+    o = (np.round(o * 256) / 256).astype(np.float32)
+    d = (d @ R.T).astype(np.float32)
+    gC = rng.normal(size=(o.shape[0], 3)).astype(np.float32)
+    announce("per-point instance (rotation, scale 1.75, time offset 11.5, wrap)")
+    ref = oracle_render(scene, o, d, None, 25.0, 0.0, inst=oi, g_rgb=gC)
+    gpu = gpu_render(tree, o, d, None, 25.0, 0.0, inst=gi)
+    compare(gpu, ref, label="pp instance")
+    g = pp_backward(tree, o, d, None, 25.0, 0.0, gC, None, inst=gi)
+    check_grads(g, ref, label="pp instance")
+
+
+def test_per_point_autograd_matches_direct_calls(scene):
+    tree = upload(scene)
+    cam = config1_camera(scene)
+    o, d = ops.pinhole_rays(cam_struct(cam))
+    for x in (tree.hh, tree.wsig, tree.basis, tree.wgam, tree.basis_g):
+        x.requires_grad_(True)
+    announce("per-point autograd RenderFn")
+    rgb, alpha, depth, nsamp = autograd.render(tree, o, d, 5.5, None, 0.0, 64)
+    target = torch.rand_like(rgb)
+    loss = ((rgb - target) ** 2).sum() + alpha.sum()
+    loss.backward()
+    g_rgb = (2 * (rgb - target)).detach().contiguous()
+    with torch.no_grad():
+        gl, gb, gbg = ops.render_backward(tree, o, d, rgb.detach(), alpha.detach(), nsamp, g_rgb,
+                                          torch.ones_like(alpha), 5.5, None, 0.0, 64)
+        ghh, gws, gwg = tree.rows_to_payload_f32(gl)
+    torch.cuda.synchronize()
+    assert rel_err(tree.hh.grad.cpu().numpy(), ghh.cpu().numpy()) < 1e-5
+    assert rel_err(tree.wsig.grad.cpu().numpy(), gws.cpu().numpy()) < 1e-5
+    assert rel_err(tree.wgam.grad.cpu().numpy(), gwg.cpu().numpy()) < 1e-5
+    assert rel_err(tree.basis.grad.cpu().numpy(), gb.cpu().numpy()) < 1e-5
+    assert rel_err(tree.basis_g.grad.cpu().numpy(), gbg.cpu().numpy()) < 1e-5
+    assert float(tree.wgam.grad.abs().max()) > 0

@@ -17,7 +17,8 @@ from typing import Dict, List, Optional, Tuple
 
 import numpy as np
 
-__all__ = ["Scene", "Camera", "Ellipsoid", "CONFIGS", "make_scene", "make_payload", "scene_for_config",
+__all__ = ["Scene", "Camera", "Ellipsoid", "CONFIGS", "make_scene", "make_scene_per_point", "make_payload",
+           "scene_for_config",
            "look_at", "ring_cameras", "orbit_camera", "random_rays", "special_rays", "stereo_cameras",
            "config5_instances", "random_rotation", "humanoid_ellipsoids", "random_ellipsoids",
            "occupancy_from_ellipsoids", "default_gamma"]
@@ -40,6 +41,8 @@ class Scene:
     gamma: np.ndarray             # [T] float32 hyperangle per frame
     seed: int = 0
     meta: Dict = field(default_factory=dict)
+    wgam: Optional[np.ndarray] = None     # [N,Cg] float32 per-point hyperangle weights, or None
+    basis_g: Optional[np.ndarray] = None  # [T,Cg] float32 hyperangle basis, or None
 
     @property
     def G(self) -> int:
@@ -207,6 +210,26 @@ def make_scene(depth: int, target_leaves: int, kind: str = "human", K: int = 16,
     hh, wsig, basis = make_payload(ijk.shape[0], K, C, T, rng)
     return Scene(depth, ijk, hh, wsig, basis, default_gamma(T), seed,
                  dict(kind=kind, radius_factor=f, target=target_leaves, ellipsoids=ells))
+
+
+def make_scene_per_point(depth: int, target_leaves: int, kind: str = "human", T: int = 300, seed: int = 0,
+                         K: int = 14, C: int = 31, Cg: int = 31, n_random: int = 3) -> Scene:
+    """The paper's full leaf (K = 14 HH per channel, C = 31 density weights, Cg = 31
+    hyperangle weights). Occupancy and payload draws as make_scene, then wgam ~ N(0, 0.2)
+    [N,Cg] and basis_g ~ N(0,1) [T,Cg] from the same stream. The density weights are drawn
+    with standard deviation sqrt(8 / C), so that the density logit has the spread it has with
+    C = 8 (the optical depth per leaf of the other workloads)."""
+    rng = np.random.default_rng(seed)
+    G = 1 << depth
+    ells = humanoid_ellipsoids(G, rng) if kind == "human" else random_ellipsoids(G, n_random, rng)
+    ijk, f = _fit_occupancy(depth, ells, target_leaves)
+    hh, wsig, basis = make_payload(ijk.shape[0], K, C, T, rng)
+    wsig = (wsig * np.float32(math.sqrt(8.0 / C))).astype(np.float32)
+    wgam = rng.normal(0.0, 0.2, size=(ijk.shape[0], Cg)).astype(np.float32)
+    basis_g = rng.normal(0.0, 1.0, size=(T, Cg)).astype(np.float32)
+    return Scene(depth, ijk, hh, wsig, basis, default_gamma(T), seed,
+                 dict(kind=kind, radius_factor=f, target=target_leaves, ellipsoids=ells, per_point=True),
+                 wgam, basis_g)
 
 
 # The five workloads (depth, target leaves, kind, K, C, T, seed).
