@@ -32,7 +32,6 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Mrays/s fwd and fwd+bwd at 1080p; achieved HBM GB/s vs peak; PSNR vs FP64"
 PEAK_HBM_GBS = 8000.0
-FWD_PAYLOAD_B = {0: 224, 1: 112, 2: 112}    # per sample: 48 HH + 8 density values
 FWD_RAY_IO_B = 24 + 24                      # o, d in; rgb, alpha, depth, nsamp out
 BWD_RAY_IO_B = 24 + 20 + 12                 # o, d; rgb, alpha, nsamp; grad_rgb
 
@@ -43,7 +42,7 @@ def log(msg):
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("render.hip", "neuvv_device.h"):
+    for f in ("render.hip", "render_pp.hip", "render_common.h", "neuvv_device.h"):
         with open(os.path.join(ROOT, "paper_2202_06088_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -72,6 +71,9 @@ def main():
     ap.add_argument("--dtype", choices=["f32", "f16", "bf16"], default="f32")
     ap.add_argument("--layout", choices=["soa", "rows"], default="rows",
                     help="leaf payload layout: 16-byte-vector SoA or leaf-major rows")
+    ap.add_argument("--form", choices=["global", "per-point"], default="global",
+                    help="global: K=16 HH, C=8 density weights, one hyperangle per frame; per-point: the "
+                         "paper's 104-value leaf, K=14, C=31, Cg=31 with the per-point hyperangle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -89,18 +91,23 @@ def main():
     import torch
     from paper_2202_06088_amd import _lib, ops
     from paper_2202_06088_amd.voctree import VOctree
-    from workloads import ring_cameras, scene_for_config
+    from workloads import CONFIGS, make_scene_per_point, ring_cameras, scene_for_config
 
     dt = {"f32": _lib.F32, "f16": _lib.F16, "bf16": _lib.BF16}[args.dtype]
     t0 = time.time()
-    log("generating the depth-9 humanoid scene (seeded)")
-    sc = scene_for_config(2)
+    log(f"generating the depth-9 humanoid scene (seeded, {args.form} hyperangle)")
+    if args.form == "global":
+        sc = scene_for_config(2)
+    else:
+        c2 = CONFIGS[2]
+        sc = make_scene_per_point(c2["depth"], c2["target"], c2["kind"], T=c2["T"], seed=c2["seed"])
     cams = ring_cameras(sc, 8, 1920, 1080, 40.0, 10.0, seed=2)
     t_frame = float(np.random.default_rng(2002).uniform(0, sc.T))
     log(f"scene: {sc.n_leaves} leaves, T={sc.T}, t={t_frame:.3f} ({time.time() - t0:.1f}s)")
     dev = "cuda"
     layout = _lib.LAYOUT_VEC_SOA if args.layout == "soa" else _lib.LAYOUT_LEAF_ROWS
-    tree = VOctree.build(sc.depth, sc.leaf_ijk, sc.hh, sc.wsig, sc.basis, sc.gamma, dt, dev, layout=layout)
+    tree = VOctree.build(sc.depth, sc.leaf_ijk, sc.hh, sc.wsig, sc.basis, sc.gamma, dt, dev, layout=layout,
+                         wgam=sc.wgam, basis_g=sc.basis_g)
     W, H = 1920, 1080
     n_cam = W * H
     n = 8 * n_cam
@@ -126,7 +133,7 @@ def main():
 
     def bwd():
         _lib.neuvv_render_backward(tree.struct(), None, n, ray_o, ray_d, None, t_frame, W, t_stop, rgb, alpha, nsamp,
-                                   g_rgb, None, grads[0], grads[1], None, stream)
+                                   g_rgb, None, grads[0], grads[1], grads[2] if tree.Cg > 0 else None, stream)
 
     log(f"warmup {args.warmup} steps")
     for _ in range(args.warmup):
@@ -151,15 +158,17 @@ def main():
     ns = nsamp.cpu().numpy().astype(np.int64)
     total_samples = int(ns.sum())
     hit = int((ns > 0).sum())
-    fwd_bytes = total_samples * FWD_PAYLOAD_B[dt] + n * FWD_RAY_IO_B
-    bwd_bytes = total_samples * (FWD_PAYLOAD_B[dt] + 448) + n * BWD_RAY_IO_B
+    values = 3 * tree.K + tree.C + tree.Cg                   # per sample: HH, density and hyperangle values
+    payload_b = values * (4 if dt == _lib.F32 else 2)
+    fwd_bytes = total_samples * payload_b + n * FWD_RAY_IO_B
+    bwd_bytes = total_samples * (payload_b + 2 * 4 * values) + n * BWD_RAY_IO_B   # + FP32 atomic read-modify-write
     log(f"fwd {fwd_ms:.3f} ms, bwd {bwd_ms:.3f} ms per launch; step {ms_step:.3f} ms; "
         f"{total_samples} samples, {hit} hit rays")
     kern = {"render_fwd": (fwd_ms, fwd_bytes), "render_bwd": (bwd_ms, bwd_bytes)}
     dom = max(kern, key=lambda k: kern[k][0])
     dms, dbytes = kern[dom]
     achieved = dbytes / (dms * 1e-3) / 1e9
-    workload = "forward_ring_d9_2M_8x1080p"
+    workload = "forward_ring_d9_2M_8x1080p" + ("" if args.form == "global" else "_per_point")
     roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(f"{dom}/{args.layout}/{args.dtype}", workload),
             "algorithmic_bytes_per_launch": dbytes, "launch_ms": round(dms, 4)}
@@ -172,7 +181,8 @@ def main():
         "metric": METRIC, "value": round(n / (ms_step * 1e-3) / 1e6, 2), "unit": "Mrays/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
-        "config": {"workload": workload, "depth": sc.depth, "leaves": sc.n_leaves, "K": sc.K, "C": sc.C,
+        "config": {"workload": workload, "depth": sc.depth, "leaves": sc.n_leaves, "K": tree.K, "C": tree.C,
+                   "Cg": tree.Cg,
                    "T": sc.T, "rays_per_step": n, "image": "8 x 1920x1080", "t_stop": t_stop,
                    "step": "render fwd + adjoint", "layout": args.layout},
         "fwd_mrays_s": round(n / (fwd_ms * 1e-3) / 1e6, 2),
@@ -207,7 +217,7 @@ def cpu_leg(sc, cams, t_frame, t_stop, rgb_gpu, g_rgb, grads, tree, budget_s):
         g = g_rgb[torch_index(g_idx, g_rgb.device)].cpu().numpy().astype(np.float64)
         t1 = time.perf_counter()
         ref = OC.render(sc.depth, sc.leaf_ijk, sc.hh, sc.wsig, sc.basis, sc.gamma, o, d, None, t_frame, t_stop,
-                        g_rgb=g, threads=threads)
+                        g_rgb=g, threads=threads, wgam=sc.wgam, basis_g=sc.basis_g)
         return g_idx, ref, time.perf_counter() - t1
 
     log(f"cpu baseline pilots ({threads} threads)")

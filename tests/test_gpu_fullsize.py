@@ -1,7 +1,9 @@
 """Full-size parity in the launch configuration bench.py times.
 
 Forward-render workload: depth-9 humanoid VOctree (~2M leaves), 8 cameras at
-1920x1080 rendered in one launch (16.6 M rays, 8x8 tiles, t_stop = 1e-4).
+1920x1080 rendered in one launch (16.6 M rays, 8x8 tiles, t_stop = 1e-4), with
+the global hyperangle table (K=16, C=8) and with the paper's per-point leaf
+(K=14, C=31, Cg=31).
 Outputs are checked on a seeded sample of pixels that the FP64 oracle
 renders one by one. The adjoint is checked in the same launch with the
 upstream gradient non-zero only on the sampled pixels, so the oracle's
@@ -14,21 +16,27 @@ import torch
 from gpu_util import DEV, announce, compare, oracle_render, rel_err, tdev, upload
 from oracle import core as OC
 from paper_2202_06088_amd import _lib, ops
-from workloads import ring_cameras, scene_for_config
+from workloads import CONFIGS, make_scene_per_point, ring_cameras, scene_for_config
 
 pytestmark = pytest.mark.gpu
 
 
-@pytest.fixture(scope="module")
-def ring():
-    announce("full size: generating the depth-9 scene")
-    sc = scene_for_config(2)
+@pytest.fixture(scope="module", params=["global", "per-point"])
+def ring(request):
+    announce(f"full size: generating the depth-9 scene ({request.param} hyperangle)")
+    if request.param == "global":
+        sc = scene_for_config(2)
+    else:
+        c2 = CONFIGS[2]
+        sc = make_scene_per_point(c2["depth"], c2["target"], c2["kind"], T=c2["T"], seed=c2["seed"])
     cams = ring_cameras(sc, 8, 1920, 1080, 40.0, 10.0, seed=2)
     t = float(np.random.default_rng(2002).uniform(0, sc.T))
     return sc, cams, t
 
 
 def test_full_ring_forward_and_adjoint_sampled(ring):
+    """The bench's launch configuration (the whole ring in one launch, 8x8 tiles), both
+    hyperangle forms; parity on sampled rays the oracle renders one by one."""
     sc, cams, t = ring
     W, H = 1920, 1080
     n_cam = W * H
@@ -77,10 +85,12 @@ def test_full_ring_forward_and_adjoint_sampled(ring):
     g_rgb[sidx] = tdev(gC)
     g_alpha[sidx] = tdev(gA)
     announce("full size: adjoint")
-    gl, gb = ops.render_backward(tree, o, d, rgb, alpha, nsamp, g_rgb, g_alpha, t, None, 1e-4, W)
+    out = ops.render_backward(tree, o, d, rgb, alpha, nsamp, g_rgb, g_alpha, t, None, 1e-4, W)
     torch.cuda.synchronize()
-    hh, ws = tree.unpack_grad(gl)
-    e = [rel_err(hh.cpu().numpy(), ref["grad_hh"]), rel_err(ws.cpu().numpy(), ref["grad_wsig"]),
-         rel_err(gb.cpu().numpy(), ref["grad_basis"])]
+    parts = tree.unpack_grad(out[0])
+    e = [rel_err(parts[0].cpu().numpy(), ref["grad_hh"]), rel_err(parts[1].cpu().numpy(), ref["grad_wsig"]),
+         rel_err(out[1].cpu().numpy(), ref["grad_basis"])]
+    if tree.Cg > 0:
+        e += [rel_err(parts[2].cpu().numpy(), ref["grad_wgam"]), rel_err(out[2].cpu().numpy(), ref["grad_basis_g"])]
     announce(f"full size adjoint rel errors {e}")
     assert max(e) <= 1e-4
