@@ -261,7 +261,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) 
     float Tr = 1.0f, Tfin = 0.0f, p0 = 0.0f, p1 = 0.0f, p2 = 0.0f, F0 = 0.0f, F1 = 0.0f, F2 = 0.0f;
     float g0 = 0.0f, g1 = 0.0f, g2 = 0.0f, ga = 0.0f;
     int ns = 0, ns_fwd = 0;
-    float bacc[2] = {0.0f, 0.0f};   // this lane's basis-gradient components (scalar time)
+    // scalar time: lane c < C holds component c of the density-basis gradient
+    // (bacc[0]) and, c < CG, of the hyperangle-basis gradient (bacc[1])
+    float bacc[2] = {0.0f, 0.0f};
 
     for (;;) {
         const uint64_t idle = __ballot(!alive);
@@ -354,6 +356,35 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) 
             if (finish) alive = false;
         }
         uint64_t m = __ballot(has);
+        if (common_t && m) {
+            // basis gradients of this step: sum over the wavefront's samples of
+            // gx wsig_c and gy wgam_c (butterfly), lane c keeping component c;
+            // the weights are read again here (from cache) rather than held
+            float sv[C], gv[CG];
+            if (has) {
+                load_leaf<DT, C>(tr.wsig, N, leaf, tr.layout, sv);
+                load_leaf<DT, CG>(tr.wgam, N, leaf, tr.layout, gv);
+            } else {
+#pragma unroll
+                for (int c = 0; c < C; ++c) sv[c] = 0.0f;
+#pragma unroll
+                for (int c = 0; c < CG; ++c) gv[c] = 0.0f;
+            }
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                float v = gx * sv[c];
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+                if (lane == c) bacc[0] += v;
+            }
+#pragma unroll
+            for (int c = 0; c < CG; ++c) {
+                float v = gy * gv[c];
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+                if (lane == c) bacc[1] += v;
+            }
+        }
         __builtin_amdgcn_wave_barrier();
         while (m) {
             const int src = __builtin_ctzll(m);
@@ -386,43 +417,37 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) 
                                               : (1.0f - f) * B[(int64_t)i0 * R + e] + f * B[(int64_t)i1 * R + e];
                     unsafeAtomicAdd(row + c, gsrc * be);
                     float* gB = dens ? io.grad_basis : io.grad_basis_g;
-                    if (gB) {
+                    if (!common_t && gB) {
+                        // a time per ray: this sample's rows of the basis gradient
                         const float wl = dens ? leaf_elem<DT, C>(tr.wsig, N, L, e, tr.layout)
                                               : leaf_elem<DT, CG>(tr.wgam, N, L, e, tr.layout);
                         const float v = gsrc * wl;
-                        if (common_t) {
-                            bacc[j] += v;
-                        } else {
-                            unsafeAtomicAdd(gB + (int64_t)i0 * R + e, (1.0f - f) * v);
-                            if (f != 0.0f) unsafeAtomicAdd(gB + (int64_t)i1 * R + e, f * v);
-                        }
+                        unsafeAtomicAdd(gB + (int64_t)i0 * R + e, (1.0f - f) * v);
+                        if (f != 0.0f) unsafeAtomicAdd(gB + (int64_t)i1 * R + e, f * v);
                     }
                 }
             }
         }
     }
-    // one shared time: sum the lanes' basis components over the block, then
+    // one shared time: sum the wavefronts' components over the block, then
     // spread them over the two interpolated rows
     if (common_t) {
-        atomicAdd(&s_acc[lane], bacc[0]);
-        atomicAdd(&s_acc[kWave + lane], bacc[1]);
+        if (lane < C) atomicAdd(&s_acc[lane], bacc[0]);
+        if (lane < CG) atomicAdd(&s_acc[kWave + lane], bacc[1]);
         __syncthreads();
-        if (threadIdx.x < 2 * kWave) {
-            const int c = threadIdx.x;
-            if (c >= 3 * K && c < 3 * K + C + CG) {
-                const bool dens = c < 3 * K + C;
-                const int e = dens ? c - 3 * K : c - 3 * K - C;
-                const int R = dens ? C : CG;
-                float* gB = dens ? io.grad_basis : io.grad_basis_g;
-                if (gB) {
-                    int i0, i1;
-                    float f;
-                    time_setup(tr, in, ra.t_scalar, i0, i1, f);
-                    const float v = s_acc[c];
-                    unsafeAtomicAdd(gB + (int64_t)i0 * R + e, (1.0f - f) * v);
-                    if (f != 0.0f) unsafeAtomicAdd(gB + (int64_t)i1 * R + e, f * v);
-                }
-            }
+        const int c = threadIdx.x;
+        const bool dens = c < C;
+        const bool gam = c >= kWave && c < kWave + CG;
+        float* gB = dens ? io.grad_basis : io.grad_basis_g;
+        if ((dens || gam) && gB) {
+            const int e = dens ? c : c - kWave;
+            const int R = dens ? C : CG;
+            int i0, i1;
+            float f;
+            time_setup(tr, in, ra.t_scalar, i0, i1, f);
+            const float v = s_acc[c];
+            unsafeAtomicAdd(gB + (int64_t)i0 * R + e, (1.0f - f) * v);
+            if (f != 0.0f) unsafeAtomicAdd(gB + (int64_t)i1 * R + e, f * v);
         }
     }
 }
