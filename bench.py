@@ -74,6 +74,8 @@ def main():
     ap.add_argument("--form", choices=["global", "per-point"], default="global",
                     help="global: K=16 HH, C=8 density weights, one hyperangle per frame; per-point: the "
                          "paper's 104-value leaf, K=14, C=31, Cg=31 with the per-point hyperangle")
+    ap.add_argument("--lighting", action="store_true",
+                    help="also time the spotlight shadow + falloff pass (light map, low-pass, shading)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -190,9 +192,56 @@ def main():
         "roofline": roof, "roofline_other_kernel": roof_other,
     }
 
+    if args.lighting:
+        result["lighting"] = lighting_leg(sc, tree, ray_o, ray_d, rgb, alpha, depth, t_frame, t_stop, W, fwd_ms,
+                                          stream, args.steps)
     if not args.no_cpu_baseline:
         result.update(cpu_leg(sc, cams, t_frame, t_stop, rgb, g_rgb, grads, tree, args.cpu_seconds))
     print(json.dumps(result), flush=True)
+
+
+def lighting_leg(sc, tree, ray_o, ray_d, rgb, alpha, depth, t_frame, t_stop, W, fwd_ms, stream, steps):
+    """Spotlight shadow and falloff (Sec. 5.2) over the ring: the light's alpha map (256 x 256,
+    one forward launch), its Gaussian low-pass and the shading of every ring pixel; timed with
+    HIP events on the launch stream, reported beside the forward render it adds to."""
+    import torch
+    from paper_2202_06088_amd import _lib, ops
+    from workloads import look_at
+    LW = LH = 256
+    cen = sc.leaf_ijk.mean(0) + 0.5
+    pos = cen + np.array([0.35 * sc.G, -0.25 * sc.G, 0.9 * sc.G])
+    c2w = np.asarray(look_at(pos, cen), np.float32)
+    f = 0.5 * LW / math.tan(math.radians(35.0))
+    cam = _lib.make_camera(LW, LH, f, f, LW / 2, LH / 2, c2w)
+    light = _lib.make_light(cam, float(sc.leaf_ijk[:, 2].min()), (0.7, 0.65, 0.6), (0.05, 0.1, 0.2), 0.8,
+                            0.5 * sc.G)
+    lo, ld = ops.pinhole_rays(cam)
+    n = ray_o.shape[0]
+    la = torch.empty(LW * LH, device=ray_o.device)
+    lrgb = torch.empty(LW * LH, 3, device=ray_o.device)
+    lns = torch.empty(LW * LH, dtype=torch.int32, device=ray_o.device)
+    smap = torch.empty(LH, LW, device=ray_o.device)
+    out = torch.empty(n, 3, device=ray_o.device)
+
+    def once():
+        _lib.neuvv_render(tree.struct(), None, LW * LH, lo, ld, None, t_frame, LW, t_stop, lrgb, la, None, lns,
+                          stream)
+        _lib.neuvv_blur(LH, LW, la, 1.5, smap, stream)
+        _lib.neuvv_shade(light, smap, n, ray_o, ray_d, rgb, alpha, depth, out, stream)
+
+    once()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        once()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    lit = int((la > 0.5).sum())
+    log(f"lighting pass {ms:.3f} ms ({100 * ms / fwd_ms:.1f} % of the forward render); light map {lit} opaque px")
+    return {"light_map": f"{LW}x{LH}", "sigma_px": 1.5, "ms": round(ms, 4), "overhead_vs_fwd": round(ms / fwd_ms, 4),
+            "light_map_opaque_px": lit}
 
 
 def cpu_leg(sc, cams, t_frame, t_stop, rgb_gpu, g_rgb, grads, tree, budget_s):

@@ -327,6 +327,52 @@ int neuvv_eval_hh(int32_t K, int64_t n, const float* dirs, const float* gam, flo
 /* Thread-local message for the last non-OK return on this thread. */
 const char* neuvv_last_error(void);
 
+/* Point light for the shading call (Sec. 5.2 "Spotlight Lighting"). */
+typedef struct {
+    neuvv_camera camera;     /* the light's pinhole camera; its centre (c2w column 3) is the point light,
+                                its image is the shadow map's */
+    float ground_z;          /* the ground: world plane z = ground_z */
+    float ground_rgb[3];     /* lit ground colour */
+    float background_rgb[3]; /* colour of rays that miss the ground */
+    float shadow_strength;   /* k in [0, 1]: shadowed ground is scaled by 1 - k A */
+    float falloff_r0;        /* > 0: performer colour scaled by (r0 / max(r, r0))^2; 0: no falloff */
+} neuvv_light;
+
+/*
+ * neuvv_blur - the Gaussian low-pass of a rendered shadow map (Sec. 5.2: a
+ * low-resolution map is filtered to remove moire): taps proportional to
+ * exp(-i^2 / (2 sigma^2)) for |i| <= round(3 sigma), normalised to sum 1,
+ * applied along rows and columns, borders clamped to the edge.
+ * height, width   map size (row-major [height][width] float32, device).
+ * in, out         device maps; distinct buffers.
+ * sigma           in (0, 16] pixels.
+ * Errors: ARG, RANGE, HIP.
+ */
+int neuvv_blur(int32_t height, int32_t width, const float* in, float sigma, float* out, void* stream);
+
+/*
+ * neuvv_shade - spotlight shadow on the ground and distance falloff
+ * (Sec. 5.2 "Spotlight Lighting") for a rendered performer layer. Per viewer
+ * ray (o, d) with the layer's premultiplied rgb, alpha and depth (outputs of
+ * neuvv_render or neuvv_compose for the same rays):
+ *   - falloff: F = (r0 / max(r, r0))^2, r = |o + depth d / |d| - light|
+ *     (F = 1 when r0 = 0 or depth is infinite);
+ *   - ground: if d_z != 0 and t = (ground_z - o_z) / d_z > 0 the ray meets the
+ *     ground at q = o + t d; q is projected into the light camera and the
+ *     shadow map sampled bilinearly at that image position (pixel centres at
+ *     +1/2, clamped to the edge inside the image, 0 outside it or behind the
+ *     light): G = ground_rgb (1 - k A); otherwise G = background_rgb;
+ *   - out = G where the ground is met before the layer's depth (t |d| <
+ *     depth), else rgb F + (1 - alpha) G.
+ * shadow_map      device [camera.height][camera.width] float32 (the light's
+ *                 alpha map, low-passed), or NULL for no shadow.
+ * ray_o, ray_d    device [n][3]; rgb device [n][3]; alpha, depth device [n].
+ * out_rgb         device [n][3].
+ * Errors: ARG, RANGE, HIP.
+ */
+int neuvv_shade(const neuvv_light* light, const float* shadow_map, int64_t n, const float* ray_o, const float* ray_d,
+                const float* rgb, const float* alpha, const float* depth, float* out_rgb, void* stream);
+
 /* Library ABI version (major * 100 + minor). */
 int neuvv_version(void);
 

@@ -3,13 +3,14 @@
 (include/neuvv.h, libneuvv.so), with a thin Python binding.
 
 Modules: _lib (ctypes binding, same names as the C ABI), voctree (tree
-container), ops (functional calls), autograd (RenderFn, ComposeFn), build
-(hipcc build of libneuvv.so).
+container), ops (functional calls, including the shadow-map low-pass and the
+lighting pass), autograd (RenderFn, ComposeFn), build (hipcc build of
+libneuvv.so).
 """
 from . import _lib  # noqa: F401
-from ._lib import BF16, F16, F32, NeuvvError, make_camera, make_instance  # noqa: F401
+from ._lib import BF16, F16, F32, NeuvvError, make_camera, make_instance, make_light  # noqa: F401
 
-__all__ = ["F32", "F16", "BF16", "NeuvvError", "make_camera", "make_instance", "load"]
+__all__ = ["F32", "F16", "BF16", "NeuvvError", "make_camera", "make_instance", "make_light", "load"]
 
 
 def load():

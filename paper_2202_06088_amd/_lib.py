@@ -43,6 +43,12 @@ class neuvv_camera(ctypes.Structure):
                 ("c2w", ctypes.c_float * 12)]
 
 
+class neuvv_light(ctypes.Structure):
+    _fields_ = [("camera", neuvv_camera), ("ground_z", ctypes.c_float), ("ground_rgb", ctypes.c_float * 3),
+                ("background_rgb", ctypes.c_float * 3), ("shadow_strength", ctypes.c_float),
+                ("falloff_r0", ctypes.c_float)]
+
+
 _P = ctypes.c_void_p
 _I32 = ctypes.c_int32
 _I64 = ctypes.c_int64
@@ -58,6 +64,8 @@ _SIGNATURES = {
                               _I32, _F, _P, _P, _P, _P, _P, _P, _P, _P, _P],
     "neuvv_grad_row_elems": [_I32, _I32, _I32],
     "neuvv_pack_rows": [_I32, _I32, _I32, _I64, _P, _P, _P, _P],
+    "neuvv_blur": [_I32, _I32, _P, _F, _P, _P],
+    "neuvv_shade": [ctypes.POINTER(neuvv_light), _P, _I64, _P, _P, _P, _P, _P, _P, _P],
     "neuvv_compose": [_I32, _I64, _P, _P, _P, _P, _P, _P, _P],
     "neuvv_compose_backward": [_I32, _I64, _P, _P, _P, _P, _P, _P, _P, _P],
     "neuvv_pinhole_rays": [ctypes.POINTER(neuvv_camera), _I64, _P, _P, _P, _P],
@@ -233,3 +241,25 @@ def make_camera(width, height, fx, fy, cx, cy, c2w) -> neuvv_camera:
     for i in range(12):
         cam.c2w[i] = flat[i]
     return cam
+
+
+def make_light(camera: neuvv_camera, ground_z, ground_rgb, background_rgb, shadow_strength, falloff_r0) -> neuvv_light:
+    L = neuvv_light()
+    L.camera = camera
+    L.ground_z = float(ground_z)
+    for i in range(3):
+        L.ground_rgb[i] = float(ground_rgb[i])
+        L.background_rgb[i] = float(background_rgb[i])
+    L.shadow_strength = float(shadow_strength)
+    L.falloff_r0 = float(falloff_r0)
+    return L
+
+
+def neuvv_blur(height, width, img_in, sigma, img_out, stream=None):
+    _check("neuvv_blur", load().neuvv_blur(int(height), int(width), _ptr(img_in), float(sigma), _ptr(img_out),
+                                           _stream(stream)))
+
+
+def neuvv_shade(light: neuvv_light, shadow_map, n, ray_o, ray_d, rgb, alpha, depth, out_rgb, stream=None):
+    _check("neuvv_shade", load().neuvv_shade(ctypes.byref(light), _ptr(shadow_map), int(n), _ptr(ray_o), _ptr(ray_d),
+                                             _ptr(rgb), _ptr(alpha), _ptr(depth), _ptr(out_rgb), _stream(stream)))

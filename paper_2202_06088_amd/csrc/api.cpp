@@ -331,4 +331,58 @@ int neuvv_eval_hh(int32_t K, int64_t n, const float* dirs, const float* gam, flo
     NEUVV_GUARD_END
 }
 
+int neuvv_blur(int32_t height, int32_t width, const float* in, float sigma, float* out, void* stream) {
+    NEUVV_GUARD_BEGIN
+    if (height < 1 || width < 1 || (int64_t)height * width > INT32_MAX)
+        return fail(NEUVV_ERR_RANGE, "map size %d x %d", height, width);
+    if (!(sigma > 0.0f) || !(sigma <= 16.0f)) return fail(NEUVV_ERR_RANGE, "sigma must be in (0, 16]");
+    if (!in || !out) return fail(NEUVV_ERR_ARG, "in / out is NULL");
+    if (in == out) return fail(NEUVV_ERR_ARG, "the low-pass cannot run in place");
+    neuvv::BlurTaps taps;
+    taps.radius = (int)(3.0 * (double)sigma + 0.5);
+    double w[2 * neuvv::kMaxBlurRadius + 1], sum = 0.0;
+    for (int i = -taps.radius; i <= taps.radius; ++i) {
+        w[i + taps.radius] = std::exp(-(double)i * i / (2.0 * (double)sigma * sigma));
+        sum += w[i + taps.radius];
+    }
+    for (int i = 0; i <= 2 * taps.radius; ++i) taps.w[i] = (float)(w[i] / sum);
+    return hip_status(neuvv::launch_blur(height, width, in, taps, out, (hipStream_t)stream), "blur launch");
+    NEUVV_GUARD_END
+}
+
+int neuvv_shade(const neuvv_light* light, const float* shadow_map, int64_t n, const float* ray_o, const float* ray_d,
+                const float* rgb, const float* alpha, const float* depth, float* out_rgb, void* stream) {
+    NEUVV_GUARD_BEGIN
+    if (!light) return fail(NEUVV_ERR_ARG, "light is NULL");
+    const neuvv_camera& c = light->camera;
+    if (c.width < 1 || c.height < 1 || (int64_t)c.width * c.height > INT32_MAX)
+        return fail(NEUVV_ERR_RANGE, "light camera size must be positive");
+    if (!(c.fx != 0.0f) || !(c.fy != 0.0f) || !std::isfinite(c.fx) || !std::isfinite(c.fy))
+        return fail(NEUVV_ERR_RANGE, "light focal lengths must be finite and non-zero");
+    if (!(light->shadow_strength >= 0.0f && light->shadow_strength <= 1.0f))
+        return fail(NEUVV_ERR_RANGE, "shadow_strength must be in [0, 1]");
+    if (!(light->falloff_r0 >= 0.0f) || !std::isfinite(light->falloff_r0))
+        return fail(NEUVV_ERR_RANGE, "falloff_r0 must be >= 0");
+    if (!std::isfinite(light->ground_z)) return fail(NEUVV_ERR_RANGE, "ground_z must be finite");
+    if (n < 0) return fail(NEUVV_ERR_ARG, "n < 0");
+    if (n > 0 && (!ray_o || !ray_d || !rgb || !alpha || !depth || !out_rgb))
+        return fail(NEUVV_ERR_ARG, "NULL buffer");
+    neuvv::LightArgs L;
+    for (int r = 0; r < 3; ++r) {
+        for (int q = 0; q < 3; ++q) L.R[3 * r + q] = c.c2w[4 * r + q];
+        L.C[r] = c.c2w[4 * r + 3];
+        L.ground[r] = light->ground_rgb[r];
+        L.bg[r] = light->background_rgb[r];
+    }
+    L.fx = c.fx; L.fy = c.fy; L.cx = c.cx; L.cy = c.cy;
+    L.W = c.width; L.H = c.height;
+    L.ground_z = light->ground_z;
+    L.k = light->shadow_strength;
+    L.r0 = light->falloff_r0;
+    return hip_status(neuvv::launch_shade(L, shadow_map, n, ray_o, ray_d, rgb, alpha, depth, out_rgb,
+                                          (hipStream_t)stream),
+                      "shade launch");
+    NEUVV_GUARD_END
+}
+
 }  // extern "C"

@@ -55,6 +55,23 @@ hipError_t launch_pack_rows(int R, int dtype, int layout, int64_t n, const float
 hipError_t launch_pack(int K, int C, int dtype, int layout, int64_t n, const float* hh_in, const float* wsig_in,
                        const int64_t* slot_of_input, void* hh_out, void* wsig_out, hipStream_t stream);
 
+// Lighting (Sec. 5.2): Gaussian taps of the shadow-map low-pass, and the light.
+constexpr int kMaxBlurRadius = 48;
+struct BlurTaps {
+    int radius;
+    float w[2 * kMaxBlurRadius + 1];
+};
+struct LightArgs {
+    float R[9], C[3];            // light camera: row-major rotation (camera to world) and centre
+    float fx, fy, cx, cy;
+    int W, H;                    // shadow-map size
+    float ground_z, ground[3], bg[3];
+    float k, r0;                 // shadow strength, falloff reference distance (0: off)
+};
+hipError_t launch_blur(int H, int W, const float* in, const BlurTaps& taps, float* out, hipStream_t stream);
+hipError_t launch_shade(const LightArgs& L, const float* shadow_map, int64_t n, const float* ray_o, const float* ray_d,
+                        const float* rgb, const float* alpha, const float* depth, float* out, hipStream_t stream);
+
 // Device properties used to size persistent grids (cached per device).
 int device_cu_count();
 

@@ -84,3 +84,18 @@ def eval_hh(K: int, dirs: torch.Tensor, gam: torch.Tensor, stream=None):
     out = torch.empty(dirs.shape[0], K, device=dirs.device)
     _lib.neuvv_eval_hh(K, dirs.shape[0], dirs, gam, out, stream)
     return out
+
+
+def blur(img: torch.Tensor, sigma: float, stream=None):
+    """Gaussian low-pass of a [H, W] float32 map (the shadow map, Sec. 5.2)."""
+    H, W = img.shape
+    out = torch.empty_like(img)
+    _lib.neuvv_blur(H, W, img.contiguous(), sigma, out, stream)
+    return out
+
+
+def shade(light: _lib.neuvv_light, shadow_map: Optional[torch.Tensor], ray_o, ray_d, rgb, alpha, depth, stream=None):
+    """Viewer colour [n, 3] of a rendered layer over the lit ground (shadow and falloff, Sec. 5.2)."""
+    out = torch.empty_like(rgb)
+    _lib.neuvv_shade(light, shadow_map, ray_o.shape[0], ray_o, ray_d, rgb, alpha, depth, out, stream)
+    return out

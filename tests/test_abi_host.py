@@ -223,6 +223,21 @@ def test_argument_errors_without_launch(lib):
     assert lib.neuvv_pack_rows(31, 0, 1, 0, None, None, None, None) == 0
     assert _lib.neuvv_grad_row_elems(16, 8) == 64
     assert _lib.neuvv_grad_row_elems(14, 31, 31) == 128
+    # lighting calls: sizes, sigma, in-place, light parameters
+    assert lib.neuvv_blur(0, 4, 8, 1.0, 16, None) == -2
+    assert lib.neuvv_blur(4, 4, 8, 0.0, 16, None) == -2
+    assert lib.neuvv_blur(4, 4, 8, 17.0, 16, None) == -2
+    assert lib.neuvv_blur(4, 4, 8, 1.0, 8, None) == -1
+    assert lib.neuvv_blur(4, 4, None, 1.0, 16, None) == -1
+    cam = _lib.make_camera(8, 8, 4.0, 4.0, 4.0, 4.0, np.eye(3, 4, dtype=np.float32))
+    light = _lib.make_light(cam, 0.0, (1, 1, 1), (0, 0, 0), 1.5, 0.0)
+    assert lib.neuvv_shade(ctypes.byref(light), None, 0, None, None, None, None, None, None, None) == -2
+    light = _lib.make_light(cam, 0.0, (1, 1, 1), (0, 0, 0), 0.5, -1.0)
+    assert lib.neuvv_shade(ctypes.byref(light), None, 0, None, None, None, None, None, None, None) == -2
+    light = _lib.make_light(cam, 0.0, (1, 1, 1), (0, 0, 0), 0.5, 2.0)
+    assert lib.neuvv_shade(ctypes.byref(light), None, 5, None, None, None, None, None, None, None) == -1
+    assert lib.neuvv_shade(ctypes.byref(light), None, 0, None, None, None, None, None, None, None) == 0
+    assert lib.neuvv_shade(None, None, 0, None, None, None, None, None, None, None) == -1
     assert lib.neuvv_grad_row_elems(14, 31, 65) == -2
     a, b = _lib.neuvv_payload_words(16, 8, _lib.F32, 10)
     assert (a, b) == (12 * 10 * 4, 2 * 10 * 4)
