@@ -169,10 +169,11 @@ typedef struct { int64_t leaf; double delta, smid, x, sig, z[3], c[3], Tin, alph
 
 /* Time re-mapping (Eq. 13): tau = t + off; wrap into [0,T) or clamp into [0,T-1];
    i0 = floor(tau), f = tau - i0, i1 = min(i0+1, T-1); the last frame is held on [T-1,T). */
-static void time_lerp(double t, double off, int wrap, int T, int* i0, int* i1, double* f) {
+static void time_lerp(double t, double off, int wrap, int T, int* i0, int* i1, double* f, double* tau_out) {
     double tau = t + off;
     if (wrap) { tau = tau - T * floor(tau / T); if (tau >= T) tau -= T; if (tau < 0) tau = 0; }
     else { if (tau < 0) tau = 0; if (tau > T - 1) tau = T - 1; }
+    *tau_out = tau;
     int a = (int)floor(tau);
     if (a > T - 1) a = T - 1;
     if (a < 0) a = 0;
@@ -193,7 +194,10 @@ int oracle_render(int depth, int64_t n_leaves, const int32_t* leaf_ijk,
                   const double* g_rgb /* NULL or [n][3] */, const double* g_alpha /* NULL or [n] */,
                   double* rgb, double* alpha, double* depth_out, int32_t* nsamp, double* tfinal,
                   double* margin /* NULL or [n][2]: min sampled delta, min |T - t_stop|/t_stop */,
-                  double* grad_hh, double* grad_wsig, double* grad_basis, int n_threads) {
+                  double* grad_hh, double* grad_wsig, double* grad_basis,
+                  const double* edit /* NULL or [N][5]: target rgb, target density (< 0: keep), first frame */,
+                  int64_t* last_leaf /* NULL or [n]: leaf of the last sample of a ray that stopped, else -1 */,
+                  int n_threads) {
     if (depth < 1 || depth > 20 || K < 1 || K > 64 || C < 1 || C > 64 || T < 1) return -3;
     if (wgam && (Cg < 1 || Cg > 64 || !basis_g)) return -3;
     hashset hs;
@@ -208,6 +212,7 @@ int oracle_render(int depth, int64_t n_leaves, const int32_t* leaf_ijk,
         sc = inst[12]; toff = inst[13]; wrap = inst[14] != 0.0;
     }
     const int want_grad = g_rgb != NULL && grad_hh != NULL;
+    if (want_grad && edit) return -3;   /* edits are a render-time appearance change: no adjoint */
     int err = 0;
     if (n_threads < 1) n_threads = 1;
 
@@ -232,8 +237,8 @@ int oracle_render(int depth, int64_t n_leaves, const int32_t* leaf_ijk,
             double dlen = sqrt(dl[0] * dl[0] + dl[1] * dl[1] + dl[2] * dl[2]);
             double dwlen = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
             double t = ray_t ? (double)ray_t[r] : t_scalar;
-            int i0, i1; double f;
-            time_lerp(t, toff, wrap, T, &i0, &i1, &f);
+            int i0, i1; double f, tau;
+            time_lerp(t, toff, wrap, T, &i0, &i1, &f, &tau);
             double b[64], h[64], dirn[3] = {0.0, 0.0, 1.0};
             if (dlen > 0.0) for (int a = 0; a < 3; ++a) dirn[a] = dl[a] / dlen;
             for (int c = 0; c < C; ++c) b[c] = (1.0 - f) * basis[i0 * C + c] + f * basis[i1 * C + c];
@@ -260,6 +265,7 @@ int oracle_render(int depth, int64_t n_leaves, const int32_t* leaf_ijk,
             if (!(u_in < u_out)) miss = 1;
             int ns = 0;
             double Tr = 1.0, col[3] = {0, 0, 0}, wsum = 0.0, dsum = 0.0, optical = 0.0;
+            if (last_leaf) last_leaf[r] = -1;
             double min_delta = INFINITY, min_stop = INFINITY;
             if (!miss) {
                 int64_t cell[3];
@@ -310,6 +316,12 @@ int oracle_render(int depth, int64_t n_leaves, const int32_t* leaf_ijk,
                                 for (int k = 0; k < K; ++k) z += hh[(q * 3 + ch) * K + k] * hk[k];
                                 s->z[ch] = z; s->c[ch] = sigmoid(z);
                             }
+                            /* appearance edit (Sec. 5.2): from frame t_d on, the target colour and,
+                               when given (>= 0), the target density replace the leaf's own */
+                            if (edit && tau >= edit[q * 5 + 4]) {
+                                for (int ch = 0; ch < 3; ++ch) s->c[ch] = edit[q * 5 + ch];
+                                if (edit[q * 5 + 3] >= 0.0) s->sig = edit[q * 5 + 3];
+                            }
                             double e = exp(-s->sig * s->delta);
                             s->alpha = -expm1(-s->sig * s->delta);
                             s->Tin = Tr;
@@ -324,7 +336,10 @@ int oracle_render(int depth, int64_t n_leaves, const int32_t* leaf_ijk,
                             if (t_stop > 0.0) {
                                 double mrg = fabs(Tr - t_stop) / t_stop;
                                 if (mrg < min_stop) min_stop = mrg;
-                                if (Tr < t_stop) break;
+                                if (Tr < t_stop) {
+                                    if (last_leaf) last_leaf[r] = q;
+                                    break;
+                                }
                             }
                         }
                         u = un;
