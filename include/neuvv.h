@@ -102,6 +102,11 @@ typedef struct {
                              the paper's 104-value leaf */
     const void* wgam;     /* hyperangle weights, storage dtype and layout of wsig (Cg > 0) */
     const float* basis_g; /* [T][Cg] hyperangle basis (Cg > 0) */
+    const float* edit;    /* NULL, or appearance edits (Sec. 5.2): [n_leaves][8] float32 rows in slot
+                             order, 16-byte aligned: target r, g, b; target density (< 0: keep the
+                             leaf's own); first frame t_d (the edit is active at local times
+                             tau >= t_d, +inf: never); a word used by neuvv_paint; 2 unused. K = 16,
+                             C = 8 form only; neuvv_render_backward rejects trees with edits */
 } neuvv_tree;
 
 /* Placement and re-timing of one tree instance (Eq. 13). A world point x is
@@ -326,6 +331,34 @@ int neuvv_eval_hh(int32_t K, int64_t n, const float* dirs, const float* gam, flo
 
 /* Thread-local message for the last non-OK return on this thread. */
 const char* neuvv_last_error(void);
+
+/*
+ * neuvv_find_terminal_leaves - for appearance editing by painting from a view
+ * (Sec. 5.2 "Appearance editing"): traces each ray as neuvv_render does and
+ * returns the leaf slot of the first sample after which the accumulated alpha
+ * 1 - T exceeds alpha_threshold (0.99 in the paper), or -1 when it never
+ * does. Equivalent to neuvv_render with t_stop = 1 - alpha_threshold,
+ * reporting the leaf of the sample that stopped the ray.
+ * alpha_threshold in (0, 1); last_leaf device [n] int32. Other arguments as
+ * neuvv_render. K = 16, C = 8 form only.
+ * Errors: ARG, RANGE, UNSUPPORTED, HIP.
+ */
+int neuvv_find_terminal_leaves(const neuvv_tree* tree, const neuvv_instance* inst, int64_t n_rays, const float* ray_o,
+                               const float* ray_d, const float* ray_t, float t_scalar, int32_t image_width,
+                               float alpha_threshold, int32_t* last_leaf, void* stream);
+
+/*
+ * neuvv_paint - writes appearance edits: every ray r with last_leaf[r] >= 0
+ * (from neuvv_find_terminal_leaves) claims that leaf; the lowest ray index
+ * wins, and the leaf's edit row becomes (colours[r], sigma_d, t_d). Rows of
+ * leaves no ray ends in are left as they are (initialise the table with
+ * t_d = +inf). last_leaf device [n_rays] int32 (entries outside
+ * [0, n_leaves) are ignored); colours device [n_rays][3]; edit device
+ * [n_leaves][8] (layout in neuvv_tree).
+ * Errors: ARG, RANGE, HIP.
+ */
+int neuvv_paint(int64_t n_rays, const int32_t* last_leaf, const float* colours, float sigma_d, float t_d,
+                int64_t n_leaves, float* edit, void* stream);
 
 /* Point light for the shading call (Sec. 5.2 "Spotlight Lighting"). */
 typedef struct {

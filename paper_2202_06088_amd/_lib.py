@@ -29,7 +29,7 @@ class neuvv_tree(ctypes.Structure):
                 ("nodes", ctypes.c_void_p), ("hh", ctypes.c_void_p), ("wsig", ctypes.c_void_p),
                 ("T", ctypes.c_int32), ("box", ctypes.c_int32 * 6), ("layout", ctypes.c_int32),
                 ("basis", ctypes.c_void_p), ("gamma", ctypes.c_void_p), ("Cg", ctypes.c_int32),
-                ("wgam", ctypes.c_void_p), ("basis_g", ctypes.c_void_p)]
+                ("wgam", ctypes.c_void_p), ("basis_g", ctypes.c_void_p), ("edit", ctypes.c_void_p)]
 
 
 class neuvv_instance(ctypes.Structure):
@@ -65,6 +65,9 @@ _SIGNATURES = {
     "neuvv_grad_row_elems": [_I32, _I32, _I32],
     "neuvv_pack_rows": [_I32, _I32, _I32, _I64, _P, _P, _P, _P],
     "neuvv_blur": [_I32, _I32, _P, _F, _P, _P],
+    "neuvv_find_terminal_leaves": [ctypes.POINTER(neuvv_tree), ctypes.POINTER(neuvv_instance), _I64, _P, _P, _P, _F,
+                                   _I32, _F, _P, _P],
+    "neuvv_paint": [_I64, _P, _P, _F, _F, _I64, _P, _P],
     "neuvv_shade": [ctypes.POINTER(neuvv_light), _P, _I64, _P, _P, _P, _P, _P, _P, _P],
     "neuvv_compose": [_I32, _I64, _P, _P, _P, _P, _P, _P, _P],
     "neuvv_compose_backward": [_I32, _I64, _P, _P, _P, _P, _P, _P, _P, _P],
@@ -263,3 +266,15 @@ def neuvv_blur(height, width, img_in, sigma, img_out, stream=None):
 def neuvv_shade(light: neuvv_light, shadow_map, n, ray_o, ray_d, rgb, alpha, depth, out_rgb, stream=None):
     _check("neuvv_shade", load().neuvv_shade(ctypes.byref(light), _ptr(shadow_map), int(n), _ptr(ray_o), _ptr(ray_d),
                                              _ptr(rgb), _ptr(alpha), _ptr(depth), _ptr(out_rgb), _stream(stream)))
+
+
+def neuvv_find_terminal_leaves(tree: neuvv_tree, inst, n_rays, ray_o, ray_d, ray_t, t_scalar, image_width,
+                               alpha_threshold, last_leaf, stream=None):
+    _check("neuvv_find_terminal_leaves", load().neuvv_find_terminal_leaves(
+        ctypes.byref(tree), _inst_ptr(inst), int(n_rays), _ptr(ray_o), _ptr(ray_d), _ptr(ray_t), float(t_scalar),
+        int(image_width), float(alpha_threshold), _ptr(last_leaf), _stream(stream)))
+
+
+def neuvv_paint(n_rays, last_leaf, colours, sigma_d, t_d, n_leaves, edit, stream=None):
+    _check("neuvv_paint", load().neuvv_paint(int(n_rays), _ptr(last_leaf), _ptr(colours), float(sigma_d), float(t_d),
+                                             int(n_leaves), _ptr(edit), _stream(stream)))

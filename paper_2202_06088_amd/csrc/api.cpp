@@ -72,6 +72,10 @@ int check_tree(const neuvv_tree* t) {
                 return fail(NEUVV_ERR_RANGE, "tree box must satisfy 0 <= lo < hi <= 2^depth on every axis");
     if (t->n_leaves > 0 && (!t->hh || !t->wsig || (t->Cg > 0 && !t->wgam)))
         return fail(NEUVV_ERR_ARG, "tree payload pointer is NULL");
+    if (t->edit && reinterpret_cast<uintptr_t>(t->edit) % 16 != 0)
+        return fail(NEUVV_ERR_ARG, "tree edit rows must be 16-byte aligned");
+    if (t->edit && t->Cg > 0)
+        return fail(NEUVV_ERR_UNSUPPORTED, "appearance edits are compiled for the K=16 C=8 form only");
     return NEUVV_OK;
 }
 
@@ -137,6 +141,7 @@ neuvv::TreeArgs tree_args(const neuvv_tree* t) {
     a.Cg = t->Cg;
     a.wgam = t->wgam;
     a.basis_g = t->basis_g;
+    a.edit = reinterpret_cast<const float4*>(t->edit);
     a.n_nodes = t->n_nodes;
     a.n_leaves = t->n_leaves;
     a.depth = t->depth;
@@ -240,7 +245,7 @@ int neuvv_render(const neuvv_tree* tree, const neuvv_instance* inst, int64_t n_r
     if ((rc = make_rays(n_rays, ray_o, ray_d, ray_t, t_scalar, image_width, ra))) return rc;
     if (!(t_stop >= 0.0f) || !std::isfinite(t_stop)) return fail(NEUVV_ERR_RANGE, "t_stop must be >= 0");
     if (n_rays > 0 && (!rgb || !alpha || !nsamp)) return fail(NEUVV_ERR_ARG, "rgb / alpha / nsamp is NULL");
-    neuvv::RenderOut out{rgb, alpha, depth, nsamp};
+    neuvv::RenderOut out{rgb, alpha, depth, nsamp, nullptr};
     const hipError_t e = tree->Cg > 0
                              ? neuvv::launch_render_pp_fwd(tree->dtype, tree_args(tree), in, ra, t_stop, out,
                                                            (hipStream_t)stream)
@@ -266,6 +271,7 @@ int neuvv_render_backward(const neuvv_tree* tree, const neuvv_instance* inst, in
     if (n_rays > 0 && (!rgb || !alpha || !nsamp || !grad_rgb))
         return fail(NEUVV_ERR_ARG, "rgb / alpha / nsamp / grad_rgb is NULL");
     if (tree->n_leaves > 0 && !grad_leaf) return fail(NEUVV_ERR_ARG, "grad_leaf is NULL");
+    if (tree->edit) return fail(NEUVV_ERR_UNSUPPORTED, "no adjoint through appearance edits");
     neuvv::BackwardIO io{rgb, alpha, nsamp, grad_rgb, grad_alpha, grad_leaf, grad_basis,
                          tree->Cg > 0 ? grad_basis_g : nullptr};
     const hipError_t e = tree->Cg > 0
@@ -328,6 +334,40 @@ int neuvv_eval_hh(int32_t K, int64_t n, const float* dirs, const float* gam, flo
     if (n < 0) return fail(NEUVV_ERR_ARG, "n < 0");
     if (n > 0 && (!dirs || !gam || !out)) return fail(NEUVV_ERR_ARG, "NULL buffer");
     return hip_status(neuvv::launch_eval_hh(K, n, dirs, gam, out, (hipStream_t)stream), "eval_hh launch");
+    NEUVV_GUARD_END
+}
+
+int neuvv_find_terminal_leaves(const neuvv_tree* tree, const neuvv_instance* inst, int64_t n_rays, const float* ray_o,
+                               const float* ray_d, const float* ray_t, float t_scalar, int32_t image_width,
+                               float alpha_threshold, int32_t* last_leaf, void* stream) {
+    NEUVV_GUARD_BEGIN
+    int rc = check_tree(tree);
+    if (rc) return rc;
+    if (tree->Cg > 0) return fail(NEUVV_ERR_UNSUPPORTED, "terminal leaves are compiled for the K=16 C=8 form only");
+    neuvv::InstArgs in;
+    if ((rc = make_inst(inst, in))) return rc;
+    neuvv::RayArgs ra;
+    if ((rc = make_rays(n_rays, ray_o, ray_d, ray_t, t_scalar, image_width, ra))) return rc;
+    if (!(alpha_threshold > 0.0f && alpha_threshold < 1.0f))
+        return fail(NEUVV_ERR_RANGE, "alpha_threshold must be in (0, 1)");
+    if (n_rays > 0 && !last_leaf) return fail(NEUVV_ERR_ARG, "last_leaf is NULL");
+    neuvv::RenderOut out{nullptr, nullptr, nullptr, nullptr, last_leaf};
+    return hip_status(neuvv::launch_render_fwd(tree->K, tree->C, tree->dtype, tree_args(tree), in, ra,
+                                               1.0f - alpha_threshold, out, (hipStream_t)stream),
+                      "terminal leaves launch");
+    NEUVV_GUARD_END
+}
+
+int neuvv_paint(int64_t n_rays, const int32_t* last_leaf, const float* colours, float sigma_d, float t_d,
+                int64_t n_leaves, float* edit, void* stream) {
+    NEUVV_GUARD_BEGIN
+    if (n_rays < 0 || n_rays > INT32_MAX) return fail(NEUVV_ERR_RANGE, "n_rays outside [0, 2^31)");
+    if (n_leaves < 0) return fail(NEUVV_ERR_ARG, "n_leaves < 0");
+    if (n_rays > 0 && (!last_leaf || !colours || !edit)) return fail(NEUVV_ERR_ARG, "NULL buffer");
+    if (std::isnan(sigma_d) || std::isnan(t_d)) return fail(NEUVV_ERR_RANGE, "sigma_d and t_d must not be NaN");
+    return hip_status(neuvv::launch_paint(n_rays, last_leaf, colours, sigma_d, t_d, n_leaves, edit,
+                                          (hipStream_t)stream),
+                      "paint launch");
     NEUVV_GUARD_END
 }
 

@@ -11,10 +11,11 @@
 namespace neuvv {
 
 struct RenderOut {
-    float* rgb;
+    float* rgb;          // each output may be nullptr (not written)
     float* alpha;
     float* depth;
     int32_t* nsamp;
+    int32_t* last_leaf;  // slot of the last sample of a ray that stopped early, else -1
 };
 
 struct BackwardIO {
@@ -71,6 +72,10 @@ struct LightArgs {
 hipError_t launch_blur(int H, int W, const float* in, const BlurTaps& taps, float* out, hipStream_t stream);
 hipError_t launch_shade(const LightArgs& L, const float* shadow_map, int64_t n, const float* ray_o, const float* ray_d,
                         const float* rgb, const float* alpha, const float* depth, float* out, hipStream_t stream);
+
+// Appearance edits: rays ending in a leaf write its edit row (lowest ray index wins).
+hipError_t launch_paint(int64_t n, const int32_t* last_leaf, const float* colours, float sigma_d, float t_d,
+                        int64_t n_leaves, float* edit, hipStream_t stream);
 
 // Device properties used to size persistent grids (cached per device).
 int device_cu_count();

@@ -349,3 +349,58 @@ hipError_t launch_pack(int K, int C, int dtype, int layout, int64_t n, const flo
 }
 
 }  // namespace neuvv
+
+namespace neuvv {
+
+// ----------------------------------------------------------------------------
+// appearance edits (Sec. 5.2 "Appearance editing"): every ray that ended in a
+// leaf claims it, the lowest ray index wins, and the winner writes its target
+// colour, density and first frame into the leaf's edit row {r, g, b, sigma_d,
+// t_d, owner, 0, 0}. Three passes: reset the owners of the leaves involved,
+// claim with atomicMin, write.
+
+__global__ __launch_bounds__(kEwBlock) void paint_reset_kernel(int64_t n, const int32_t* __restrict__ last_leaf,
+                                                               int64_t n_leaves, int32_t* __restrict__ words) {
+    for (int64_t r = blockIdx.x * (int64_t)kEwBlock + threadIdx.x; r < n; r += (int64_t)gridDim.x * kEwBlock) {
+        const int32_t L = last_leaf[r];
+        if (L >= 0 && L < n_leaves) words[8 * (int64_t)L + 5] = 0x7fffffff;
+    }
+}
+
+__global__ __launch_bounds__(kEwBlock) void paint_claim_kernel(int64_t n, const int32_t* __restrict__ last_leaf,
+                                                               int64_t n_leaves, int32_t* __restrict__ words) {
+    for (int64_t r = blockIdx.x * (int64_t)kEwBlock + threadIdx.x; r < n; r += (int64_t)gridDim.x * kEwBlock) {
+        const int32_t L = last_leaf[r];
+        if (L >= 0 && L < n_leaves) atomicMin(words + 8 * (int64_t)L + 5, (int32_t)r);
+    }
+}
+
+__global__ __launch_bounds__(kEwBlock) void paint_write_kernel(int64_t n, const int32_t* __restrict__ last_leaf,
+                                                               int64_t n_leaves, const float* __restrict__ colours,
+                                                               float sigma_d, float t_d, float* __restrict__ edit) {
+    int32_t* words = reinterpret_cast<int32_t*>(edit);
+    for (int64_t r = blockIdx.x * (int64_t)kEwBlock + threadIdx.x; r < n; r += (int64_t)gridDim.x * kEwBlock) {
+        const int32_t L = last_leaf[r];
+        if (L < 0 || L >= n_leaves || words[8 * (int64_t)L + 5] != (int32_t)r) continue;
+        float* row = edit + 8 * (int64_t)L;
+        row[0] = colours[3 * r];
+        row[1] = colours[3 * r + 1];
+        row[2] = colours[3 * r + 2];
+        row[3] = sigma_d;
+        row[4] = t_d;
+    }
+}
+
+hipError_t launch_paint(int64_t n, const int32_t* last_leaf, const float* colours, float sigma_d, float t_d,
+                        int64_t n_leaves, float* edit, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    int32_t* words = reinterpret_cast<int32_t*>(edit);
+    const int g = ew_grid(n);
+    hipLaunchKernelGGL(paint_reset_kernel, dim3(g), dim3(kEwBlock), 0, stream, n, last_leaf, n_leaves, words);
+    hipLaunchKernelGGL(paint_claim_kernel, dim3(g), dim3(kEwBlock), 0, stream, n, last_leaf, n_leaves, words);
+    hipLaunchKernelGGL(paint_write_kernel, dim3(g), dim3(kEwBlock), 0, stream, n, last_leaf, n_leaves, colours,
+                       sigma_d, t_d, edit);
+    return hipGetLastError();
+}
+
+}  // namespace neuvv

@@ -208,6 +208,7 @@ struct TreeArgs {
     int32_t Cg;          // per-point hyperangle weights per leaf (0: the global table gamma)
     const void* wgam;    // [N] rows of Cg weights, storage dtype and layout of wsig
     const float* basis_g;   // [T][Cg] hyperangle basis
+    const float4* edit;     // nullptr, or [N][2] rows {r, g, b, sigma_d}, {t_d, owner, 0, 0} (appearance edits)
 };
 
 struct InstArgs {
@@ -255,6 +256,7 @@ struct RaySetup {
     float dir[3];      // unit local direction
     int i0, i1;
     float f;
+    float tau;         // local time after re-timing (appearance edits are gated on it)
     bool hit;
 };
 
@@ -262,7 +264,7 @@ struct RaySetup {
 // [0, T-1]; frames i0 = floor(tau), i1 = min(i0 + 1, T - 1), weight f = tau - i0
 // (0 on the held last frame). tau is kept compensated so f is accurate.
 __device__ __forceinline__ void time_setup(const TreeArgs& tr, const InstArgs& in, float t, int& i0_out,
-                                           int& i1_out, float& f_out) {
+                                           int& i1_out, float& f_out, float* tau_out = nullptr) {
     const int T = tr.T;
     const float Tf = (float)T;
     df tau = df_two_sum(t, in.time_offset);
@@ -283,6 +285,7 @@ __device__ __forceinline__ void time_setup(const TreeArgs& tr, const InstArgs& i
     i0_out = i0;
     i1_out = i0 + 1 < T ? i0 + 1 : T - 1;
     f_out = f;
+    if (tau_out) *tau_out = df_f(tau);
 }
 
 // IDENT: the instance is the identity (known at compile time), so the local
@@ -390,7 +393,7 @@ __device__ __forceinline__ void ray_setup(const TreeArgs& tr, const InstArgs& in
     rs.u_in = u_in;
     rs.u_out = u_out;
     rs.hit = hit;
-    time_setup(tr, in, t, rs.i0, rs.i1, rs.f);
+    time_setup(tr, in, t, rs.i0, rs.i1, rs.f, &rs.tau);
 }
 
 // ----------------------------------------------------------------------------

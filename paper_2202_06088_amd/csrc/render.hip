@@ -52,9 +52,12 @@ __device__ __forceinline__ void ray_basis(const TreeArgs& tr, const RaySetup& rs
 // forward
 
 
-template <int K, int C, int DT, bool IDENT>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) void render_fwd_kernel(TreeArgs tr, InstArgs in, RayArgs ra, float t_stop,
-                                                            RenderOut out) {
+// EDIT: the tree carries appearance edits (Sec. 5.2): from its first frame on,
+// an edited leaf's target colour (and target density, when >= 0) replace the
+// evaluated ones.
+template <int K, int C, int DT, bool IDENT, bool EDIT>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) void render_fwd_kernel(
+    TreeArgs tr, InstArgs in, RayArgs ra, float t_stop, RenderOut out) {
     __shared__ int4 s_nodes[kLdsNodesFwd];
     __shared__ int s_path[kMaxLevels * kBlock];
     const int n_lds = stage_top_nodes<kLdsNodesFwd>(tr, s_nodes);
@@ -68,7 +71,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
     Walk w;
     float h[K], bv[C];
     float Tr = 1.0f, acc0 = 0.0f, acc1 = 0.0f, acc2 = 0.0f, wsum = 0.0f, dsum = 0.0f;
-    int ns = 0;
+    int ns = 0, last = -1;
 
     for (;;) {
         const uint64_t idle = __ballot(!alive);
@@ -121,7 +124,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
         if (alive) {
             float delta, umid;
             const int leaf = walk_next(tr, s_nodes, n_lds, path, kBlock, rs, w, delta, umid);
-            bool finish = leaf < 0;
+            bool finish = leaf < 0, stopped = false;
             if (!finish) {
                 float wv[3 * K], sv[C];
                 load_leaf<DT, 3 * K>(tr.hh, tr.n_leaves, leaf, tr.layout, wv);
@@ -136,24 +139,35 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
                     z1 = fmaf(wv[K + k], h[k], z1);
                     z2 = fmaf(wv[2 * K + k], h[k], z2);
                 }
-                const float sig = softplus_f(x);
+                float sig = softplus_f(x);
+                float c0 = sigmoid_f(z0), c1 = sigmoid_f(z1), c2 = sigmoid_f(z2);
+                if constexpr (EDIT) {
+                    const float4 e0 = tr.edit[2 * (int64_t)leaf], e1 = tr.edit[2 * (int64_t)leaf + 1];
+                    if (rs.tau >= e1.x) {
+                        c0 = e0.x; c1 = e0.y; c2 = e0.z;
+                        if (e0.w >= 0.0f) sig = e0.w;
+                    }
+                }
                 const float od = sig * delta;
                 const float a = -expm1f(-od);
                 const float wt = Tr * a;
-                acc0 = fmaf(wt, sigmoid_f(z0), acc0);
-                acc1 = fmaf(wt, sigmoid_f(z1), acc1);
-                acc2 = fmaf(wt, sigmoid_f(z2), acc2);
+                acc0 = fmaf(wt, c0, acc0);
+                acc1 = fmaf(wt, c1, acc1);
+                acc2 = fmaf(wt, c2, acc2);
                 wsum += wt;
                 dsum = fmaf(wt, umid * rs.len_world, dsum);
                 Tr *= expf(-od);
                 ++ns;
+                last = leaf;
                 finish = t_stop > 0.0f && Tr < t_stop;
+                stopped = finish;
             }
             if (finish) {
-                out.rgb[3 * ray] = acc0; out.rgb[3 * ray + 1] = acc1; out.rgb[3 * ray + 2] = acc2;
-                out.alpha[ray] = 1.0f - Tr;
+                if (out.rgb) { out.rgb[3 * ray] = acc0; out.rgb[3 * ray + 1] = acc1; out.rgb[3 * ray + 2] = acc2; }
+                if (out.alpha) out.alpha[ray] = 1.0f - Tr;
                 if (out.depth) out.depth[ray] = wsum > 0.0f ? dsum / wsum : INFINITY;
-                out.nsamp[ray] = ns;
+                if (out.nsamp) out.nsamp[ray] = ns;
+                if (out.last_leaf) out.last_leaf[ray] = stopped ? last : -1;
                 alive = false;
             }
         }
@@ -390,17 +404,23 @@ int device_cu_count() {
     return cached[dev];
 }
 
-template <int K, int C, int DT>
-static hipError_t fwd_t(const TreeArgs& tr, const InstArgs& in, const RayArgs& ra, float t_stop, const RenderOut& o,
+template <int K, int C, int DT, bool EDIT>
+static hipError_t fwd_e(const TreeArgs& tr, const InstArgs& in, const RayArgs& ra, float t_stop, const RenderOut& o,
                         hipStream_t st) {
     if (in.identity) {
-        auto kern = render_fwd_kernel<K, C, DT, true>;
+        auto kern = render_fwd_kernel<K, C, DT, true, EDIT>;
         hipLaunchKernelGGL(kern, dim3(grid_for(kern, ra)), dim3(kBlock), 0, st, tr, in, ra, t_stop, o);
     } else {
-        auto kern = render_fwd_kernel<K, C, DT, false>;
+        auto kern = render_fwd_kernel<K, C, DT, false, EDIT>;
         hipLaunchKernelGGL(kern, dim3(grid_for(kern, ra)), dim3(kBlock), 0, st, tr, in, ra, t_stop, o);
     }
     return hipGetLastError();
+}
+
+template <int K, int C, int DT>
+static hipError_t fwd_t(const TreeArgs& tr, const InstArgs& in, const RayArgs& ra, float t_stop, const RenderOut& o,
+                        hipStream_t st) {
+    return tr.edit ? fwd_e<K, C, DT, true>(tr, in, ra, t_stop, o, st) : fwd_e<K, C, DT, false>(tr, in, ra, t_stop, o, st);
 }
 
 template <int K, int C, int DT>

@@ -149,12 +149,15 @@ __device__ __forceinline__ int stage_top_nodes(const TreeArgs& tr, int4* s_nodes
 }
 
 __device__ __forceinline__ void write_miss(const RenderOut& out, int64_t ray) {
-    out.rgb[3 * ray] = 0.0f;
-    out.rgb[3 * ray + 1] = 0.0f;
-    out.rgb[3 * ray + 2] = 0.0f;
-    out.alpha[ray] = 0.0f;
+    if (out.rgb) {
+        out.rgb[3 * ray] = 0.0f;
+        out.rgb[3 * ray + 1] = 0.0f;
+        out.rgb[3 * ray + 2] = 0.0f;
+    }
+    if (out.alpha) out.alpha[ray] = 0.0f;
     if (out.depth) out.depth[ray] = INFINITY;
-    out.nsamp[ray] = 0;
+    if (out.nsamp) out.nsamp[ray] = 0;
+    if (out.last_leaf) out.last_leaf[ray] = -1;
 }
 
 __device__ __forceinline__ float readlane_f(float v, int lane) {

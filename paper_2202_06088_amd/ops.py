@@ -99,3 +99,25 @@ def shade(light: _lib.neuvv_light, shadow_map: Optional[torch.Tensor], ray_o, ra
     out = torch.empty_like(rgb)
     _lib.neuvv_shade(light, shadow_map, ray_o.shape[0], ray_o, ray_d, rgb, alpha, depth, out, stream)
     return out
+
+
+def terminal_leaves(tree: VOctree, ray_o, ray_d, t=0.0, inst=None, alpha_threshold: float = 0.99,
+                    image_width: int = 0, stream=None):
+    """Leaf slot where each ray's accumulated alpha first exceeds the threshold, or -1 (Sec. 5.2)."""
+    n = ray_o.shape[0]
+    out = torch.empty(n, dtype=torch.int32, device=_dev(ray_o))
+    ray_t = t if isinstance(t, torch.Tensor) else None
+    t_scalar = 0.0 if ray_t is not None else float(t)
+    _lib.neuvv_find_terminal_leaves(tree.struct(), inst, n, ray_o, ray_d, ray_t, t_scalar, image_width,
+                                    alpha_threshold, out, stream)
+    return out
+
+
+def paint(tree: VOctree, last_leaf: torch.Tensor, colours: torch.Tensor, sigma_d: float = -1.0, t_d: float = 0.0,
+          stream=None):
+    """Writes the target colours into the tree's edit table at the rays' terminal leaves."""
+    if tree.edit is None:
+        tree.enable_edits()
+    _lib.neuvv_paint(last_leaf.shape[0], last_leaf, colours.contiguous(), sigma_d, t_d, tree.n_leaves, tree.edit,
+                     stream)
+    return tree.edit

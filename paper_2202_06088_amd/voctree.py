@@ -45,6 +45,7 @@ class VOctree:
     Cg: int = 0                  # per-point hyperangle weights per leaf (Eq. 6); 0 = global gamma table
     wgam: Optional[torch.Tensor] = None     # packed hyperangle weights (storage dtype)
     basis_g: Optional[torch.Tensor] = None  # [T, Cg] float32 hyperangle basis
+    edit: Optional[torch.Tensor] = None     # [N, 8] float32 appearance-edit rows (slot order), or None
 
     @classmethod
     def build(cls, depth: int, leaf_ijk, hh, wsig, basis, gamma, dtype: int = _lib.F32,
@@ -114,7 +115,21 @@ class VOctree:
         s.Cg = self.Cg
         if self.Cg > 0:
             s.wgam, s.basis_g = self.wgam.data_ptr(), self.basis_g.data_ptr()
+        s.edit = None if self.edit is None else self.edit.data_ptr()
         return s
+
+    def enable_edits(self):
+        """Attaches an appearance-edit table (Sec. 5.2) with every edit inactive (first frame
+        +inf, target density -1 = keep); neuvv_paint fills it."""
+        e = torch.zeros(self.n_leaves, 8, dtype=torch.float32, device=self.nodes.device)
+        e[:, 3] = -1.0
+        e[:, 4] = float("inf")
+        self.edit = e
+        return e
+
+    def edits_per_input(self) -> torch.Tensor:
+        """The edit table as [N, 5] (rgb, sigma_d, t_d) per input leaf."""
+        return self.edit[self.slot_of_input][:, :5]
 
     @property
     def grad_row(self) -> int:

@@ -209,6 +209,21 @@ def test_argument_errors_without_launch(lib):
     t.Cg = 0
     assert lib.neuvv_render(ctypes.byref(t), None, 0, None, None, None, 0.0, 0, 0.0, None, None, None, None,
                             None) == -5
+    # appearance edits: K=16 C=8 form only, 16-byte aligned rows; terminal-leaf and paint arguments
+    t.K, t.C, t.Cg, t.edit = 14, 31, 31, 64
+    assert lib.neuvv_render(ctypes.byref(t), None, 0, None, None, None, 0.0, 0, 0.0, None, None, None, None,
+                            None) == -5
+    t.K, t.C, t.Cg, t.gamma, t.edit = 16, 8, 0, 8, 72
+    assert lib.neuvv_render(ctypes.byref(t), None, 0, None, None, None, 0.0, 0, 0.0, None, None, None, None,
+                            None) == -1
+    t.edit = None
+    assert lib.neuvv_find_terminal_leaves(ctypes.byref(t), None, 0, None, None, None, 0.0, 0, 1.0, None,
+                                          None) == -2
+    assert lib.neuvv_find_terminal_leaves(ctypes.byref(t), None, 0, None, None, None, 0.0, 0, 0.99, None,
+                                          None) == 0
+    assert lib.neuvv_paint(3, None, None, 1.0, 0.0, 10, None, None) == -1
+    assert lib.neuvv_paint(-1, None, None, 1.0, 0.0, 10, None, None) == -2
+    assert lib.neuvv_paint(0, None, None, 1.0, 0.0, 10, None, None) == 0
     assert lib.neuvv_compose(0, 10, None, None, None, None, None, None, None) == -2
     assert lib.neuvv_compose(17, 10, None, None, None, None, None, None, None) == -2
     assert lib.neuvv_compose(2, 10, None, None, None, None, None, None, None) == -1
