@@ -76,6 +76,9 @@ def main():
                          "paper's 104-value leaf, K=14, C=31, Cg=31 with the per-point hyperangle")
     ap.add_argument("--lighting", action="store_true",
                     help="also time the spotlight shadow + falloff pass (light map, low-pass, shading)")
+    ap.add_argument("--editing", action="store_true",
+                    help="also time appearance editing: terminal leaves + paint from one camera, and the forward "
+                         "render with the edits active")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -195,9 +198,59 @@ def main():
     if args.lighting:
         result["lighting"] = lighting_leg(sc, tree, ray_o, ray_d, rgb, alpha, depth, t_frame, t_stop, W, fwd_ms,
                                           stream, args.steps)
+    if args.editing:
+        if tree.Cg > 0:
+            log("appearance edits are compiled for the global form only; --editing skipped")
+        else:
+            result["editing"] = editing_leg(tree, ray_o, ray_d, rgb, alpha, depth, nsamp, t_frame, t_stop, W, H,
+                                            fwd_ms, stream, args.steps)
     if not args.no_cpu_baseline:
         result.update(cpu_leg(sc, cams, t_frame, t_stop, rgb, g_rgb, grads, tree, args.cpu_seconds))
     print(json.dumps(result), flush=True)
+
+
+def editing_leg(tree, ray_o, ray_d, rgb, alpha, depth, nsamp, t_frame, t_stop, W, H, fwd_ms, stream, steps):
+    """Appearance editing (Sec. 5.2) on the ring: terminal leaves (alpha beyond 0.99) and paint
+    of a seeded pattern from the first camera, then the ring's forward render with the edit
+    table attached and active; HIP events on the launch stream."""
+    import torch
+    from paper_2202_06088_amd import _lib
+    n_cam = W * H
+    n = ray_o.shape[0]
+    last = torch.empty(n_cam, dtype=torch.int32, device=ray_o.device)
+    gen = torch.Generator(device=ray_o.device)
+    gen.manual_seed(2004)
+    colours = torch.rand(n_cam, 3, device=ray_o.device, generator=gen)
+    tree.enable_edits()
+
+    def paint_once():
+        _lib.neuvv_find_terminal_leaves(tree.struct(), None, n_cam, ray_o[:n_cam], ray_d[:n_cam], None, t_frame, W,
+                                        0.99, last, stream)
+        _lib.neuvv_paint(n_cam, last, colours, -1.0, 0.0, tree.n_leaves, tree.edit, stream)
+
+    def render_once():
+        _lib.neuvv_render(tree.struct(), None, n, ray_o, ray_d, None, t_frame, W, t_stop, rgb, alpha, depth, nsamp,
+                          stream)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    paint_ms = timed(paint_once)
+    painted = int((tree.edit[:, 4] == 0.0).sum())
+    edited_ms = timed(render_once)
+    tree.edit = None
+    log(f"editing: paint one camera {paint_ms:.3f} ms ({painted} leaves); edited ring forward {edited_ms:.3f} ms "
+        f"vs {fwd_ms:.3f} ms plain")
+    return {"paint_one_camera_ms": round(paint_ms, 4), "painted_leaves": painted,
+            "edited_forward_ms": round(edited_ms, 4), "overhead_vs_fwd": round(edited_ms / fwd_ms - 1.0, 4)}
 
 
 def lighting_leg(sc, tree, ray_o, ray_d, rgb, alpha, depth, t_frame, t_stop, W, fwd_ms, stream, steps):
