@@ -47,7 +47,7 @@ def _load():
         lib.oracle_render.argtypes = [ctypes.c_int, ctypes.c_int64, P, ctypes.c_int, ctypes.c_int, P, P,
                                       ctypes.c_int, P, P, ctypes.c_int, P, P, P, P, P, ctypes.c_int64, P, P, P,
                                       ctypes.c_double, ctypes.c_double, P, P,
-                                      P, P, P, P, P, P, P, P, P, P, P, ctypes.c_int]
+                                      P, P, P, P, P, P, P, P, P, P, P, ctypes.c_int, P, P, ctypes.c_int]
         lib.oracle_pinhole_rays.restype = None
         lib.oracle_pinhole_rays.argtypes = [ctypes.c_int, ctypes.c_int, P, P, ctypes.c_int64, P, P, P]
         lib.oracle_hh_basis.restype = None
@@ -101,7 +101,8 @@ class Instance:
 
 def render(depth: int, leaf_ijk, hh, wsig, basis, gamma, ray_o, ray_d, ray_t=None, t_scalar=0.0,
            t_stop=1e-4, inst: Optional[Instance] = None, g_rgb=None, g_alpha=None,
-           want_grad_basis=True, threads: Optional[int] = None, wgam=None, basis_g=None, edit=None):
+           want_grad_basis=True, threads: Optional[int] = None, wgam=None, basis_g=None, edit=None,
+           segments: bool = False):
     """FP64 render of float32 rays through a tree given by its leaf cells.
 
     leaf_ijk [N,3] int; hh [N,3,K]; wsig [N,C]; basis [T,C]; gamma [T] (all as
@@ -114,6 +115,9 @@ def render(depth: int, leaf_ijk, hh, wsig, basis, gamma, ray_o, ray_d, ray_t=Non
     grad_basis [T,C] (and grad_wgam [N,Cg], grad_basis_g [T,Cg]) of
     <g_rgb, rgb> + <g_alpha, alpha>, and last_leaf [n]: the input index of the
     leaf of a ray's last sample when the ray stopped (T < t_stop), else -1.
+    With segments=True also seg [n, cap, 6] (every composited sample's ray interval
+    [u_in, u_out), density per leaf unit and colour; nsamp[r] rows valid) and len [n]
+    (leaf units per unit of the ray parameter).
     edit [N,5] (target rgb, target density or < 0 to keep it, first frame t_d)
     replaces a leaf's colour (and density) at local times tau >= t_d, the
     appearance edit of Sec. 5.2; no gradient is taken with edits.
@@ -144,6 +148,11 @@ def render(depth: int, leaf_ijk, hh, wsig, basis, gamma, ray_o, ray_d, ray_t=Non
                last_leaf=np.full(n, -1, np.int64))
     if edit is not None:
         edit = _c(edit, np.float64).reshape(N, 5)
+    cap = 0
+    if segments:
+        cap = 3 * (1 << depth) + 8
+        out["seg"] = np.zeros((n, cap, 6))
+        out["len"] = np.zeros(n)
     gr = ga = None
     if g_rgb is not None:
         gr = _c(g_rgb, np.float64).reshape(-1, 3)
@@ -160,7 +169,8 @@ def render(depth: int, leaf_ijk, hh, wsig, basis, gamma, ray_o, ray_d, ray_t=Non
                            _p(gr), _p(ga), _p(out["rgb"]), _p(out["alpha"]), _p(out["depth"]),
                            _p(out["nsamp"]), _p(out["tfinal"]), _p(out["margin"]),
                            _p(out.get("grad_hh")), _p(out.get("grad_wsig")), _p(out.get("grad_basis")),
-                           _p(edit), _p(out["last_leaf"]), int(threads or default_threads()))
+                           _p(edit), _p(out["last_leaf"]), int(cap), _p(out.get("seg")), _p(out.get("len")),
+                           int(threads or default_threads()))
     if rc != 0:
         raise RuntimeError(f"oracle_render failed with code {rc}")
     return out

@@ -165,7 +165,7 @@ static int64_t hs_find(const hashset* h, int64_t i, int64_t j, int64_t k) {
 static double softplus(double x) { return (x > 0 ? x : 0.0) + log1p(exp(-fabs(x))); }
 static double sigmoid(double x) { return 1.0 / (1.0 + exp(-x)); }
 
-typedef struct { int64_t leaf; double delta, smid, x, sig, z[3], c[3], Tin, alpha, yg, gam; } sample_t;
+typedef struct { int64_t leaf; double delta, smid, x, sig, z[3], c[3], Tin, alpha, yg, gam, ua, ub; } sample_t;
 
 /* Time re-mapping (Eq. 13): tau = t + off; wrap into [0,T) or clamp into [0,T-1];
    i0 = floor(tau), f = tau - i0, i1 = min(i0+1, T-1); the last frame is held on [T-1,T). */
@@ -182,7 +182,7 @@ static void time_lerp(double t, double off, int wrap, int T, int* i0, int* i1, d
     *i0 = a; *i1 = a + 1 < T ? a + 1 : T - 1; *f = fr;
 }
 
-/* Returns 0 on success, -1 allocation failure, -2 duplicate leaf, -3 bad argument. */
+/* Returns 0 on success, -1 allocation failure, -2 duplicate leaf, -3 bad argument, -4 seg_cap too small. */
 int oracle_render(int depth, int64_t n_leaves, const int32_t* leaf_ijk,
                   int K, int C, const double* hh /*[N][3][K]*/, const double* wsig /*[N][C]*/,
                   int T, const double* basis /*[T][C]*/, const double* gamma /*[T]*/,
@@ -197,6 +197,9 @@ int oracle_render(int depth, int64_t n_leaves, const int32_t* leaf_ijk,
                   double* grad_hh, double* grad_wsig, double* grad_basis,
                   const double* edit /* NULL or [N][5]: target rgb, target density (< 0: keep), first frame */,
                   int64_t* last_leaf /* NULL or [n]: leaf of the last sample of a ray that stopped, else -1 */,
+                  int seg_cap, double* seg_out /* NULL or [n][seg_cap][6]: every sample's ray interval
+                                                   [u_in, u_out), density (per leaf unit), colour */,
+                  double* len_out /* NULL or [n]: leaf units per unit of the ray parameter */,
                   int n_threads) {
     if (depth < 1 || depth > 20 || K < 1 || K > 64 || C < 1 || C > 64 || T < 1) return -3;
     if (wgam && (Cg < 1 || Cg > 64 || !basis_g)) return -3;
@@ -292,6 +295,7 @@ int oracle_render(int depth, int64_t n_leaves, const int32_t* leaf_ijk,
                         if (q >= 0) {
                             sample_t* s = &S[ns];
                             s->leaf = q;
+                            s->ua = u; s->ub = un;
                             s->delta = (un - u) * dlen;
                             s->smid = 0.5 * (u + un) * dwlen;
                             double x = 0.0;
@@ -347,6 +351,19 @@ int oracle_render(int depth, int64_t n_leaves, const int32_t* leaf_ijk,
                     if (un >= u_out) break;
                     cell[amin] += dl[amin] > 0.0 ? 1 : -1;
                     if (cell[amin] < 0 || cell[amin] >= Gi) break;
+                }
+            }
+            if (len_out) len_out[r] = dlen;
+            if (seg_out) {
+                if (ns > seg_cap) {
+#pragma omp atomic write
+                    err = -4;
+                } else {
+                    for (int k = 0; k < ns; ++k) {
+                        double* o6 = seg_out + ((int64_t)r * seg_cap + k) * 6;
+                        o6[0] = S[k].ua; o6[1] = S[k].ub; o6[2] = S[k].sig;
+                        o6[3] = S[k].c[0]; o6[4] = S[k].c[1]; o6[5] = S[k].c[2];
+                    }
                 }
             }
             for (int ch = 0; ch < 3; ++ch) rgb[3 * r + ch] = col[ch];
