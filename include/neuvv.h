@@ -333,6 +333,32 @@ int neuvv_eval_hh(int32_t K, int64_t n, const float* dirs, const float* gam, flo
 const char* neuvv_last_error(void);
 
 /*
+ * neuvv_render_multi - exact rendering of n_inst (1..4) placed instances that
+ * may interpenetrate or duplicate one another (Sec. 5.1; Alg. 1 blends
+ * separately rendered layers, which is exact only when they are disjoint in
+ * depth along each ray). Every instance k maps the world ray to its local ray
+ * with the same parameter u (neuvv_instance), and its leaves give intervals
+ * of u with constant density sigma (per leaf unit) and colour c. The ray is
+ * cut at every boundary of every instance; on each piece [u, u + du) the
+ * instances covering it contribute extinction kappa_k = sigma |d| / scale_k
+ * per unit u, the piece's optical depth is sum_k kappa_k du and its colour the
+ * kappa-weighted mean of theirs, and the pieces are composited front to back
+ * as in neuvv_render (Eq. 8; same early stop; nsamp counts pieces; depth is
+ * the weighted mean world distance of the piece midpoints). With one
+ * instance the result is neuvv_render's.
+ * trees           host array of n_inst tree pointers (the same tree may appear
+ *                 several times); K = 16, C = 8, no per-point hyperangle, no
+ *                 edits, one storage dtype.
+ * insts           host array of n_inst instances, or NULL (all identity).
+ * Other arguments as neuvv_render.
+ * Errors: ARG, RANGE, UNSUPPORTED, HIP.
+ */
+int neuvv_render_multi(int32_t n_inst, const neuvv_tree* const* trees, const neuvv_instance* insts, int64_t n_rays,
+                       const float* ray_o, const float* ray_d, const float* ray_t, float t_scalar,
+                       int32_t image_width, float t_stop, float* rgb, float* alpha, float* depth, int32_t* nsamp,
+                       void* stream);
+
+/*
  * neuvv_find_terminal_leaves - for appearance editing by painting from a view
  * (Sec. 5.2 "Appearance editing"): traces each ray as neuvv_render does and
  * returns the leaf slot of the first sample after which the accumulated alpha

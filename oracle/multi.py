@@ -32,7 +32,8 @@ def render_multi(scenes: Sequence, insts: Sequence[Optional[OC.Instance]], ray_o
                  t_stop: float, dtypes_round=None):
     """scenes: objects with depth, leaf_ijk, hh, wsig, basis, gamma (and optionally the rounded payload via
     dtypes_round: a function scene -> (hh, wsig)); returns rgb [n,3], alpha, depth, nsamp, margin [n]
-    (smallest relative distance of T to t_stop at a stop test)."""
+    (smallest relative distance of T to t_stop at a stop test) and min_piece [n] (shortest composited
+    piece, in leaf units of the finest instance)."""
     o = np.asarray(ray_o, np.float32)
     d = np.asarray(ray_d, np.float32)
     n = o.shape[0]
@@ -44,7 +45,7 @@ def render_multi(scenes: Sequence, insts: Sequence[Optional[OC.Instance]], ray_o
         per.append(r)
     dw = np.linalg.norm(d.astype(np.float64), axis=1)
     out = dict(rgb=np.zeros((n, 3)), alpha=np.zeros(n), depth=np.full(n, np.inf), nsamp=np.zeros(n, np.int32),
-               margin=np.full(n, np.inf))
+               margin=np.full(n, np.inf), min_piece=np.full(n, np.inf))
     for r in range(n):
         segs: List[np.ndarray] = []
         for k, res in enumerate(per):
@@ -67,6 +68,8 @@ def render_multi(scenes: Sequence, insts: Sequence[Optional[OC.Instance]], ray_o
                 continue
             kap = act[:, 2]
             ksum = kap.sum()
+            lens = [per[k]["len"][r] for k in range(len(per)) if per[k]["nsamp"][r]]
+            out["min_piece"][r] = min(out["min_piece"][r], (b - a) * max(lens))
             c = (kap[:, None] * act[:, 3:6]).sum(0) / ksum
             tau = ksum * (b - a)
             alpha = -np.expm1(-tau)

@@ -68,6 +68,7 @@ _SIGNATURES = {
     "neuvv_find_terminal_leaves": [ctypes.POINTER(neuvv_tree), ctypes.POINTER(neuvv_instance), _I64, _P, _P, _P, _F,
                                    _I32, _F, _P, _P],
     "neuvv_paint": [_I64, _P, _P, _F, _F, _I64, _P, _P],
+    "neuvv_render_multi": [_I32, _P, _P, _I64, _P, _P, _P, _F, _I32, _F, _P, _P, _P, _P, _P],
     "neuvv_shade": [ctypes.POINTER(neuvv_light), _P, _I64, _P, _P, _P, _P, _P, _P, _P],
     "neuvv_compose": [_I32, _I64, _P, _P, _P, _P, _P, _P, _P],
     "neuvv_compose_backward": [_I32, _I64, _P, _P, _P, _P, _P, _P, _P, _P],
@@ -278,3 +279,18 @@ def neuvv_find_terminal_leaves(tree: neuvv_tree, inst, n_rays, ray_o, ray_d, ray
 def neuvv_paint(n_rays, last_leaf, colours, sigma_d, t_d, n_leaves, edit, stream=None):
     _check("neuvv_paint", load().neuvv_paint(int(n_rays), _ptr(last_leaf), _ptr(colours), float(sigma_d), float(t_d),
                                              int(n_leaves), _ptr(edit), _stream(stream)))
+
+
+def neuvv_render_multi(trees, insts, n_rays, ray_o, ray_d, ray_t, t_scalar, image_width, t_stop, rgb, alpha, depth,
+                       nsamp, stream=None):
+    """trees: list of neuvv_tree structs; insts: list of neuvv_instance (or None = identity)."""
+    L = len(trees)
+    tarr = (ctypes.POINTER(neuvv_tree) * L)(*[ctypes.pointer(t) for t in trees])
+    iarr = None
+    if insts is not None:
+        iarr = (neuvv_instance * L)(*[make_instance(np.eye(3), np.zeros(3), 1.0, 0.0, 0) if i is None else i
+                                      for i in insts])
+    _check("neuvv_render_multi", load().neuvv_render_multi(
+        L, ctypes.cast(tarr, ctypes.c_void_p), None if iarr is None else ctypes.cast(iarr, ctypes.c_void_p),
+        int(n_rays), _ptr(ray_o), _ptr(ray_d), _ptr(ray_t), float(t_scalar), int(image_width), float(t_stop),
+        _ptr(rgb), _ptr(alpha), _ptr(depth), _ptr(nsamp), _stream(stream)))

@@ -13,7 +13,8 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libneuvv.so")
-SOURCES = ["render.hip", "render_pp.hip", "misc.hip", "lighting.hip", "api.cpp", "build_voctree.cpp"]
+SOURCES = ["render.hip", "render_pp.hip", "render_multi.hip", "misc.hip", "lighting.hip", "api.cpp",
+           "build_voctree.cpp"]
 ARCH = os.environ.get("NEUVV_ARCH", "gfx950")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function"]

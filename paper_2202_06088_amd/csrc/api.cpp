@@ -337,6 +337,41 @@ int neuvv_eval_hh(int32_t K, int64_t n, const float* dirs, const float* gam, flo
     NEUVV_GUARD_END
 }
 
+int neuvv_render_multi(int32_t n_inst, const neuvv_tree* const* trees, const neuvv_instance* insts, int64_t n_rays,
+                       const float* ray_o, const float* ray_d, const float* ray_t, float t_scalar,
+                       int32_t image_width, float t_stop, float* rgb, float* alpha, float* depth, int32_t* nsamp,
+                       void* stream) {
+    NEUVV_GUARD_BEGIN
+    if (n_inst < 1 || n_inst > 4) return fail(NEUVV_ERR_RANGE, "n_inst = %d outside [1, 4]", n_inst);
+    if (!trees) return fail(NEUVV_ERR_ARG, "trees is NULL");
+    neuvv::MultiArgs ma;
+    int dtype = -1;
+    for (int k = 0; k < n_inst; ++k) {
+        int rc = check_tree(trees[k]);
+        if (rc) return rc;
+        if (trees[k]->K != 16 || trees[k]->C != 8 || trees[k]->Cg != 0 || trees[k]->edit)
+            return fail(NEUVV_ERR_UNSUPPORTED, "the exact merge is compiled for the K=16 C=8 form without edits");
+        if (dtype >= 0 && trees[k]->dtype != dtype)
+            return fail(NEUVV_ERR_UNSUPPORTED, "all trees of one merge must share the storage dtype");
+        dtype = trees[k]->dtype;
+        ma.tr[k] = tree_args(trees[k]);
+        if ((rc = make_inst(insts ? &insts[k] : nullptr, ma.in[k]))) return rc;
+    }
+    for (int k = n_inst; k < 4; ++k) {
+        ma.tr[k] = ma.tr[0];
+        ma.in[k] = ma.in[0];
+    }
+    neuvv::RayArgs ra;
+    int rc = make_rays(n_rays, ray_o, ray_d, ray_t, t_scalar, image_width, ra);
+    if (rc) return rc;
+    if (!(t_stop >= 0.0f) || !std::isfinite(t_stop)) return fail(NEUVV_ERR_RANGE, "t_stop must be >= 0");
+    if (n_rays > 0 && (!rgb || !alpha || !nsamp)) return fail(NEUVV_ERR_ARG, "rgb / alpha / nsamp is NULL");
+    neuvv::RenderOut out{rgb, alpha, depth, nsamp, nullptr};
+    return hip_status(neuvv::launch_render_multi(n_inst, dtype, ma, ra, t_stop, out, (hipStream_t)stream),
+                      "render_multi launch");
+    NEUVV_GUARD_END
+}
+
 int neuvv_find_terminal_leaves(const neuvv_tree* tree, const neuvv_instance* inst, int64_t n_rays, const float* ray_o,
                                const float* ray_d, const float* ray_t, float t_scalar, int32_t image_width,
                                float alpha_threshold, int32_t* last_leaf, void* stream) {

@@ -38,6 +38,13 @@ hipError_t launch_render_fwd(int K, int C, int dtype, const TreeArgs& tr, const 
                              float t_stop, const RenderOut& out, hipStream_t stream);
 hipError_t launch_render_bwd(int K, int C, int dtype, const TreeArgs& tr, const InstArgs& in, const RayArgs& ra,
                              const BackwardIO& io, hipStream_t stream);
+// Exact merge of up to 4 instances along each ray (K = 16, C = 8 form).
+struct MultiArgs {
+    TreeArgs tr[4];
+    InstArgs in[4];
+};
+hipError_t launch_render_multi(int L, int dtype, const MultiArgs& ma, const RayArgs& ra, float t_stop,
+                               const RenderOut& out, hipStream_t stream);
 // Per-point hyperangle form (K = 14, C = 31, Cg = 31).
 hipError_t launch_render_pp_fwd(int dtype, const TreeArgs& tr, const InstArgs& in, const RayArgs& ra, float t_stop,
                                 const RenderOut& out, hipStream_t stream);

@@ -464,8 +464,9 @@ __device__ __forceinline__ df entry_param(const RaySetup& rs, const Walk& w) {
 }
 
 // Advances to the next occupied leaf segment of positive length. Returns its
-// slot and writes delta (leaf units) and umid (ray parameter of the segment
-// midpoint); returns -1 when the ray has left the box. path points at this
+// slot and writes delta (leaf units), umid (ray parameter of the segment
+// midpoint) and the segment's compensated bounds [seg_a, seg_b) in the ray
+// parameter; returns -1 when the ray has left the box. path points at this
 // lane's column of a [kMaxLevels][stride] LDS array of node rows; s_nodes
 // holds the first n_lds rows of the node table.
 //
@@ -477,7 +478,7 @@ __device__ __forceinline__ df entry_param(const RaySetup& rs, const Walk& w) {
 // parameters. The sequence of cells is therefore that of the exact walk.
 __device__ __forceinline__ int walk_next(const TreeArgs& tr, const int4* __restrict__ s_nodes, int n_lds,
                                          int* path, int stride, const RaySetup& rs, Walk& w, float& delta,
-                                         float& umid) {
+                                         float& umid, df& seg_a, df& seg_b) {
     const int Dp = tr.depth;
     const int G = 1 << Dp;
     const int last = (Dp + 1) / 2 - 1;   // last node level
@@ -585,6 +586,8 @@ __device__ __forceinline__ int walk_next(const TreeArgs& tr, const int4* __restr
             if (df_lt(u0, ux)) {
                 delta = df_f(df_sub(ux, u0)) * rs.len_local;
                 umid = 0.5f * (df_f(u0) + df_f(ux));
+                seg_a = u0;
+                seg_b = ux;
                 produced = delta > 0.0f;
             }
             if (!exact_ue && !last) { ue = ux; exact_ue = true; }
@@ -636,6 +639,14 @@ __device__ __forceinline__ int walk_next(const TreeArgs& tr, const int4* __restr
         if (produced) return leaf;
     }
     return -1;
+}
+
+// The same without the segment's compensated bounds [seg_a, seg_b).
+__device__ __forceinline__ int walk_next(const TreeArgs& tr, const int4* __restrict__ s_nodes, int n_lds,
+                                         int* path, int stride, const RaySetup& rs, Walk& w, float& delta,
+                                         float& umid) {
+    df a, b;
+    return walk_next(tr, s_nodes, n_lds, path, stride, rs, w, delta, umid, a, b);
 }
 
 }  // namespace neuvv
