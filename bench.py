@@ -79,6 +79,8 @@ def main():
     ap.add_argument("--editing", action="store_true",
                     help="also time appearance editing: terminal leaves + paint from one camera, and the forward "
                          "render with the edits active")
+    ap.add_argument("--multi", type=int, default=0,
+                    help="also time the exact merge of this many (2..4) interpenetrating placements of the tree")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -198,6 +200,12 @@ def main():
     if args.lighting:
         result["lighting"] = lighting_leg(sc, tree, ray_o, ray_d, rgb, alpha, depth, t_frame, t_stop, W, fwd_ms,
                                           stream, args.steps)
+    if args.multi:
+        if tree.Cg > 0 or not 2 <= args.multi <= 4:
+            log("--multi needs the global form and 2..4 instances; skipped")
+        else:
+            result["multi"] = multi_leg(sc, tree, args.multi, ray_o, ray_d, t_frame, t_stop, W, fwd_ms, stream,
+                                        args.steps)
     if args.editing:
         if tree.Cg > 0:
             log("appearance edits are compiled for the global form only; --editing skipped")
@@ -207,6 +215,45 @@ def main():
     if not args.no_cpu_baseline:
         result.update(cpu_leg(sc, cams, t_frame, t_stop, rgb, g_rgb, grads, tree, args.cpu_seconds))
     print(json.dumps(result), flush=True)
+
+
+def multi_leg(sc, tree, L, ray_o, ray_d, t_frame, t_stop, W, fwd_ms, stream, steps):
+    """Exact merge of L interpenetrating placements of the tree on the ring: copies rotated about the
+    vertical axis through the leaves' centroid by 2 pi k / (3 L) and shifted by a few percent of the
+    grid, with time offsets 37 k; HIP events on the launch stream."""
+    import torch
+    from paper_2202_06088_amd import _lib
+    c = sc.leaf_ijk.mean(0) + 0.5
+    insts = []
+    for k in range(L):
+        th = 2 * math.pi * k / (3 * L)
+        R = np.array([[math.cos(th), -math.sin(th), 0], [math.sin(th), math.cos(th), 0], [0, 0, 1]], np.float32)
+        trans = c - R @ c + np.array([0.04 * sc.G * k, -0.03 * sc.G * k, 0.0])
+        insts.append(_lib.make_instance(R, trans, 1.0, 37.0 * k, 1))
+    n = ray_o.shape[0]
+    rgb = torch.empty(n, 3, device=ray_o.device)
+    alpha = torch.empty(n, device=ray_o.device)
+    depth = torch.empty(n, device=ray_o.device)
+    nsamp = torch.empty(n, dtype=torch.int32, device=ray_o.device)
+    trees = [tree.struct()] * L
+
+    def once():
+        _lib.neuvv_render_multi(trees, insts, n, ray_o, ray_d, None, t_frame, W, t_stop, rgb, alpha, depth, nsamp,
+                                stream)
+
+    once()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        once()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    pieces = int(nsamp.sum())
+    log(f"multi L={L}: {ms:.3f} ms ({n / ms / 1e3:.0f} Mrays/s), {pieces} pieces; single forward {fwd_ms:.3f} ms")
+    return {"instances": L, "ms": round(ms, 4), "mrays_s": round(n / (ms * 1e-3) / 1e6, 2), "pieces": pieces,
+            "vs_single_fwd": round(ms / fwd_ms, 3)}
 
 
 def editing_leg(tree, ray_o, ray_d, rgb, alpha, depth, nsamp, t_frame, t_stop, W, H, fwd_ms, stream, steps):
