@@ -40,9 +40,11 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(workload: str) -> str:
+    """Hash of the sources the workload's render kernels are built from."""
+    main = "render_pp.hip" if workload.endswith("per_point") else "render.hip"
     h = hashlib.sha256()
-    for f in ("render.hip", "render_pp.hip", "render_common.h", "neuvv_device.h"):
+    for f in (main, "render_common.h", "neuvv_device.h"):
         with open(os.path.join(ROOT, "paper_2202_06088_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -58,7 +60,7 @@ def measured_traffic(kernel: str, workload: str):
     except (OSError, ValueError):
         return None
     e = rec.get(workload, {}).get(kernel)
-    if not e or e.get("source_hash") != kernel_source_hash():
+    if not e or e.get("source_hash") != kernel_source_hash(workload):
         return None
     return e.get("bytes_per_launch")
 

@@ -466,7 +466,11 @@ __device__ __forceinline__ df entry_param(const RaySetup& rs, const Walk& w) {
 // Advances to the next occupied leaf segment of positive length. Returns its
 // slot and writes delta (leaf units), umid (ray parameter of the segment
 // midpoint) and the segment's compensated bounds [seg_a, seg_b) in the ray
-// parameter; returns -1 when the ray has left the box. path points at this
+// parameter; returns -1 when the ray has left the box. With kBudget > 0 at
+// most kBudget cells are visited per call, and -2 says that the budget ran out
+// before a segment was found (the next call resumes the walk): lanes of a
+// wavefront in long empty stretches then stop holding back the lanes that
+// have a sample to evaluate. path points at this
 // lane's column of a [kMaxLevels][stride] LDS array of node rows; s_nodes
 // holds the first n_lds rows of the node table.
 //
@@ -476,6 +480,7 @@ __device__ __forceinline__ df entry_param(const RaySetup& rs, const Walk& w) {
 // bound of the decision threshold is it redone in compensated arithmetic.
 // Segment lengths of leaves always come from compensated entry and exit
 // parameters. The sequence of cells is therefore that of the exact walk.
+template <int kBudget = 0>
 __device__ __forceinline__ int walk_next(const TreeArgs& tr, const int4* __restrict__ s_nodes, int n_lds,
                                          int* path, int stride, const RaySetup& rs, Walk& w, float& delta,
                                          float& umid, df& seg_a, df& seg_b) {
@@ -484,7 +489,9 @@ __device__ __forceinline__ int walk_next(const TreeArgs& tr, const int4* __restr
     const int last = (Dp + 1) / 2 - 1;   // last node level
     const int max_steps = 3 * G + 16;
     constexpr float kRel = 1.0e-6f;   // bound on the relative error of a float estimate (~16 ulp)
+    int budget = kBudget;
     while (!w.done) {
+        if (kBudget > 0 && budget-- == 0) return -2;
         if (++w.steps > max_steps) { w.done = true; break; }
         // descend from the deepest valid ancestor; sh = log2 of the edge of the
         // empty octree node or leaf reached
@@ -642,11 +649,12 @@ __device__ __forceinline__ int walk_next(const TreeArgs& tr, const int4* __restr
 }
 
 // The same without the segment's compensated bounds [seg_a, seg_b).
+template <int kBudget = 0>
 __device__ __forceinline__ int walk_next(const TreeArgs& tr, const int4* __restrict__ s_nodes, int n_lds,
                                          int* path, int stride, const RaySetup& rs, Walk& w, float& delta,
                                          float& umid) {
     df a, b;
-    return walk_next(tr, s_nodes, n_lds, path, stride, rs, w, delta, umid, a, b);
+    return walk_next<kBudget>(tr, s_nodes, n_lds, path, stride, rs, w, delta, umid, a, b);
 }
 
 }  // namespace neuvv

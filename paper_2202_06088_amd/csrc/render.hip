@@ -14,11 +14,12 @@
 // next slots to them in lane order with mbcnt, and advances its
 // (wave-uniform) cursor by the popcount.
 //
-// Per lane: walk_next() descends the octree to the next occupied leaf
-// (top node rows from LDS, the rest from L2/HBM, the current brick's node in
-// registers), the leaf's 16-byte-vector
-// structure-of-arrays payload is gathered, colour and density evaluated in
-// float32 and composited. The per-sample HH contraction is a 3x16 times 16
+// Per lane: each iteration of the wavefront's loop advances the walk by one
+// cell (top node rows from LDS, the rest from L2/HBM, the current brick's
+// node in registers); a lane whose cell is an occupied leaf gathers the
+// leaf's payload (one contiguous row per leaf, or 16-byte-vector
+// structure-of-arrays) in 16-byte loads, evaluates colour and density in
+// float32 and composites. The per-sample HH contraction is a 3x16 times 16
 // matrix-vector product with a different matrix per sample, so it stays on
 // the vector ALUs; the kernel is bound by memory traffic and latency.
 #include <hip/hip_runtime.h>
@@ -123,9 +124,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
         if (n_idle == kWave) break;
         if (alive) {
             float delta, umid;
-            const int leaf = walk_next(tr, s_nodes, n_lds, path, kBlock, rs, w, delta, umid);
-            bool finish = leaf < 0, stopped = false;
-            if (!finish) {
+            const int leaf = walk_next<kWalkBudget>(tr, s_nodes, n_lds, path, kBlock, rs, w, delta, umid);
+            bool finish = leaf == -1, stopped = false;
+            if (leaf >= 0) {
                 float wv[3 * K], sv[C];
                 load_leaf<DT, 3 * K>(tr.hh, tr.n_leaves, leaf, tr.layout, wv);
                 load_leaf<DT, C>(tr.wsig, tr.n_leaves, leaf, tr.layout, sv);
@@ -284,9 +285,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
         float gz0 = 0.0f, gz1 = 0.0f, gz2 = 0.0f, gx = 0.0f;
         if (alive) {
             float delta, umid;
-            leaf = walk_next(tr, s_nodes, n_lds, path, kBlock, rs, w, delta, umid);
-            bool finish = leaf < 0;
-            if (!finish) {
+            leaf = walk_next<kWalkBudget>(tr, s_nodes, n_lds, path, kBlock, rs, w, delta, umid);
+            bool finish = leaf == -1;
+            if (leaf >= 0) {
                 float wv[3 * K], sv[C];
                 load_leaf<DT, 3 * K>(tr.hh, N, leaf, tr.layout, wv);
                 load_leaf<DT, C>(tr.wsig, N, leaf, tr.layout, sv);

@@ -14,6 +14,12 @@ namespace neuvv {
 
 constexpr int kBlock = 256;
 
+// cells a lane's walk visits per iteration of the wavefront's loop: one step
+// at a time, so that a lane with a sample to evaluate never waits for lanes
+// crossing long empty stretches (those finish their stretch over several
+// iterations instead)
+constexpr int kWalkBudget = 1;
+
 template <int DT>
 struct StoreTraits;
 template <>

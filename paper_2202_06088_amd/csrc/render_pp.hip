@@ -27,6 +27,10 @@ constexpr int K = 14;
 constexpr int C = 31;
 constexpr int CG = 31;
 constexpr int ROW = ((3 * K + C + CG + 63) / 64) * 64;   // 128
+// cells per walk call in the adjoint: every loop iteration with a sample
+// pays the wavefront-wide butterfly of the basis gradients, so its walk
+// takes longer strides than the forward's
+constexpr int kWalkBudgetBwd = 8;
 constexpr int kLdsNodes = 1024;
 constexpr float kPi = 3.14159265358979323846f;
 }  // namespace pp
@@ -188,9 +192,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) 
         if (n_idle == kWave) break;
         if (alive) {
             float delta, umid;
-            const int leaf = walk_next(tr, s_nodes, n_lds, path, kBlock, rs, w, delta, umid);
-            bool finish = leaf < 0;
-            if (!finish) {
+            const int leaf = walk_next<kWalkBudget>(tr, s_nodes, n_lds, path, kBlock, rs, w, delta, umid);
+            bool finish = leaf == -1;
+            if (leaf >= 0) {
                 PPSample<DT> p;
                 pp_eval<DT>(tr, rs, Y, s_b, s_bg, leaf, p);
                 const float sig = softplus_f(p.x);
@@ -315,9 +319,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) 
         float gz0 = 0.0f, gz1 = 0.0f, gz2 = 0.0f, gx = 0.0f, gy = 0.0f;
         if (alive) {
             float delta, umid;
-            leaf = walk_next(tr, s_nodes, n_lds, path, kBlock, rs, w, delta, umid);
-            bool finish = leaf < 0;
-            if (!finish) {
+            leaf = walk_next<kWalkBudgetBwd>(tr, s_nodes, n_lds, path, kBlock, rs, w, delta, umid);
+            bool finish = leaf == -1;
+            if (leaf >= 0) {
                 PPSample<DT> p;
                 pp_eval<DT>(tr, rs, Y, s_b, s_bg, leaf, p);
                 const float sig = softplus_f(p.x);
