@@ -12,11 +12,13 @@
  *   - Pointers named "device" are HIP device pointers owned by the caller;
  *     pointers named "host" are host memory owned by the caller. The library
  *     keeps no pointer after a call returns. The only device memory it
- *     allocates is the 1 KiB of work-queue counters that neuvv_render and
- *     neuvv_render_backward take per call from the stream-ordered allocator
- *     (hipMallocAsync on the call's stream, released with hipFreeAsync after
- *     the kernel); each call has its own, so calls on different streams do
- *     not interfere.
+ *     allocates is per-call scratch of the render calls (neuvv_render,
+ *     neuvv_render_backward, neuvv_find_terminal_leaves, neuvv_render_multi):
+ *     2 KiB of work-queue counters plus a candidate list of 4 bytes per work
+ *     slot (rounded up to 64 slots), taken in stream order on the call's
+ *     stream from a memory pool the library keeps per device (it keeps freed
+ *     memory for later calls) and freed in stream order after the kernels;
+ *     each call has its own, so calls on different streams do not interfere.
  *   - "stream" is a hipStream_t (NULL = the null stream). GPU work is queued
  *     on it asynchronously; the caller synchronises. Argument errors are
  *     detected on the host before anything is queued.

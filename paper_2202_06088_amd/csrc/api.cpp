@@ -120,6 +120,8 @@ int make_rays(int64_t n, const float* o, const float* d, const float* t, float t
     ra.img_w = image_width;
     ra.refill_min = refill_min();
     ra.queue = nullptr;
+    ra.list = nullptr;
+    ra.count = nullptr;
     if (image_width > 0) {
         const int64_t rows = (n + image_width - 1) / image_width;
         ra.tiles_x = (image_width + 7) / 8;

@@ -87,4 +87,10 @@ hipError_t launch_paint(int64_t n, const int32_t* last_leaf, const float* colour
 // Device properties used to size persistent grids (cached per device).
 int device_cu_count();
 
+// Stream-ordered scratch of a launch (work-queue counters, candidate lists):
+// taken from a memory pool the library keeps per device, which holds on to
+// its memory between calls instead of returning it at every synchronisation.
+hipError_t work_alloc(void** p, size_t bytes, hipStream_t stream);
+hipError_t work_free(void* p, hipStream_t stream);
+
 }  // namespace neuvv

@@ -231,6 +231,11 @@ struct RayArgs {
     int64_t n_slots;     // work slots (64 per 8x8 tile when img_w > 0, else n)
     int32_t refill_min;  // idle lanes that trigger a refill of the wavefront
     unsigned long long* queue;   // work-queue counters of the launch (set by the launcher)
+    // candidate form (set by the launcher): the rays a cull pass kept, listed in
+    // the slot range of their XCD part, with the per-part counts; nullptr: the
+    // work items are the slots themselves
+    const int32_t* list;
+    const unsigned long long* count;
 };
 
 // Work slot -> ray index, -1 when the slot is padding of a ragged tile.

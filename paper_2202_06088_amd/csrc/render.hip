@@ -26,6 +26,8 @@
 
 #include <math.h>
 
+#include <mutex>
+
 #include "launch.h"
 #include "neuvv_device.h"
 #include "render_common.h"
@@ -101,7 +103,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
                             o[0] = ra.o[3 * ray]; o[1] = ra.o[3 * ray + 1]; o[2] = ra.o[3 * ray + 2];
                             d[0] = ra.d[3 * ray]; d[1] = ra.d[3 * ray + 1]; d[2] = ra.d[3 * ray + 2];
                             t = ra.t ? ra.t[ray] : ra.t_scalar;
-                            cand = ray_may_hit<IDENT>(tr, in, o, d);
+                            cand = ra.list != nullptr || ray_may_hit<IDENT>(tr, in, o, d);
                             if (!cand) write_miss(out, ray);
                         }
                     }
@@ -242,7 +244,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
                     const int r = lane_rank(need);
                     if (r < take) {
                         ray = chunk_ray(ra, cc, cc.pos + r);
-                        cand = ray >= 0 && io.nsamp[ray] > 0;
+                        cand = ray >= 0 && (ra.list != nullptr || io.nsamp[ray] > 0);
                     }
                 }
                 cc.pos += take;
@@ -393,6 +395,41 @@ bool render_supported(int K, int C, int Cg, int dtype) {
 
 int grad_row_elems(int K, int C, int Cg) { return ((3 * K + C + Cg + 63) / 64) * 64; }
 
+namespace {
+std::mutex g_pool_mu;
+hipMemPool_t g_pool[64] = {};
+bool g_pool_tried[64] = {};
+}  // namespace
+
+hipError_t work_alloc(void** p, size_t bytes, hipStream_t stream) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    hipMemPool_t pool = nullptr;
+    if (dev >= 0 && dev < 64) {
+        std::lock_guard<std::mutex> lk(g_pool_mu);
+        if (!g_pool_tried[dev]) {
+            g_pool_tried[dev] = true;
+            hipMemPoolProps props = {};
+            props.allocType = hipMemAllocationTypePinned;
+            props.location.type = hipMemLocationTypeDevice;
+            props.location.id = dev;
+            hipMemPool_t mp = nullptr;
+            if (hipMemPoolCreate(&mp, &props) == hipSuccess) {
+                uint64_t keep = ~0ull;   // keep freed memory for the next call
+                if (hipMemPoolSetAttribute(mp, hipMemPoolAttrReleaseThreshold, &keep) == hipSuccess)
+                    g_pool[dev] = mp;
+                else
+                    (void)hipMemPoolDestroy(mp);
+            }
+        }
+        pool = g_pool[dev];
+    }
+    return pool ? hipMallocFromPoolAsync(p, bytes, pool, stream) : hipMallocAsync(p, bytes, stream);
+}
+
+hipError_t work_free(void* p, hipStream_t stream) { return hipFreeAsync(p, stream); }
+
 int device_cu_count() {
     static int cached[64] = {0};
     int dev = 0;
@@ -443,9 +480,9 @@ hipError_t launch_render_fwd(int K, int C, int dtype, const TreeArgs& tr, const 
     (void)C;
     if (ra.n_slots <= 0) return hipSuccess;
     switch (dtype) {
-        case 0: return with_queue(ra, stream, [&](const RayArgs& r) { return fwd_t<16, 8, 0>(tr, in, r, t_stop, out, stream); });
-        case 1: return with_queue(ra, stream, [&](const RayArgs& r) { return fwd_t<16, 8, 1>(tr, in, r, t_stop, out, stream); });
-        default: return with_queue(ra, stream, [&](const RayArgs& r) { return fwd_t<16, 8, 2>(tr, in, r, t_stop, out, stream); });
+        case 0: return with_candidates<0>(tr, in, ra, out, nullptr, stream, [&](const RayArgs& r) { return fwd_t<16, 8, 0>(tr, in, r, t_stop, out, stream); });
+        case 1: return with_candidates<0>(tr, in, ra, out, nullptr, stream, [&](const RayArgs& r) { return fwd_t<16, 8, 1>(tr, in, r, t_stop, out, stream); });
+        default: return with_candidates<0>(tr, in, ra, out, nullptr, stream, [&](const RayArgs& r) { return fwd_t<16, 8, 2>(tr, in, r, t_stop, out, stream); });
     }
 }
 
@@ -455,9 +492,9 @@ hipError_t launch_render_bwd(int K, int C, int dtype, const TreeArgs& tr, const 
     (void)C;
     if (ra.n_slots <= 0) return hipSuccess;
     switch (dtype) {
-        case 0: return with_queue(ra, stream, [&](const RayArgs& r) { return bwd_t<16, 8, 0>(tr, in, r, io, stream); });
-        case 1: return with_queue(ra, stream, [&](const RayArgs& r) { return bwd_t<16, 8, 1>(tr, in, r, io, stream); });
-        default: return with_queue(ra, stream, [&](const RayArgs& r) { return bwd_t<16, 8, 2>(tr, in, r, io, stream); });
+        case 0: return with_candidates<1>(tr, in, ra, RenderOut{}, io.nsamp, stream, [&](const RayArgs& r) { return bwd_t<16, 8, 0>(tr, in, r, io, stream); });
+        case 1: return with_candidates<1>(tr, in, ra, RenderOut{}, io.nsamp, stream, [&](const RayArgs& r) { return bwd_t<16, 8, 1>(tr, in, r, io, stream); });
+        default: return with_candidates<1>(tr, in, ra, RenderOut{}, io.nsamp, stream, [&](const RayArgs& r) { return bwd_t<16, 8, 2>(tr, in, r, io, stream); });
     }
 }
 

@@ -82,6 +82,10 @@ __device__ __forceinline__ int lane_rank(uint64_t mask) {
 }
 
 // Dynamic chunk distribution: kQueues counters, 128 bytes apart, one per XCD.
+// The chunk range [0, n_chunks) is cut into kQueues contiguous parts. In the
+// candidate form a cull pass has listed the rays worth walking of part x in
+// list[lo_x * 64 ...] (count[x] of them), and chunks are 64 consecutive
+// entries of that list.
 constexpr int kQueues = 8;
 constexpr int kQueueStride = 16;
 
@@ -90,7 +94,8 @@ struct ChunkCursor {
     int tried;      // queues drained so far (wave-uniform)
     int pos;        // slots of the current chunk handed out; 64 = take a new chunk
     int px0;        // x of the tile's first pixel (images)
-    int64_t base;   // ray index of the chunk's first slot
+    int len;        // candidate form: entries in the current chunk
+    int64_t base;   // ray index of the chunk's first slot (candidate form: list index)
 };
 
 __device__ __forceinline__ ChunkCursor chunk_cursor() {
@@ -99,6 +104,7 @@ __device__ __forceinline__ ChunkCursor chunk_cursor() {
     c.tried = 0;
     c.pos = kWave;
     c.px0 = 0;
+    c.len = 0;
     c.base = 0;
     return c;
 }
@@ -115,7 +121,19 @@ __device__ __forceinline__ bool next_chunk(const RayArgs& ra, ChunkCursor& cc) {
         if ((int)(threadIdx.x & 63) == leader) t = atomicAdd(ra.queue + x * kQueueStride, 1ull);
         const uint32_t t_lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)t);
         const uint32_t t_hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(t >> 32));
-        const int64_t k = lo + (int64_t)(((uint64_t)t_hi << 32) | t_lo);
+        const int64_t t64 = (int64_t)(((uint64_t)t_hi << 32) | t_lo);
+        if (ra.list) {
+            const int64_t cnt = (int64_t)ra.count[x * kQueueStride];
+            if (t64 * 64 < cnt) {
+                cc.pos = 0;
+                cc.base = lo * 64 + t64 * 64;
+                cc.len = cnt - t64 * 64 < 64 ? (int)(cnt - t64 * 64) : 64;
+                return true;
+            }
+            ++cc.tried;
+            continue;
+        }
+        const int64_t k = lo + t64;
         if (k < hi) {
             cc.pos = 0;
             if (ra.img_w > 0) {
@@ -134,6 +152,7 @@ __device__ __forceinline__ bool next_chunk(const RayArgs& ra, ChunkCursor& cc) {
 
 // Ray index of slot `within` (0..63) of the current chunk, -1 for padding.
 __device__ __forceinline__ int64_t chunk_ray(const RayArgs& ra, const ChunkCursor& cc, int within) {
+    if (ra.list) return within < cc.len ? (int64_t)ra.list[cc.base + within] : -1;
     int64_t r;
     if (ra.img_w > 0) {
         if (cc.px0 + (within & 7) >= ra.img_w) return -1;
@@ -184,20 +203,123 @@ static int grid_for(KernelT kernel, const RayArgs& ra) {
 
 // Work-queue counters of one launch: 1 KiB of stream-ordered scratch, zeroed
 // by a one-block kernel (no memset node, so the sequence may be captured in a
-// graph) and freed after the render kernel in stream order.
+// graph) and freed after the render kernel in stream order. The candidate
+// form adds kQueues counts (the second KiB) and a list of n_chunks * 64
+// int32 ray indices.
 static __global__ void zero_queue_kernel(unsigned long long* q) { q[threadIdx.x] = 0ull; }
 
+// Cull pass of the candidate form: each wavefront tests kCullGroup chunks of
+// one XCD part at a time (64 slots per chunk, one per lane), reserves room for
+// the rays it keeps with one atomic on the part's count, and lists them in
+// slot order. MODE 0 (forward): keep the rays the plain-float box test cannot
+// reject and write the miss outputs of the others. MODE 1 (adjoint): keep the
+// rays whose forward composited a sample (the others carry no gradient). The
+// pass is bound by the 24 bytes of ray per slot it reads; at high occupancy
+// it runs near HBM bandwidth, where the render kernel's refill rounds would
+// take one memory latency per round for every ray.
+constexpr int kCullGroup = 8;
+
+template <int MODE, bool IDENT>
+static __global__ __launch_bounds__(kBlock) void cull_kernel(TreeArgs tr, InstArgs in, RayArgs ra, RenderOut out,
+                                                              const int32_t* nsamp, int32_t* list,
+                                                              unsigned long long* count) {
+    const int lane = threadIdx.x & 63;
+    const int x = (int)(blockIdx.x & (kQueues - 1));
+    const int64_t n_chunks = (ra.n_slots + 63) >> 6;
+    const int64_t lo = n_chunks * x / kQueues, hi = n_chunks * (x + 1) / kQueues;
+    const int64_t nw = (int64_t)(gridDim.x / kQueues) * (kBlock / kWave);
+    const int64_t wi = (int64_t)(blockIdx.x / kQueues) * (kBlock / kWave) + (threadIdx.x >> 6);
+    for (int64_t c0 = lo + wi * kCullGroup; c0 < hi; c0 += nw * kCullGroup) {
+        uint64_t keep[kCullGroup];
+        int32_t rays[kCullGroup];
+        int total = 0;
+#pragma unroll
+        for (int j = 0; j < kCullGroup; ++j) {
+            const int64_t c = c0 + j;
+            const int64_t ray = c < hi ? slot_to_ray(ra, c * 64 + lane) : -1;
+            bool k = false;
+            if (ray >= 0) {
+                if constexpr (MODE == 0) {
+                    const float o[3] = {ra.o[3 * ray], ra.o[3 * ray + 1], ra.o[3 * ray + 2]};
+                    const float d[3] = {ra.d[3 * ray], ra.d[3 * ray + 1], ra.d[3 * ray + 2]};
+                    k = ray_may_hit<IDENT>(tr, in, o, d);
+                    if (!k) write_miss(out, ray);
+                } else {
+                    k = nsamp[ray] > 0;
+                }
+            }
+            keep[j] = __ballot(k);
+            rays[j] = (int32_t)ray;
+            total += __popcll(keep[j]);
+        }
+        if (total == 0) continue;   // wave-uniform
+        unsigned long long b = 0;
+        if (lane == 0) b = atomicAdd(count + x * kQueueStride, (unsigned long long)total);
+        const uint32_t b_lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)b);
+        const uint32_t b_hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(b >> 32));
+        int64_t at = lo * 64 + (int64_t)(((uint64_t)b_hi << 32) | b_lo);
+#pragma unroll
+        for (int j = 0; j < kCullGroup; ++j) {
+            if ((keep[j] >> lane) & 1ull) list[at + lane_rank(keep[j])] = rays[j];
+            at += __popcll(keep[j]);
+        }
+    }
+}
+
+template <int MODE>
+static hipError_t launch_cull(const TreeArgs& tr, const InstArgs& in, const RayArgs& ra, const RenderOut& out,
+                              const int32_t* nsamp, int32_t* list, unsigned long long* count, hipStream_t st) {
+    const int64_t n_chunks = (ra.n_slots + 63) >> 6;
+    const int64_t groups = (n_chunks / kQueues + 1 + kCullGroup - 1) / kCullGroup;   // per part, at most
+    int64_t blocks = (groups + (kBlock / kWave) - 1) / (kBlock / kWave);
+    const int64_t cap = (int64_t)device_cu_count() * 2;
+    if (blocks > cap) blocks = cap;
+    if (blocks < 1) blocks = 1;
+    const dim3 grid((unsigned)(blocks * kQueues));
+    if (in.identity)
+        hipLaunchKernelGGL((cull_kernel<MODE, true>), grid, dim3(kBlock), 0, st, tr, in, ra, out, nsamp, list, count);
+    else
+        hipLaunchKernelGGL((cull_kernel<MODE, false>), grid, dim3(kBlock), 0, st, tr, in, ra, out, nsamp, list, count);
+    return hipGetLastError();
+}
+
+// Runs launch(ra) with the launch's queue counters set; rays are the slots.
 template <typename Launch>
 static hipError_t with_queue(const RayArgs& ra_in, hipStream_t st, Launch&& launch) {
     RayArgs ra = ra_in;
     void* q = nullptr;
-    hipError_t e = hipMallocAsync(&q, kQueues * kQueueStride * sizeof(unsigned long long), st);
+    hipError_t e = work_alloc(&q, kQueues * kQueueStride * sizeof(unsigned long long), st);
     if (e != hipSuccess) return e;
     ra.queue = static_cast<unsigned long long*>(q);
     hipLaunchKernelGGL(zero_queue_kernel, dim3(1), dim3(kQueues * kQueueStride), 0, st, ra.queue);
     e = hipGetLastError();
     if (e == hipSuccess) e = launch(ra);
-    const hipError_t f = hipFreeAsync(q, st);
+    const hipError_t f = work_free(q, st);
+    return e != hipSuccess ? e : f;
+}
+
+// Candidate form: cull pass (MODE as in cull_kernel), then launch(ra) over the
+// listed rays. Ray indices must fit int32; larger launches take the slot form.
+template <int MODE, typename Launch>
+static hipError_t with_candidates(const TreeArgs& tr, const InstArgs& in, const RayArgs& ra_in,
+                                  const RenderOut& out, const int32_t* nsamp, hipStream_t st, Launch&& launch) {
+    if (ra_in.n > (int64_t)INT32_MAX) return with_queue(ra_in, st, launch);
+    const int64_t n_chunks = (ra_in.n_slots + 63) >> 6;
+    const size_t qbytes = 2 * kQueues * kQueueStride * sizeof(unsigned long long);
+    RayArgs ra = ra_in;
+    void* q = nullptr;
+    hipError_t e = work_alloc(&q, qbytes + (size_t)n_chunks * 64 * sizeof(int32_t), st);
+    if (e != hipSuccess) return e;
+    ra.queue = static_cast<unsigned long long*>(q);
+    unsigned long long* count = ra.queue + kQueues * kQueueStride;
+    int32_t* list = reinterpret_cast<int32_t*>(static_cast<char*>(q) + qbytes);
+    ra.count = count;
+    ra.list = list;
+    hipLaunchKernelGGL(zero_queue_kernel, dim3(1), dim3(2 * kQueues * kQueueStride), 0, st, ra.queue);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = launch_cull<MODE>(tr, in, ra_in, out, nsamp, list, count, st);
+    if (e == hipSuccess) e = launch(ra);
+    const hipError_t f = work_free(q, st);
     return e != hipSuccess ? e : f;
 }
 

@@ -169,7 +169,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) 
                             o[0] = ra.o[3 * ray]; o[1] = ra.o[3 * ray + 1]; o[2] = ra.o[3 * ray + 2];
                             d[0] = ra.d[3 * ray]; d[1] = ra.d[3 * ray + 1]; d[2] = ra.d[3 * ray + 2];
                             t = ra.t ? ra.t[ray] : ra.t_scalar;
-                            cand = ray_may_hit<IDENT>(tr, in, o, d);
+                            cand = ra.list != nullptr || ray_may_hit<IDENT>(tr, in, o, d);
                             if (!cand) write_miss(out, ray);
                         }
                     }
@@ -287,7 +287,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) 
                     const int r = lane_rank(need);
                     if (r < take) {
                         ray = chunk_ray(ra, cc, cc.pos + r);
-                        cand = ray >= 0 && io.nsamp[ray] > 0;
+                        cand = ray >= 0 && (ra.list != nullptr || io.nsamp[ray] > 0);
                     }
                 }
                 cc.pos += take;
@@ -489,9 +489,9 @@ hipError_t launch_render_pp_fwd(int dtype, const TreeArgs& tr, const InstArgs& i
                                 const RenderOut& out, hipStream_t stream) {
     if (ra.n_slots <= 0) return hipSuccess;
     switch (dtype) {
-        case 0: return with_queue(ra, stream, [&](const RayArgs& r) { return pp_fwd_t<0>(tr, in, r, t_stop, out, stream); });
-        case 1: return with_queue(ra, stream, [&](const RayArgs& r) { return pp_fwd_t<1>(tr, in, r, t_stop, out, stream); });
-        default: return with_queue(ra, stream, [&](const RayArgs& r) { return pp_fwd_t<2>(tr, in, r, t_stop, out, stream); });
+        case 0: return with_candidates<0>(tr, in, ra, out, nullptr, stream, [&](const RayArgs& r) { return pp_fwd_t<0>(tr, in, r, t_stop, out, stream); });
+        case 1: return with_candidates<0>(tr, in, ra, out, nullptr, stream, [&](const RayArgs& r) { return pp_fwd_t<1>(tr, in, r, t_stop, out, stream); });
+        default: return with_candidates<0>(tr, in, ra, out, nullptr, stream, [&](const RayArgs& r) { return pp_fwd_t<2>(tr, in, r, t_stop, out, stream); });
     }
 }
 
@@ -499,9 +499,9 @@ hipError_t launch_render_pp_bwd(int dtype, const TreeArgs& tr, const InstArgs& i
                                 const BackwardIO& io, hipStream_t stream) {
     if (ra.n_slots <= 0) return hipSuccess;
     switch (dtype) {
-        case 0: return with_queue(ra, stream, [&](const RayArgs& r) { return pp_bwd_t<0>(tr, in, r, io, stream); });
-        case 1: return with_queue(ra, stream, [&](const RayArgs& r) { return pp_bwd_t<1>(tr, in, r, io, stream); });
-        default: return with_queue(ra, stream, [&](const RayArgs& r) { return pp_bwd_t<2>(tr, in, r, io, stream); });
+        case 0: return with_candidates<1>(tr, in, ra, RenderOut{}, io.nsamp, stream, [&](const RayArgs& r) { return pp_bwd_t<0>(tr, in, r, io, stream); });
+        case 1: return with_candidates<1>(tr, in, ra, RenderOut{}, io.nsamp, stream, [&](const RayArgs& r) { return pp_bwd_t<1>(tr, in, r, io, stream); });
+        default: return with_candidates<1>(tr, in, ra, RenderOut{}, io.nsamp, stream, [&](const RayArgs& r) { return pp_bwd_t<2>(tr, in, r, io, stream); });
     }
 }
 
