@@ -13,7 +13,7 @@
  *     pointers named "host" are host memory owned by the caller. The library
  *     keeps no pointer after a call returns. The only device memory it
  *     allocates is per-call scratch of the render calls (neuvv_render,
- *     neuvv_render_backward, neuvv_find_terminal_leaves, neuvv_render_multi):
+ *     neuvv_render_backward, neuvv_find_terminal_leaves; neuvv_render_multi takes the counters only):
  *     2 KiB of work-queue counters plus a candidate list of 4 bytes per work
  *     slot (rounded up to 64 slots), taken in stream order on the call's
  *     stream from a memory pool the library keeps per device (it keeps freed

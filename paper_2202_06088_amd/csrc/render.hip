@@ -152,14 +152,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
                     }
                 }
                 const float od = sig * delta;
-                const float a = -expm1f(-od);
+                float a, e_od;
+                absorb(od, a, e_od);
                 const float wt = Tr * a;
                 acc0 = fmaf(wt, c0, acc0);
                 acc1 = fmaf(wt, c1, acc1);
                 acc2 = fmaf(wt, c2, acc2);
                 wsum += wt;
                 dsum = fmaf(wt, umid * rs.len_world, dsum);
-                Tr *= expf(-od);
+                Tr *= e_od;
                 ++ns;
                 last = leaf;
                 finish = t_stop > 0.0f && Tr < t_stop;
@@ -308,8 +309,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
                 }
                 const float sig = softplus_f(x);
                 const float od = sig * delta;
-                const float a = -expm1f(-od);
-                const float e = expf(-od);
+                float a, e;
+                absorb(od, a, e);
                 const float wt = Tr * a;
                 const float Tn = Tr * e;
                 const float c0 = sigmoid_f(z0), c1 = sigmoid_f(z1), c2 = sigmoid_f(z2);

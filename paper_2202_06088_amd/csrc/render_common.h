@@ -74,8 +74,35 @@ __device__ __forceinline__ void load_leaf(const void* base, int64_t N, int64_t s
     }
 }
 
-__device__ __forceinline__ float softplus_f(float x) { return fmaxf(x, 0.0f) + log1pf(expf(-fabsf(x))); }
-__device__ __forceinline__ float sigmoid_f(float x) { return 1.0f / (1.0f + expf(-x)); }
+// Per-sample transcendentals on the hardware base-2 exponential, base-2
+// logarithm and reciprocal (about 1 ulp each) instead of the correctly
+// rounded library sequences, which cost several times the instructions.
+// exp_hw: e^x = 2^(x log2 e); relative error 1 ulp plus |x| * 6e-8 from
+// rounding the scaled argument (below 1e-6 for the |x| < 15 of colour
+// logits and optical depths).
+__device__ __forceinline__ float exp_hw(float x) { return __builtin_amdgcn_exp2f(x * 1.44269504088896341f); }
+__device__ __forceinline__ float sigmoid_f(float x) { return __builtin_amdgcn_rcpf(1.0f + exp_hw(-x)); }
+// log(1 + e), e in [0, 1]: the logarithm of the rounded u = 1 + e, scaled by
+// e / (u - 1) to undo the rounding of u (a few ulp).
+__device__ __forceinline__ float log1p_hw(float e) {
+    const float u = 1.0f + e;
+    const float lg = __builtin_amdgcn_logf(u) * 0.693147180559945309f;
+    return u == 1.0f ? e : lg * (e * __builtin_amdgcn_rcpf(u - 1.0f));
+}
+__device__ __forceinline__ float softplus_f(float x) { return fmaxf(x, 0.0f) + log1p_hw(exp_hw(-fabsf(x))); }
+// Opacity a = 1 - e^-od and transmittance factor e = e^-od of an optical
+// depth od >= 0 (Eq. 8). Below od = 1/4 the series of 1 - e^-od to the
+// seventh power (truncation below 2e-9 relative) keeps a accurate where
+// 1 - e would cancel; above it a = 1 - e loses at most 3e-7 relative.
+__device__ __forceinline__ void absorb(float od, float& a, float& e) {
+    const float s = od * fmaf(od, fmaf(od, fmaf(od, fmaf(od, fmaf(od, fmaf(od, 1.0f / 5040.0f, -1.0f / 720.0f),
+                                                                      1.0f / 120.0f), -1.0f / 24.0f), 1.0f / 6.0f),
+                                         -0.5f), 1.0f);
+    const float x = exp_hw(-od);
+    const bool small = od < 0.25f;
+    a = small ? s : 1.0f - x;
+    e = small ? 1.0f - s : x;
+}
 
 __device__ __forceinline__ int lane_rank(uint64_t mask) {
     return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));

@@ -178,7 +178,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 8))) 
             if (have_nb && ksum > 0.0f) {
                 const float du = df_f(df_sub(nb, u));
                 const float od = ksum * du;
-                const float a = -expm1f(-od);
+                float a, e_od;
+                absorb(od, a, e_od);
                 const float wt = Tr * a;
                 const float inv = 1.0f / ksum;
                 acc0 = fmaf(wt, kc0 * inv, acc0);
@@ -186,7 +187,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 8))) 
                 acc2 = fmaf(wt, kc2 * inv, acc2);
                 wsum += wt;
                 dsum = fmaf(wt, 0.5f * (df_f(u) + df_f(nb)) * dlen, dsum);
-                Tr *= expf(-od);
+                Tr *= e_od;
                 ++ns;
                 finish = t_stop > 0.0f && Tr < t_stop;
             }

@@ -199,14 +199,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) 
                 pp_eval<DT>(tr, rs, Y, s_b, s_bg, leaf, p);
                 const float sig = softplus_f(p.x);
                 const float od = sig * delta;
-                const float a = -expm1f(-od);
+                float a, e_od;
+                absorb(od, a, e_od);
                 const float wt = Tr * a;
                 acc0 = fmaf(wt, sigmoid_f(p.z0), acc0);
                 acc1 = fmaf(wt, sigmoid_f(p.z1), acc1);
                 acc2 = fmaf(wt, sigmoid_f(p.z2), acc2);
                 wsum += wt;
                 dsum = fmaf(wt, umid * rs.len_world, dsum);
-                Tr *= expf(-od);
+                Tr *= e_od;
                 ++ns;
                 finish = t_stop > 0.0f && Tr < t_stop;
             }
@@ -326,8 +327,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) 
                 pp_eval<DT>(tr, rs, Y, s_b, s_bg, leaf, p);
                 const float sig = softplus_f(p.x);
                 const float od = sig * delta;
-                const float a = -expm1f(-od);
-                const float e = expf(-od);
+                float a, e;
+                absorb(od, a, e);
                 const float wt = Tr * a;
                 const float Tn = Tr * e;
                 const float c0 = sigmoid_f(p.z0), c1 = sigmoid_f(p.z1), c2 = sigmoid_f(p.z2);
