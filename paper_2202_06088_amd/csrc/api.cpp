@@ -133,6 +133,19 @@ int make_rays(int64_t n, const float* o, const float* d, const float* t, float t
     return NEUVV_OK;
 }
 
+// Sample records of the two-phase adjoint: NEUVV_BWD_RECORDS overrides (0
+// turns the records off); by default room for two samples per ray, at least
+// 2^20, at most 2^31 - 1. Samples beyond the room take per-sample atomics.
+int64_t record_cap(int64_t n_rays) {
+    const char* e = getenv("NEUVV_BWD_RECORDS");
+    int64_t cap = 2 * n_rays;
+    if (cap < (int64_t)1 << 20) cap = (int64_t)1 << 20;
+    if (e && *e) cap = atoll(e);
+    if (cap < 0) cap = 0;
+    if (cap > (int64_t)INT32_MAX) cap = INT32_MAX;
+    return cap;
+}
+
 neuvv::TreeArgs tree_args(const neuvv_tree* t) {
     neuvv::TreeArgs a;
     a.nodes = reinterpret_cast<const int4*>(t->nodes);
@@ -275,7 +288,7 @@ int neuvv_render_backward(const neuvv_tree* tree, const neuvv_instance* inst, in
     if (tree->n_leaves > 0 && !grad_leaf) return fail(NEUVV_ERR_ARG, "grad_leaf is NULL");
     if (tree->edit) return fail(NEUVV_ERR_UNSUPPORTED, "no adjoint through appearance edits");
     neuvv::BackwardIO io{rgb, alpha, nsamp, grad_rgb, grad_alpha, grad_leaf, grad_basis,
-                         tree->Cg > 0 ? grad_basis_g : nullptr};
+                         tree->Cg > 0 ? grad_basis_g : nullptr, record_cap(n_rays)};
     const hipError_t e = tree->Cg > 0
                              ? neuvv::launch_render_pp_bwd(tree->dtype, tree_args(tree), in, ra, io,
                                                            (hipStream_t)stream)

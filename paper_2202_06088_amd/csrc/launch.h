@@ -27,6 +27,19 @@ struct BackwardIO {
     float* grad_leaf;    // [n_leaves][grad_row_elems(K, C, Cg)]
     float* grad_basis;
     float* grad_basis_g;   // per-point hyperangle basis gradient (Cg > 0), or nullptr
+    int64_t record_cap;    // two-phase adjoint: sample records at most (0: per-sample atomics only)
+};
+
+// Per-sample records of the two-phase adjoint: a sample's gradient with
+// respect to its colour logits and density logit is written once and linked
+// into its leaf's list; a second pass sums each leaf's list into its
+// gradient row (one row addition per leaf instead of one per sample).
+struct RecordArgs {
+    int32_t* head;                 // [n_leaves] first record of the leaf's list, -1: none
+    int2* link;                    // [cap] {next record of the same leaf (-1: end), ray}
+    float4* g;                     // [cap] {dL/dz_r, dL/dz_g, dL/dz_b, dL/dx}
+    unsigned long long* counter;   // records handed out so far
+    int64_t cap;
 };
 
 // Each returns hipSuccess or the launch error. K, C, dtype must be supported

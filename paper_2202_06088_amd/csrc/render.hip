@@ -194,7 +194,7 @@ __host__ __device__ constexpr int grad_row() { return ((3 * K + C + 63) / 64) * 
 
 template <int K, int C, int DT, bool IDENT>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) void render_bwd_kernel(
-    TreeArgs tr, InstArgs in, RayArgs ra, BackwardIO io) {
+    TreeArgs tr, InstArgs in, RayArgs ra, BackwardIO io, RecordArgs rec) {
     constexpr int ROW = grad_row<K, C>();
     __shared__ int4 s_nodes[kLdsNodesBwd];
     __shared__ int s_path[kMaxLevels * kBlock];
@@ -223,6 +223,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
     float Tr = 1.0f, Tfin = 0.0f, p0 = 0.0f, p1 = 0.0f, p2 = 0.0f, F0 = 0.0f, F1 = 0.0f, F2 = 0.0f;
     float g0 = 0.0f, g1 = 0.0f, g2 = 0.0f, ga = 0.0f;
     int ns = 0, ns_fwd = 0;
+    int rbase = -1;   // record of the ray's next sample; -1: its samples take the atomic scatter
 
     for (;;) {
         const uint64_t idle = __ballot(!alive);
@@ -231,7 +232,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
             // Acquisition: idle lanes take the next slots while at least refill_min
             // lanes are idle; rays that composited no sample carry no gradient and
             // are passed over. The setup then runs once for all taken rays together.
-            bool cand = false;
+            bool cand = false, fresh = false;
             for (;;) {
                 const uint64_t need = __ballot(!alive && !cand);
                 const int n_need = __popcll(need);
@@ -278,13 +279,32 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
                         for (int c = 0; c < C; ++c) gb[c] = 0.0f;
                     }
                     alive = true;
+                    fresh = true;
                 }
+            }
+            if (rec.head) {
+                // records for the rays taken this round: one atomic per wavefront
+                // hands out consecutive room for all their samples
+                const int want = fresh ? ns_fwd : 0;
+                int incl = want;
+#pragma unroll
+                for (int off = 1; off < kWave; off <<= 1) {
+                    const int v = __shfl_up(incl, off);
+                    if (lane >= off) incl += v;
+                }
+                const int total = __shfl(incl, kWave - 1);
+                unsigned long long b = 0;
+                if (lane == 0 && total > 0) b = atomicAdd(rec.counter, (unsigned long long)total);
+                const uint32_t b_lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)b);
+                const uint32_t b_hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(b >> 32));
+                const int64_t first = (int64_t)(((uint64_t)b_hi << 32) | b_lo) + (incl - want);
+                if (fresh) rbase = first + want <= rec.cap ? (int)first : -1;
             }
             continue;
         }
         if (n_idle == kWave) break;
         bool has = false;
-        int leaf = -1;
+        int leaf = -1, my_rec = -1;
         float gz0 = 0.0f, gz1 = 0.0f, gz2 = 0.0f, gx = 0.0f;
         if (alive) {
             float delta, umid;
@@ -328,6 +348,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
 #pragma unroll
                 for (int c = 0; c < C; ++c) gb[c] = fmaf(gx, sv[c], gb[c]);
                 has = true;
+                if (rbase >= 0) my_rec = rbase + ns;
                 Tr = Tn;
                 ++ns;
                 finish = ns >= ns_fwd;
@@ -343,8 +364,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
                 alive = false;
             }
         }
-        // every lane of the wavefront adds one component of each produced row
-        uint64_t m = __ballot(has);
+        if (my_rec >= 0) {
+            rec.g[my_rec] = make_float4(gz0, gz1, gz2, gx);
+            const int nxt = atomicExch(rec.head + leaf, my_rec);
+            rec.link[my_rec] = make_int2(nxt, (int)ray);
+        }
+        // samples without a record: every lane of the wavefront adds one
+        // component of each produced row
+        uint64_t m = __ballot(has && my_rec < 0);
         __builtin_amdgcn_wave_barrier();
         while (m) {
             const int src = __builtin_ctzll(m);
@@ -383,6 +410,73 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
             unsafeAtomicAdd(io.grad_basis + (int64_t)i0 * C + threadIdx.x, (1.0f - f) * v);
             if (f != 0.0f) unsafeAtomicAdd(io.grad_basis + (int64_t)i1 * C + threadIdx.x, f * v);
         }
+    }
+}
+
+// ----------------------------------------------------------------------------
+// second pass of the two-phase adjoint
+//
+// One lane per leaf walks the leaf's record list: for every record it redoes
+// the ray's setup and basis (the same functions on the same inputs as the
+// adjoint, so h and b are those the sample used) and adds gz_ch h_k and
+// gx b_c into the row it holds in registers. The wavefront's 64 rows are then
+// transposed through LDS and each is added to the gradient array with one
+// atomic instruction of 3K + C lanes, as the per-sample scatter did, but once
+// per leaf.
+
+static __global__ void record_init_kernel(int32_t* head, int64_t n, unsigned long long* counter) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) head[i] = -1;
+    if (i == 0) *counter = 0ull;
+}
+
+template <int K, int C, bool IDENT>
+__global__ __launch_bounds__(kBlock) void reduce_records_kernel(TreeArgs tr, InstArgs in, RayArgs ra,
+                                                                RecordArgs rec, float* grad_leaf) {
+    constexpr int ROW = grad_row<K, C>();
+    constexpr int R = 3 * K + C;
+    __shared__ float s_row[kBlock / kWave][kWave][R + 1];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t n_waves = (int64_t)gridDim.x * (kBlock / kWave);
+    for (int64_t base = ((int64_t)blockIdx.x * (kBlock / kWave) + wv) * kWave; base < tr.n_leaves;
+         base += n_waves * kWave) {
+        const int64_t L = base + lane;
+        int i = L < tr.n_leaves ? rec.head[L] : -1;
+        const bool any = i >= 0;
+        float acc[R];
+#pragma unroll
+        for (int c = 0; c < R; ++c) acc[c] = 0.0f;
+        while (i >= 0) {
+            const int2 lk = rec.link[i];
+            const float4 g = rec.g[i];
+            const int64_t ray = lk.y;
+            const float o[3] = {ra.o[3 * ray], ra.o[3 * ray + 1], ra.o[3 * ray + 2]};
+            const float d[3] = {ra.d[3 * ray], ra.d[3 * ray + 1], ra.d[3 * ray + 2]};
+            const float t = ra.t ? ra.t[ray] : ra.t_scalar;
+            RaySetup rs;
+            ray_setup<IDENT>(tr, in, o, d, t, rs);
+            float h[K], bv[C];
+            ray_basis<K, C>(tr, rs, h, bv);
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                acc[k] = fmaf(g.x, h[k], acc[k]);
+                acc[K + k] = fmaf(g.y, h[k], acc[K + k]);
+                acc[2 * K + k] = fmaf(g.z, h[k], acc[2 * K + k]);
+            }
+#pragma unroll
+            for (int c = 0; c < C; ++c) acc[3 * K + c] = fmaf(g.w, bv[c], acc[3 * K + c]);
+            i = lk.x;
+        }
+#pragma unroll
+        for (int c = 0; c < R; ++c) s_row[wv][lane][c] = acc[c];
+        uint64_t m = __ballot(any);
+        __builtin_amdgcn_wave_barrier();
+        while (m) {
+            const int j = __builtin_ctzll(m);
+            m &= m - 1;
+            if (lane < R) unsafeAtomicAdd(grad_leaf + (base + j) * ROW + lane, s_row[wv][j][lane]);
+        }
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -465,14 +559,52 @@ static hipError_t fwd_t(const TreeArgs& tr, const InstArgs& in, const RayArgs& r
 template <int K, int C, int DT>
 static hipError_t bwd_t(const TreeArgs& tr, const InstArgs& in, const RayArgs& ra, const BackwardIO& io,
                         hipStream_t st) {
-    if (in.identity) {
-        auto kern = render_bwd_kernel<K, C, DT, true>;
-        hipLaunchKernelGGL(kern, dim3(grid_for(kern, ra)), dim3(kBlock), 0, st, tr, in, ra, io);
-    } else {
-        auto kern = render_bwd_kernel<K, C, DT, false>;
-        hipLaunchKernelGGL(kern, dim3(grid_for(kern, ra)), dim3(kBlock), 0, st, tr, in, ra, io);
+    // records need int32 ray and record indices
+    const int64_t cap = ra.n <= (int64_t)INT32_MAX && tr.n_leaves > 0 ? io.record_cap : 0;
+    RecordArgs rec{};
+    void* mem = nullptr;
+    if (cap > 0) {
+        const size_t head_b = ((size_t)tr.n_leaves * sizeof(int32_t) + 255) & ~(size_t)255;
+        const size_t link_b = (size_t)cap * sizeof(int2), g_b = (size_t)cap * sizeof(float4);
+        hipError_t e = work_alloc(&mem, 256 + head_b + link_b + g_b, st);
+        if (e != hipSuccess) return e;
+        char* p = static_cast<char*>(mem);
+        rec.counter = reinterpret_cast<unsigned long long*>(p);
+        rec.head = reinterpret_cast<int32_t*>(p + 256);
+        rec.link = reinterpret_cast<int2*>(p + 256 + head_b);
+        rec.g = reinterpret_cast<float4*>(p + 256 + head_b + link_b);
+        rec.cap = cap;
+        hipLaunchKernelGGL(record_init_kernel, dim3((unsigned)((tr.n_leaves + 255) / 256)), dim3(256), 0, st,
+                           rec.head, tr.n_leaves, rec.counter);
     }
-    return hipGetLastError();
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) {
+        if (in.identity) {
+            auto kern = render_bwd_kernel<K, C, DT, true>;
+            hipLaunchKernelGGL(kern, dim3(grid_for(kern, ra)), dim3(kBlock), 0, st, tr, in, ra, io, rec);
+        } else {
+            auto kern = render_bwd_kernel<K, C, DT, false>;
+            hipLaunchKernelGGL(kern, dim3(grid_for(kern, ra)), dim3(kBlock), 0, st, tr, in, ra, io, rec);
+        }
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess && cap > 0) {
+        int64_t blocks = (tr.n_leaves + kBlock - 1) / kBlock;
+        const int64_t lim = (int64_t)device_cu_count() * 8;
+        if (blocks > lim) blocks = lim;
+        if (in.identity)
+            hipLaunchKernelGGL((reduce_records_kernel<K, C, true>), dim3((unsigned)blocks), dim3(kBlock), 0, st, tr,
+                               in, ra, rec, io.grad_leaf);
+        else
+            hipLaunchKernelGGL((reduce_records_kernel<K, C, false>), dim3((unsigned)blocks), dim3(kBlock), 0, st, tr,
+                               in, ra, rec, io.grad_leaf);
+        e = hipGetLastError();
+    }
+    if (mem) {
+        const hipError_t f = work_free(mem, st);
+        if (e == hipSuccess) e = f;
+    }
+    return e;
 }
 
 hipError_t launch_render_fwd(int K, int C, int dtype, const TreeArgs& tr, const InstArgs& in, const RayArgs& ra,

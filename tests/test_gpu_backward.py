@@ -52,6 +52,34 @@ def test_backward_config1_scalar_time(layout):
         check(gpu, ref, label=f"cfg1 t={t}")
 
 
+@pytest.mark.parametrize("records", ["0", "777", None])
+def test_backward_record_modes(records, monkeypatch):
+    """The two-phase adjoint (per-sample records summed per leaf) against the oracle,
+    with the records off (per-sample atomics only), with room for 777 records (the
+    rest of the samples take the atomics in the same call) and with the default room;
+    scalar and per-ray time."""
+    if records is None:
+        monkeypatch.delenv("NEUVV_BWD_RECORDS", raising=False)
+    else:
+        monkeypatch.setenv("NEUVV_BWD_RECORDS", records)
+    sc = scene_for_config(1)
+    tree = upload(sc)
+    cam = config1_camera(sc)
+    o, d = OC.pinhole_rays(64, 64, cam.intr(), cam.c2w)
+    rng = np.random.default_rng(47)
+    gC = rng.normal(size=(o.shape[0], 3)).astype(np.float32)
+    gA = rng.normal(size=o.shape[0]).astype(np.float32)
+    t = rng.uniform(0, sc.T - 1, o.shape[0]).astype(np.float32)
+    announce(f"backward records={records}")
+    ref = oracle_render(sc, o, d, None, 4.0, 0.0, g_rgb=gC, g_alpha=gA)
+    gpu = run_backward(tree, o, d, None, 4.0, 0.0, gC, gA, image_width=64)
+    assert int(gpu[3].sum()) > 3000
+    check(gpu, ref, label=f"records={records} scalar t")
+    ref = oracle_render(sc, o, d, t, 0.0, 0.0, g_rgb=gC, g_alpha=gA)
+    gpu = run_backward(tree, o, d, t, 0.0, 0.0, gC, gA, image_width=64)
+    check(gpu, ref, label=f"records={records} per-ray t")
+
+
 def test_backward_training_step_per_ray_time():
     """Reduced training step: 16 seeded cameras, random (camera, pixel) rays, random t,
     L2 loss against a target render of a second payload draw."""
