@@ -36,9 +36,10 @@ struct BackwardIO {
 // gradient row (one row addition per leaf instead of one per sample).
 struct RecordArgs {
     int32_t* head;                 // [n_leaves] first record of the leaf's list, -1: none
-    int2* link;                    // [cap] {next record of the same leaf (-1: end), ray}
-    float4* g;                     // [cap] {dL/dz_r, dL/dz_g, dL/dz_b, dL/dx}
-    unsigned long long* counter;   // records handed out so far
+    int4* rec;                     // [cap][2]: {dL/dz_r, dL/dz_g, dL/dz_b, dL/dx} (float bits),
+                                   //           {next record of the same leaf (-1: end), ray, 0, 0}
+    unsigned long long* counter;   // records handed out so far, one counter per XCD part of the room
+    unsigned long long* leaf_cursor;   // second pass: leaves handed out so far
     int64_t cap;
 };
 

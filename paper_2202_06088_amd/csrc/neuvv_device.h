@@ -324,7 +324,7 @@ __device__ __forceinline__ bool ray_may_hit(const TreeArgs& tr, const InstArgs& 
         if (dfl[a] == 0.0f) {
             pass = pass && of[a] >= lo && of[a] < hi;
         } else {
-            const float iv = 1.0f / dfl[a];
+            const float iv = __builtin_amdgcn_rcpf(dfl[a]);   // 1 ulp: far inside the margin
             const float t0 = (lo - of[a]) * iv, t1 = (hi - of[a]) * iv;
             tn = fmaxf(tn, fminf(t0, t1));
             tf = fminf(tf, fmaxf(t0, t1));
@@ -333,13 +333,50 @@ __device__ __forceinline__ bool ray_may_hit(const TreeArgs& tr, const InstArgs& 
     return !small || (pass && tn < tf);
 }
 
+// Local direction of a ray (compensated D = R^T d / s), |D| (leaf units per
+// unit of the ray parameter), |d| and the unit local direction; dmax = the
+// largest |D| component.
+template <bool IDENT>
+__device__ __forceinline__ void ray_direction(const InstArgs& in, const float d[3], RaySetup& rs, float& dmax) {
+    if constexpr (IDENT) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) rs.D[a] = df_from(d[a]);
+    } else {
+        df s = df_from(in.scale);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            df ad = df_two_prod(d[0], in.rot[a]);
+            ad = df_add(ad, df_two_prod(d[1], in.rot[3 + a]));
+            ad = df_add(ad, df_two_prod(d[2], in.rot[6 + a]));
+            rs.D[a] = df_div(ad, s);
+        }
+    }
+    float dl2 = 0.0f, dw2 = 0.0f;
+    dmax = 0.0f;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        float v = df_f(rs.D[a]);
+        dl2 += v * v;
+        dw2 += d[a] * d[a];
+        dmax = fmaxf(dmax, fabsf(v));
+    }
+    rs.len_local = sqrtf(dl2);
+    rs.len_world = sqrtf(dw2);
+    const float inv_len = rs.len_local > 0.0f ? 1.0f / rs.len_local : 0.0f;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) rs.dir[a] = df_f(rs.D[a]) * inv_len;
+    if (!(rs.len_local > 0.0f)) rs.dir[2] = 1.0f;
+}
+
 // Exact per-ray setup (compensated geometry); call for rays ray_may_hit accepts.
 template <bool IDENT>
 __device__ __forceinline__ void ray_setup(const TreeArgs& tr, const InstArgs& in, const float o[3],
                                           const float d[3], float t, RaySetup& rs) {
+    float dmax;
+    ray_direction<IDENT>(in, d, rs, dmax);
     if constexpr (IDENT) {
 #pragma unroll
-        for (int a = 0; a < 3; ++a) { rs.O[a] = df_from(o[a]); rs.D[a] = df_from(d[a]); }
+        for (int a = 0; a < 3; ++a) rs.O[a] = df_from(o[a]);
     } else {
         df diff[3];
 #pragma unroll
@@ -350,28 +387,10 @@ __device__ __forceinline__ void ray_setup(const TreeArgs& tr, const InstArgs& in
             df ao = df_mul_f(diff[0], in.rot[a]);
             ao = df_add(ao, df_mul_f(diff[1], in.rot[3 + a]));
             ao = df_add(ao, df_mul_f(diff[2], in.rot[6 + a]));
-            df ad = df_two_prod(d[0], in.rot[a]);
-            ad = df_add(ad, df_two_prod(d[1], in.rot[3 + a]));
-            ad = df_add(ad, df_two_prod(d[2], in.rot[6 + a]));
             rs.O[a] = df_div(ao, s);
-            rs.D[a] = df_div(ad, s);
         }
     }
-    float dl2 = 0.0f, dw2 = 0.0f, dmax = 0.0f;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        float v = df_f(rs.D[a]);
-        dl2 += v * v;
-        dw2 += d[a] * d[a];
-        dmax = fmaxf(dmax, fabsf(v));
-    }
-    rs.len_local = sqrtf(dl2);
-    rs.len_world = sqrtf(dw2);
     bool hit = rs.len_local > 0.0f;
-    float inv_len = hit ? 1.0f / rs.len_local : 0.0f;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) rs.dir[a] = df_f(rs.D[a]) * inv_len;
-    if (!hit) rs.dir[2] = 1.0f;
     // clip to the occupied-cell box [lo, hi) (no occupied cell lies outside it).
     // Direction components below 1e-20 of the largest are treated as zero: their
     // plane crossings lie beyond any representable ray parameter.

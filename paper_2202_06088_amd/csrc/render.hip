@@ -191,6 +191,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
 template <int K, int C>
 __host__ __device__ constexpr int grad_row() { return ((3 * K + C + 63) / 64) * 64; }
 
+// records a wavefront takes from its XCD's counter at a time
+constexpr int kRecBlock = 2048;
+// LDS rows per wavefront for the transposition of finished leaf rows
+constexpr int kFlushSlots = 16;
+
 
 template <int K, int C, int DT, bool IDENT>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) void render_bwd_kernel(
@@ -223,7 +228,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
     float Tr = 1.0f, Tfin = 0.0f, p0 = 0.0f, p1 = 0.0f, p2 = 0.0f, F0 = 0.0f, F1 = 0.0f, F2 = 0.0f;
     float g0 = 0.0f, g1 = 0.0f, g2 = 0.0f, ga = 0.0f;
     int ns = 0, ns_fwd = 0;
-    int rbase = -1;   // record of the ray's next sample; -1: its samples take the atomic scatter
+    // records: the wavefront fills blocks of kRecBlock consecutive records,
+    // taken from its XCD's part of the room; [wrec, wend) is what is left of
+    // the current block (wave-uniform)
+    int64_t wrec = 0, wend = 0;
 
     for (;;) {
         const uint64_t idle = __ballot(!alive);
@@ -232,7 +240,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
             // Acquisition: idle lanes take the next slots while at least refill_min
             // lanes are idle; rays that composited no sample carry no gradient and
             // are passed over. The setup then runs once for all taken rays together.
-            bool cand = false, fresh = false;
+            bool cand = false;
             for (;;) {
                 const uint64_t need = __ballot(!alive && !cand);
                 const int n_need = __popcll(need);
@@ -279,26 +287,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
                         for (int c = 0; c < C; ++c) gb[c] = 0.0f;
                     }
                     alive = true;
-                    fresh = true;
                 }
-            }
-            if (rec.head) {
-                // records for the rays taken this round: one atomic per wavefront
-                // hands out consecutive room for all their samples
-                const int want = fresh ? ns_fwd : 0;
-                int incl = want;
-#pragma unroll
-                for (int off = 1; off < kWave; off <<= 1) {
-                    const int v = __shfl_up(incl, off);
-                    if (lane >= off) incl += v;
-                }
-                const int total = __shfl(incl, kWave - 1);
-                unsigned long long b = 0;
-                if (lane == 0 && total > 0) b = atomicAdd(rec.counter, (unsigned long long)total);
-                const uint32_t b_lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)b);
-                const uint32_t b_hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(b >> 32));
-                const int64_t first = (int64_t)(((uint64_t)b_hi << 32) | b_lo) + (incl - want);
-                if (fresh) rbase = first + want <= rec.cap ? (int)first : -1;
             }
             continue;
         }
@@ -348,7 +337,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
 #pragma unroll
                 for (int c = 0; c < C; ++c) gb[c] = fmaf(gx, sv[c], gb[c]);
                 has = true;
-                if (rbase >= 0) my_rec = rbase + ns;
                 Tr = Tn;
                 ++ns;
                 finish = ns >= ns_fwd;
@@ -364,10 +352,32 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
                 alive = false;
             }
         }
-        if (my_rec >= 0) {
-            rec.g[my_rec] = make_float4(gz0, gz1, gz2, gx);
-            const int nxt = atomicExch(rec.head + leaf, my_rec);
-            rec.link[my_rec] = make_int2(nxt, (int)ray);
+        if (rec.head) {
+            // this iteration's samples take consecutive records in lane order, so
+            // the record stores of the wavefront are contiguous
+            const uint64_t hm = __ballot(has);
+            const int n_has = __popcll(hm);
+            if (n_has > 0 && wrec + n_has > wend) {
+                const int x = cc.home;
+                const int64_t lo = rec.cap * x / kQueues, hi = rec.cap * (x + 1) / kQueues;
+                unsigned long long b = 0;
+                if (lane == 0) b = atomicAdd(rec.counter + x * kQueueStride, (unsigned long long)kRecBlock);
+                const uint32_t b_lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)b);
+                const uint32_t b_hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(b >> 32));
+                const int64_t first = lo + (int64_t)(((uint64_t)b_hi << 32) | b_lo);
+                wrec = first;
+                wend = first + kRecBlock <= hi ? first + kRecBlock : (first < hi ? hi : first);
+            }
+            if (n_has > 0 && wrec + n_has <= wend) {
+                if (has) {
+                    my_rec = (int)(wrec + lane_rank(hm));
+                    rec.rec[2 * (int64_t)my_rec] =
+                        make_int4(__float_as_int(gz0), __float_as_int(gz1), __float_as_int(gz2), __float_as_int(gx));
+                    const int nxt = atomicExch(rec.head + leaf, my_rec);
+                    rec.rec[2 * (int64_t)my_rec + 1] = make_int4(nxt, (int)ray, 0, 0);
+                }
+                wrec += n_has;
+            }
         }
         // samples without a record: every lane of the wavefront adds one
         // component of each produced row
@@ -416,18 +426,24 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
 // ----------------------------------------------------------------------------
 // second pass of the two-phase adjoint
 //
-// One lane per leaf walks the leaf's record list: for every record it redoes
-// the ray's setup and basis (the same functions on the same inputs as the
-// adjoint, so h and b are those the sample used) and adds gz_ch h_k and
-// gx b_c into the row it holds in registers. The wavefront's 64 rows are then
-// transposed through LDS and each is added to the gradient array with one
-// atomic instruction of 3K + C lanes, as the per-sample scatter did, but once
-// per leaf.
+// Each lane sums one leaf's record list into a row held in registers: per
+// record it redoes the ray's local direction, time frames and basis (the
+// functions and inputs of the adjoint, so h and b are those the sample used)
+// and adds gz_ch h_k and gx b_c. Lists differ in length by an order of
+// magnitude, so a lane whose list has ended takes the next leaf of its
+// wavefront's batch instead of waiting for the longest list of the
+// wavefront (batches of 64 leaves, wavefront w taking batches w, w + W, ...:
+// a shared cursor would serialise on its one address). A finished row is
+// transposed through LDS and added to the gradient array with one atomic
+// instruction of 3K + C lanes, as the per-sample scatter did, but once per
+// leaf. The link of a lane's next record is loaded one record ahead.
 
-static __global__ void record_init_kernel(int32_t* head, int64_t n, unsigned long long* counter) {
+static __global__ void record_init_kernel(int32_t* head, int64_t n, unsigned long long* counter,
+                                          unsigned long long* leaf_cursor) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) head[i] = -1;
-    if (i == 0) *counter = 0ull;
+    if (i < kQueues) counter[i * kQueueStride] = 0ull;
+    if (i == 0) *leaf_cursor = 0ull;
 }
 
 template <int K, int C, bool IDENT>
@@ -435,26 +451,70 @@ __global__ __launch_bounds__(kBlock) void reduce_records_kernel(TreeArgs tr, Ins
                                                                 RecordArgs rec, float* grad_leaf) {
     constexpr int ROW = grad_row<K, C>();
     constexpr int R = 3 * K + C;
-    __shared__ float s_row[kBlock / kWave][kWave][R + 1];
+    __shared__ float s_row[kBlock / kWave][kFlushSlots][R + 1];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int64_t n_waves = (int64_t)gridDim.x * (kBlock / kWave);
-    for (int64_t base = ((int64_t)blockIdx.x * (kBlock / kWave) + wv) * kWave; base < tr.n_leaves;
-         base += n_waves * kWave) {
-        const int64_t L = base + lane;
-        int i = L < tr.n_leaves ? rec.head[L] : -1;
-        const bool any = i >= 0;
-        float acc[R];
+    const int N = (int)tr.n_leaves;
+
+    int leaf = -1;                // this lane's leaf; -1: idle
+    int4 ra0 = make_int4(0, 0, 0, 0), ra1 = make_int4(-1, 0, 0, 0);   // its current record
+    float acc[R];
 #pragma unroll
-        for (int c = 0; c < R; ++c) acc[c] = 0.0f;
-        while (i >= 0) {
-            const int2 lk = rec.link[i];
-            const float4 g = rec.g[i];
-            const int64_t ray = lk.y;
-            const float o[3] = {ra.o[3 * ray], ra.o[3 * ray + 1], ra.o[3 * ray + 2]};
-            const float d[3] = {ra.d[3 * ray], ra.d[3 * ray + 1], ra.d[3 * ray + 2]};
+    for (int c = 0; c < R; ++c) acc[c] = 0.0f;
+    int cur = 0, end = 0;         // wave-uniform: leaves [cur, end) of the batch not yet handed out
+    bool more = true;
+    const int64_t n_waves = (int64_t)gridDim.x * (kBlock / kWave);
+    int64_t batch = (int64_t)blockIdx.x * (kBlock / kWave) + wv;
+
+    for (;;) {
+        // hand leaves to idle lanes, passing over leaves without records
+        for (;;) {
+            const uint64_t idle = __ballot(leaf < 0);
+            if (!idle || !more) break;
+            if (cur >= end) {
+                const int64_t b0 = batch * kWave;
+                batch += n_waves;
+                if (b0 >= N) {
+                    more = false;
+                    break;
+                }
+                cur = (int)b0;
+                end = b0 + kWave < N ? (int)(b0 + kWave) : N;
+            }
+            const int avail = end - cur, n_idle = __popcll(idle);
+            if (leaf < 0) {
+                const int r = lane_rank(idle);
+                if (r < avail) {
+                    const int L = cur + r;
+                    const int h0 = rec.head[L];
+                    if (h0 >= 0) {
+                        leaf = L;
+                        ra0 = rec.rec[2 * (int64_t)h0];
+                        ra1 = rec.rec[2 * (int64_t)h0 + 1];
+                    }
+                }
+            }
+            cur += n_idle < avail ? n_idle : avail;
+        }
+        if (!__ballot(leaf >= 0)) break;   // no work left (more is false)
+        bool done = false;
+        if (leaf >= 0) {
+            const int nxt = ra1.x;
+            const int64_t ray = ra1.y;
+            // the next record is loaded while this one is summed
+            int4 nx0 = make_int4(0, 0, 0, 0), nx1 = make_int4(-1, 0, 0, 0);
+            if (nxt >= 0) {
+                nx0 = rec.rec[2 * (int64_t)nxt];
+                nx1 = rec.rec[2 * (int64_t)nxt + 1];
+            }
+            const float4 g = make_float4(__int_as_float(ra0.x), __int_as_float(ra0.y), __int_as_float(ra0.z),
+                                         __int_as_float(ra0.w));
+            const f3v dv = load3(ra.d + 3 * ray);
+            const float d[3] = {dv.x, dv.y, dv.z};
             const float t = ra.t ? ra.t[ray] : ra.t_scalar;
             RaySetup rs;
-            ray_setup<IDENT>(tr, in, o, d, t, rs);
+            float dmax;
+            ray_direction<IDENT>(in, d, rs, dmax);
+            time_setup(tr, in, t, rs.i0, rs.i1, rs.f);
             float h[K], bv[C];
             ray_basis<K, C>(tr, rs, h, bv);
 #pragma unroll
@@ -465,18 +525,35 @@ __global__ __launch_bounds__(kBlock) void reduce_records_kernel(TreeArgs tr, Ins
             }
 #pragma unroll
             for (int c = 0; c < C; ++c) acc[3 * K + c] = fmaf(g.w, bv[c], acc[3 * K + c]);
-            i = lk.x;
+            ra0 = nx0;
+            ra1 = nx1;
+            done = nxt < 0;
         }
+        // finished rows go through kFlushSlots LDS rows at a time (a few lanes
+        // finish per iteration)
+        uint64_t dm = __ballot(done);
+        while (dm) {
+            const int r = lane_rank(dm);
+            const bool mine = ((dm >> lane) & 1ull) && r < kFlushSlots;
+            if (mine) {
 #pragma unroll
-        for (int c = 0; c < R; ++c) s_row[wv][lane][c] = acc[c];
-        uint64_t m = __ballot(any);
-        __builtin_amdgcn_wave_barrier();
-        while (m) {
-            const int j = __builtin_ctzll(m);
-            m &= m - 1;
-            if (lane < R) unsafeAtomicAdd(grad_leaf + (base + j) * ROW + lane, s_row[wv][j][lane]);
+                for (int c = 0; c < R; ++c) {
+                    s_row[wv][r][c] = acc[c];
+                    acc[c] = 0.0f;
+                }
+            }
+            uint64_t sm = __ballot(mine);
+            __builtin_amdgcn_wave_barrier();
+            for (int q = 0; sm; ++q) {
+                const int j = __builtin_ctzll(sm);
+                sm &= sm - 1;
+                const int L = __builtin_amdgcn_readlane(leaf, j);
+                if (lane < R) unsafeAtomicAdd(grad_leaf + (int64_t)L * ROW + lane, s_row[wv][q][lane]);
+            }
+            __builtin_amdgcn_wave_barrier();
+            if (mine) leaf = -1;
+            dm = __ballot(done && leaf >= 0);
         }
-        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -560,22 +637,24 @@ template <int K, int C, int DT>
 static hipError_t bwd_t(const TreeArgs& tr, const InstArgs& in, const RayArgs& ra, const BackwardIO& io,
                         hipStream_t st) {
     // records need int32 ray and record indices
-    const int64_t cap = ra.n <= (int64_t)INT32_MAX && tr.n_leaves > 0 ? io.record_cap : 0;
+    const int64_t cap =
+        ra.n <= (int64_t)INT32_MAX && tr.n_leaves > 0 && tr.n_leaves <= (int64_t)INT32_MAX ? io.record_cap : 0;
     RecordArgs rec{};
     void* mem = nullptr;
     if (cap > 0) {
         const size_t head_b = ((size_t)tr.n_leaves * sizeof(int32_t) + 255) & ~(size_t)255;
-        const size_t link_b = (size_t)cap * sizeof(int2), g_b = (size_t)cap * sizeof(float4);
-        hipError_t e = work_alloc(&mem, 256 + head_b + link_b + g_b, st);
+        const size_t rec_b = (size_t)cap * 2 * sizeof(int4);
+        constexpr size_t hdr = 2048;   // kQueues counters 128 bytes apart, the leaf cursor
+        hipError_t e = work_alloc(&mem, hdr + head_b + rec_b, st);
         if (e != hipSuccess) return e;
         char* p = static_cast<char*>(mem);
         rec.counter = reinterpret_cast<unsigned long long*>(p);
-        rec.head = reinterpret_cast<int32_t*>(p + 256);
-        rec.link = reinterpret_cast<int2*>(p + 256 + head_b);
-        rec.g = reinterpret_cast<float4*>(p + 256 + head_b + link_b);
+        rec.leaf_cursor = reinterpret_cast<unsigned long long*>(p + 1024);
+        rec.head = reinterpret_cast<int32_t*>(p + hdr);
+        rec.rec = reinterpret_cast<int4*>(p + hdr + head_b);
         rec.cap = cap;
         hipLaunchKernelGGL(record_init_kernel, dim3((unsigned)((tr.n_leaves + 255) / 256)), dim3(256), 0, st,
-                           rec.head, tr.n_leaves, rec.counter);
+                           rec.head, tr.n_leaves, rec.counter, rec.leaf_cursor);
     }
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) {
@@ -589,8 +668,9 @@ static hipError_t bwd_t(const TreeArgs& tr, const InstArgs& in, const RayArgs& r
         e = hipGetLastError();
     }
     if (e == hipSuccess && cap > 0) {
+        // persistent: four blocks per CU
         int64_t blocks = (tr.n_leaves + kBlock - 1) / kBlock;
-        const int64_t lim = (int64_t)device_cu_count() * 8;
+        const int64_t lim = (int64_t)device_cu_count() * 4;
         if (blocks > lim) blocks = lim;
         if (in.identity)
             hipLaunchKernelGGL((reduce_records_kernel<K, C, true>), dim3((unsigned)blocks), dim3(kBlock), 0, st, tr,

@@ -200,12 +200,21 @@ __device__ __forceinline__ int stage_top_nodes(const TreeArgs& tr, int4* s_nodes
     return n_lds;
 }
 
+// 12-byte vector access to a ray's origin or direction, or a pixel's colour
+// (one dwordx3 memory instruction instead of three).
+typedef float f3v __attribute__((ext_vector_type(3)));
+__device__ __forceinline__ f3v load3(const float* p) {
+    f3v v;
+    __builtin_memcpy(&v, p, 12);
+    return v;
+}
+__device__ __forceinline__ void store3(float* p, float x, float y, float z) {
+    const f3v v = {x, y, z};
+    __builtin_memcpy(p, &v, 12);
+}
+
 __device__ __forceinline__ void write_miss(const RenderOut& out, int64_t ray) {
-    if (out.rgb) {
-        out.rgb[3 * ray] = 0.0f;
-        out.rgb[3 * ray + 1] = 0.0f;
-        out.rgb[3 * ray + 2] = 0.0f;
-    }
+    if (out.rgb) store3(out.rgb + 3 * ray, 0.0f, 0.0f, 0.0f);
     if (out.alpha) out.alpha[ray] = 0.0f;
     if (out.depth) out.depth[ray] = INFINITY;
     if (out.nsamp) out.nsamp[ray] = 0;
@@ -237,14 +246,14 @@ static __global__ void zero_queue_kernel(unsigned long long* q) { q[threadIdx.x]
 
 // Cull pass of the candidate form: each wavefront tests kCullGroup chunks of
 // one XCD part at a time (64 slots per chunk, one per lane), reserves room for
-// the rays it keeps with one atomic on the part's count, and lists them in
-// slot order. MODE 0 (forward): keep the rays the plain-float box test cannot
+// the rays it keeps with one atomic on the part's count (atomics on one
+// address serialise, so the groups are large), and lists them in slot order. MODE 0 (forward): keep the rays the plain-float box test cannot
 // reject and write the miss outputs of the others. MODE 1 (adjoint): keep the
 // rays whose forward composited a sample (the others carry no gradient). The
 // pass is bound by the 24 bytes of ray per slot it reads; at high occupancy
 // it runs near HBM bandwidth, where the render kernel's refill rounds would
 // take one memory latency per round for every ray.
-constexpr int kCullGroup = 8;
+constexpr int kCullGroup = 32;
 
 template <int MODE, bool IDENT>
 static __global__ __launch_bounds__(kBlock) void cull_kernel(TreeArgs tr, InstArgs in, RayArgs ra, RenderOut out,
@@ -267,8 +276,9 @@ static __global__ __launch_bounds__(kBlock) void cull_kernel(TreeArgs tr, InstAr
             bool k = false;
             if (ray >= 0) {
                 if constexpr (MODE == 0) {
-                    const float o[3] = {ra.o[3 * ray], ra.o[3 * ray + 1], ra.o[3 * ray + 2]};
-                    const float d[3] = {ra.d[3 * ray], ra.d[3 * ray + 1], ra.d[3 * ray + 2]};
+                    const f3v ov = load3(ra.o + 3 * ray), dv = load3(ra.d + 3 * ray);
+                    const float o[3] = {ov.x, ov.y, ov.z};
+                    const float d[3] = {dv.x, dv.y, dv.z};
                     k = ray_may_hit<IDENT>(tr, in, o, d);
                     if (!k) write_miss(out, ray);
                 } else {
