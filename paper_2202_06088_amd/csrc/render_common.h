@@ -265,6 +265,74 @@ static __global__ __launch_bounds__(kBlock) void cull_kernel(TreeArgs tr, InstAr
     const int64_t lo = n_chunks * x / kQueues, hi = n_chunks * (x + 1) / kQueues;
     const int64_t nw = (int64_t)(gridDim.x / kQueues) * (kBlock / kWave);
     const int64_t wi = (int64_t)(blockIdx.x / kQueues) * (kBlock / kWave) + (threadIdx.x >> 6);
+    if (ra.img_w > 0) {
+        // Images: a wavefront takes a segment of up to 8 horizontally adjacent
+        // tiles and walks its 8 pixel rows, one row of 64 pixels per pass, so
+        // its ray loads and miss stores are contiguous; the rays kept are then
+        // listed tile by tile in slot order from the per-row ballots.
+        if (hi <= lo) return;
+        const int64_t tiles_x = ra.tiles_x;
+        const int64_t ty_lo = lo / tiles_x, ty_hi = (hi - 1) / tiles_x;
+        const int64_t nseg = (tiles_x + 7) / 8;
+        const int64_t n_seg = (ty_hi - ty_lo + 1) * nseg;
+        const int jt = lane >> 3;   // tile of the lane within the segment
+        for (int64_t sg = wi; sg < n_seg; sg += nw) {
+            const int64_t ty = ty_lo + sg / nseg, j = sg - (sg / nseg) * nseg;
+            const int64_t row0 = ty * tiles_x;
+            int64_t kx0 = 8 * j, kx1 = 8 * j + 8 < tiles_x ? 8 * j + 8 : tiles_x;
+            if (kx0 < lo - row0) kx0 = lo - row0;
+            if (kx1 > hi - row0) kx1 = hi - row0;
+            if (kx0 >= kx1) continue;   // wave-uniform
+            const int64_t tx = 8 * j + jt;
+            const int64_t px = 8 * tx + (lane & 7);
+            const bool lane_ok = tx >= kx0 && tx < kx1 && px < ra.img_w;
+            uint64_t keep[8];
+            int total = 0;
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                const int64_t ray = (8 * ty + r) * ra.img_w + px;
+                bool k = false;
+                if (lane_ok && ray < ra.n) {
+                    if constexpr (MODE == 0) {
+                        const f3v ov = load3(ra.o + 3 * ray), dv = load3(ra.d + 3 * ray);
+                        const float o[3] = {ov.x, ov.y, ov.z};
+                        const float d[3] = {dv.x, dv.y, dv.z};
+                        k = ray_may_hit<IDENT>(tr, in, o, d);
+                        if (!k) write_miss(out, ray);
+                    } else {
+                        k = nsamp[ray] > 0;
+                    }
+                }
+                keep[r] = __ballot(k);
+                total += __popcll(keep[r]);
+            }
+            if (total == 0) continue;   // wave-uniform
+            unsigned long long b = 0;
+            if (lane == 0) b = atomicAdd(count + x * kQueueStride, (unsigned long long)total);
+            const uint32_t b_lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)b);
+            const uint32_t b_hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(b >> 32));
+            const int64_t at = lo * 64 + (int64_t)(((uint64_t)b_hi << 32) | b_lo);
+            // this lane's tile: its kept-slot mask (bit 8r + column) and the rays
+            // kept in the segment's earlier tiles
+            uint64_t tm = 0ull;
+            int before = 0;
+            const uint64_t below = jt ? (~0ull >> (64 - 8 * jt)) : 0ull;
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                tm |= ((keep[r] >> (8 * jt)) & 0xffull) << (8 * r);
+                before += __popcll(keep[r] & below);
+            }
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                if ((keep[r] >> lane) & 1ull) {
+                    const int within = 8 * r + (lane & 7);
+                    const int64_t ray = (8 * ty + r) * ra.img_w + px;
+                    list[at + before + __popcll(tm & ((1ull << within) - 1ull))] = (int32_t)ray;
+                }
+            }
+        }
+        return;
+    }
     for (int64_t c0 = lo + wi * kCullGroup; c0 < hi; c0 += nw * kCullGroup) {
         uint64_t keep[kCullGroup];
         int32_t rays[kCullGroup];
