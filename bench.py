@@ -33,7 +33,8 @@ sys.path.insert(0, ROOT)
 METRIC = "Mrays/s fwd and fwd+bwd at 1080p; achieved HBM GB/s vs peak; PSNR vs FP64"
 PEAK_HBM_GBS = 8000.0
 FWD_RAY_IO_B = 24 + 24                      # o, d in; rgb, alpha, depth, nsamp out
-BWD_RAY_IO_B = 24 + 20 + 12                 # o, d; rgb, alpha, nsamp; grad_rgb
+BWD_RAY_NSAMP_B = 4                         # every ray: nsamp (rays without samples carry no gradient)
+BWD_HIT_IO_B = 24 + 16 + 12                 # rays with samples: o, d; rgb, alpha; grad_rgb
 
 
 def log(msg):
@@ -169,8 +170,14 @@ def main():
     hit = int((ns > 0).sum())
     values = 3 * tree.K + tree.C + tree.Cg                   # per sample: HH, density and hyperangle values
     payload_b = values * (4 if dt == _lib.F32 else 2)
+    # leaves whose gradient row the adjoint changes (each row is read and written once)
+    grads = tree.zero_grads()
+    bwd()
+    torch.cuda.synchronize()
+    touched = int((grads[0][:, :values] != 0).any(dim=1).sum().item())
     fwd_bytes = total_samples * payload_b + n * FWD_RAY_IO_B
-    bwd_bytes = total_samples * (payload_b + 2 * 4 * values) + n * BWD_RAY_IO_B   # + FP32 atomic read-modify-write
+    bwd_bytes = (total_samples * payload_b + touched * 2 * 4 * values + n * BWD_RAY_NSAMP_B +
+                 hit * BWD_HIT_IO_B)
     log(f"fwd {fwd_ms:.3f} ms, bwd {bwd_ms:.3f} ms per launch; step {ms_step:.3f} ms; "
         f"{total_samples} samples, {hit} hit rays")
     kern = {"render_fwd": (fwd_ms, fwd_bytes), "render_bwd": (bwd_ms, bwd_bytes)}
@@ -195,7 +202,7 @@ def main():
                    "T": sc.T, "rays_per_step": n, "image": "8 x 1920x1080", "t_stop": t_stop,
                    "step": "render fwd + adjoint", "layout": args.layout},
         "fwd_mrays_s": round(n / (fwd_ms * 1e-3) / 1e6, 2),
-        "samples_per_step": total_samples, "hit_rays": hit,
+        "samples_per_step": total_samples, "hit_rays": hit, "leaves_touched": touched,
         "roofline": roof, "roofline_other_kernel": roof_other,
     }
 

@@ -191,10 +191,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
 template <int K, int C>
 __host__ __device__ constexpr int grad_row() { return ((3 * K + C + 63) / 64) * 64; }
 
-// records a wavefront takes from its XCD's counter at a time
-constexpr int kRecBlock = 2048;
-// LDS rows per wavefront for the transposition of finished leaf rows
-constexpr int kFlushSlots = 16;
 
 
 template <int K, int C, int DT, bool IDENT>
@@ -438,13 +434,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
 // instruction of 3K + C lanes, as the per-sample scatter did, but once per
 // leaf. The link of a lane's next record is loaded one record ahead.
 
-static __global__ void record_init_kernel(int32_t* head, int64_t n, unsigned long long* counter,
-                                          unsigned long long* leaf_cursor) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) head[i] = -1;
-    if (i < kQueues) counter[i * kQueueStride] = 0ull;
-    if (i == 0) *leaf_cursor = 0ull;
-}
 
 template <int K, int C, bool IDENT>
 __global__ __launch_bounds__(kBlock) void reduce_records_kernel(TreeArgs tr, InstArgs in, RayArgs ra,
@@ -641,22 +630,7 @@ static hipError_t bwd_t(const TreeArgs& tr, const InstArgs& in, const RayArgs& r
         ra.n <= (int64_t)INT32_MAX && tr.n_leaves > 0 && tr.n_leaves <= (int64_t)INT32_MAX ? io.record_cap : 0;
     RecordArgs rec{};
     void* mem = nullptr;
-    if (cap > 0) {
-        const size_t head_b = ((size_t)tr.n_leaves * sizeof(int32_t) + 255) & ~(size_t)255;
-        const size_t rec_b = (size_t)cap * 2 * sizeof(int4);
-        constexpr size_t hdr = 2048;   // kQueues counters 128 bytes apart, the leaf cursor
-        hipError_t e = work_alloc(&mem, hdr + head_b + rec_b, st);
-        if (e != hipSuccess) return e;
-        char* p = static_cast<char*>(mem);
-        rec.counter = reinterpret_cast<unsigned long long*>(p);
-        rec.leaf_cursor = reinterpret_cast<unsigned long long*>(p + 1024);
-        rec.head = reinterpret_cast<int32_t*>(p + hdr);
-        rec.rec = reinterpret_cast<int4*>(p + hdr + head_b);
-        rec.cap = cap;
-        hipLaunchKernelGGL(record_init_kernel, dim3((unsigned)((tr.n_leaves + 255) / 256)), dim3(256), 0, st,
-                           rec.head, tr.n_leaves, rec.counter, rec.leaf_cursor);
-    }
-    hipError_t e = hipGetLastError();
+    hipError_t e = records_begin(tr, cap, st, rec, mem);
     if (e == hipSuccess) {
         if (in.identity) {
             auto kern = render_bwd_kernel<K, C, DT, true>;

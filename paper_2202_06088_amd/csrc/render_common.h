@@ -428,4 +428,44 @@ static hipError_t with_candidates(const TreeArgs& tr, const InstArgs& in, const 
     return e != hipSuccess ? e : f;
 }
 
+// ----------------------------------------------------------------------------
+// records of the two-phase adjoint (see RecordArgs)
+
+// records a wavefront takes from its XCD's counter at a time
+constexpr int kRecBlock = 2048;
+// LDS rows per wavefront for the transposition of finished leaf rows
+constexpr int kFlushSlots = 16;
+
+static __global__ void record_init_kernel(int32_t* head, int64_t n, unsigned long long* counter,
+                                          unsigned long long* leaf_cursor) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) head[i] = -1;
+    if (i < kQueues) counter[i * kQueueStride] = 0ull;
+    if (i == 0) *leaf_cursor = 0ull;
+}
+
+// Takes the record scratch of one adjoint launch (cap > 0) from the pool and
+// queues its initialisation: kQueues counters 128 bytes apart and a leaf
+// cursor, the leaf heads (-1) and room for cap records of 32 bytes. With
+// cap == 0 rec stays empty (per-sample atomics only).
+static hipError_t records_begin(const TreeArgs& tr, int64_t cap, hipStream_t st, RecordArgs& rec, void*& mem) {
+    rec = RecordArgs{};
+    mem = nullptr;
+    if (cap <= 0) return hipSuccess;
+    const size_t head_b = ((size_t)tr.n_leaves * sizeof(int32_t) + 255) & ~(size_t)255;
+    const size_t rec_b = (size_t)cap * 2 * sizeof(int4);
+    constexpr size_t hdr = 2048;
+    hipError_t e = work_alloc(&mem, hdr + head_b + rec_b, st);
+    if (e != hipSuccess) return e;
+    char* p = static_cast<char*>(mem);
+    rec.counter = reinterpret_cast<unsigned long long*>(p);
+    rec.leaf_cursor = reinterpret_cast<unsigned long long*>(p + 1024);
+    rec.head = reinterpret_cast<int32_t*>(p + hdr);
+    rec.rec = reinterpret_cast<int4*>(p + hdr + head_b);
+    rec.cap = cap;
+    hipLaunchKernelGGL(record_init_kernel, dim3((unsigned)((tr.n_leaves + 255) / 256)), dim3(256), 0, st, rec.head,
+                       tr.n_leaves, rec.counter, rec.leaf_cursor);
+    return hipGetLastError();
+}
+
 }  // namespace neuvv

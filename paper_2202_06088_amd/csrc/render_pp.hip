@@ -27,10 +27,10 @@ constexpr int K = 14;
 constexpr int C = 31;
 constexpr int CG = 31;
 constexpr int ROW = ((3 * K + C + CG + 63) / 64) * 64;   // 128
-// cells per walk call in the adjoint: every loop iteration with a sample
-// pays the wavefront-wide butterfly of the basis gradients, so its walk
-// takes longer strides than the forward's
-constexpr int kWalkBudgetBwd = 8;
+// cells per walk call in the adjoint (as in the forward: the basis gradients'
+// wavefront-wide butterfly, which made longer strides pay, only runs for
+// samples without a record)
+constexpr int kWalkBudgetBwd = kWalkBudget;
 constexpr int kLdsNodes = 1024;
 constexpr float kPi = 3.14159265358979323846f;
 }  // namespace pp
@@ -238,7 +238,7 @@ __device__ __forceinline__ int pp_component(int j, int lane) { return j * kWave 
 
 template <int DT, bool IDENT>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) void render_pp_bwd_kernel(
-    TreeArgs tr, InstArgs in, RayArgs ra, BackwardIO io) {
+    TreeArgs tr, InstArgs in, RayArgs ra, BackwardIO io, RecordArgs rec) {
     using namespace pp;
     __shared__ int4 s_nodes[kLdsNodes];
     __shared__ int s_path[kMaxLevels * kBlock];
@@ -269,6 +269,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) 
     // scalar time: lane c < C holds component c of the density-basis gradient
     // (bacc[0]) and, c < CG, of the hyperangle-basis gradient (bacc[1])
     float bacc[2] = {0.0f, 0.0f};
+    // records (scalar time only): [wrec, wend) is what is left of the
+    // wavefront's current block of records (wave-uniform)
+    int64_t wrec = 0, wend = 0;
 
     for (;;) {
         const uint64_t idle = __ballot(!alive);
@@ -316,7 +319,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) 
         }
         if (n_idle == kWave) break;
         bool has = false;
-        int leaf = -1;
+        int leaf = -1, my_rec = -1;
         float gz0 = 0.0f, gz1 = 0.0f, gz2 = 0.0f, gx = 0.0f, gy = 0.0f;
         if (alive) {
             float delta, umid;
@@ -360,6 +363,35 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) 
             }
             if (finish) alive = false;
         }
+        if (rec.head) {
+            // records: this iteration's samples take consecutive records in lane
+            // order; their leaf rows and basis gradients are summed per leaf later
+            const uint64_t hm = __ballot(has);
+            const int n_has = __popcll(hm);
+            if (n_has > 0 && wrec + n_has > wend) {
+                const int x = cc.home;
+                const int64_t lo = rec.cap * x / kQueues, hi = rec.cap * (x + 1) / kQueues;
+                unsigned long long b = 0;
+                if (lane == 0) b = atomicAdd(rec.counter + x * kQueueStride, (unsigned long long)kRecBlock);
+                const uint32_t b_lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)b);
+                const uint32_t b_hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(b >> 32));
+                const int64_t first = lo + (int64_t)(((uint64_t)b_hi << 32) | b_lo);
+                wrec = first;
+                wend = first + kRecBlock <= hi ? first + kRecBlock : (first < hi ? hi : first);
+            }
+            if (n_has > 0 && wrec + n_has <= wend) {
+                if (has) {
+                    my_rec = (int)(wrec + lane_rank(hm));
+                    rec.rec[2 * (int64_t)my_rec] =
+                        make_int4(__float_as_int(gz0), __float_as_int(gz1), __float_as_int(gz2), __float_as_int(gx));
+                    const int nxt = atomicExch(rec.head + leaf, my_rec);
+                    rec.rec[2 * (int64_t)my_rec + 1] = make_int4(nxt, (int)ray, __float_as_int(gy), 0);
+                }
+                wrec += n_has;
+            }
+        }
+        // samples without a record: basis gradients and the atomic row scatter
+        has = has && my_rec < 0;
         uint64_t m = __ballot(has);
         if (common_t && m) {
             // basis gradients of this step: sum over the wavefront's samples of
@@ -458,6 +490,180 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) 
 }
 
 // ----------------------------------------------------------------------------
+// second pass of the two-phase adjoint (scalar time)
+//
+// One lane per leaf, with lane refill as in the global form. With one time
+// for every ray the leaf's hyperangle gamma, hence its radial factors g, are
+// the same for all its samples: they are computed once when the lane takes
+// the leaf. Per record the lane redoes the ray's direction and its degree-2
+// harmonics Y (the adjoint's functions and inputs), forms h = hh14(g, Y) and
+// adds gz_ch h_k; the density and hyperangle parts of the row are
+// (sum gx) B(tau) and (sum gy) B^gamma(tau), and the basis gradients
+// (sum gx) w^sigma and (sum gy) w^gamma, so only the 42 HH sums and the two
+// scalar sums are held.
+
+template <int DT, bool IDENT>
+__global__ __launch_bounds__(kBlock) void reduce_pp_records_kernel(TreeArgs tr, InstArgs in, RayArgs ra,
+                                                                   RecordArgs rec, BackwardIO io) {
+    using namespace pp;
+    constexpr int R = 3 * K + 2;   // HH sums, sum gx, sum gy
+    // a finished leaf's slot: its sums, then its w^sigma and w^gamma rows
+    __shared__ float s_row[kBlock / kWave][kFlushSlots][R + C + CG + 1];
+    __shared__ float s_brow[C], s_bgrow[CG];
+    __shared__ float s_acc[2 * kWave];
+    stage_common_rows(tr, in, ra.t_scalar, s_brow, s_bgrow);
+    if (threadIdx.x < 2 * kWave) s_acc[threadIdx.x] = 0.0f;
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int N = (int)tr.n_leaves;
+    const int64_t n_waves = (int64_t)gridDim.x * (kBlock / kWave);
+    int64_t batch = (int64_t)blockIdx.x * (kBlock / kWave) + wv;
+
+    int leaf = -1;
+    int4 ra0 = make_int4(0, 0, 0, 0), ra1 = make_int4(-1, 0, 0, 0);
+    float g[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) g[q] = 0.0f;
+    float acc[R];
+#pragma unroll
+    for (int c = 0; c < R; ++c) acc[c] = 0.0f;
+    float bacc[2] = {0.0f, 0.0f};   // lane c: components c of the two basis gradients
+    int cur = 0, end = 0;
+    bool more = true;
+
+    for (;;) {
+        for (;;) {
+            const uint64_t idle = __ballot(leaf < 0);
+            if (!idle || !more) break;
+            if (cur >= end) {
+                const int64_t b0 = batch * kWave;
+                batch += n_waves;
+                if (b0 >= N) {
+                    more = false;
+                    break;
+                }
+                cur = (int)b0;
+                end = b0 + kWave < N ? (int)(b0 + kWave) : N;
+            }
+            const int avail = end - cur, n_idle = __popcll(idle);
+            if (leaf < 0) {
+                const int r = lane_rank(idle);
+                if (r < avail) {
+                    const int L = cur + r;
+                    const int h0 = rec.head[L];
+                    if (h0 >= 0) {
+                        leaf = L;
+                        ra0 = rec.rec[2 * (int64_t)h0];
+                        ra1 = rec.rec[2 * (int64_t)h0 + 1];
+                        float gv[CG];
+                        load_leaf<DT, CG>(tr.wgam, tr.n_leaves, L, tr.layout, gv);
+                        float y = 0.0f;
+#pragma unroll
+                        for (int c = 0; c < CG; ++c) y = fmaf(gv[c], s_bgrow[c], y);
+                        const float gam = kPi * sigmoid_f(y);
+                        float sn, cs, dg[6];
+                        sincosf(gam, &sn, &cs);
+                        radial_n2(sn, cs, g, dg);
+                    }
+                }
+            }
+            cur += n_idle < avail ? n_idle : avail;
+        }
+        if (!__ballot(leaf >= 0)) break;
+        bool done = false;
+        if (leaf >= 0) {
+            const int nxt = ra1.x;
+            const int64_t ray = ra1.y;
+            int4 nx0 = make_int4(0, 0, 0, 0), nx1 = make_int4(-1, 0, 0, 0);
+            if (nxt >= 0) {
+                nx0 = rec.rec[2 * (int64_t)nxt];
+                nx1 = rec.rec[2 * (int64_t)nxt + 1];
+            }
+            const float gz0 = __int_as_float(ra0.x), gz1 = __int_as_float(ra0.y), gz2 = __int_as_float(ra0.z);
+            const f3v dv = load3(ra.d + 3 * ray);
+            const float d[3] = {dv.x, dv.y, dv.z};
+            RaySetup rs;
+            float dmax;
+            ray_direction<IDENT>(in, d, rs, dmax);
+            float Y[8], h[K];
+            sh_deg2(rs.dir[0], rs.dir[1], rs.dir[2], Y);
+            hh14(g, Y, h);
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                acc[k] = fmaf(gz0, h[k], acc[k]);
+                acc[K + k] = fmaf(gz1, h[k], acc[K + k]);
+                acc[2 * K + k] = fmaf(gz2, h[k], acc[2 * K + k]);
+            }
+            acc[3 * K] += __int_as_float(ra0.w);
+            acc[3 * K + 1] += __int_as_float(ra1.z);
+            ra0 = nx0;
+            ra1 = nx1;
+            done = nxt < 0;
+        }
+        uint64_t dm = __ballot(done);
+        while (dm) {
+            const int r = lane_rank(dm);
+            const bool mine = ((dm >> lane) & 1ull) && r < kFlushSlots;
+            if (mine) {
+                // the weights for the basis gradients, loaded by all finishing
+                // lanes at once rather than one leaf at a time below
+                float sv[C], gv[CG];
+                load_leaf<DT, C>(tr.wsig, tr.n_leaves, leaf, tr.layout, sv);
+                load_leaf<DT, CG>(tr.wgam, tr.n_leaves, leaf, tr.layout, gv);
+#pragma unroll
+                for (int c = 0; c < R; ++c) {
+                    s_row[wv][r][c] = acc[c];
+                    acc[c] = 0.0f;
+                }
+#pragma unroll
+                for (int c = 0; c < C; ++c) s_row[wv][r][R + c] = sv[c];
+#pragma unroll
+                for (int c = 0; c < CG; ++c) s_row[wv][r][R + C + c] = gv[c];
+            }
+            uint64_t sm = __ballot(mine);
+            __builtin_amdgcn_wave_barrier();
+            for (int q = 0; sm; ++q) {
+                const int j = __builtin_ctzll(sm);
+                sm &= sm - 1;
+                const int L = __builtin_amdgcn_readlane(leaf, j);
+                const float sgx = s_row[wv][q][3 * K], sgy = s_row[wv][q][3 * K + 1];
+                float* row = io.grad_leaf + (int64_t)L * ROW;
+#pragma unroll
+                for (int jj = 0; jj < 2; ++jj) {
+                    const int c = pp_component(jj, lane);
+                    if (c < 3 * K) unsafeAtomicAdd(row + c, s_row[wv][q][c]);
+                    else if (c < 3 * K + C) unsafeAtomicAdd(row + c, sgx * s_brow[c - 3 * K]);
+                    else if (c < 3 * K + C + CG) unsafeAtomicAdd(row + c, sgy * s_bgrow[c - 3 * K - C]);
+                }
+                if (lane < C) bacc[0] = fmaf(sgx, s_row[wv][q][R + lane], bacc[0]);
+                if (lane < CG) bacc[1] = fmaf(sgy, s_row[wv][q][R + C + lane], bacc[1]);
+            }
+            __builtin_amdgcn_wave_barrier();
+            if (mine) leaf = -1;
+            dm = __ballot(done && leaf >= 0);
+        }
+    }
+    // basis gradients: sum over the block, spread over the two interpolated rows
+    if (lane < C) atomicAdd(&s_acc[lane], bacc[0]);
+    if (lane < CG) atomicAdd(&s_acc[kWave + lane], bacc[1]);
+    __syncthreads();
+    const int c = threadIdx.x;
+    const bool dens = c < C;
+    const bool gam = c >= kWave && c < kWave + CG;
+    float* gB = dens ? io.grad_basis : io.grad_basis_g;
+    if ((dens || gam) && gB) {
+        const int e = dens ? c : c - kWave;
+        const int Rb = dens ? C : CG;
+        int i0, i1;
+        float f;
+        time_setup(tr, in, ra.t_scalar, i0, i1, f);
+        const float v = s_acc[c];
+        unsafeAtomicAdd(gB + (int64_t)i0 * Rb + e, (1.0f - f) * v);
+        if (f != 0.0f) unsafeAtomicAdd(gB + (int64_t)i1 * Rb + e, f * v);
+    }
+}
+
+// ----------------------------------------------------------------------------
 // launchers
 
 template <int DT>
@@ -476,14 +682,41 @@ static hipError_t pp_fwd_t(const TreeArgs& tr, const InstArgs& in, const RayArgs
 template <int DT>
 static hipError_t pp_bwd_t(const TreeArgs& tr, const InstArgs& in, const RayArgs& ra, const BackwardIO& io,
                            hipStream_t st) {
-    if (in.identity) {
-        auto kern = render_pp_bwd_kernel<DT, true>;
-        hipLaunchKernelGGL(kern, dim3(grid_for(kern, ra)), dim3(kBlock), 0, st, tr, in, ra, io);
-    } else {
-        auto kern = render_pp_bwd_kernel<DT, false>;
-        hipLaunchKernelGGL(kern, dim3(grid_for(kern, ra)), dim3(kBlock), 0, st, tr, in, ra, io);
+    // records with one time for every ray (the per-leaf sums rely on it)
+    const int64_t cap = ra.t == nullptr && ra.n <= (int64_t)INT32_MAX && tr.n_leaves > 0 &&
+                                tr.n_leaves <= (int64_t)INT32_MAX
+                            ? io.record_cap
+                            : 0;
+    RecordArgs rec{};
+    void* mem = nullptr;
+    hipError_t e = records_begin(tr, cap, st, rec, mem);
+    if (e == hipSuccess) {
+        if (in.identity) {
+            auto kern = render_pp_bwd_kernel<DT, true>;
+            hipLaunchKernelGGL(kern, dim3(grid_for(kern, ra)), dim3(kBlock), 0, st, tr, in, ra, io, rec);
+        } else {
+            auto kern = render_pp_bwd_kernel<DT, false>;
+            hipLaunchKernelGGL(kern, dim3(grid_for(kern, ra)), dim3(kBlock), 0, st, tr, in, ra, io, rec);
+        }
+        e = hipGetLastError();
     }
-    return hipGetLastError();
+    if (e == hipSuccess && cap > 0) {
+        int64_t blocks = (tr.n_leaves + kBlock - 1) / kBlock;
+        const int64_t lim = (int64_t)device_cu_count() * 4;
+        if (blocks > lim) blocks = lim;
+        if (in.identity)
+            hipLaunchKernelGGL((reduce_pp_records_kernel<DT, true>), dim3((unsigned)blocks), dim3(kBlock), 0, st, tr,
+                               in, ra, rec, io);
+        else
+            hipLaunchKernelGGL((reduce_pp_records_kernel<DT, false>), dim3((unsigned)blocks), dim3(kBlock), 0, st,
+                               tr, in, ra, rec, io);
+        e = hipGetLastError();
+    }
+    if (mem) {
+        const hipError_t f = work_free(mem, st);
+        if (e == hipSuccess) e = f;
+    }
+    return e;
 }
 
 hipError_t launch_render_pp_fwd(int dtype, const TreeArgs& tr, const InstArgs& in, const RayArgs& ra, float t_stop,
