@@ -12,13 +12,16 @@
  *   - Pointers named "device" are HIP device pointers owned by the caller;
  *     pointers named "host" are host memory owned by the caller. The library
  *     keeps no pointer after a call returns. The only device memory it
- *     allocates is per-call scratch of the render calls (neuvv_render,
- *     neuvv_render_backward, neuvv_find_terminal_leaves; neuvv_render_multi takes the counters only):
- *     2 KiB of work-queue counters plus a candidate list of 4 bytes per work
- *     slot (rounded up to 64 slots), taken in stream order on the call's
- *     stream from a memory pool the library keeps per device (it keeps freed
- *     memory for later calls) and freed in stream order after the kernels;
- *     each call has its own, so calls on different streams do not interfere.
+ *     allocates is per-call scratch of the render calls: neuvv_render,
+ *     neuvv_render_backward and neuvv_find_terminal_leaves take 2 KiB of
+ *     work-queue counters plus a candidate list of 4 bytes per work slot
+ *     (rounded up to 64 slots); neuvv_render_backward also takes the records
+ *     of its two-phase adjoint (4 bytes per leaf plus 32 bytes per record of
+ *     room, see there); neuvv_render_multi takes the counters only. Scratch
+ *     is taken in stream order on the call's stream from a memory pool the
+ *     library keeps per device (it keeps freed memory for later calls) and
+ *     freed in stream order after the kernels; each call has its own, so
+ *     calls on different streams do not interfere.
  *   - "stream" is a hipStream_t (NULL = the null stream). GPU work is queued
  *     on it asynchronously; the caller synchronises. Argument errors are
  *     detected on the host before anything is queued.
@@ -264,7 +267,17 @@ int neuvv_render(const neuvv_tree* tree, const neuvv_instance* inst, int64_t n_r
  * per sample is stored by the forward pass):
  *     dL/dsigma_k = delta_k (T_{k+1} <g, c_k> - <g, rgb - rgb_{<=k}>) + g_a delta_k T_final
  *     dL/dz_k,ch  = g_ch w_k c_k,ch (1 - c_k,ch)
- * and scatter-adds (atomically) into the leaf gradients and the basis rows.
+ * and adds them (atomically) into the leaf gradients and the basis rows.
+ * Two-phase adjoint: each sample's dL/dz and dL/dsigma (and dL/dy, Cg > 0)
+ * are written once as a 32-byte record linked into its leaf's list; a second
+ * kernel sums every list and adds each touched leaf's row once. The room for
+ * records is 2 per ray, at least 2^20, at most 2^31 - 1 (the environment
+ * variable NEUVV_BWD_RECORDS, read at every call, sets it; 0 turns records
+ * off); samples beyond it are added per sample in the same call. Records
+ * are used with image_width or not, for n_rays and n_leaves below 2^31, and
+ * with Cg > 0 only when ray_t is NULL (one time for all rays). Summation
+ * order follows the atomics, so results may differ between runs in the last
+ * bits, as with any atomic accumulation.
  * Arguments as neuvv_render, plus
  * rgb, alpha, nsamp  device forward outputs for the same rays and inputs.
  * grad_rgb        device [n][3]; grad_alpha device [n] or NULL (zero).

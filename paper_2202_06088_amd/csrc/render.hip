@@ -181,12 +181,20 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
 // ----------------------------------------------------------------------------
 // adjoint
 //
-// Scatter of the leaf gradients, transposed: a sample's 3K + C gradient values
-// form one row of the leaf-major gradient array, and the whole wavefront adds
-// that row with one atomic instruction (lane c = component c). An atomic whose
-// lanes fall in one 256-byte row is handled as a couple of L2 line
-// operations, where one whose lanes hit 64 different leaves costs 64; the
-// per-ray basis h and density row b every lane needs for this are kept in LDS.
+// Two phases. Here each ray replays its samples and writes, per sample, a
+// 32-byte record of its gradients with respect to the colour logits and the
+// density logit, linked into the list of its leaf; reduce_records_kernel
+// below then sums every leaf's list and adds the leaf's row once. Records
+// are taken in blocks per wavefront and written at consecutive indices, so
+// the record stores of a wavefront are contiguous.
+//
+// Samples without a record (the room is full, or records are off) take the
+// per-sample scatter: a sample's 3K + C gradient values form one row of the
+// leaf-major gradient array, and the whole wavefront adds that row with one
+// atomic instruction (lane c = component c). An atomic whose lanes fall in
+// one 256-byte row is handled as a couple of line operations, where one
+// whose lanes hit 64 different leaves costs 64; the per-ray basis h and
+// density row b every lane needs for this are kept in LDS.
 
 template <int K, int C>
 __host__ __device__ constexpr int grad_row() { return ((3 * K + C + 63) / 64) * 64; }
