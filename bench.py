@@ -21,6 +21,7 @@ import argparse
 import hashlib
 import json
 import math
+import re
 import os
 import sys
 import time
@@ -42,12 +43,15 @@ def log(msg):
 
 
 def kernel_source_hash(workload: str) -> str:
-    """Hash of the sources the workload's render kernels are built from."""
+    """Hash of the sources the workload's render kernels are built from, comments and blank lines
+    left out (a comment edit does not change the kernels)."""
     main = "render_pp.hip" if workload.endswith("per_point") else "render.hip"
     h = hashlib.sha256()
     for f in (main, "render_common.h", "neuvv_device.h"):
-        with open(os.path.join(ROOT, "paper_2202_06088_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2202_06088_amd", "csrc", f), encoding="utf-8") as fh:
+            text = re.sub(r"/\*.*?\*/", "", fh.read(), flags=re.S)
+        lines = [ln.split("//", 1)[0].rstrip() for ln in text.splitlines()]
+        h.update("\n".join(ln for ln in lines if ln.strip()).encode())
     return h.hexdigest()[:16]
 
 
