@@ -36,6 +36,7 @@ PEAK_HBM_GBS = 8000.0
 FWD_RAY_IO_B = 24 + 24                      # o, d in; rgb, alpha, depth, nsamp out
 BWD_RAY_NSAMP_B = 4                         # every ray: nsamp (rays without samples carry no gradient)
 BWD_HIT_IO_B = 24 + 16 + 12                 # rays with samples: o, d; rgb, alpha; grad_rgb
+TRACE_SAMPLE_B = 32                         # traced step: one trace entry per sample
 
 
 def log(msg):
@@ -88,6 +89,9 @@ def main():
                          "render with the edits active")
     ap.add_argument("--multi", type=int, default=0,
                     help="also time the exact merge of this many (2..4) interpenetrating placements of the tree")
+    ap.add_argument("--no-trace", action="store_true",
+                    help="time neuvv_render + neuvv_render_backward (the adjoint walks again) instead of the traced "
+                         "pair (the adjoint replays the forward's per-sample trace; K = 16, C = 8 form)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -141,13 +145,28 @@ def main():
     stream = torch.cuda.current_stream()
     t_stop = 1e-4
 
+    traced = not args.no_trace and tree.Cg == 0
+    # trace room: one sample per ray covers the ring (0.69 per ray); a ray whose samples do not fit
+    # would be walked again by the adjoint
+    trace_cap = n
+    trace = torch.empty(_lib.neuvv_trace_bytes(n, trace_cap), dtype=torch.uint8, device=dev) if traced else None
+
     def fwd():
-        _lib.neuvv_render(tree.struct(), None, n, ray_o, ray_d, None, t_frame, W, t_stop, rgb, alpha, depth, nsamp,
-                          stream)
+        if traced:
+            _lib.neuvv_render_trace(tree.struct(), None, n, ray_o, ray_d, None, t_frame, W, t_stop, rgb, alpha, depth,
+                                    nsamp, trace, trace_cap, stream)
+        else:
+            _lib.neuvv_render(tree.struct(), None, n, ray_o, ray_d, None, t_frame, W, t_stop, rgb, alpha, depth,
+                              nsamp, stream)
 
     def bwd():
-        _lib.neuvv_render_backward(tree.struct(), None, n, ray_o, ray_d, None, t_frame, W, t_stop, rgb, alpha, nsamp,
-                                   g_rgb, None, grads[0], grads[1], grads[2] if tree.Cg > 0 else None, stream)
+        if traced:
+            _lib.neuvv_render_backward_trace(tree.struct(), None, n, ray_o, ray_d, None, t_frame, W, t_stop, rgb,
+                                             alpha, nsamp, g_rgb, None, grads[0], grads[1], trace, trace_cap, stream)
+        else:
+            _lib.neuvv_render_backward(tree.struct(), None, n, ray_o, ray_d, None, t_frame, W, t_stop, rgb, alpha,
+                                       nsamp, g_rgb, None, grads[0], grads[1], grads[2] if tree.Cg > 0 else None,
+                                       stream)
 
     log(f"warmup {args.warmup} steps")
     for _ in range(args.warmup):
@@ -182,6 +201,12 @@ def main():
     fwd_bytes = total_samples * payload_b + n * FWD_RAY_IO_B
     bwd_bytes = (total_samples * payload_b + touched * 2 * 4 * values + n * BWD_RAY_NSAMP_B +
                  hit * BWD_HIT_IO_B)
+    if traced:
+        # the trace is state kept between the passes: written per sample by the forward, read by the
+        # adjoint, which then reads only the C density weights of the leaf (basis gradient) per sample
+        elem = 4 if dt == _lib.F32 else 2
+        fwd_bytes += total_samples * TRACE_SAMPLE_B
+        bwd_bytes += total_samples * (TRACE_SAMPLE_B + tree.C * elem - payload_b)
     log(f"fwd {fwd_ms:.3f} ms, bwd {bwd_ms:.3f} ms per launch; step {ms_step:.3f} ms; "
         f"{total_samples} samples, {hit} hit rays")
     kern = {"render_fwd": (fwd_ms, fwd_bytes), "render_bwd": (bwd_ms, bwd_bytes)}
@@ -204,7 +229,7 @@ def main():
         "config": {"workload": workload, "depth": sc.depth, "leaves": sc.n_leaves, "K": tree.K, "C": tree.C,
                    "Cg": tree.Cg,
                    "T": sc.T, "rays_per_step": n, "image": "8 x 1920x1080", "t_stop": t_stop,
-                   "step": "render fwd + adjoint", "layout": args.layout},
+                   "step": "render fwd + adjoint" + (" (traced)" if traced else ""), "layout": args.layout},
         "fwd_mrays_s": round(n / (fwd_ms * 1e-3) / 1e6, 2),
         "samples_per_step": total_samples, "hit_rays": hit, "leaves_touched": touched,
         "roofline": roof, "roofline_other_kernel": roof_other,

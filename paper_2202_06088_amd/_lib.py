@@ -62,6 +62,10 @@ _SIGNATURES = {
                      _P, _P, _P, _P, _P],
     "neuvv_render_backward": [ctypes.POINTER(neuvv_tree), ctypes.POINTER(neuvv_instance), _I64, _P, _P, _P, _F,
                               _I32, _F, _P, _P, _P, _P, _P, _P, _P, _P, _P],
+    "neuvv_render_trace": [ctypes.POINTER(neuvv_tree), ctypes.POINTER(neuvv_instance), _I64, _P, _P, _P, _F, _I32,
+                           _F, _P, _P, _P, _P, _P, _I64, _P],
+    "neuvv_render_backward_trace": [ctypes.POINTER(neuvv_tree), ctypes.POINTER(neuvv_instance), _I64, _P, _P, _P,
+                                    _F, _I32, _F, _P, _P, _P, _P, _P, _P, _P, _P, _I64, _P],
     "neuvv_grad_row_elems": [_I32, _I32, _I32],
     "neuvv_pack_rows": [_I32, _I32, _I32, _I64, _P, _P, _P, _P],
     "neuvv_blur": [_I32, _I32, _P, _F, _P, _P],
@@ -101,6 +105,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.neuvv_last_error.argtypes = []
     lib.neuvv_version.restype = ctypes.c_int
     lib.neuvv_version.argtypes = []
+    lib.neuvv_trace_bytes.restype = ctypes.c_int64
+    lib.neuvv_trace_bytes.argtypes = [_I64, _I64]
     _lib = lib
     return lib
 
@@ -193,6 +199,30 @@ def neuvv_render_backward(tree: neuvv_tree, inst, n_rays, ray_o, ray_d, ray_t, t
         ctypes.byref(tree), _inst_ptr(inst), int(n_rays), _ptr(ray_o), _ptr(ray_d), _ptr(ray_t), float(t_scalar),
         int(image_width), float(t_stop), _ptr(rgb), _ptr(alpha), _ptr(nsamp), _ptr(grad_rgb), _ptr(grad_alpha),
         _ptr(grad_leaf), _ptr(grad_basis), _ptr(grad_basis_g), _stream(stream)))
+
+
+def neuvv_trace_bytes(n_rays: int, trace_cap: int) -> int:
+    v = load().neuvv_trace_bytes(int(n_rays), int(trace_cap))
+    if v < 0:
+        raise NeuvvError("neuvv_trace_bytes", -1, "negative argument")
+    return v
+
+
+def neuvv_render_trace(tree: neuvv_tree, inst, n_rays, ray_o, ray_d, ray_t, t_scalar, image_width, t_stop,
+                       rgb, alpha, depth, nsamp, trace, trace_cap, stream=None):
+    _check("neuvv_render_trace", load().neuvv_render_trace(
+        ctypes.byref(tree), _inst_ptr(inst), int(n_rays), _ptr(ray_o), _ptr(ray_d), _ptr(ray_t), float(t_scalar),
+        int(image_width), float(t_stop), _ptr(rgb), _ptr(alpha), _ptr(depth), _ptr(nsamp), _ptr(trace),
+        int(trace_cap), _stream(stream)))
+
+
+def neuvv_render_backward_trace(tree: neuvv_tree, inst, n_rays, ray_o, ray_d, ray_t, t_scalar, image_width, t_stop,
+                                rgb, alpha, nsamp, grad_rgb, grad_alpha, grad_leaf, grad_basis, trace, trace_cap,
+                                stream=None):
+    _check("neuvv_render_backward_trace", load().neuvv_render_backward_trace(
+        ctypes.byref(tree), _inst_ptr(inst), int(n_rays), _ptr(ray_o), _ptr(ray_d), _ptr(ray_t), float(t_scalar),
+        int(image_width), float(t_stop), _ptr(rgb), _ptr(alpha), _ptr(nsamp), _ptr(grad_rgb), _ptr(grad_alpha),
+        _ptr(grad_leaf), _ptr(grad_basis), _ptr(trace), int(trace_cap), _stream(stream)))
 
 
 def neuvv_grad_row_elems(K: int, C: int, Cg: int = 0) -> int:

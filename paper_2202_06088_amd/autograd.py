@@ -1,6 +1,7 @@
-"""torch.autograd wrappers: the forward saves only rgb, alpha and nsamp per
-ray; the backward kernel replays the compositing with the transmittance
-recomputed (Sec. 4.3 "Optimization")."""
+"""torch.autograd wrappers: the forward saves rgb, alpha and nsamp per ray
+(and, for the K = 16, C = 8 form, a trace of its samples with room for two
+per ray); the backward kernel replays the compositing with the transmittance
+recomputed (Sec. 4.3 "Optimization"), from the trace where it holds the ray."""
 from __future__ import annotations
 
 import torch
@@ -26,8 +27,10 @@ class RenderFn(torch.autograd.Function):
             own += [(wgam, tree.wgam), (basis_g, tree.basis_g)]
         if any(a is None or a.data_ptr() != b.data_ptr() for a, b in own):
             raise ValueError("the payload and basis tensors must be the tree's own")
-        rgb, alpha, depth, nsamp = ops.render(tree, ray_o, ray_d, t, inst, t_stop, image_width)
-        ctx.tree, ctx.inst, ctx.t_stop, ctx.image_width = tree, inst, t_stop, image_width
+        n = ray_o.shape[0]
+        trace = ops.Trace(n, 2 * n, ray_o.device) if tree.Cg == 0 and 0 < n < 2 ** 30 else None
+        rgb, alpha, depth, nsamp = ops.render(tree, ray_o, ray_d, t, inst, t_stop, image_width, trace=trace)
+        ctx.tree, ctx.inst, ctx.t_stop, ctx.image_width, ctx.trace = tree, inst, t_stop, image_width, trace
         ctx.t_scalar = None if isinstance(t, torch.Tensor) else float(t)
         ctx.save_for_backward(ray_o, ray_d, rgb, alpha, nsamp, t if isinstance(t, torch.Tensor) else None)
         ctx.mark_non_differentiable(depth, nsamp)
@@ -43,7 +46,8 @@ class RenderFn(torch.autograd.Function):
         want_basis = ctx.needs_input_grad[2] or (tree.Cg > 0 and ctx.needs_input_grad[4])
         out = ops.render_backward(tree, ray_o, ray_d, rgb, alpha, nsamp, g_rgb.contiguous(),
                                   None if g_alpha is None else g_alpha.contiguous(), t_arg, ctx.inst,
-                                  ctx.t_stop, ctx.image_width, want_basis=want_basis)
+                                  ctx.t_stop, ctx.image_width, want_basis=want_basis, trace=ctx.trace)
+        ctx.trace = None
         parts = tree.rows_to_payload_f32(out[0])
         g_basis = out[1] if ctx.needs_input_grad[2] else None
         if tree.Cg > 0:

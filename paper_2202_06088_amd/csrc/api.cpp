@@ -248,10 +248,19 @@ int neuvv_pack_leaves(int32_t K, int32_t C, int32_t dtype, int32_t layout, int64
     NEUVV_GUARD_END
 }
 
-int neuvv_render(const neuvv_tree* tree, const neuvv_instance* inst, int64_t n_rays, const float* ray_o,
-                 const float* ray_d, const float* ray_t, float t_scalar, int32_t image_width, float t_stop,
-                 float* rgb, float* alpha, float* depth, int32_t* nsamp, void* stream) {
-    NEUVV_GUARD_BEGIN
+// Checks a trace buffer argument (traced calls only).
+static int check_trace(const neuvv_tree* tree, int64_t n_rays, const void* trace, int64_t trace_cap) {
+    if (tree->Cg > 0) return fail(NEUVV_ERR_UNSUPPORTED, "traces are for the K = 16, C = 8 form");
+    if (!trace) return fail(NEUVV_ERR_ARG, "trace is NULL");
+    if (reinterpret_cast<uintptr_t>(trace) % 256) return fail(NEUVV_ERR_ARG, "trace must be 256-byte aligned");
+    if (trace_cap < 0 || trace_cap > (int64_t)INT32_MAX) return fail(NEUVV_ERR_RANGE, "trace_cap outside [0, 2^31)");
+    if (n_rays > (int64_t)INT32_MAX) return fail(NEUVV_ERR_RANGE, "traced calls take fewer than 2^31 rays");
+    return NEUVV_OK;
+}
+
+static int render_impl(const neuvv_tree* tree, const neuvv_instance* inst, int64_t n_rays, const float* ray_o,
+                const float* ray_d, const float* ray_t, float t_scalar, int32_t image_width, float t_stop, float* rgb,
+                float* alpha, float* depth, int32_t* nsamp, void* trace, int64_t trace_cap, void* stream) {
     int rc = check_tree(tree);
     if (rc) return rc;
     neuvv::InstArgs in;
@@ -261,21 +270,20 @@ int neuvv_render(const neuvv_tree* tree, const neuvv_instance* inst, int64_t n_r
     if (!(t_stop >= 0.0f) || !std::isfinite(t_stop)) return fail(NEUVV_ERR_RANGE, "t_stop must be >= 0");
     if (n_rays > 0 && (!rgb || !alpha || !nsamp)) return fail(NEUVV_ERR_ARG, "rgb / alpha / nsamp is NULL");
     neuvv::RenderOut out{rgb, alpha, depth, nsamp, nullptr};
+    if (trace) out.trace = neuvv::trace_layout(trace, n_rays, trace_cap);
     const hipError_t e = tree->Cg > 0
                              ? neuvv::launch_render_pp_fwd(tree->dtype, tree_args(tree), in, ra, t_stop, out,
                                                            (hipStream_t)stream)
                              : neuvv::launch_render_fwd(tree->K, tree->C, tree->dtype, tree_args(tree), in, ra,
                                                         t_stop, out, (hipStream_t)stream);
     return hip_status(e, "render launch");
-    NEUVV_GUARD_END
 }
 
-int neuvv_render_backward(const neuvv_tree* tree, const neuvv_instance* inst, int64_t n_rays,
-                          const float* ray_o, const float* ray_d, const float* ray_t, float t_scalar,
-                          int32_t image_width, float t_stop, const float* rgb, const float* alpha,
-                          const int32_t* nsamp, const float* grad_rgb, const float* grad_alpha, float* grad_leaf,
-                          float* grad_basis, float* grad_basis_g, void* stream) {
-    NEUVV_GUARD_BEGIN
+static int backward_impl(const neuvv_tree* tree, const neuvv_instance* inst, int64_t n_rays, const float* ray_o,
+                  const float* ray_d, const float* ray_t, float t_scalar, int32_t image_width, float t_stop,
+                  const float* rgb, const float* alpha, const int32_t* nsamp, const float* grad_rgb,
+                  const float* grad_alpha, float* grad_leaf, float* grad_basis, float* grad_basis_g,
+                  const void* trace, int64_t trace_cap, void* stream) {
     int rc = check_tree(tree);
     if (rc) return rc;
     neuvv::InstArgs in;
@@ -289,12 +297,65 @@ int neuvv_render_backward(const neuvv_tree* tree, const neuvv_instance* inst, in
     if (tree->edit) return fail(NEUVV_ERR_UNSUPPORTED, "no adjoint through appearance edits");
     neuvv::BackwardIO io{rgb, alpha, nsamp, grad_rgb, grad_alpha, grad_leaf, grad_basis,
                          tree->Cg > 0 ? grad_basis_g : nullptr, record_cap(n_rays)};
+    if (trace) io.trace = neuvv::trace_layout(const_cast<void*>(trace), n_rays, trace_cap);
     const hipError_t e = tree->Cg > 0
                              ? neuvv::launch_render_pp_bwd(tree->dtype, tree_args(tree), in, ra, io,
                                                            (hipStream_t)stream)
                              : neuvv::launch_render_bwd(tree->K, tree->C, tree->dtype, tree_args(tree), in, ra, io,
                                                         (hipStream_t)stream);
     return hip_status(e, "render_backward launch");
+}
+
+int neuvv_render(const neuvv_tree* tree, const neuvv_instance* inst, int64_t n_rays, const float* ray_o,
+                 const float* ray_d, const float* ray_t, float t_scalar, int32_t image_width, float t_stop,
+                 float* rgb, float* alpha, float* depth, int32_t* nsamp, void* stream) {
+    NEUVV_GUARD_BEGIN
+    return render_impl(tree, inst, n_rays, ray_o, ray_d, ray_t, t_scalar, image_width, t_stop, rgb, alpha, depth,
+                       nsamp, nullptr, 0, stream);
+    NEUVV_GUARD_END
+}
+
+int neuvv_render_backward(const neuvv_tree* tree, const neuvv_instance* inst, int64_t n_rays,
+                          const float* ray_o, const float* ray_d, const float* ray_t, float t_scalar,
+                          int32_t image_width, float t_stop, const float* rgb, const float* alpha,
+                          const int32_t* nsamp, const float* grad_rgb, const float* grad_alpha, float* grad_leaf,
+                          float* grad_basis, float* grad_basis_g, void* stream) {
+    NEUVV_GUARD_BEGIN
+    return backward_impl(tree, inst, n_rays, ray_o, ray_d, ray_t, t_scalar, image_width, t_stop, rgb, alpha, nsamp,
+                         grad_rgb, grad_alpha, grad_leaf, grad_basis, grad_basis_g, nullptr, 0, stream);
+    NEUVV_GUARD_END
+}
+
+int64_t neuvv_trace_bytes(int64_t n_rays, int64_t trace_cap) {
+    if (n_rays < 0 || trace_cap < 0) return -1;
+    return (int64_t)neuvv::trace_bytes(n_rays, trace_cap);
+}
+
+int neuvv_render_trace(const neuvv_tree* tree, const neuvv_instance* inst, int64_t n_rays, const float* ray_o,
+                       const float* ray_d, const float* ray_t, float t_scalar, int32_t image_width, float t_stop,
+                       float* rgb, float* alpha, float* depth, int32_t* nsamp, void* trace, int64_t trace_cap,
+                       void* stream) {
+    NEUVV_GUARD_BEGIN
+    int rc = check_tree(tree);
+    if (rc) return rc;
+    if ((rc = check_trace(tree, n_rays, trace, trace_cap))) return rc;
+    return render_impl(tree, inst, n_rays, ray_o, ray_d, ray_t, t_scalar, image_width, t_stop, rgb, alpha, depth,
+                       nsamp, trace, trace_cap, stream);
+    NEUVV_GUARD_END
+}
+
+int neuvv_render_backward_trace(const neuvv_tree* tree, const neuvv_instance* inst, int64_t n_rays,
+                                const float* ray_o, const float* ray_d, const float* ray_t, float t_scalar,
+                                int32_t image_width, float t_stop, const float* rgb, const float* alpha,
+                                const int32_t* nsamp, const float* grad_rgb, const float* grad_alpha,
+                                float* grad_leaf, float* grad_basis, const void* trace, int64_t trace_cap,
+                                void* stream) {
+    NEUVV_GUARD_BEGIN
+    int rc = check_tree(tree);
+    if (rc) return rc;
+    if ((rc = check_trace(tree, n_rays, trace, trace_cap))) return rc;
+    return backward_impl(tree, inst, n_rays, ray_o, ray_d, ray_t, t_scalar, image_width, t_stop, rgb, alpha, nsamp,
+                         grad_rgb, grad_alpha, grad_leaf, grad_basis, nullptr, trace, trace_cap, stream);
     NEUVV_GUARD_END
 }
 

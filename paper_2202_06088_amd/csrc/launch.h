@@ -10,12 +10,25 @@
 
 namespace neuvv {
 
+// Per-sample trace of a forward call, replayed by the adjoint of the same
+// call instead of walking the tree and evaluating the leaves again.
+struct TraceArgs {
+    int32_t* head;                 // [n_rays] first sample of the ray's trace; -1: none (the adjoint walks)
+    int4* smp;                     // [cap][2]: {leaf, delta, x, c_r} {c_g, c_b, next (-1: last), 0} (float bits)
+    unsigned long long* counter;   // kQueues counters 128 bytes apart
+    int64_t cap;
+};
+// Bytes of a trace buffer for n rays and room for cap samples, and its layout.
+size_t trace_bytes(int64_t n, int64_t cap);
+TraceArgs trace_layout(void* buf, int64_t n, int64_t cap);
+
 struct RenderOut {
     float* rgb;          // each output may be nullptr (not written)
     float* alpha;
     float* depth;
     int32_t* nsamp;
     int32_t* last_leaf;  // slot of the last sample of a ray that stopped early, else -1
+    TraceArgs trace;     // head == nullptr: no trace (K = 16, C = 8 form only)
 };
 
 struct BackwardIO {
@@ -28,6 +41,7 @@ struct BackwardIO {
     float* grad_basis;
     float* grad_basis_g;   // per-point hyperangle basis gradient (Cg > 0), or nullptr
     int64_t record_cap;    // two-phase adjoint: sample records at most (0: per-sample atomics only)
+    TraceArgs trace;       // head == nullptr: walk every ray (K = 16, C = 8 form only)
 };
 
 // Per-sample records of the two-phase adjoint: a sample's gradient with

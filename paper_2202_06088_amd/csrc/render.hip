@@ -35,7 +35,7 @@
 namespace neuvv {
 
 // node rows (16 B each) staged in LDS: the top levels of the tree
-constexpr int kLdsNodesFwd = 2048;
+constexpr int kLdsNodesFwd = 1024;
 constexpr int kLdsNodesBwd = 1024;
 
 template <int K, int C>
@@ -58,11 +58,18 @@ __device__ __forceinline__ void ray_basis(const TreeArgs& tr, const RaySetup& rs
 // EDIT: the tree carries appearance edits (Sec. 5.2): from its first frame on,
 // an edited leaf's target colour (and target density, when >= 0) replace the
 // evaluated ones.
-template <int K, int C, int DT, bool IDENT, bool EDIT>
+// TRACE: every sample is also written to out.trace (its leaf, segment length,
+// density logit and colours, linked in ray order), so that the adjoint of the
+// same call replays the samples instead of walking and evaluating again. The
+// samples of one iteration take consecutive entries in lane order, from
+// blocks per wavefront; a ray whose samples do not all fit gets head -1.
+template <int K, int C, int DT, bool IDENT, bool EDIT, bool TRACE>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) void render_fwd_kernel(
     TreeArgs tr, InstArgs in, RayArgs ra, float t_stop, RenderOut out) {
     __shared__ int4 s_nodes[kLdsNodesFwd];
     __shared__ int s_path[kMaxLevels * kBlock];
+    __shared__ float s_h[kBlock * K];
+    __shared__ float s_b[kBlock * C];
     const int n_lds = stage_top_nodes<kLdsNodesFwd>(tr, s_nodes);
     int* path = s_path + threadIdx.x;
     ChunkCursor cc = chunk_cursor();
@@ -72,9 +79,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
     int64_t ray = -1;
     RaySetup rs;
     Walk w;
-    float h[K], bv[C];
+    // the ray's basis h and density row b live in LDS (this lane's columns)
+    float* const hl = s_h + threadIdx.x * K;
+    float* const bl = s_b + threadIdx.x * C;
     float Tr = 1.0f, acc0 = 0.0f, acc1 = 0.0f, acc2 = 0.0f, wsum = 0.0f, dsum = 0.0f;
     int ns = 0, last = -1;
+    int t_first = -1, t_prev = -1;   // trace: the ray's first and latest entries; t_first -2: broken
+    int64_t tcur = 0, tend = 0;      // trace: what is left of the wavefront's block (wave-uniform)
 
     for (;;) {
         const uint64_t idle = __ballot(!alive);
@@ -114,9 +125,17 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
                 ray_setup<IDENT>(tr, in, o, d, t, rs);
                 Tr = 1.0f; acc0 = acc1 = acc2 = 0.0f; wsum = dsum = 0.0f; ns = 0;
                 if (rs.hit) {
-                    ray_basis<K, C>(tr, rs, h, bv);
+                    {
+                        float h[K], bv[C];
+                        ray_basis<K, C>(tr, rs, h, bv);
+#pragma unroll
+                        for (int k = 0; k < K; ++k) hl[k] = h[k];
+#pragma unroll
+                        for (int c = 0; c < C; ++c) bl[c] = bv[c];
+                    }
                     walk_begin(tr, rs, w);
                     alive = true;
+                    t_first = t_prev = -1;
                 } else {
                     write_miss(out, ray);
                 }
@@ -124,23 +143,27 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
             continue;
         }
         if (n_idle == kWave) break;
+        bool finish = false, stopped = false;
+        int leaf = -1;
+        float delta = 0.0f, tx = 0.0f, tc0 = 0.0f, tc1 = 0.0f, tc2 = 0.0f;
         if (alive) {
-            float delta, umid;
-            const int leaf = walk_next<kWalkBudget>(tr, s_nodes, n_lds, path, kBlock, rs, w, delta, umid);
-            bool finish = leaf == -1, stopped = false;
+            float umid;
+            leaf = walk_next<kWalkBudget>(tr, s_nodes, n_lds, path, kBlock, rs, w, delta, umid);
+            finish = leaf == -1;
             if (leaf >= 0) {
                 float wv[3 * K], sv[C];
                 load_leaf<DT, 3 * K>(tr.hh, tr.n_leaves, leaf, tr.layout, wv);
                 load_leaf<DT, C>(tr.wsig, tr.n_leaves, leaf, tr.layout, sv);
                 float x = 0.0f;
 #pragma unroll
-                for (int c = 0; c < C; ++c) x = fmaf(sv[c], bv[c], x);
+                for (int c = 0; c < C; ++c) x = fmaf(sv[c], bl[c], x);
                 float z0 = 0.0f, z1 = 0.0f, z2 = 0.0f;
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
-                    z0 = fmaf(wv[k], h[k], z0);
-                    z1 = fmaf(wv[K + k], h[k], z1);
-                    z2 = fmaf(wv[2 * K + k], h[k], z2);
+                    const float hk = hl[k];
+                    z0 = fmaf(wv[k], hk, z0);
+                    z1 = fmaf(wv[K + k], hk, z1);
+                    z2 = fmaf(wv[2 * K + k], hk, z2);
                 }
                 float sig = softplus_f(x);
                 float c0 = sigmoid_f(z0), c1 = sigmoid_f(z1), c2 = sigmoid_f(z2);
@@ -165,15 +188,35 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
                 last = leaf;
                 finish = t_stop > 0.0f && Tr < t_stop;
                 stopped = finish;
+                tx = x; tc0 = c0; tc1 = c1; tc2 = c2;
             }
-            if (finish) {
-                if (out.rgb) { out.rgb[3 * ray] = acc0; out.rgb[3 * ray + 1] = acc1; out.rgb[3 * ray + 2] = acc2; }
-                if (out.alpha) out.alpha[ray] = 1.0f - Tr;
-                if (out.depth) out.depth[ray] = wsum > 0.0f ? dsum / wsum : INFINITY;
-                if (out.nsamp) out.nsamp[ray] = ns;
-                if (out.last_leaf) out.last_leaf[ray] = stopped ? last : -1;
-                alive = false;
+        }
+        if constexpr (TRACE) {
+            const uint64_t hm = __ballot(leaf >= 0);
+            const int n_s = __popcll(hm);
+            const int64_t at = n_s > 0 ? take_items(out.trace.counter, out.trace.cap, cc.home, n_s, tcur, tend) : -1;
+            if (leaf >= 0) {
+                if (at >= 0 && t_first != -2) {
+                    const int slot = (int)(at + lane_rank(hm));
+                    out.trace.smp[2 * (int64_t)slot] =
+                        make_int4(leaf, __float_as_int(delta), __float_as_int(tx), __float_as_int(tc0));
+                    out.trace.smp[2 * (int64_t)slot + 1] = make_int4(__float_as_int(tc1), __float_as_int(tc2), -1, 0);
+                    if (t_prev >= 0) reinterpret_cast<int*>(out.trace.smp + 2 * (int64_t)t_prev + 1)[2] = slot;
+                    else t_first = slot;
+                    t_prev = slot;
+                } else {
+                    t_first = -2;   // incomplete: the adjoint walks this ray
+                }
             }
+        }
+        if (alive && finish) {
+            if (out.rgb) store3(out.rgb + 3 * ray, acc0, acc1, acc2);
+            if (out.alpha) out.alpha[ray] = 1.0f - Tr;
+            if (out.depth) out.depth[ray] = wsum > 0.0f ? dsum / wsum : INFINITY;
+            if (out.nsamp) out.nsamp[ray] = ns;
+            if (out.last_leaf) out.last_leaf[ray] = stopped ? last : -1;
+            if constexpr (TRACE) out.trace.head[ray] = t_first >= 0 ? t_first : -1;
+            alive = false;
         }
     }
 }
@@ -201,17 +244,23 @@ __host__ __device__ constexpr int grad_row() { return ((3 * K + C + 63) / 64) * 
 
 
 
-template <int K, int C, int DT, bool IDENT>
+// REPLAY: every ray of the launch has a trace in io.trace (the forward's
+// samples) and replays it (segment length, density logit and colours)
+// without walking the tree or reading the HH coefficients; otherwise the
+// rays walk.
+template <int K, int C, int DT, bool IDENT, bool REPLAY>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) void render_bwd_kernel(
     TreeArgs tr, InstArgs in, RayArgs ra, BackwardIO io, RecordArgs rec) {
     constexpr int ROW = grad_row<K, C>();
-    __shared__ int4 s_nodes[kLdsNodesBwd];
-    __shared__ int s_path[kMaxLevels * kBlock];
+    // a replaying launch does not walk: no node rows or paths
+    constexpr int kNodes = REPLAY ? 1 : kLdsNodesBwd;
+    __shared__ int4 s_nodes[kNodes];
+    __shared__ int s_path[REPLAY ? 1 : kMaxLevels * kBlock];
     __shared__ float s_h[kBlock * K];
     __shared__ float s_b[kBlock * C];
     __shared__ float s_gb[C];
     if (threadIdx.x < C) s_gb[threadIdx.x] = 0.0f;   // made visible by the barrier in stage_top_nodes
-    const int n_lds = stage_top_nodes<kLdsNodesBwd>(tr, s_nodes);
+    const int n_lds = stage_top_nodes<kNodes>(tr, s_nodes);
     int* path = s_path + threadIdx.x;
     ChunkCursor cc = chunk_cursor();
     bool more = true;   // wave-uniform: chunks may be left
@@ -232,6 +281,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
     float Tr = 1.0f, Tfin = 0.0f, p0 = 0.0f, p1 = 0.0f, p2 = 0.0f, F0 = 0.0f, F1 = 0.0f, F2 = 0.0f;
     float g0 = 0.0f, g1 = 0.0f, g2 = 0.0f, ga = 0.0f;
     int ns = 0, ns_fwd = 0;
+    int tnext = -1;        // replay: the ray's next sample
     // records: the wavefront fills blocks of kRecBlock consecutive records,
     // taken from its XCD's part of the room; [wrec, wend) is what is left of
     // the current block (wave-uniform)
@@ -277,7 +327,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
 #pragma unroll
                         for (int c = 0; c < C; ++c) s_b[threadIdx.x * C + c] = bv[c];
                     }
-                    walk_begin(tr, rs, w);
+                    if constexpr (REPLAY) tnext = io.trace.head[ray];
+                    else walk_begin(tr, rs, w);
                     ns_fwd = io.nsamp[ray];
                     ns = 0;
                     Tr = 1.0f;
@@ -300,33 +351,56 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
         int leaf = -1, my_rec = -1;
         float gz0 = 0.0f, gz1 = 0.0f, gz2 = 0.0f, gx = 0.0f;
         if (alive) {
-            float delta, umid;
-            leaf = walk_next<kWalkBudget>(tr, s_nodes, n_lds, path, kBlock, rs, w, delta, umid);
-            bool finish = leaf == -1;
-            if (leaf >= 0) {
-                float wv[3 * K], sv[C];
-                load_leaf<DT, 3 * K>(tr.hh, N, leaf, tr.layout, wv);
-                load_leaf<DT, C>(tr.wsig, N, leaf, tr.layout, sv);
-                const float* hl = s_h + threadIdx.x * K;
-                const float* bl = s_b + threadIdx.x * C;
-                float x = 0.0f;
-#pragma unroll
-                for (int c = 0; c < C; ++c) x = fmaf(sv[c], bl[c], x);
-                float z0 = 0.0f, z1 = 0.0f, z2 = 0.0f;
-#pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    const float hk = hl[k];
-                    z0 = fmaf(wv[k], hk, z0);
-                    z1 = fmaf(wv[K + k], hk, z1);
-                    z2 = fmaf(wv[2 * K + k], hk, z2);
+            float delta = 0.0f;
+            bool finish;
+            float x = 0.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
+            float sv[C];
+            if constexpr (REPLAY) {
+                // replay the forward's sample
+                if (tnext >= 0) {
+                    const int4 A = io.trace.smp[2 * (int64_t)tnext], B = io.trace.smp[2 * (int64_t)tnext + 1];
+                    leaf = A.x;
+                    delta = __int_as_float(A.y);
+                    x = __int_as_float(A.z);
+                    c0 = __int_as_float(A.w);
+                    c1 = __int_as_float(B.x);
+                    c2 = __int_as_float(B.y);
+                    tnext = B.z;
+                    if (io.grad_basis) load_leaf<DT, C>(tr.wsig, N, leaf, tr.layout, sv);
                 }
+                finish = leaf < 0;
+            } else {
+                float umid;
+                leaf = walk_next<kWalkBudget>(tr, s_nodes, n_lds, path, kBlock, rs, w, delta, umid);
+                finish = leaf == -1;
+                if (leaf >= 0) {
+                    float wv[3 * K];
+                    load_leaf<DT, 3 * K>(tr.hh, N, leaf, tr.layout, wv);
+                    load_leaf<DT, C>(tr.wsig, N, leaf, tr.layout, sv);
+                    const float* hl = s_h + threadIdx.x * K;
+                    const float* bl = s_b + threadIdx.x * C;
+#pragma unroll
+                    for (int c = 0; c < C; ++c) x = fmaf(sv[c], bl[c], x);
+                    float z0 = 0.0f, z1 = 0.0f, z2 = 0.0f;
+#pragma unroll
+                    for (int k = 0; k < K; ++k) {
+                        const float hk = hl[k];
+                        z0 = fmaf(wv[k], hk, z0);
+                        z1 = fmaf(wv[K + k], hk, z1);
+                        z2 = fmaf(wv[2 * K + k], hk, z2);
+                    }
+                    c0 = sigmoid_f(z0);
+                    c1 = sigmoid_f(z1);
+                    c2 = sigmoid_f(z2);
+                }
+            }
+            if (leaf >= 0) {
                 const float sig = softplus_f(x);
                 const float od = sig * delta;
                 float a, e;
                 absorb(od, a, e);
                 const float wt = Tr * a;
                 const float Tn = Tr * e;
-                const float c0 = sigmoid_f(z0), c1 = sigmoid_f(z1), c2 = sigmoid_f(z2);
                 p0 = fmaf(wt, c0, p0);
                 p1 = fmaf(wt, c1, p1);
                 p2 = fmaf(wt, c2, p2);
@@ -338,8 +412,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
                 gz0 = g0 * wt * c0 * (1.0f - c0);
                 gz1 = g1 * wt * c1 * (1.0f - c1);
                 gz2 = g2 * wt * c2 * (1.0f - c2);
+                if (io.grad_basis) {
 #pragma unroll
-                for (int c = 0; c < C; ++c) gb[c] = fmaf(gx, sv[c], gb[c]);
+                    for (int c = 0; c < C; ++c) gb[c] = fmaf(gx, sv[c], gb[c]);
+                }
                 has = true;
                 Tr = Tn;
                 ++ns;
@@ -361,26 +437,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
             // the record stores of the wavefront are contiguous
             const uint64_t hm = __ballot(has);
             const int n_has = __popcll(hm);
-            if (n_has > 0 && wrec + n_has > wend) {
-                const int x = cc.home;
-                const int64_t lo = rec.cap * x / kQueues, hi = rec.cap * (x + 1) / kQueues;
-                unsigned long long b = 0;
-                if (lane == 0) b = atomicAdd(rec.counter + x * kQueueStride, (unsigned long long)kRecBlock);
-                const uint32_t b_lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)b);
-                const uint32_t b_hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(b >> 32));
-                const int64_t first = lo + (int64_t)(((uint64_t)b_hi << 32) | b_lo);
-                wrec = first;
-                wend = first + kRecBlock <= hi ? first + kRecBlock : (first < hi ? hi : first);
-            }
-            if (n_has > 0 && wrec + n_has <= wend) {
+            const int64_t at = n_has > 0 ? take_items(rec.counter, rec.cap, cc.home, n_has, wrec, wend) : -1;
+            if (at >= 0) {
                 if (has) {
-                    my_rec = (int)(wrec + lane_rank(hm));
+                    my_rec = (int)(at + lane_rank(hm));
                     rec.rec[2 * (int64_t)my_rec] =
                         make_int4(__float_as_int(gz0), __float_as_int(gz1), __float_as_int(gz2), __float_as_int(gx));
                     const int nxt = atomicExch(rec.head + leaf, my_rec);
                     rec.rec[2 * (int64_t)my_rec + 1] = make_int4(nxt, (int)ray, 0, 0);
                 }
-                wrec += n_has;
             }
         }
         // samples without a record: every lane of the wavefront adds one
@@ -599,6 +664,23 @@ hipError_t work_alloc(void** p, size_t bytes, hipStream_t stream) {
 
 hipError_t work_free(void* p, hipStream_t stream) { return hipFreeAsync(p, stream); }
 
+size_t trace_bytes(int64_t n, int64_t cap) {
+    const size_t head_b = ((size_t)(n > 0 ? n : 0) * sizeof(int32_t) + 255) & ~(size_t)255;
+    return 2048 + head_b + (size_t)(cap > 0 ? cap : 0) * 2 * sizeof(int4);
+}
+
+TraceArgs trace_layout(void* buf, int64_t n, int64_t cap) {
+    TraceArgs t{};
+    if (!buf) return t;
+    const size_t head_b = ((size_t)(n > 0 ? n : 0) * sizeof(int32_t) + 255) & ~(size_t)255;
+    char* p = static_cast<char*>(buf);
+    t.counter = reinterpret_cast<unsigned long long*>(p);
+    t.head = reinterpret_cast<int32_t*>(p + 2048);
+    t.smp = reinterpret_cast<int4*>(p + 2048 + head_b);
+    t.cap = cap;
+    return t;
+}
+
 int device_cu_count() {
     static int cached[64] = {0};
     int dev = 0;
@@ -611,14 +693,18 @@ int device_cu_count() {
     return cached[dev];
 }
 
-template <int K, int C, int DT, bool EDIT>
+template <int K, int C, int DT, bool EDIT, bool TRACE>
 static hipError_t fwd_e(const TreeArgs& tr, const InstArgs& in, const RayArgs& ra, float t_stop, const RenderOut& o,
                         hipStream_t st) {
+    if constexpr (TRACE) {
+        // the trace's allocation counters start at zero
+        hipLaunchKernelGGL(zero_queue_kernel, dim3(1), dim3(kQueues * kQueueStride), 0, st, o.trace.counter);
+    }
     if (in.identity) {
-        auto kern = render_fwd_kernel<K, C, DT, true, EDIT>;
+        auto kern = render_fwd_kernel<K, C, DT, true, EDIT, TRACE>;
         hipLaunchKernelGGL(kern, dim3(grid_for(kern, ra)), dim3(kBlock), 0, st, tr, in, ra, t_stop, o);
     } else {
-        auto kern = render_fwd_kernel<K, C, DT, false, EDIT>;
+        auto kern = render_fwd_kernel<K, C, DT, false, EDIT, TRACE>;
         hipLaunchKernelGGL(kern, dim3(grid_for(kern, ra)), dim3(kBlock), 0, st, tr, in, ra, t_stop, o);
     }
     return hipGetLastError();
@@ -627,7 +713,24 @@ static hipError_t fwd_e(const TreeArgs& tr, const InstArgs& in, const RayArgs& r
 template <int K, int C, int DT>
 static hipError_t fwd_t(const TreeArgs& tr, const InstArgs& in, const RayArgs& ra, float t_stop, const RenderOut& o,
                         hipStream_t st) {
-    return tr.edit ? fwd_e<K, C, DT, true>(tr, in, ra, t_stop, o, st) : fwd_e<K, C, DT, false>(tr, in, ra, t_stop, o, st);
+    if (o.trace.head)
+        return tr.edit ? fwd_e<K, C, DT, true, true>(tr, in, ra, t_stop, o, st)
+                       : fwd_e<K, C, DT, false, true>(tr, in, ra, t_stop, o, st);
+    return tr.edit ? fwd_e<K, C, DT, true, false>(tr, in, ra, t_stop, o, st)
+                   : fwd_e<K, C, DT, false, false>(tr, in, ra, t_stop, o, st);
+}
+
+template <int K, int C, int DT, bool REPLAY>
+static hipError_t bwd_k(const TreeArgs& tr, const InstArgs& in, const RayArgs& ra, const BackwardIO& io,
+                        const RecordArgs& rec, hipStream_t st) {
+    if (in.identity) {
+        auto kern = render_bwd_kernel<K, C, DT, true, REPLAY>;
+        hipLaunchKernelGGL(kern, dim3(grid_for(kern, ra)), dim3(kBlock), 0, st, tr, in, ra, io, rec);
+    } else {
+        auto kern = render_bwd_kernel<K, C, DT, false, REPLAY>;
+        hipLaunchKernelGGL(kern, dim3(grid_for(kern, ra)), dim3(kBlock), 0, st, tr, in, ra, io, rec);
+    }
+    return hipGetLastError();
 }
 
 template <int K, int C, int DT>
@@ -640,14 +743,17 @@ static hipError_t bwd_t(const TreeArgs& tr, const InstArgs& in, const RayArgs& r
     void* mem = nullptr;
     hipError_t e = records_begin(tr, cap, st, rec, mem);
     if (e == hipSuccess) {
-        if (in.identity) {
-            auto kern = render_bwd_kernel<K, C, DT, true>;
-            hipLaunchKernelGGL(kern, dim3(grid_for(kern, ra)), dim3(kBlock), 0, st, tr, in, ra, io, rec);
+        // one cull pass and render adjoint per source of samples: rays that walk,
+        // and (traced forward) rays that replay their trace
+        auto walk = [&](const RayArgs& r) { return bwd_k<K, C, DT, false>(tr, in, r, io, rec, st); };
+        auto replay = [&](const RayArgs& r) { return bwd_k<K, C, DT, true>(tr, in, r, io, rec, st); };
+        if (io.trace.head) {
+            if (ra.n > (int64_t)INT32_MAX) return hipErrorInvalidValue;   // traced calls take candidate lists
+            e = with_candidates<2>(tr, in, ra, RenderOut{}, io.nsamp, st, walk, io.trace.head);
+            if (e == hipSuccess) e = with_candidates<3>(tr, in, ra, RenderOut{}, io.nsamp, st, replay, io.trace.head);
         } else {
-            auto kern = render_bwd_kernel<K, C, DT, false>;
-            hipLaunchKernelGGL(kern, dim3(grid_for(kern, ra)), dim3(kBlock), 0, st, tr, in, ra, io, rec);
+            e = with_candidates<1>(tr, in, ra, RenderOut{}, io.nsamp, st, walk);
         }
-        e = hipGetLastError();
     }
     if (e == hipSuccess && cap > 0) {
         // persistent: four blocks per CU
@@ -687,9 +793,9 @@ hipError_t launch_render_bwd(int K, int C, int dtype, const TreeArgs& tr, const 
     (void)C;
     if (ra.n_slots <= 0) return hipSuccess;
     switch (dtype) {
-        case 0: return with_candidates<1>(tr, in, ra, RenderOut{}, io.nsamp, stream, [&](const RayArgs& r) { return bwd_t<16, 8, 0>(tr, in, r, io, stream); });
-        case 1: return with_candidates<1>(tr, in, ra, RenderOut{}, io.nsamp, stream, [&](const RayArgs& r) { return bwd_t<16, 8, 1>(tr, in, r, io, stream); });
-        default: return with_candidates<1>(tr, in, ra, RenderOut{}, io.nsamp, stream, [&](const RayArgs& r) { return bwd_t<16, 8, 2>(tr, in, r, io, stream); });
+        case 0: return bwd_t<16, 8, 0>(tr, in, ra, io, stream);
+        case 1: return bwd_t<16, 8, 1>(tr, in, ra, io, stream);
+        default: return bwd_t<16, 8, 2>(tr, in, ra, io, stream);
     }
 }
 

@@ -247,9 +247,12 @@ static __global__ void zero_queue_kernel(unsigned long long* q) { q[threadIdx.x]
 // Cull pass of the candidate form: each wavefront tests kCullGroup chunks of
 // one XCD part at a time (64 slots per chunk, one per lane), reserves room for
 // the rays it keeps with one atomic on the part's count (atomics on one
-// address serialise, so the groups are large), and lists them in slot order. MODE 0 (forward): keep the rays the plain-float box test cannot
-// reject and write the miss outputs of the others. MODE 1 (adjoint): keep the
-// rays whose forward composited a sample (the others carry no gradient). The
+// address serialise, so the groups are large), and lists them in slot order.
+// MODE 0 (forward): keep the rays the plain-float box test cannot reject and
+// write the miss outputs of the others. MODE 1 (adjoint): keep the rays whose
+// forward composited a sample (the others carry no gradient); MODE 2 and 3
+// (adjoint of a traced forward): of those, the rays without a trace (head
+// < 0) and the rays with one. The
 // pass is bound by the 24 bytes of ray per slot it reads; at high occupancy
 // it runs near HBM bandwidth, where the render kernel's refill rounds would
 // take one memory latency per round for every ray.
@@ -257,7 +260,8 @@ constexpr int kCullGroup = 32;
 
 template <int MODE, bool IDENT>
 static __global__ __launch_bounds__(kBlock) void cull_kernel(TreeArgs tr, InstArgs in, RayArgs ra, RenderOut out,
-                                                              const int32_t* nsamp, int32_t* list,
+                                                              const int32_t* nsamp, const int32_t* head,
+                                                              int32_t* list,
                                                               unsigned long long* count) {
     const int lane = threadIdx.x & 63;
     const int x = (int)(blockIdx.x & (kQueues - 1));
@@ -301,6 +305,8 @@ static __global__ __launch_bounds__(kBlock) void cull_kernel(TreeArgs tr, InstAr
                         if (!k) write_miss(out, ray);
                     } else {
                         k = nsamp[ray] > 0;
+                        if constexpr (MODE == 2) k = k && head[ray] < 0;
+                        if constexpr (MODE == 3) k = k && head[ray] >= 0;
                     }
                 }
                 keep[r] = __ballot(k);
@@ -351,6 +357,8 @@ static __global__ __launch_bounds__(kBlock) void cull_kernel(TreeArgs tr, InstAr
                     if (!k) write_miss(out, ray);
                 } else {
                     k = nsamp[ray] > 0;
+                    if constexpr (MODE == 2) k = k && head[ray] < 0;
+                    if constexpr (MODE == 3) k = k && head[ray] >= 0;
                 }
             }
             keep[j] = __ballot(k);
@@ -373,7 +381,8 @@ static __global__ __launch_bounds__(kBlock) void cull_kernel(TreeArgs tr, InstAr
 
 template <int MODE>
 static hipError_t launch_cull(const TreeArgs& tr, const InstArgs& in, const RayArgs& ra, const RenderOut& out,
-                              const int32_t* nsamp, int32_t* list, unsigned long long* count, hipStream_t st) {
+                              const int32_t* nsamp, const int32_t* head, int32_t* list, unsigned long long* count,
+                              hipStream_t st) {
     const int64_t n_chunks = (ra.n_slots + 63) >> 6;
     const int64_t groups = (n_chunks / kQueues + 1 + kCullGroup - 1) / kCullGroup;   // per part, at most
     int64_t blocks = (groups + (kBlock / kWave) - 1) / (kBlock / kWave);
@@ -382,9 +391,9 @@ static hipError_t launch_cull(const TreeArgs& tr, const InstArgs& in, const RayA
     if (blocks < 1) blocks = 1;
     const dim3 grid((unsigned)(blocks * kQueues));
     if (in.identity)
-        hipLaunchKernelGGL((cull_kernel<MODE, true>), grid, dim3(kBlock), 0, st, tr, in, ra, out, nsamp, list, count);
+        hipLaunchKernelGGL((cull_kernel<MODE, true>), grid, dim3(kBlock), 0, st, tr, in, ra, out, nsamp, head, list, count);
     else
-        hipLaunchKernelGGL((cull_kernel<MODE, false>), grid, dim3(kBlock), 0, st, tr, in, ra, out, nsamp, list, count);
+        hipLaunchKernelGGL((cull_kernel<MODE, false>), grid, dim3(kBlock), 0, st, tr, in, ra, out, nsamp, head, list, count);
     return hipGetLastError();
 }
 
@@ -407,7 +416,8 @@ static hipError_t with_queue(const RayArgs& ra_in, hipStream_t st, Launch&& laun
 // listed rays. Ray indices must fit int32; larger launches take the slot form.
 template <int MODE, typename Launch>
 static hipError_t with_candidates(const TreeArgs& tr, const InstArgs& in, const RayArgs& ra_in,
-                                  const RenderOut& out, const int32_t* nsamp, hipStream_t st, Launch&& launch) {
+                                  const RenderOut& out, const int32_t* nsamp, hipStream_t st, Launch&& launch,
+                                  const int32_t* head = nullptr) {
     if (ra_in.n > (int64_t)INT32_MAX) return with_queue(ra_in, st, launch);
     const int64_t n_chunks = (ra_in.n_slots + 63) >> 6;
     const size_t qbytes = 2 * kQueues * kQueueStride * sizeof(unsigned long long);
@@ -422,7 +432,7 @@ static hipError_t with_candidates(const TreeArgs& tr, const InstArgs& in, const 
     ra.list = list;
     hipLaunchKernelGGL(zero_queue_kernel, dim3(1), dim3(2 * kQueues * kQueueStride), 0, st, ra.queue);
     e = hipGetLastError();
-    if (e == hipSuccess) e = launch_cull<MODE>(tr, in, ra_in, out, nsamp, list, count, st);
+    if (e == hipSuccess) e = launch_cull<MODE>(tr, in, ra_in, out, nsamp, head, list, count, st);
     if (e == hipSuccess) e = launch(ra);
     const hipError_t f = work_free(q, st);
     return e != hipSuccess ? e : f;
@@ -442,6 +452,29 @@ static __global__ void record_init_kernel(int32_t* head, int64_t n, unsigned lon
     if (i < n) head[i] = -1;
     if (i < kQueues) counter[i * kQueueStride] = 0ull;
     if (i == 0) *leaf_cursor = 0ull;
+}
+
+// Wave-uniform allocation of n (<= kRecBlock) consecutive items from blocks of
+// kRecBlock taken from one counter per XCD; XCD x owns items
+// [cap x / kQueues, cap (x + 1) / kQueues). [cur, end) is what is left of the
+// wavefront's current block. Returns the first item, or -1 when the XCD's
+// part is exhausted. Call with every lane of the wavefront active.
+__device__ __forceinline__ int64_t take_items(unsigned long long* counter, int64_t cap, int home, int n, int64_t& cur,
+                                              int64_t& end) {
+    if (cur + n > end) {
+        const int64_t lo = cap * home / kQueues, hi = cap * (home + 1) / kQueues;
+        unsigned long long b = 0;
+        if ((threadIdx.x & 63) == 0) b = atomicAdd(counter + home * kQueueStride, (unsigned long long)kRecBlock);
+        const uint32_t b_lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)b);
+        const uint32_t b_hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(b >> 32));
+        const int64_t first = lo + (int64_t)(((uint64_t)b_hi << 32) | b_lo);
+        cur = first;
+        end = first + kRecBlock <= hi ? first + kRecBlock : (first < hi ? hi : first);
+    }
+    if (cur + n > end) return -1;
+    const int64_t at = cur;
+    cur += n;
+    return at;
 }
 
 // Takes the record scratch of one adjoint launch (cap > 0) from the pool and

@@ -368,26 +368,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) 
             // order; their leaf rows and basis gradients are summed per leaf later
             const uint64_t hm = __ballot(has);
             const int n_has = __popcll(hm);
-            if (n_has > 0 && wrec + n_has > wend) {
-                const int x = cc.home;
-                const int64_t lo = rec.cap * x / kQueues, hi = rec.cap * (x + 1) / kQueues;
-                unsigned long long b = 0;
-                if (lane == 0) b = atomicAdd(rec.counter + x * kQueueStride, (unsigned long long)kRecBlock);
-                const uint32_t b_lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)b);
-                const uint32_t b_hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(b >> 32));
-                const int64_t first = lo + (int64_t)(((uint64_t)b_hi << 32) | b_lo);
-                wrec = first;
-                wend = first + kRecBlock <= hi ? first + kRecBlock : (first < hi ? hi : first);
-            }
-            if (n_has > 0 && wrec + n_has <= wend) {
+            const int64_t at = n_has > 0 ? take_items(rec.counter, rec.cap, cc.home, n_has, wrec, wend) : -1;
+            if (at >= 0) {
                 if (has) {
-                    my_rec = (int)(wrec + lane_rank(hm));
+                    my_rec = (int)(at + lane_rank(hm));
                     rec.rec[2 * (int64_t)my_rec] =
                         make_int4(__float_as_int(gz0), __float_as_int(gz1), __float_as_int(gz2), __float_as_int(gx));
                     const int nxt = atomicExch(rec.head + leaf, my_rec);
                     rec.rec[2 * (int64_t)my_rec + 1] = make_int4(nxt, (int)ray, __float_as_int(gy), 0);
                 }
-                wrec += n_has;
             }
         }
         // samples without a record: basis gradients and the atomic row scatter

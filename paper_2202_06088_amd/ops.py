@@ -16,9 +16,23 @@ def _dev(x: torch.Tensor):
     return x.device
 
 
+class Trace:
+    """Per-sample trace of one forward call (neuvv_render_trace), replayed by the adjoint of the
+    same call (neuvv_render_backward_trace). Room for `cap` samples; rays whose samples do not
+    fit are walked again by the adjoint."""
+
+    def __init__(self, n_rays: int, cap: int, device):
+        self.n_rays = int(n_rays)
+        self.cap = int(cap)
+        self.buf = torch.empty(_lib.neuvv_trace_bytes(self.n_rays, self.cap), dtype=torch.uint8, device=device)
+        assert self.buf.data_ptr() % 256 == 0
+
+
 def render(tree: VOctree, ray_o: torch.Tensor, ray_d: torch.Tensor, t=0.0, inst: Optional[_lib.neuvv_instance] = None,
-           t_stop: float = 1e-4, image_width: int = 0, want_depth: bool = True, stream=None, out=None):
-    """Returns (rgb [n,3], alpha [n], depth [n] or None, nsamp [n] int32)."""
+           t_stop: float = 1e-4, image_width: int = 0, want_depth: bool = True, stream=None, out=None,
+           trace: Optional[Trace] = None):
+    """Returns (rgb [n,3], alpha [n], depth [n] or None, nsamp [n] int32); with a Trace the call
+    also records its samples there."""
     dev = _dev(ray_o)
     n = ray_o.shape[0]
     ray_t = t if isinstance(t, torch.Tensor) else None
@@ -30,26 +44,36 @@ def render(tree: VOctree, ray_o: torch.Tensor, ray_d: torch.Tensor, t=0.0, inst:
         nsamp = torch.empty(n, dtype=torch.int32, device=dev)
     else:
         rgb, alpha, depth, nsamp = out
-    _lib.neuvv_render(tree.struct(), inst, n, ray_o, ray_d, ray_t, t_scalar, image_width, t_stop, rgb, alpha,
-                      depth, nsamp, stream)
+    if trace is not None:
+        assert trace.n_rays == n
+        _lib.neuvv_render_trace(tree.struct(), inst, n, ray_o, ray_d, ray_t, t_scalar, image_width, t_stop, rgb,
+                                alpha, depth, nsamp, trace.buf, trace.cap, stream)
+    else:
+        _lib.neuvv_render(tree.struct(), inst, n, ray_o, ray_d, ray_t, t_scalar, image_width, t_stop, rgb, alpha,
+                          depth, nsamp, stream)
     return rgb, alpha, depth, nsamp
 
 
 def render_backward(tree: VOctree, ray_o, ray_d, rgb, alpha, nsamp, grad_rgb, grad_alpha=None, t=0.0,
                     inst=None, t_stop: float = 1e-4, image_width: int = 0, grads=None, want_basis=True,
-                    stream=None):
+                    stream=None, trace: Optional[Trace] = None):
     """Accumulates into float32 buffers (fresh zeros if grads is None) and returns them:
     (grad_leaf [N, ROW], grad_basis [T, C]), plus grad_basis_g [T, Cg] for a tree with
-    per-point hyperangle weights."""
+    per-point hyperangle weights. With the Trace of the forward call, replays its samples."""
     if grads is None:
         grads = tree.zero_grads()
     gl, gb = grads[0], grads[1]
     gbg = grads[2] if tree.Cg > 0 else None
     ray_t = t if isinstance(t, torch.Tensor) else None
     t_scalar = 0.0 if ray_t is not None else float(t)
-    _lib.neuvv_render_backward(tree.struct(), inst, ray_o.shape[0], ray_o, ray_d, ray_t, t_scalar, image_width,
-                               t_stop, rgb, alpha, nsamp, grad_rgb, grad_alpha, gl, gb if want_basis else None,
-                               gbg if want_basis else None, stream)
+    if trace is not None:
+        _lib.neuvv_render_backward_trace(tree.struct(), inst, ray_o.shape[0], ray_o, ray_d, ray_t, t_scalar,
+                                         image_width, t_stop, rgb, alpha, nsamp, grad_rgb, grad_alpha, gl,
+                                         gb if want_basis else None, trace.buf, trace.cap, stream)
+    else:
+        _lib.neuvv_render_backward(tree.struct(), inst, ray_o.shape[0], ray_o, ray_d, ray_t, t_scalar, image_width,
+                                   t_stop, rgb, alpha, nsamp, grad_rgb, grad_alpha, gl, gb if want_basis else None,
+                                   gbg if want_basis else None, stream)
     return (gl, gb, gbg) if tree.Cg > 0 else (gl, gb)
 
 

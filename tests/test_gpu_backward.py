@@ -80,6 +80,78 @@ def test_backward_record_modes(records, monkeypatch):
     check(gpu, ref, label=f"records={records} per-ray t")
 
 
+def test_backward_ragged_image():
+    """Rays as a 67-wide image with a partial last row: 8x8 tiles that overhang the image and XCD
+    parts that cut tile rows, for the adjoint's cull and records."""
+    sc = scene_for_config(1)
+    tree = upload(sc)
+    rng = np.random.default_rng(48)
+    cam = config1_camera(sc)
+    o, d = OC.pinhole_rays(64, 64, cam.intr(), cam.c2w)
+    n = 67 * 44 + 13
+    sel = rng.choice(o.shape[0], n, replace=False)
+    o, d = o[sel], d[sel]
+    gC = rng.normal(size=(n, 3)).astype(np.float32)
+    announce("ragged-image backward 67 wide")
+    ref = oracle_render(sc, o, d, None, 3.0, 1e-4, g_rgb=gC)
+    gC[ref["margin"][:, 1] < 1e-3] = 0.0
+    ref = oracle_render(sc, o, d, None, 3.0, 1e-4, g_rgb=gC)
+    gpu = run_backward(tree, o, d, None, 3.0, 1e-4, gC, None, image_width=67)
+    assert int(gpu[3].sum()) > 3000
+    check(gpu, ref, label="ragged image")
+
+
+@pytest.mark.parametrize("cap", [None, 500, 0])
+def test_traced_step(cap):
+    """neuvv_render_trace / neuvv_render_backward_trace: the traced forward gives the plain
+    forward's outputs bit for bit; the adjoint replayed from the trace matches the oracle, with
+    room for every sample, for 500 (most rays walk again) and for none; scalar and per-ray time,
+    identity and a placed instance."""
+    sc = scene_for_config(1)
+    tree = upload(sc)
+    cam = config1_camera(sc)
+    o, d = OC.pinhole_rays(64, 64, cam.intr(), cam.c2w)
+    n = o.shape[0]
+    rng = np.random.default_rng(49)
+    gC = rng.normal(size=(n, 3)).astype(np.float32)
+    gA = rng.normal(size=n).astype(np.float32)
+    tr = rng.uniform(0, sc.T - 1, n).astype(np.float32)
+    R = np.array([[0.0, -1.0, 0.0], [1.0, 0.0, 0.0], [0.0, 0.0, 1.0]], np.float32)
+    oi, gi = inst_pair(R, [float(sc.G), 0.0, 0.0], 1.0, 0.5, 0)
+    oo, dd = tdev(o), tdev(d)
+    for t, inst, ginst in ((4.0, None, None), (tr, None, None), (2.0, oi, gi)):
+        tt = tdev(t) if isinstance(t, np.ndarray) else t
+        label = f"trace cap={cap} t={'per-ray' if isinstance(t, np.ndarray) else t} inst={inst is not None}"
+        announce(label)
+        plain = ops.render(tree, oo, dd, tt, ginst, 1e-4, 64)
+        trace = ops.Trace(n, 2 * n if cap is None else cap, oo.device)
+        traced = ops.render(tree, oo, dd, tt, ginst, 1e-4, 64, trace=trace)
+        torch.cuda.synchronize()
+        for a, b in zip(plain, traced):
+            assert torch.equal(a, b)
+        rgb, alpha, depth, nsamp = traced
+        gl, gb = ops.render_backward(tree, oo, dd, rgb, alpha, nsamp, tdev(gC), tdev(gA), tt, ginst, 1e-4, 64,
+                                     trace=trace)
+        torch.cuda.synchronize()
+        hh, ws = tree.unpack_grad(gl)
+        gpu = (hh.cpu().numpy(), ws.cpu().numpy(), gb.cpu().numpy())
+        ref = oracle_render(sc, o, d, t if isinstance(t, np.ndarray) else None,
+                            0.0 if isinstance(t, np.ndarray) else t, 1e-4, inst=inst, g_rgb=gC, g_alpha=gA)
+        amb = ref["margin"][:, 1] < 1e-3
+        if amb.any():   # rays whose stop decision is within rounding: compare without their gradient
+            gC2, gA2 = gC.copy(), gA.copy()
+            gC2[amb], gA2[amb] = 0.0, 0.0
+            ref = oracle_render(sc, o, d, t if isinstance(t, np.ndarray) else None,
+                                0.0 if isinstance(t, np.ndarray) else t, 1e-4, inst=inst, g_rgb=gC2, g_alpha=gA2)
+            gl, gb = ops.render_backward(tree, oo, dd, rgb, alpha, nsamp, tdev(gC2), tdev(gA2), tt, ginst, 1e-4,
+                                         64, trace=trace)
+            torch.cuda.synchronize()
+            hh, ws = tree.unpack_grad(gl)
+            gpu = (hh.cpu().numpy(), ws.cpu().numpy(), gb.cpu().numpy())
+        assert int(nsamp.sum()) > 3000
+        check(gpu, ref, label=label)
+
+
 def test_backward_training_step_per_ray_time():
     """Reduced training step: 16 seeded cameras, random (camera, pixel) rays, random t,
     L2 loss against a target render of a second payload draw."""
