@@ -66,6 +66,7 @@ __device__ __forceinline__ void ray_basis(const TreeArgs& tr, const RaySetup& rs
 template <int K, int C, int DT, bool IDENT, bool EDIT, bool TRACE>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) void render_fwd_kernel(
     TreeArgs tr, InstArgs in, RayArgs ra, float t_stop, RenderOut out) {
+    if (no_candidates(ra)) return;
     __shared__ int4 s_nodes[kLdsNodesFwd];
     __shared__ int s_path[kMaxLevels * kBlock];
     __shared__ float s_h[kBlock * K];
@@ -249,8 +250,9 @@ __host__ __device__ constexpr int grad_row() { return ((3 * K + C + 63) / 64) * 
 // without walking the tree or reading the HH coefficients; otherwise the
 // rays walk.
 template <int K, int C, int DT, bool IDENT, bool REPLAY>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) void render_bwd_kernel(
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(REPLAY ? 4 : 3, 8))) void render_bwd_kernel(
     TreeArgs tr, InstArgs in, RayArgs ra, BackwardIO io, RecordArgs rec) {
+    if (no_candidates(ra)) return;
     constexpr int ROW = grad_row<K, C>();
     // a replaying launch does not walk: no node rows or paths
     constexpr int kNodes = REPLAY ? 1 : kLdsNodesBwd;

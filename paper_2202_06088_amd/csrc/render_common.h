@@ -190,6 +190,16 @@ __device__ __forceinline__ int64_t chunk_ray(const RayArgs& ra, const ChunkCurso
     return r < ra.n ? r : -1;
 }
 
+// True when a candidate-form launch has no candidates at all (every block
+// then leaves before staging anything; the same answer for every thread).
+__device__ __forceinline__ bool no_candidates(const RayArgs& ra) {
+    if (!ra.list) return false;
+    unsigned long long total = 0;
+#pragma unroll
+    for (int x = 0; x < kQueues; ++x) total += ra.count[x * kQueueStride];
+    return total == 0;
+}
+
 // Stages the first min(n_nodes, CAP) node rows (the top levels, stored
 // first) in LDS; returns their number.
 template <int CAP>

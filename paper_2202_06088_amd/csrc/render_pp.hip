@@ -125,6 +125,7 @@ __device__ __forceinline__ void pp_eval(const TreeArgs& tr, const RaySetup& rs, 
 template <int DT, bool IDENT>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) void render_pp_fwd_kernel(
     TreeArgs tr, InstArgs in, RayArgs ra, float t_stop, RenderOut out) {
+    if (no_candidates(ra)) return;
     using namespace pp;
     __shared__ int4 s_nodes[kLdsNodes];
     __shared__ int s_path[kMaxLevels * kBlock];
@@ -239,6 +240,7 @@ __device__ __forceinline__ int pp_component(int j, int lane) { return j * kWave 
 template <int DT, bool IDENT>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) void render_pp_bwd_kernel(
     TreeArgs tr, InstArgs in, RayArgs ra, BackwardIO io, RecordArgs rec) {
+    if (no_candidates(ra)) return;
     using namespace pp;
     __shared__ int4 s_nodes[kLdsNodes];
     __shared__ int s_path[kMaxLevels * kBlock];
