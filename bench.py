@@ -215,12 +215,13 @@ def main():
     achieved = dbytes / (dms * 1e-3) / 1e9
     workload = "forward_ring_d9_2M_8x1080p" + ("" if args.form == "global" else "_per_point")
     roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(f"{dom}/{args.layout}/{args.dtype}", workload),
+            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(f"{dom}/{args.layout}/{args.dtype}{'/traced' if traced else ''}", workload),
             "algorithmic_bytes_per_launch": dbytes, "launch_ms": round(dms, 4)}
     other = [k for k in kern if k != dom][0]
     roof_other = {"kernel": other, "achieved": round(kern[other][1] / (kern[other][0] * 1e-3) / 1e9, 1),
                   "launch_ms": round(kern[other][0], 4), "algorithmic_bytes_per_launch": kern[other][1],
-                  "traffic": measured_traffic(f"{other}/{args.layout}/{args.dtype}", workload)}
+                  "traffic": measured_traffic(f"{other}/{args.layout}/{args.dtype}{'/traced' if traced else ''}",
+                                              workload)}
 
     result = {
         "metric": METRIC, "value": round(n / (ms_step * 1e-3) / 1e6, 2), "unit": "Mrays/s", "n_gpus": 1,
