@@ -236,21 +236,34 @@ def main():
         "roofline": roof, "roofline_other_kernel": roof_other,
     }
 
+    # the legs below compare against a plain forward (neuvv_render, no trace written)
+    plain_fwd_ms = fwd_ms
+    if traced and (args.lighting or args.multi or args.editing):
+        torch.cuda.synchronize()
+        p0, p1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        p0.record(stream)
+        for _ in range(args.steps):
+            _lib.neuvv_render(tree.struct(), None, n, ray_o, ray_d, None, t_frame, W, t_stop, rgb, alpha, depth,
+                              nsamp, stream)
+        p1.record(stream)
+        torch.cuda.synchronize()
+        plain_fwd_ms = p0.elapsed_time(p1) / args.steps
+        log(f"plain forward (no trace) {plain_fwd_ms:.3f} ms")
     if args.lighting:
-        result["lighting"] = lighting_leg(sc, tree, ray_o, ray_d, rgb, alpha, depth, t_frame, t_stop, W, fwd_ms,
-                                          stream, args.steps)
+        result["lighting"] = lighting_leg(sc, tree, ray_o, ray_d, rgb, alpha, depth, t_frame, t_stop, W,
+                                          plain_fwd_ms, stream, args.steps)
     if args.multi:
         if tree.Cg > 0 or not 2 <= args.multi <= 4:
             log("--multi needs the global form and 2..4 instances; skipped")
         else:
-            result["multi"] = multi_leg(sc, tree, args.multi, ray_o, ray_d, t_frame, t_stop, W, fwd_ms, stream,
-                                        args.steps)
+            result["multi"] = multi_leg(sc, tree, args.multi, ray_o, ray_d, t_frame, t_stop, W, plain_fwd_ms,
+                                        stream, args.steps)
     if args.editing:
         if tree.Cg > 0:
             log("appearance edits are compiled for the global form only; --editing skipped")
         else:
             result["editing"] = editing_leg(tree, ray_o, ray_d, rgb, alpha, depth, nsamp, t_frame, t_stop, W, H,
-                                            fwd_ms, stream, args.steps)
+                                            plain_fwd_ms, stream, args.steps)
     if not args.no_cpu_baseline:
         result.update(cpu_leg(sc, cams, t_frame, t_stop, rgb, g_rgb, grads, tree, args.cpu_seconds))
     print(json.dumps(result), flush=True)

@@ -268,8 +268,18 @@ static __global__ void zero_queue_kernel(unsigned long long* q) { q[threadIdx.x]
 // take one memory latency per round for every ray.
 constexpr int kCullGroup = 32;
 
-template <int MODE, bool IDENT>
-static __global__ __launch_bounds__(kBlock) void cull_kernel(TreeArgs tr, InstArgs in, RayArgs ra, RenderOut out,
+// Coarse test of one placed tree (the forward's cull).
+template <bool IDENT>
+struct TreeHit {
+    TreeArgs tr;
+    InstArgs in;
+    __device__ __forceinline__ bool operator()(const float o[3], const float d[3]) const {
+        return ray_may_hit<IDENT>(tr, in, o, d);
+    }
+};
+
+template <int MODE, class Hit>
+static __global__ __launch_bounds__(kBlock) void cull_kernel(Hit hit, RayArgs ra, RenderOut out,
                                                               const int32_t* nsamp, const int32_t* head,
                                                               int32_t* list,
                                                               unsigned long long* count) {
@@ -311,7 +321,7 @@ static __global__ __launch_bounds__(kBlock) void cull_kernel(TreeArgs tr, InstAr
                         const f3v ov = load3(ra.o + 3 * ray), dv = load3(ra.d + 3 * ray);
                         const float o[3] = {ov.x, ov.y, ov.z};
                         const float d[3] = {dv.x, dv.y, dv.z};
-                        k = ray_may_hit<IDENT>(tr, in, o, d);
+                        k = hit(o, d);
                         if (!k) write_miss(out, ray);
                     } else {
                         k = nsamp[ray] > 0;
@@ -363,7 +373,7 @@ static __global__ __launch_bounds__(kBlock) void cull_kernel(TreeArgs tr, InstAr
                     const f3v ov = load3(ra.o + 3 * ray), dv = load3(ra.d + 3 * ray);
                     const float o[3] = {ov.x, ov.y, ov.z};
                     const float d[3] = {dv.x, dv.y, dv.z};
-                    k = ray_may_hit<IDENT>(tr, in, o, d);
+                    k = hit(o, d);
                     if (!k) write_miss(out, ray);
                 } else {
                     k = nsamp[ray] > 0;
@@ -389,10 +399,9 @@ static __global__ __launch_bounds__(kBlock) void cull_kernel(TreeArgs tr, InstAr
     }
 }
 
-template <int MODE>
-static hipError_t launch_cull(const TreeArgs& tr, const InstArgs& in, const RayArgs& ra, const RenderOut& out,
-                              const int32_t* nsamp, const int32_t* head, int32_t* list, unsigned long long* count,
-                              hipStream_t st) {
+template <int MODE, class Hit>
+static hipError_t launch_cull_hit(const Hit& hit, const RayArgs& ra, const RenderOut& out, const int32_t* nsamp,
+                                  const int32_t* head, int32_t* list, unsigned long long* count, hipStream_t st) {
     const int64_t n_chunks = (ra.n_slots + 63) >> 6;
     const int64_t groups = (n_chunks / kQueues + 1 + kCullGroup - 1) / kCullGroup;   // per part, at most
     int64_t blocks = (groups + (kBlock / kWave) - 1) / (kBlock / kWave);
@@ -400,11 +409,16 @@ static hipError_t launch_cull(const TreeArgs& tr, const InstArgs& in, const RayA
     if (blocks > cap) blocks = cap;
     if (blocks < 1) blocks = 1;
     const dim3 grid((unsigned)(blocks * kQueues));
-    if (in.identity)
-        hipLaunchKernelGGL((cull_kernel<MODE, true>), grid, dim3(kBlock), 0, st, tr, in, ra, out, nsamp, head, list, count);
-    else
-        hipLaunchKernelGGL((cull_kernel<MODE, false>), grid, dim3(kBlock), 0, st, tr, in, ra, out, nsamp, head, list, count);
+    hipLaunchKernelGGL((cull_kernel<MODE, Hit>), grid, dim3(kBlock), 0, st, hit, ra, out, nsamp, head, list, count);
     return hipGetLastError();
+}
+
+template <int MODE>
+static hipError_t launch_cull(const TreeArgs& tr, const InstArgs& in, const RayArgs& ra, const RenderOut& out,
+                              const int32_t* nsamp, const int32_t* head, int32_t* list, unsigned long long* count,
+                              hipStream_t st) {
+    if (in.identity) return launch_cull_hit<MODE>(TreeHit<true>{tr, in}, ra, out, nsamp, head, list, count, st);
+    return launch_cull_hit<MODE>(TreeHit<false>{tr, in}, ra, out, nsamp, head, list, count, st);
 }
 
 // Runs launch(ra) with the launch's queue counters set; rays are the slots.
@@ -422,12 +436,11 @@ static hipError_t with_queue(const RayArgs& ra_in, hipStream_t st, Launch&& laun
     return e != hipSuccess ? e : f;
 }
 
-// Candidate form: cull pass (MODE as in cull_kernel), then launch(ra) over the
-// listed rays. Ray indices must fit int32; larger launches take the slot form.
-template <int MODE, typename Launch>
-static hipError_t with_candidates(const TreeArgs& tr, const InstArgs& in, const RayArgs& ra_in,
-                                  const RenderOut& out, const int32_t* nsamp, hipStream_t st, Launch&& launch,
-                                  const int32_t* head = nullptr) {
+// Candidate form: cull(list, count) lists the rays, then launch(ra) runs over
+// them. Ray indices must fit int32; larger launches take the slot form (the
+// render kernels then test every ray themselves).
+template <typename Cull, typename Launch>
+static hipError_t with_list(const RayArgs& ra_in, hipStream_t st, Cull&& cull, Launch&& launch) {
     if (ra_in.n > (int64_t)INT32_MAX) return with_queue(ra_in, st, launch);
     const int64_t n_chunks = (ra_in.n_slots + 63) >> 6;
     const size_t qbytes = 2 * kQueues * kQueueStride * sizeof(unsigned long long);
@@ -442,10 +455,23 @@ static hipError_t with_candidates(const TreeArgs& tr, const InstArgs& in, const 
     ra.list = list;
     hipLaunchKernelGGL(zero_queue_kernel, dim3(1), dim3(2 * kQueues * kQueueStride), 0, st, ra.queue);
     e = hipGetLastError();
-    if (e == hipSuccess) e = launch_cull<MODE>(tr, in, ra_in, out, nsamp, head, list, count, st);
+    if (e == hipSuccess) e = cull(list, count);
     if (e == hipSuccess) e = launch(ra);
     const hipError_t f = work_free(q, st);
     return e != hipSuccess ? e : f;
+}
+
+// Candidate form with the cull pass of one placed tree (MODE as in cull_kernel).
+template <int MODE, typename Launch>
+static hipError_t with_candidates(const TreeArgs& tr, const InstArgs& in, const RayArgs& ra_in,
+                                  const RenderOut& out, const int32_t* nsamp, hipStream_t st, Launch&& launch,
+                                  const int32_t* head = nullptr) {
+    return with_list(
+        ra_in, st,
+        [&](int32_t* list, unsigned long long* count) {
+            return launch_cull<MODE>(tr, in, ra_in, out, nsamp, head, list, count, st);
+        },
+        launch);
 }
 
 // ----------------------------------------------------------------------------

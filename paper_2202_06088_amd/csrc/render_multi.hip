@@ -16,7 +16,9 @@
 // Per lane and instance, the ray setup, walk state and current segment stay
 // in registers (the HH basis is recomputed at each segment fetch); with 4
 // instances that needs the accumulation registers too, so the kernel runs one
-// wavefront per SIMD. Work distribution is that of render.hip.
+// wavefront per SIMD. Work distribution is that of render.hip: a cull pass
+// (here: may the ray hit any instance) lists the candidate rays per XCD
+// part, and persistent wavefronts take 64-ray chunks of the lists.
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -73,9 +75,22 @@ __device__ __forceinline__ void fetch_segment(const TreeArgs& tr, const int4* s_
     sg.has = true;
 }
 
+// Coarse test of L placed trees: may the ray hit any of them (the cull pass).
+template <int L>
+struct AnyTreeHit {
+    MultiArgs ma;
+    __device__ __forceinline__ bool operator()(const float o[3], const float d[3]) const {
+        bool h = false;
+#pragma unroll
+        for (int k = 0; k < L; ++k) h = h || ray_may_hit<false>(ma.tr[k], ma.in[k], o, d);
+        return h;
+    }
+};
+
 template <int L, int DT>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 8))) void render_multi_kernel(
     MultiArgs ma, RayArgs ra, float t_stop, RenderOut out) {
+    if (no_candidates(ra)) return;
     __shared__ int4 s_nodes[L][kLdsNodesMulti];
     __shared__ int s_path[L][kMaxLevels * kBlock];
     int n_lds[L];
@@ -120,8 +135,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 8))) 
                             o[0] = ra.o[3 * ray]; o[1] = ra.o[3 * ray + 1]; o[2] = ra.o[3 * ray + 2];
                             d[0] = ra.d[3 * ray]; d[1] = ra.d[3 * ray + 1]; d[2] = ra.d[3 * ray + 2];
                             t = ra.t ? ra.t[ray] : ra.t_scalar;
-#pragma unroll
-                            for (int k = 0; k < L; ++k) cand = cand || ray_may_hit<false>(ma.tr[k], ma.in[k], o, d);
+                            cand = ra.list != nullptr || AnyTreeHit<L>{ma}(o, d);
                             if (!cand) write_miss(out, ray);
                         }
                     }
@@ -216,9 +230,17 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 8))) 
 
 template <int L, int DT>
 static hipError_t multi_t(const MultiArgs& ma, const RayArgs& ra, float t_stop, const RenderOut& o, hipStream_t st) {
-    auto kern = render_multi_kernel<L, DT>;
-    hipLaunchKernelGGL(kern, dim3(grid_for(kern, ra)), dim3(kBlock), 0, st, ma, ra, t_stop, o);
-    return hipGetLastError();
+    // cull pass over every instance, then the merge over the listed rays
+    return with_list(
+        ra, st,
+        [&](int32_t* list, unsigned long long* count) {
+            return launch_cull_hit<0>(AnyTreeHit<L>{ma}, ra, o, nullptr, nullptr, list, count, st);
+        },
+        [&](const RayArgs& r) {
+            auto kern = render_multi_kernel<L, DT>;
+            hipLaunchKernelGGL(kern, dim3(grid_for(kern, r)), dim3(kBlock), 0, st, ma, r, t_stop, o);
+            return hipGetLastError();
+        });
 }
 
 template <int DT>
@@ -236,9 +258,9 @@ hipError_t launch_render_multi(int L, int dtype, const MultiArgs& ma, const RayA
                                const RenderOut& out, hipStream_t stream) {
     if (ra.n_slots <= 0) return hipSuccess;
     switch (dtype) {
-        case 0: return with_queue(ra, stream, [&](const RayArgs& r) { return multi_l<0>(L, ma, r, t_stop, out, stream); });
-        case 1: return with_queue(ra, stream, [&](const RayArgs& r) { return multi_l<1>(L, ma, r, t_stop, out, stream); });
-        default: return with_queue(ra, stream, [&](const RayArgs& r) { return multi_l<2>(L, ma, r, t_stop, out, stream); });
+        case 0: return multi_l<0>(L, ma, ra, t_stop, out, stream);
+        case 1: return multi_l<1>(L, ma, ra, t_stop, out, stream);
+        default: return multi_l<2>(L, ma, ra, t_stop, out, stream);
     }
 }
 
