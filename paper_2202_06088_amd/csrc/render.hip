@@ -270,6 +270,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(REPLAY ?
     const bool per_ray_t = ra.t != nullptr;
     const int lane = threadIdx.x & 63;
     const int wbase = threadIdx.x - lane;
+    // one time for every ray and records: the basis gradient of recorded samples
+    // is summed per leaf by the reduction (sum gx times w^sigma), not here
+    const bool basis_late = rec.head != nullptr && !per_ray_t;
+    const bool basis_here = io.grad_basis != nullptr && !basis_late;
 
     bool alive = false;
     int64_t ray = -1;
@@ -368,7 +372,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(REPLAY ?
                     c1 = __int_as_float(B.x);
                     c2 = __int_as_float(B.y);
                     tnext = B.z;
-                    if (io.grad_basis) load_leaf<DT, C>(tr.wsig, N, leaf, tr.layout, sv);
+                    if (basis_here) load_leaf<DT, C>(tr.wsig, N, leaf, tr.layout, sv);
                 }
                 finish = leaf < 0;
             } else {
@@ -414,7 +418,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(REPLAY ?
                 gz0 = g0 * wt * c0 * (1.0f - c0);
                 gz1 = g1 * wt * c1 * (1.0f - c1);
                 gz2 = g2 * wt * c2 * (1.0f - c2);
-                if (io.grad_basis) {
+                if (basis_here) {
 #pragma unroll
                     for (int c = 0; c < C; ++c) gb[c] = fmaf(gx, sv[c], gb[c]);
                 }
@@ -449,6 +453,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(REPLAY ?
                     rec.rec[2 * (int64_t)my_rec + 1] = make_int4(nxt, (int)ray, 0, 0);
                 }
             }
+        }
+        if (basis_late && io.grad_basis && has && my_rec < 0) {
+            // a sample without a record: its basis gradient stays here
+            float sw[C];
+            load_leaf<DT, C>(tr.wsig, N, leaf, tr.layout, sw);
+#pragma unroll
+            for (int c = 0; c < C; ++c) gb[c] = fmaf(gx, sw[c], gb[c]);
         }
         // samples without a record: every lane of the wavefront adds one
         // component of each produced row
@@ -510,20 +521,28 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(REPLAY ?
 // leaf. The link of a lane's next record is loaded one record ahead.
 
 
-template <int K, int C, bool IDENT>
+// grad_basis (one time for every ray, else nullptr): the basis gradient of the
+// recorded samples, (sum gx) w^sigma per leaf, summed over the block and
+// spread over the two interpolated rows.
+template <int K, int C, int DT, bool IDENT>
 __global__ __launch_bounds__(kBlock) void reduce_records_kernel(TreeArgs tr, InstArgs in, RayArgs ra,
-                                                                RecordArgs rec, float* grad_leaf) {
+                                                                RecordArgs rec, float* grad_leaf, float* grad_basis) {
     constexpr int ROW = grad_row<K, C>();
     constexpr int R = 3 * K + C;
-    __shared__ float s_row[kBlock / kWave][kFlushSlots][R + 1];
+    // a finished leaf's slot: its row, sum gx, its w^sigma
+    __shared__ float s_row[kBlock / kWave][kFlushSlots][R + 1 + C + 1];
+    __shared__ float s_gb[C];
+    if (threadIdx.x < C) s_gb[threadIdx.x] = 0.0f;
+    __syncthreads();
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int N = (int)tr.n_leaves;
+    float bacc = 0.0f;   // lane c < C: component c of the basis gradient
 
     int leaf = -1;                // this lane's leaf; -1: idle
     int4 ra0 = make_int4(0, 0, 0, 0), ra1 = make_int4(-1, 0, 0, 0);   // its current record
-    float acc[R];
+    float acc[R + 1];             // the row, then sum gx
 #pragma unroll
-    for (int c = 0; c < R; ++c) acc[c] = 0.0f;
+    for (int c = 0; c <= R; ++c) acc[c] = 0.0f;
     int cur = 0, end = 0;         // wave-uniform: leaves [cur, end) of the batch not yet handed out
     bool more = true;
     const int64_t n_waves = (int64_t)gridDim.x * (kBlock / kWave);
@@ -589,6 +608,7 @@ __global__ __launch_bounds__(kBlock) void reduce_records_kernel(TreeArgs tr, Ins
             }
 #pragma unroll
             for (int c = 0; c < C; ++c) acc[3 * K + c] = fmaf(g.w, bv[c], acc[3 * K + c]);
+            acc[R] += g.w;
             ra0 = nx0;
             ra1 = nx1;
             done = nxt < 0;
@@ -600,8 +620,14 @@ __global__ __launch_bounds__(kBlock) void reduce_records_kernel(TreeArgs tr, Ins
             const int r = lane_rank(dm);
             const bool mine = ((dm >> lane) & 1ull) && r < kFlushSlots;
             if (mine) {
+                if (grad_basis) {
+                    float sw[C];
+                    load_leaf<DT, C>(tr.wsig, tr.n_leaves, leaf, tr.layout, sw);
 #pragma unroll
-                for (int c = 0; c < R; ++c) {
+                    for (int c = 0; c < C; ++c) s_row[wv][r][R + 1 + c] = sw[c];
+                }
+#pragma unroll
+                for (int c = 0; c <= R; ++c) {
                     s_row[wv][r][c] = acc[c];
                     acc[c] = 0.0f;
                 }
@@ -613,10 +639,23 @@ __global__ __launch_bounds__(kBlock) void reduce_records_kernel(TreeArgs tr, Ins
                 sm &= sm - 1;
                 const int L = __builtin_amdgcn_readlane(leaf, j);
                 if (lane < R) unsafeAtomicAdd(grad_leaf + (int64_t)L * ROW + lane, s_row[wv][q][lane]);
+                if (grad_basis && lane < C) bacc = fmaf(s_row[wv][q][R], s_row[wv][q][R + 1 + lane], bacc);
             }
             __builtin_amdgcn_wave_barrier();
             if (mine) leaf = -1;
             dm = __ballot(done && leaf >= 0);
+        }
+    }
+    if (grad_basis) {
+        if (lane < C) atomicAdd(&s_gb[lane], bacc);
+        __syncthreads();
+        if (threadIdx.x < C) {
+            int i0, i1;
+            float f;
+            time_setup(tr, in, ra.t_scalar, i0, i1, f);
+            const float v = s_gb[threadIdx.x];
+            unsafeAtomicAdd(grad_basis + (int64_t)i0 * C + threadIdx.x, (1.0f - f) * v);
+            if (f != 0.0f) unsafeAtomicAdd(grad_basis + (int64_t)i1 * C + threadIdx.x, f * v);
         }
     }
 }
@@ -762,12 +801,13 @@ static hipError_t bwd_t(const TreeArgs& tr, const InstArgs& in, const RayArgs& r
         int64_t blocks = (tr.n_leaves + kBlock - 1) / kBlock;
         const int64_t lim = (int64_t)device_cu_count() * 4;
         if (blocks > lim) blocks = lim;
+        float* gbasis = ra.t == nullptr ? io.grad_basis : nullptr;
         if (in.identity)
-            hipLaunchKernelGGL((reduce_records_kernel<K, C, true>), dim3((unsigned)blocks), dim3(kBlock), 0, st, tr,
-                               in, ra, rec, io.grad_leaf);
+            hipLaunchKernelGGL((reduce_records_kernel<K, C, DT, true>), dim3((unsigned)blocks), dim3(kBlock), 0, st,
+                               tr, in, ra, rec, io.grad_leaf, gbasis);
         else
-            hipLaunchKernelGGL((reduce_records_kernel<K, C, false>), dim3((unsigned)blocks), dim3(kBlock), 0, st, tr,
-                               in, ra, rec, io.grad_leaf);
+            hipLaunchKernelGGL((reduce_records_kernel<K, C, DT, false>), dim3((unsigned)blocks), dim3(kBlock), 0, st,
+                               tr, in, ra, rec, io.grad_leaf, gbasis);
         e = hipGetLastError();
     }
     if (mem) {
