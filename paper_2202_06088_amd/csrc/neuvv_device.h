@@ -115,22 +115,27 @@ __device__ __forceinline__ int df_cell(df a, int sign) {
 // spherical harmonic of the unit direction d = (x, y, z), polar axis z, no
 // Condon-Shortley phase (cos m phi for m > 0, sin |m| phi for m < 0). Order:
 // n = 0.., l = 0..n, m = -l..l. Constants are the closed forms evaluated.
-__device__ __forceinline__ void hh_all(float x, float y, float z, float gam, float (&h)[30]) {
+// Radial factors g_nl of the hyperangle gamma, n + l <= 3 (order g00, g10, g11,
+// g20, g21, g22, g30, g31, g32, g33).
+__device__ __forceinline__ void hh_radial(float gam, float (&g)[10]) {
     float s, c;
     sincosf(gam, &s, &c);
     const float c2 = c * c, s2 = s * s;
-    // radial factors g_nl
-    const float g00 = 0.7978845608028654f;                       // sqrt(2/pi)
-    const float g10 = 1.5957691216057308f * c;                   // 2 sqrt(2/pi) cos
-    const float g11 = 0.9213177319235613f * s;                   // 2 sqrt(2/(3pi)) sin
-    const float g20 = 0.7978845608028654f * (4.0f * c2 - 1.0f);  // sqrt(2/pi) U_2
-    const float g21 = 2.256758334191025f * s * c;                // (1/sqrt(pi)) sin * 4 cos
-    const float g22 = 1.009253008808064f * s2;                   // 8/sqrt(20 pi) sin^2
-    const float g30 = 0.7978845608028654f * c * (8.0f * c2 - 4.0f);  // sqrt(2/pi) U_3
-    const float g31 = 0.41202581549140227f * s * (12.0f * c2 - 2.0f); // 2 sqrt(2/(15pi)) sin C^2_2
-    const float g32 = 2.854598585844434f * c * s2;               // 8/sqrt(90 pi) sin^2 * 6 cos
-    const float g33 = 1.0789368501515768f * s2 * s;              // 48/sqrt(630 pi) sin^3
-    // real spherical harmonics up to degree 3
+    g[0] = 0.7978845608028654f;                        // sqrt(2/pi)
+    g[1] = 1.5957691216057308f * c;                    // 2 sqrt(2/pi) cos
+    g[2] = 0.9213177319235613f * s;                    // 2 sqrt(2/(3pi)) sin
+    g[3] = 0.7978845608028654f * (4.0f * c2 - 1.0f);   // sqrt(2/pi) U_2
+    g[4] = 2.256758334191025f * s * c;                 // (1/sqrt(pi)) sin * 4 cos
+    g[5] = 1.009253008808064f * s2;                    // 8/sqrt(20 pi) sin^2
+    g[6] = 0.7978845608028654f * c * (8.0f * c2 - 4.0f);    // sqrt(2/pi) U_3
+    g[7] = 0.41202581549140227f * s * (12.0f * c2 - 2.0f);  // 2 sqrt(2/(15pi)) sin C^2_2
+    g[8] = 2.854598585844434f * c * s2;                // 8/sqrt(90 pi) sin^2 * 6 cos
+    g[9] = 1.0789368501515768f * s2 * s;               // 48/sqrt(630 pi) sin^3
+}
+
+// The 30 HH values from the radial factors and the unit direction (x, y, z):
+// h = g_nl Y_lm with real spherical harmonics up to degree 3.
+__device__ __forceinline__ void hh_assemble(const float (&g)[10], float x, float y, float z, float (&h)[30]) {
     const float x2 = x * x, y2 = y * y, z2 = z * z;
     const float Y00 = 0.28209479177387814f;
     const float k1 = 0.4886025119029199f;
@@ -143,17 +148,23 @@ __device__ __forceinline__ void hh_all(float x, float y, float z, float gam, flo
     const float Y3n1 = k31 * y * (5.0f * z2 - 1.0f), Y30 = 0.3731763325901154f * z * (5.0f * z2 - 3.0f);
     const float Y31 = k31 * x * (5.0f * z2 - 1.0f), Y32 = 1.445305721320277f * z * (x2 - y2);
     const float Y33 = k33 * x * (x2 - 3.0f * y2);
-    h[0] = g00 * Y00;
-    h[1] = g10 * Y00;
-    h[2] = g11 * Y1n1; h[3] = g11 * Y10; h[4] = g11 * Y11;
-    h[5] = g20 * Y00;
-    h[6] = g21 * Y1n1; h[7] = g21 * Y10; h[8] = g21 * Y11;
-    h[9] = g22 * Y2n2; h[10] = g22 * Y2n1; h[11] = g22 * Y20; h[12] = g22 * Y21; h[13] = g22 * Y22;
-    h[14] = g30 * Y00;
-    h[15] = g31 * Y1n1; h[16] = g31 * Y10; h[17] = g31 * Y11;
-    h[18] = g32 * Y2n2; h[19] = g32 * Y2n1; h[20] = g32 * Y20; h[21] = g32 * Y21; h[22] = g32 * Y22;
-    h[23] = g33 * Y3n3; h[24] = g33 * Y3n2; h[25] = g33 * Y3n1; h[26] = g33 * Y30;
-    h[27] = g33 * Y31; h[28] = g33 * Y32; h[29] = g33 * Y33;
+    h[0] = g[0] * Y00;
+    h[1] = g[1] * Y00;
+    h[2] = g[2] * Y1n1; h[3] = g[2] * Y10; h[4] = g[2] * Y11;
+    h[5] = g[3] * Y00;
+    h[6] = g[4] * Y1n1; h[7] = g[4] * Y10; h[8] = g[4] * Y11;
+    h[9] = g[5] * Y2n2; h[10] = g[5] * Y2n1; h[11] = g[5] * Y20; h[12] = g[5] * Y21; h[13] = g[5] * Y22;
+    h[14] = g[6] * Y00;
+    h[15] = g[7] * Y1n1; h[16] = g[7] * Y10; h[17] = g[7] * Y11;
+    h[18] = g[8] * Y2n2; h[19] = g[8] * Y2n1; h[20] = g[8] * Y20; h[21] = g[8] * Y21; h[22] = g[8] * Y22;
+    h[23] = g[9] * Y3n3; h[24] = g[9] * Y3n2; h[25] = g[9] * Y3n1; h[26] = g[9] * Y30;
+    h[27] = g[9] * Y31; h[28] = g[9] * Y32; h[29] = g[9] * Y33;
+}
+
+__device__ __forceinline__ void hh_all(float x, float y, float z, float gam, float (&h)[30]) {
+    float g[10];
+    hh_radial(gam, g);
+    hh_assemble(g, x, y, z, h);
 }
 
 // Per-point hyperangle form (Eq. 6), first 14 functions (all n <= 2): the

@@ -521,17 +521,37 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(REPLAY ?
 // leaf. The link of a lane's next record is loaded one record ahead.
 
 
-// grad_basis (one time for every ray, else nullptr): the basis gradient of the
-// recorded samples, (sum gx) w^sigma per leaf, summed over the block and
-// spread over the two interpolated rows.
-template <int K, int C, int DT, bool IDENT>
+// COMMON_T (one time for every ray): the hyperangle gamma(tau) and the
+// density-basis row b(tau) are the same for all records, so the radial factors
+// of the HH basis and b are computed once, a record costs only its ray's
+// harmonics, and a lane holds the 3K HH sums and sum gx; the row's density
+// part is then (sum gx) b and the basis gradient (sum gx) w^sigma per leaf,
+// summed over the block and spread over the two interpolated rows (when
+// grad_basis is given). Otherwise every record redoes its ray's time frames
+// and basis, and the basis gradient stays with the adjoint.
+template <int K, int C, int DT, bool IDENT, bool COMMON_T>
 __global__ __launch_bounds__(kBlock) void reduce_records_kernel(TreeArgs tr, InstArgs in, RayArgs ra,
                                                                 RecordArgs rec, float* grad_leaf, float* grad_basis) {
     constexpr int ROW = grad_row<K, C>();
     constexpr int R = 3 * K + C;
-    // a finished leaf's slot: its row, sum gx, its w^sigma
-    __shared__ float s_row[kBlock / kWave][kFlushSlots][R + 1 + C + 1];
+    constexpr int NA = COMMON_T ? 3 * K : R;   // row sums a lane holds; acc[NA] = sum gx
+    // a finished leaf's slot: its sums, sum gx, its w^sigma
+    __shared__ float s_row[kBlock / kWave][kFlushSlots][NA + 1 + C + 1];
     __shared__ float s_gb[C];
+    __shared__ float s_bc[C];
+    // scalar time: radial factors and density row of the common frame (the
+    // arithmetic of ray_basis, so the values are the adjoint's)
+    float gq[10];
+    if constexpr (COMMON_T) {
+        int ci0, ci1;
+        float cf;
+        time_setup(tr, in, ra.t_scalar, ci0, ci1, cf);
+        const float gam = (1.0f - cf) * tr.gamma[ci0] + cf * tr.gamma[ci1];
+        hh_radial(gam, gq);
+        if (threadIdx.x < C)
+            s_bc[threadIdx.x] = (1.0f - cf) * tr.basis[(int64_t)ci0 * C + threadIdx.x] +
+                                cf * tr.basis[(int64_t)ci1 * C + threadIdx.x];
+    }
     if (threadIdx.x < C) s_gb[threadIdx.x] = 0.0f;
     __syncthreads();
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -540,9 +560,9 @@ __global__ __launch_bounds__(kBlock) void reduce_records_kernel(TreeArgs tr, Ins
 
     int leaf = -1;                // this lane's leaf; -1: idle
     int4 ra0 = make_int4(0, 0, 0, 0), ra1 = make_int4(-1, 0, 0, 0);   // its current record
-    float acc[R + 1];             // the row, then sum gx
+    float acc[NA + 1];
 #pragma unroll
-    for (int c = 0; c <= R; ++c) acc[c] = 0.0f;
+    for (int c = 0; c <= NA; ++c) acc[c] = 0.0f;
     int cur = 0, end = 0;         // wave-uniform: leaves [cur, end) of the batch not yet handed out
     bool more = true;
     const int64_t n_waves = (int64_t)gridDim.x * (kBlock / kWave);
@@ -593,22 +613,30 @@ __global__ __launch_bounds__(kBlock) void reduce_records_kernel(TreeArgs tr, Ins
                                          __int_as_float(ra0.w));
             const f3v dv = load3(ra.d + 3 * ray);
             const float d[3] = {dv.x, dv.y, dv.z};
-            const float t = ra.t ? ra.t[ray] : ra.t_scalar;
             RaySetup rs;
             float dmax;
             ray_direction<IDENT>(in, d, rs, dmax);
-            time_setup(tr, in, t, rs.i0, rs.i1, rs.f);
-            float h[K], bv[C];
-            ray_basis<K, C>(tr, rs, h, bv);
+            float h[K];
+            if constexpr (COMMON_T) {
+                float hall[30];
+                hh_assemble(gq, rs.dir[0], rs.dir[1], rs.dir[2], hall);
+#pragma unroll
+                for (int k = 0; k < K; ++k) h[k] = hall[k];
+            } else {
+                const float t = ra.t ? ra.t[ray] : ra.t_scalar;
+                time_setup(tr, in, t, rs.i0, rs.i1, rs.f);
+                float bv[C];
+                ray_basis<K, C>(tr, rs, h, bv);
+#pragma unroll
+                for (int c = 0; c < C; ++c) acc[3 * K + c] = fmaf(g.w, bv[c], acc[3 * K + c]);
+            }
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 acc[k] = fmaf(g.x, h[k], acc[k]);
                 acc[K + k] = fmaf(g.y, h[k], acc[K + k]);
                 acc[2 * K + k] = fmaf(g.z, h[k], acc[2 * K + k]);
             }
-#pragma unroll
-            for (int c = 0; c < C; ++c) acc[3 * K + c] = fmaf(g.w, bv[c], acc[3 * K + c]);
-            acc[R] += g.w;
+            acc[NA] += g.w;
             ra0 = nx0;
             ra1 = nx1;
             done = nxt < 0;
@@ -624,10 +652,10 @@ __global__ __launch_bounds__(kBlock) void reduce_records_kernel(TreeArgs tr, Ins
                     float sw[C];
                     load_leaf<DT, C>(tr.wsig, tr.n_leaves, leaf, tr.layout, sw);
 #pragma unroll
-                    for (int c = 0; c < C; ++c) s_row[wv][r][R + 1 + c] = sw[c];
+                    for (int c = 0; c < C; ++c) s_row[wv][r][NA + 1 + c] = sw[c];
                 }
 #pragma unroll
-                for (int c = 0; c <= R; ++c) {
+                for (int c = 0; c <= NA; ++c) {
                     s_row[wv][r][c] = acc[c];
                     acc[c] = 0.0f;
                 }
@@ -638,8 +666,13 @@ __global__ __launch_bounds__(kBlock) void reduce_records_kernel(TreeArgs tr, Ins
                 const int j = __builtin_ctzll(sm);
                 sm &= sm - 1;
                 const int L = __builtin_amdgcn_readlane(leaf, j);
-                if (lane < R) unsafeAtomicAdd(grad_leaf + (int64_t)L * ROW + lane, s_row[wv][q][lane]);
-                if (grad_basis && lane < C) bacc = fmaf(s_row[wv][q][R], s_row[wv][q][R + 1 + lane], bacc);
+                const float sgx = s_row[wv][q][NA];
+                if (lane < 3 * K || (!COMMON_T && lane < R)) {
+                    unsafeAtomicAdd(grad_leaf + (int64_t)L * ROW + lane, s_row[wv][q][lane]);
+                } else if (COMMON_T && lane < R) {
+                    unsafeAtomicAdd(grad_leaf + (int64_t)L * ROW + lane, sgx * s_bc[lane - 3 * K]);
+                }
+                if (grad_basis && lane < C) bacc = fmaf(sgx, s_row[wv][q][NA + 1 + lane], bacc);
             }
             __builtin_amdgcn_wave_barrier();
             if (mine) leaf = -1;
@@ -801,13 +834,22 @@ static hipError_t bwd_t(const TreeArgs& tr, const InstArgs& in, const RayArgs& r
         int64_t blocks = (tr.n_leaves + kBlock - 1) / kBlock;
         const int64_t lim = (int64_t)device_cu_count() * 4;
         if (blocks > lim) blocks = lim;
-        float* gbasis = ra.t == nullptr ? io.grad_basis : nullptr;
-        if (in.identity)
-            hipLaunchKernelGGL((reduce_records_kernel<K, C, DT, true>), dim3((unsigned)blocks), dim3(kBlock), 0, st,
-                               tr, in, ra, rec, io.grad_leaf, gbasis);
-        else
-            hipLaunchKernelGGL((reduce_records_kernel<K, C, DT, false>), dim3((unsigned)blocks), dim3(kBlock), 0, st,
-                               tr, in, ra, rec, io.grad_leaf, gbasis);
+        const dim3 grid((unsigned)blocks);
+        if (ra.t == nullptr) {
+            if (in.identity)
+                hipLaunchKernelGGL((reduce_records_kernel<K, C, DT, true, true>), grid, dim3(kBlock), 0, st, tr, in,
+                                   ra, rec, io.grad_leaf, io.grad_basis);
+            else
+                hipLaunchKernelGGL((reduce_records_kernel<K, C, DT, false, true>), grid, dim3(kBlock), 0, st, tr, in,
+                                   ra, rec, io.grad_leaf, io.grad_basis);
+        } else {
+            if (in.identity)
+                hipLaunchKernelGGL((reduce_records_kernel<K, C, DT, true, false>), grid, dim3(kBlock), 0, st, tr, in,
+                                   ra, rec, io.grad_leaf, nullptr);
+            else
+                hipLaunchKernelGGL((reduce_records_kernel<K, C, DT, false, false>), grid, dim3(kBlock), 0, st, tr,
+                                   in, ra, rec, io.grad_leaf, nullptr);
+        }
         e = hipGetLastError();
     }
     if (mem) {
