@@ -563,40 +563,16 @@ __global__ __launch_bounds__(kBlock) void reduce_records_kernel(TreeArgs tr, Ins
     float acc[NA + 1];
 #pragma unroll
     for (int c = 0; c <= NA; ++c) acc[c] = 0.0f;
-    int cur = 0, end = 0;         // wave-uniform: leaves [cur, end) of the batch not yet handed out
-    bool more = true;
-    const int64_t n_waves = (int64_t)gridDim.x * (kBlock / kWave);
-    int64_t batch = (int64_t)blockIdx.x * (kBlock / kWave) + wv;
+    LeafFeeder feeder = leaf_feeder(wv);
+    __shared__ int2 s_q[kBlock / kWave][kWave];
 
     for (;;) {
-        // hand leaves to idle lanes, passing over leaves without records
-        for (;;) {
-            const uint64_t idle = __ballot(leaf < 0);
-            if (!idle || !more) break;
-            if (cur >= end) {
-                const int64_t b0 = batch * kWave;
-                batch += n_waves;
-                if (b0 >= N) {
-                    more = false;
-                    break;
-                }
-                cur = (int)b0;
-                end = b0 + kWave < N ? (int)(b0 + kWave) : N;
-            }
-            const int avail = end - cur, n_idle = __popcll(idle);
-            if (leaf < 0) {
-                const int r = lane_rank(idle);
-                if (r < avail) {
-                    const int L = cur + r;
-                    const int h0 = rec.head[L];
-                    if (h0 >= 0) {
-                        leaf = L;
-                        ra0 = rec.rec[2 * (int64_t)h0];
-                        ra1 = rec.rec[2 * (int64_t)h0 + 1];
-                    }
-                }
-            }
-            cur += n_idle < avail ? n_idle : avail;
+        // hand leaves with records to idle lanes; a lane that got one loads its first record
+        int first = -1;
+        feed_leaves(feeder, rec, tr.n_leaves, s_q[wv], leaf, first);
+        if (first >= 0) {
+            ra0 = rec.rec[2 * (int64_t)first];
+            ra1 = rec.rec[2 * (int64_t)first + 1];
         }
         if (!__ballot(leaf >= 0)) break;   // no work left (more is false)
         bool done = false;

@@ -513,6 +513,65 @@ __device__ __forceinline__ int64_t take_items(unsigned long long* counter, int64
     return at;
 }
 
+// Hands leaves with records to the idle lanes of a reduction wavefront.
+// Wavefront w takes 64-leaf batches w, w + W, ...; a batch's heads are read in
+// one load (lane = leaf) and its leaves with records are compacted into a
+// per-wavefront LDS queue of {leaf, first record}, from which idle lanes take
+// entries in lane order.
+struct LeafFeeder {
+    int64_t batch;     // next batch of this wavefront
+    int64_t n_waves;
+    int cnt, pos;      // wave-uniform: queue entries, entries handed out
+    bool more;         // wave-uniform: batches may be left
+};
+
+__device__ __forceinline__ LeafFeeder leaf_feeder(int wave_in_block) {
+    LeafFeeder f;
+    f.batch = (int64_t)blockIdx.x * (kBlock / kWave) + wave_in_block;
+    f.n_waves = (int64_t)gridDim.x * (kBlock / kWave);
+    f.cnt = f.pos = 0;
+    f.more = true;
+    return f;
+}
+
+// Gives idle lanes (leaf < 0) a leaf and its first record while leaves are left.
+// q: this wavefront's LDS queue of kWave entries. Call with every lane active.
+__device__ __forceinline__ void feed_leaves(LeafFeeder& f, const RecordArgs& rec, int64_t n_leaves, int2* q,
+                                            int& leaf, int& first) {
+    const int lane = threadIdx.x & 63;
+    for (;;) {
+        const uint64_t idle = __ballot(leaf < 0);
+        if (!idle || !f.more) break;
+        if (f.pos >= f.cnt) {
+            const int64_t b0 = f.batch * kWave;
+            f.batch += f.n_waves;
+            if (b0 >= n_leaves) {
+                f.more = false;
+                break;
+            }
+            const int64_t L = b0 + lane;
+            const int h = L < n_leaves ? rec.head[L] : -1;
+            const uint64_t m = __ballot(h >= 0);
+            __builtin_amdgcn_wave_barrier();
+            if (h >= 0) q[lane_rank(m)] = make_int2((int)L, h);
+            __builtin_amdgcn_wave_barrier();
+            f.cnt = __popcll(m);
+            f.pos = 0;
+            continue;
+        }
+        const int avail = f.cnt - f.pos, n_idle = __popcll(idle);
+        if (leaf < 0) {
+            const int r = lane_rank(idle);
+            if (r < avail) {
+                const int2 e = q[f.pos + r];
+                leaf = e.x;
+                first = e.y;
+            }
+        }
+        f.pos += n_idle < avail ? n_idle : avail;
+    }
+}
+
 // Takes the record scratch of one adjoint launch (cap > 0) from the pool and
 // queues its initialisation: kQueues counters 128 bytes apart and a leaf
 // cursor, the leaf heads (-1) and room for cap records of 32 bytes. With

@@ -506,9 +506,6 @@ __global__ __launch_bounds__(kBlock) void reduce_pp_records_kernel(TreeArgs tr, 
     if (threadIdx.x < 2 * kWave) s_acc[threadIdx.x] = 0.0f;
     __syncthreads();
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int N = (int)tr.n_leaves;
-    const int64_t n_waves = (int64_t)gridDim.x * (kBlock / kWave);
-    int64_t batch = (int64_t)blockIdx.x * (kBlock / kWave) + wv;
 
     int leaf = -1;
     int4 ra0 = make_int4(0, 0, 0, 0), ra1 = make_int4(-1, 0, 0, 0);
@@ -519,46 +516,26 @@ __global__ __launch_bounds__(kBlock) void reduce_pp_records_kernel(TreeArgs tr, 
 #pragma unroll
     for (int c = 0; c < R; ++c) acc[c] = 0.0f;
     float bacc[2] = {0.0f, 0.0f};   // lane c: components c of the two basis gradients
-    int cur = 0, end = 0;
-    bool more = true;
+    LeafFeeder feeder = leaf_feeder(wv);
+    __shared__ int2 s_q[kBlock / kWave][kWave];
 
     for (;;) {
-        for (;;) {
-            const uint64_t idle = __ballot(leaf < 0);
-            if (!idle || !more) break;
-            if (cur >= end) {
-                const int64_t b0 = batch * kWave;
-                batch += n_waves;
-                if (b0 >= N) {
-                    more = false;
-                    break;
-                }
-                cur = (int)b0;
-                end = b0 + kWave < N ? (int)(b0 + kWave) : N;
-            }
-            const int avail = end - cur, n_idle = __popcll(idle);
-            if (leaf < 0) {
-                const int r = lane_rank(idle);
-                if (r < avail) {
-                    const int L = cur + r;
-                    const int h0 = rec.head[L];
-                    if (h0 >= 0) {
-                        leaf = L;
-                        ra0 = rec.rec[2 * (int64_t)h0];
-                        ra1 = rec.rec[2 * (int64_t)h0 + 1];
-                        float gv[CG];
-                        load_leaf<DT, CG>(tr.wgam, tr.n_leaves, L, tr.layout, gv);
-                        float y = 0.0f;
+        // hand leaves with records to idle lanes; a lane that got one loads its
+        // first record and computes the leaf's radial factors
+        int first = -1;
+        feed_leaves(feeder, rec, tr.n_leaves, s_q[wv], leaf, first);
+        if (first >= 0) {
+            ra0 = rec.rec[2 * (int64_t)first];
+            ra1 = rec.rec[2 * (int64_t)first + 1];
+            float gv[CG];
+            load_leaf<DT, CG>(tr.wgam, tr.n_leaves, leaf, tr.layout, gv);
+            float y = 0.0f;
 #pragma unroll
-                        for (int c = 0; c < CG; ++c) y = fmaf(gv[c], s_bgrow[c], y);
-                        const float gam = kPi * sigmoid_f(y);
-                        float sn, cs, dg[6];
-                        sincosf(gam, &sn, &cs);
-                        radial_n2(sn, cs, g, dg);
-                    }
-                }
-            }
-            cur += n_idle < avail ? n_idle : avail;
+            for (int c = 0; c < CG; ++c) y = fmaf(gv[c], s_bgrow[c], y);
+            const float gam = kPi * sigmoid_f(y);
+            float sn, cs, dg[6];
+            sincosf(gam, &sn, &cs);
+            radial_n2(sn, cs, g, dg);
         }
         if (!__ballot(leaf >= 0)) break;
         bool done = false;
