@@ -92,11 +92,18 @@ def main():
     ap.add_argument("--no-trace", action="store_true",
                     help="time neuvv_render + neuvv_render_backward (the adjoint walks again) instead of the traced "
                          "pair (the adjoint replays the forward's per-sample trace; K = 16, C = 8 form)")
+    ap.add_argument("--workload", choices=["ring", "train", "mixed", "multi"], default="ring",
+                    help="ring: the forward-render ring (the default line). train: the differentiable training "
+                         "step (depth 8, 65,536 random rays, per-ray t, L2 loss). mixed: depth-10 stereo 2048x2048 "
+                         "per eye, forward at FP32 / FP16 / BF16 storage. multi: four depth-9 FP16 trees placed "
+                         "and re-timed, rendered as layers, composed (Alg. 1) and differentiated")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration for profiles)")
     args = ap.parse_args()
+    if args.workload != "ring":
+        return workload_bench(args)
     if args.calibrate_copy:
         calibrate_copy()
         return
@@ -267,6 +274,142 @@ def main():
     if not args.no_cpu_baseline:
         result.update(cpu_leg(sc, cams, t_frame, t_stop, rgb, g_rgb, grads, tree, args.cpu_seconds))
     print(json.dumps(result), flush=True)
+
+
+def _timed(fn, steps, stream):
+    """Average ms of fn() over steps calls, HIP events on the launch stream (after one warm call)."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def workload_bench(args):
+    """The other workloads (parity-tested in tests/test_gpu_workloads.py), timed with the library's calls:
+    one JSON line each, value = rays per second of the timed unit."""
+    import torch
+    from paper_2202_06088_amd import _lib, ops
+    from workloads import config5_instances, make_scene, orbit_camera, ring_cameras, scene_for_config, stereo_cameras
+    from paper_2202_06088_amd.voctree import VOctree
+    if args.gpus != 1:
+        log("one GPU only")
+        sys.exit(2)
+    dev = "cuda"
+    stream = torch.cuda.current_stream()
+    t_stop = 1e-4
+
+    def upload(sc, dt):
+        return VOctree.build(sc.depth, sc.leaf_ijk, sc.hh, sc.wsig, sc.basis, sc.gamma, dt, dev)
+
+    out = {"metric": METRIC, "unit": "Mrays/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "data": "synthetic"}
+    if args.workload == "train":
+        sc = scene_for_config(3)
+        rng = np.random.default_rng(1003)
+        tgt = type(sc)(sc.depth, sc.leaf_ijk, rng.normal(0, 0.3, sc.hh.shape).astype(np.float32), sc.wsig,
+                       sc.basis, sc.gamma)
+        cams = ring_cameras(sc, 8, 960, 540, 40.0, 10.0, seed=31) + ring_cameras(sc, 8, 960, 540, 40.0, -15.0,
+                                                                                   seed=32)
+        n = 65536
+        ci = rng.integers(0, 16, n)
+        pix = rng.integers(0, 960 * 540, n).astype(np.int32)
+        o = torch.empty(n, 3, device=dev)
+        d = torch.empty(n, 3, device=dev)
+        for c in range(16):
+            m = np.nonzero(ci == c)[0]
+            cs = _lib.make_camera(960, 540, cams[c].fx, cams[c].fy, cams[c].cx, cams[c].cy, cams[c].c2w)
+            oo, dd = ops.pinhole_rays(cs, torch.from_numpy(pix[m]).to(dev))
+            idx = torch.from_numpy(m).to(dev)
+            o[idx], d[idx] = oo, dd
+        t = torch.from_numpy(rng.uniform(0, 300, n).astype(np.float32)).to(dev)
+        tree, ttree = upload(sc, _lib.F32), upload(tgt, _lib.F32)
+        target = ops.render(ttree, o, d, t, None, t_stop)[0]
+        trace = ops.Trace(n, 2 * n, dev)
+        grads = tree.zero_grads()
+
+        def step():
+            rgb, alpha, depth, nsamp = ops.render(tree, o, d, t, None, t_stop, trace=trace)
+            g = 2.0 * (rgb - target)                     # d/dC of sum ||C - C*||^2 (Eq. 10)
+            ops.render_backward(tree, o, d, rgb, alpha, nsamp, g, None, t, None, t_stop, grads=grads, trace=trace)
+
+        for _ in range(args.warmup):
+            step()
+        ms = _timed(step, args.steps, stream)
+        out.update(value=round(n / (ms * 1e-3) / 1e6, 2), ms_per_step=round(ms, 4), dtype="f32",
+                   config={"workload": "train_d8_500k_65536rays", "leaves": sc.n_leaves, "rays_per_step": n,
+                           "step": "traced render + L2 loss gradient + adjoint, per-ray t"})
+        log(f"train: {ms:.3f} ms per step ({n} rays, {sc.n_leaves} leaves)")
+    elif args.workload == "mixed":
+        sc = scene_for_config(4)
+        W = H = 2048
+        eyes = stereo_cameras(sc, W, H, 90.0, seed=4)
+        t = float(np.random.default_rng(4004).uniform(0, sc.T))
+        rays = []
+        for cam in eyes:
+            cs = _lib.make_camera(W, H, cam.fx, cam.fy, cam.cx, cam.cy, cam.c2w)
+            rays.append(ops.pinhole_rays(cs))
+        n = 2 * W * H
+        per = {}
+        for name, dt in (("f32", _lib.F32), ("f16", _lib.F16), ("bf16", _lib.BF16)):
+            tree = upload(sc, dt)
+            bufs = [(torch.empty(W * H, 3, device=dev), torch.empty(W * H, device=dev), torch.empty(W * H, device=dev),
+                     torch.empty(W * H, dtype=torch.int32, device=dev)) for _ in eyes]
+
+            def frame():
+                for (o, d), b in zip(rays, bufs):
+                    ops.render(tree, o, d, t, None, t_stop, W, out=b)
+
+            for _ in range(args.warmup):
+                frame()
+            ms = _timed(frame, args.steps, stream)
+            per[name] = {"ms_per_stereo_frame": round(ms, 4), "mrays_s": round(n / (ms * 1e-3) / 1e6, 2)}
+            log(f"mixed {name}: {ms:.3f} ms per stereo frame")
+            del tree
+        out.update(value=per["f16"]["mrays_s"], ms_per_step=per["f16"]["ms_per_stereo_frame"], dtype="f16",
+                   config={"workload": "mixed_d10_8M_stereo2048", "leaves": sc.n_leaves, "rays_per_step": n,
+                           "step": "forward of one stereo frame", "per_dtype": per})
+    else:
+        W, H = 1920, 1080
+        scenes = [make_scene(9, 2_000_000, "human", K=16, C=8, T=300, seed=50 + i) for i in range(4)]
+        G = scenes[0].G
+        insts = [_lib.make_instance(p["rot"], p["trans"], p["scale"], p["time_offset"], p["wrap"])
+                 for p in config5_instances(G, 4, seed=55)]
+        cam = orbit_camera((0.0, 0.0, 0.45 * G), 3.2 * G, 0.4, 0.25, W, H, 50.0)
+        o, d = ops.pinhole_rays(_lib.make_camera(W, H, cam.fx, cam.fy, cam.cx, cam.cy, cam.c2w))
+        t = 37.5
+        trees = [upload(s, _lib.F16) for s in scenes]
+        grads = [tr.zero_grads() for tr in trees]
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(5005)
+        g_out = torch.randn(W * H, 3, device=dev, generator=gen)
+
+        def step():
+            layers = [ops.render(tr, o, d, t, ins, t_stop, W) for tr, ins in zip(trees, insts)]
+            rgb_l = torch.stack([l[0] for l in layers])
+            a_l = torch.stack([l[1] for l in layers])
+            d_l = torch.stack([l[2] for l in layers])
+            ops.compose(rgb_l, a_l, d_l)
+            g_rgb_l, g_a_l = ops.compose_backward(rgb_l, a_l, d_l, g_out, None)
+            for i, (tr, ins) in enumerate(zip(trees, insts)):
+                l = layers[i]
+                ops.render_backward(tr, o, d, l[0], l[1], l[3], g_rgb_l[i].contiguous(), g_a_l[i].contiguous(), t,
+                                    ins, t_stop, W, grads=grads[i])
+
+        for _ in range(args.warmup):
+            step()
+        ms = _timed(step, args.steps, stream)
+        n = W * H
+        out.update(value=round(n / (ms * 1e-3) / 1e6, 2), ms_per_step=round(ms, 4), dtype="f16",
+                   config={"workload": "multi_4xd9_1080p_fp16", "leaves": [s.n_leaves for s in scenes],
+                           "rays_per_step": n, "step": "4 layer renders + compose + compose adjoint + 4 adjoints"})
+        log(f"multi: {ms:.3f} ms per step (4 layers of {n} rays)")
+    print(json.dumps(out), flush=True)
 
 
 def multi_leg(sc, tree, L, ray_o, ray_d, t_frame, t_stop, W, fwd_ms, stream, steps):
