@@ -15,7 +15,8 @@ namespace neuvv {
 struct TraceArgs {
     int32_t* head;                 // [n_rays] first sample of the ray's trace; -1: none (the adjoint walks)
     int4* smp;                     // [cap][2]: {leaf, delta, x, c_r} {c_g, c_b, next (-1: last), 0} (float bits)
-    unsigned long long* counter;   // kQueues counters 128 bytes apart
+    unsigned long long* counter;   // kQueues counters 128 bytes apart: the first 1024 bytes of a 2048-byte
+                                   // header whose second half takes the stores of samples without a slot
     int64_t cap;
 };
 // Bytes of a trace buffer for n rays and room for cap samples, and its layout.

@@ -63,6 +63,15 @@ __device__ __forceinline__ void ray_basis(const TreeArgs& tr, const RaySetup& rs
 // same call replays the samples instead of walking and evaluating again. The
 // samples of one iteration take consecutive entries in lane order, from
 // blocks per wavefront; a ray whose samples do not all fit gets head -1.
+// A sample's entry is stored one sample later, when the slot it links to is
+// known, right after that sample's payload loads: vector-memory counters
+// retire in issue order, so stores issued before a load would make every wait
+// on that load (the walk's node reads, the payload) wait for them too. The
+// ray's last entry is stored when it finishes. The store is unconditional for
+// every lane with a sample: a ray's first sample stores a placeholder into
+// its own slot (which the same lane overwrites later), and a ray whose trace
+// is incomplete stores into its last slot, or, if it has none, into the spare
+// half of the trace header.
 template <int K, int C, int DT, bool IDENT, bool EDIT, bool TRACE>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) void render_fwd_kernel(
     TreeArgs tr, InstArgs in, RayArgs ra, float t_stop, RenderOut out) {
@@ -85,7 +94,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
     float* const bl = s_b + threadIdx.x * C;
     float Tr = 1.0f, acc0 = 0.0f, acc1 = 0.0f, acc2 = 0.0f, wsum = 0.0f, dsum = 0.0f;
     int ns = 0, last = -1;
-    int t_first = -1, t_prev = -1;   // trace: the ray's first and latest entries; t_first -2: broken
+    int t_first = -1;                // trace: the ray's first entry; -2: broken
+    // trace: the previous sample, written once the slot of the next is known
+    int pslot = -1, pleaf = 0;
+    float pdelta = 0.0f, px = 0.0f, pc0 = 0.0f, pc1 = 0.0f, pc2 = 0.0f;
     int64_t tcur = 0, tend = 0;      // trace: what is left of the wavefront's block (wave-uniform)
 
     for (;;) {
@@ -136,7 +148,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
                     }
                     walk_begin(tr, rs, w);
                     alive = true;
-                    t_first = t_prev = -1;
+                    t_first = -1;
+                    pslot = -1;
                 } else {
                     write_miss(out, ray);
                 }
@@ -146,15 +159,39 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
         if (n_idle == kWave) break;
         bool finish = false, stopped = false;
         int leaf = -1;
-        float delta = 0.0f, tx = 0.0f, tc0 = 0.0f, tc1 = 0.0f, tc2 = 0.0f;
+        float delta = 0.0f, umid = 0.0f;
         if (alive) {
-            float umid;
             leaf = walk_next<kWalkBudget>(tr, s_nodes, n_lds, path, kBlock, rs, w, delta, umid);
             finish = leaf == -1;
+        }
+        int cur = -1;
+        if constexpr (TRACE) {
+            const uint64_t hm = __ballot(leaf >= 0);
+            const int n_s = __popcll(hm);
+            const int64_t at = n_s > 0 ? take_items(out.trace.counter, out.trace.cap, cc.home, n_s, tcur, tend) : -1;
             if (leaf >= 0) {
+                if (at >= 0 && t_first != -2) {
+                    cur = (int)(at + lane_rank(hm));
+                    if (t_first == -1) t_first = cur;
+                } else {
+                    t_first = -2;   // incomplete: the adjoint walks this ray
+                }
+            }
+        }
+        if (leaf >= 0) {
+            {
                 float wv[3 * K], sv[C];
                 load_leaf<DT, 3 * K>(tr.hh, tr.n_leaves, leaf, tr.layout, wv);
                 load_leaf<DT, C>(tr.wsig, tr.n_leaves, leaf, tr.layout, sv);
+                if constexpr (TRACE) {
+                    // the previous sample's entry, linked to this one
+                    const int tgt = pslot >= 0 ? pslot : cur;
+                    int4* dst = tgt >= 0 ? out.trace.smp + 2 * (int64_t)tgt
+                                         : reinterpret_cast<int4*>(reinterpret_cast<char*>(out.trace.counter) + 1024) +
+                                               2 * (threadIdx.x & 31);
+                    dst[0] = make_int4(pleaf, __float_as_int(pdelta), __float_as_int(px), __float_as_int(pc0));
+                    dst[1] = make_int4(__float_as_int(pc1), __float_as_int(pc2), cur, 0);
+                }
                 float x = 0.0f;
 #pragma unroll
                 for (int c = 0; c < C; ++c) x = fmaf(sv[c], bl[c], x);
@@ -189,24 +226,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
                 last = leaf;
                 finish = t_stop > 0.0f && Tr < t_stop;
                 stopped = finish;
-                tx = x; tc0 = c0; tc1 = c1; tc2 = c2;
-            }
-        }
-        if constexpr (TRACE) {
-            const uint64_t hm = __ballot(leaf >= 0);
-            const int n_s = __popcll(hm);
-            const int64_t at = n_s > 0 ? take_items(out.trace.counter, out.trace.cap, cc.home, n_s, tcur, tend) : -1;
-            if (leaf >= 0) {
-                if (at >= 0 && t_first != -2) {
-                    const int slot = (int)(at + lane_rank(hm));
-                    out.trace.smp[2 * (int64_t)slot] =
-                        make_int4(leaf, __float_as_int(delta), __float_as_int(tx), __float_as_int(tc0));
-                    out.trace.smp[2 * (int64_t)slot + 1] = make_int4(__float_as_int(tc1), __float_as_int(tc2), -1, 0);
-                    if (t_prev >= 0) reinterpret_cast<int*>(out.trace.smp + 2 * (int64_t)t_prev + 1)[2] = slot;
-                    else t_first = slot;
-                    t_prev = slot;
-                } else {
-                    t_first = -2;   // incomplete: the adjoint walks this ray
+                if constexpr (TRACE) {
+                    if (cur >= 0) pslot = cur;
+                    pleaf = leaf; pdelta = delta; px = x; pc0 = c0; pc1 = c1; pc2 = c2;
                 }
             }
         }
@@ -216,7 +238,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
             if (out.depth) out.depth[ray] = wsum > 0.0f ? dsum / wsum : INFINITY;
             if (out.nsamp) out.nsamp[ray] = ns;
             if (out.last_leaf) out.last_leaf[ray] = stopped ? last : -1;
-            if constexpr (TRACE) out.trace.head[ray] = t_first >= 0 ? t_first : -1;
+            if constexpr (TRACE) {
+                if (t_first >= 0) {
+                    out.trace.smp[2 * (int64_t)pslot] =
+                        make_int4(pleaf, __float_as_int(pdelta), __float_as_int(px), __float_as_int(pc0));
+                    out.trace.smp[2 * (int64_t)pslot + 1] = make_int4(__float_as_int(pc1), __float_as_int(pc2), -1, 0);
+                }
+                out.trace.head[ray] = t_first >= 0 ? t_first : -1;
+            }
             alive = false;
         }
     }
