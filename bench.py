@@ -36,7 +36,7 @@ PEAK_HBM_GBS = 8000.0
 FWD_RAY_IO_B = 24 + 24                      # o, d in; rgb, alpha, depth, nsamp out
 BWD_RAY_NSAMP_B = 4                         # every ray: nsamp (rays without samples carry no gradient)
 BWD_HIT_IO_B = 24 + 16 + 12                 # rays with samples: o, d; rgb, alpha; grad_rgb
-TRACE_SAMPLE_B = 32                         # traced step: one trace entry per sample
+TRACE_SAMPLE_B = {0: 32, 31: 48}            # traced step: trace bytes per sample (global form, per-point form)
 
 
 def log(msg):
@@ -91,7 +91,7 @@ def main():
                     help="also time the exact merge of this many (2..4) interpenetrating placements of the tree")
     ap.add_argument("--no-trace", action="store_true",
                     help="time neuvv_render + neuvv_render_backward (the adjoint walks again) instead of the traced "
-                         "pair (the adjoint replays the forward's per-sample trace; K = 16, C = 8 form)")
+                         "pair (the adjoint replays the forward's per-sample trace)")
     ap.add_argument("--workload", choices=["ring", "train", "mixed", "multi"], default="ring",
                     help="ring: the forward-render ring (the default line). train: the differentiable training "
                          "step (depth 8, 65,536 random rays, per-ray t, L2 loss). mixed: depth-10 stereo 2048x2048 "
@@ -152,10 +152,10 @@ def main():
     stream = torch.cuda.current_stream()
     t_stop = 1e-4
 
-    traced = not args.no_trace and tree.Cg == 0
-    # trace room: one sample per ray covers the ring (0.69 per ray); a ray whose samples do not fit
-    # would be walked again by the adjoint
-    trace_cap = n
+    traced = not args.no_trace
+    # trace room: one sample per ray covers the ring (0.69 per ray; a per-point sample takes two
+    # 32-byte entries); a ray whose samples do not fit would be walked again by the adjoint
+    trace_cap = n * (2 if tree.Cg > 0 else 1)
     trace = torch.empty(_lib.neuvv_trace_bytes(n, trace_cap), dtype=torch.uint8, device=dev) if traced else None
 
     def fwd():
@@ -169,7 +169,8 @@ def main():
     def bwd():
         if traced:
             _lib.neuvv_render_backward_trace(tree.struct(), None, n, ray_o, ray_d, None, t_frame, W, t_stop, rgb,
-                                             alpha, nsamp, g_rgb, None, grads[0], grads[1], trace, trace_cap, stream)
+                                             alpha, nsamp, g_rgb, None, grads[0], grads[1],
+                                             grads[2] if tree.Cg > 0 else None, trace, trace_cap, stream)
         else:
             _lib.neuvv_render_backward(tree.struct(), None, n, ray_o, ray_d, None, t_frame, W, t_stop, rgb, alpha,
                                        nsamp, g_rgb, None, grads[0], grads[1], grads[2] if tree.Cg > 0 else None,
@@ -205,15 +206,19 @@ def main():
     bwd()
     torch.cuda.synchronize()
     touched = int((grads[0][:, :values] != 0).any(dim=1).sum().item())
+    elem = 4 if dt == _lib.F32 else 2
+    # the adjoint: the leaf payload per sample (walking) or the trace entry (replaying); per touched
+    # leaf its gradient row, read and written once, and its density and hyperangle weights (the
+    # basis gradients are summed per leaf); per ray nsamp, per hit ray its inputs
+    per_leaf = touched * (2 * 4 * values + (tree.C + tree.Cg) * elem)
     fwd_bytes = total_samples * payload_b + n * FWD_RAY_IO_B
-    bwd_bytes = (total_samples * payload_b + touched * 2 * 4 * values + n * BWD_RAY_NSAMP_B +
-                 hit * BWD_HIT_IO_B)
+    bwd_bytes = total_samples * payload_b + per_leaf + n * BWD_RAY_NSAMP_B + hit * BWD_HIT_IO_B
     if traced:
-        # the trace is state kept between the passes: written per sample by the forward, read by the
-        # adjoint, which then reads only the C density weights of the leaf (basis gradient) per sample
-        elem = 4 if dt == _lib.F32 else 2
-        fwd_bytes += total_samples * TRACE_SAMPLE_B
-        bwd_bytes += total_samples * (TRACE_SAMPLE_B + tree.C * elem - payload_b)
+        # the trace is state kept between the passes: written per sample by the forward, read in
+        # place of the payload by the adjoint
+        tb = TRACE_SAMPLE_B[tree.Cg]
+        fwd_bytes += total_samples * tb
+        bwd_bytes += total_samples * (tb - payload_b)
     log(f"fwd {fwd_ms:.3f} ms, bwd {bwd_ms:.3f} ms per launch; step {ms_step:.3f} ms; "
         f"{total_samples} samples, {hit} hit rays")
     kern = {"render_fwd": (fwd_ms, fwd_bytes), "render_bwd": (bwd_ms, bwd_bytes)}

@@ -298,26 +298,29 @@ int neuvv_render_backward(const neuvv_tree* tree, const neuvv_instance* inst, in
                           float* grad_leaf, float* grad_basis, float* grad_basis_g, void* stream);
 
 /*
- * Traced training step (K = 16, C = 8 form). neuvv_render_trace renders as
+ * Traced training step (both compiled forms). neuvv_render_trace renders as
  * neuvv_render and also records every composited sample of the call in a
- * caller-owned trace buffer: the leaf, the segment length delta, the density
- * logit x and the colours c (Eq. 4, 5, 8), linked in ray order.
- * neuvv_render_backward_trace is neuvv_render_backward (grad_basis_g absent)
- * for the same tree, rays, times, instance and t_stop, replaying each ray's
- * samples from the trace instead of walking the tree and evaluating the leaves
- * again; the gradients are the same up to rounding. The trace holds room for
- * trace_cap samples; a ray whose samples do not all fit is marked untraced
- * and its adjoint walks as in neuvv_render_backward, so any trace_cap >= 0 is
- * correct (a cap near the call's total of nsamp avoids walking).
+ * caller-owned trace buffer, linked in ray order: the leaf, the segment
+ * length delta, the density logit x and the colours c (Eq. 4, 5, 8), and for
+ * the per-point form (Cg > 0) the hyperangle logit y and dz/dgamma of the
+ * three colour logits (Eq. 6). neuvv_render_backward_trace is
+ * neuvv_render_backward for the same tree, rays, times, instance and t_stop,
+ * replaying each ray's samples from the trace instead of walking the tree and
+ * evaluating the leaves again; the gradients are the same up to rounding. A
+ * ray whose samples do not all fit is marked untraced and its adjoint walks
+ * as in neuvv_render_backward, so any trace_cap >= 0 is correct (room near
+ * the call's total of nsamp avoids walking).
  * trace           device buffer of neuvv_trace_bytes(n_rays, trace_cap) bytes,
  *                 256-byte aligned, owned by the caller; written by
  *                 neuvv_render_trace, read by neuvv_render_backward_trace, and
  *                 valid until the next neuvv_render_trace into it. Its content
  *                 is private to the library.
- * trace_cap       room in samples, in [0, 2^31); the same value in both calls.
+ * trace_cap       room in 32-byte entries, in [0, 2^31); the same value in both
+ *                 calls. A sample takes one entry in the K = 16, C = 8 form and
+ *                 two in the per-point form.
  * n_rays          below 2^31 for the traced calls.
- * Errors: those of neuvv_render / neuvv_render_backward, and UNSUPPORTED for
- * trees with Cg > 0.
+ * grad_basis_g    as in neuvv_render_backward (per-point form only).
+ * Errors: those of neuvv_render / neuvv_render_backward.
  */
 int64_t neuvv_trace_bytes(int64_t n_rays, int64_t trace_cap);   /* -1 for negative arguments */
 int neuvv_render_trace(const neuvv_tree* tree, const neuvv_instance* inst, int64_t n_rays, const float* ray_o,
@@ -328,8 +331,8 @@ int neuvv_render_backward_trace(const neuvv_tree* tree, const neuvv_instance* in
                                 const float* ray_o, const float* ray_d, const float* ray_t, float t_scalar,
                                 int32_t image_width, float t_stop, const float* rgb, const float* alpha,
                                 const int32_t* nsamp, const float* grad_rgb, const float* grad_alpha,
-                                float* grad_leaf, float* grad_basis, const void* trace, int64_t trace_cap,
-                                void* stream);
+                                float* grad_leaf, float* grad_basis, float* grad_basis_g, const void* trace,
+                                int64_t trace_cap, void* stream);
 
 /*
  * neuvv_compose - depth-aware alpha blending of L rendered layers (Alg. 1),

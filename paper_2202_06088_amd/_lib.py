@@ -65,7 +65,7 @@ _SIGNATURES = {
     "neuvv_render_trace": [ctypes.POINTER(neuvv_tree), ctypes.POINTER(neuvv_instance), _I64, _P, _P, _P, _F, _I32,
                            _F, _P, _P, _P, _P, _P, _I64, _P],
     "neuvv_render_backward_trace": [ctypes.POINTER(neuvv_tree), ctypes.POINTER(neuvv_instance), _I64, _P, _P, _P,
-                                    _F, _I32, _F, _P, _P, _P, _P, _P, _P, _P, _P, _I64, _P],
+                                    _F, _I32, _F, _P, _P, _P, _P, _P, _P, _P, _P, _P, _I64, _P],
     "neuvv_grad_row_elems": [_I32, _I32, _I32],
     "neuvv_pack_rows": [_I32, _I32, _I32, _I64, _P, _P, _P, _P],
     "neuvv_blur": [_I32, _I32, _P, _F, _P, _P],
@@ -217,12 +217,12 @@ def neuvv_render_trace(tree: neuvv_tree, inst, n_rays, ray_o, ray_d, ray_t, t_sc
 
 
 def neuvv_render_backward_trace(tree: neuvv_tree, inst, n_rays, ray_o, ray_d, ray_t, t_scalar, image_width, t_stop,
-                                rgb, alpha, nsamp, grad_rgb, grad_alpha, grad_leaf, grad_basis, trace, trace_cap,
-                                stream=None):
+                                rgb, alpha, nsamp, grad_rgb, grad_alpha, grad_leaf, grad_basis, grad_basis_g, trace,
+                                trace_cap, stream=None):
     _check("neuvv_render_backward_trace", load().neuvv_render_backward_trace(
         ctypes.byref(tree), _inst_ptr(inst), int(n_rays), _ptr(ray_o), _ptr(ray_d), _ptr(ray_t), float(t_scalar),
         int(image_width), float(t_stop), _ptr(rgb), _ptr(alpha), _ptr(nsamp), _ptr(grad_rgb), _ptr(grad_alpha),
-        _ptr(grad_leaf), _ptr(grad_basis), _ptr(trace), int(trace_cap), _stream(stream)))
+        _ptr(grad_leaf), _ptr(grad_basis), _ptr(grad_basis_g), _ptr(trace), int(trace_cap), _stream(stream)))
 
 
 def neuvv_grad_row_elems(K: int, C: int, Cg: int = 0) -> int:

@@ -1,6 +1,6 @@
 """torch.autograd wrappers: the forward saves rgb, alpha and nsamp per ray
-(and, for the K = 16, C = 8 form, a trace of its samples with room for two
-per ray); the backward kernel replays the compositing with the transmittance
+and a trace of its samples with room for two per ray; the backward kernel
+replays the compositing with the transmittance
 recomputed (Sec. 4.3 "Optimization"), from the trace where it holds the ray."""
 from __future__ import annotations
 
@@ -28,7 +28,8 @@ class RenderFn(torch.autograd.Function):
         if any(a is None or a.data_ptr() != b.data_ptr() for a, b in own):
             raise ValueError("the payload and basis tensors must be the tree's own")
         n = ray_o.shape[0]
-        trace = ops.Trace(n, 2 * n, ray_o.device) if tree.Cg == 0 and 0 < n < 2 ** 30 else None
+        # room for two samples per ray (a per-point sample takes two entries)
+        trace = ops.Trace(n, (4 if tree.Cg > 0 else 2) * n, ray_o.device) if 0 < n < 2 ** 29 else None
         rgb, alpha, depth, nsamp = ops.render(tree, ray_o, ray_d, t, inst, t_stop, image_width, trace=trace)
         ctx.tree, ctx.inst, ctx.t_stop, ctx.image_width, ctx.trace = tree, inst, t_stop, image_width, trace
         ctx.t_scalar = None if isinstance(t, torch.Tensor) else float(t)

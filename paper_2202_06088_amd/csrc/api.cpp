@@ -249,8 +249,7 @@ int neuvv_pack_leaves(int32_t K, int32_t C, int32_t dtype, int32_t layout, int64
 }
 
 // Checks a trace buffer argument (traced calls only).
-static int check_trace(const neuvv_tree* tree, int64_t n_rays, const void* trace, int64_t trace_cap) {
-    if (tree->Cg > 0) return fail(NEUVV_ERR_UNSUPPORTED, "traces are for the K = 16, C = 8 form");
+static int check_trace(int64_t n_rays, const void* trace, int64_t trace_cap) {
     if (!trace) return fail(NEUVV_ERR_ARG, "trace is NULL");
     if (reinterpret_cast<uintptr_t>(trace) % 256) return fail(NEUVV_ERR_ARG, "trace must be 256-byte aligned");
     if (trace_cap < 0 || trace_cap > (int64_t)INT32_MAX) return fail(NEUVV_ERR_RANGE, "trace_cap outside [0, 2^31)");
@@ -338,7 +337,7 @@ int neuvv_render_trace(const neuvv_tree* tree, const neuvv_instance* inst, int64
     NEUVV_GUARD_BEGIN
     int rc = check_tree(tree);
     if (rc) return rc;
-    if ((rc = check_trace(tree, n_rays, trace, trace_cap))) return rc;
+    if ((rc = check_trace(n_rays, trace, trace_cap))) return rc;
     return render_impl(tree, inst, n_rays, ray_o, ray_d, ray_t, t_scalar, image_width, t_stop, rgb, alpha, depth,
                        nsamp, trace, trace_cap, stream);
     NEUVV_GUARD_END
@@ -348,14 +347,14 @@ int neuvv_render_backward_trace(const neuvv_tree* tree, const neuvv_instance* in
                                 const float* ray_o, const float* ray_d, const float* ray_t, float t_scalar,
                                 int32_t image_width, float t_stop, const float* rgb, const float* alpha,
                                 const int32_t* nsamp, const float* grad_rgb, const float* grad_alpha,
-                                float* grad_leaf, float* grad_basis, const void* trace, int64_t trace_cap,
-                                void* stream) {
+                                float* grad_leaf, float* grad_basis, float* grad_basis_g, const void* trace,
+                                int64_t trace_cap, void* stream) {
     NEUVV_GUARD_BEGIN
     int rc = check_tree(tree);
     if (rc) return rc;
-    if ((rc = check_trace(tree, n_rays, trace, trace_cap))) return rc;
+    if ((rc = check_trace(n_rays, trace, trace_cap))) return rc;
     return backward_impl(tree, inst, n_rays, ray_o, ray_d, ray_t, t_scalar, image_width, t_stop, rgb, alpha, nsamp,
-                         grad_rgb, grad_alpha, grad_leaf, grad_basis, nullptr, trace, trace_cap, stream);
+                         grad_rgb, grad_alpha, grad_leaf, grad_basis, grad_basis_g, trace, trace_cap, stream);
     NEUVV_GUARD_END
 }
 

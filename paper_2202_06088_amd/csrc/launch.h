@@ -14,7 +14,9 @@ namespace neuvv {
 // call instead of walking the tree and evaluating the leaves again.
 struct TraceArgs {
     int32_t* head;                 // [n_rays] first sample of the ray's trace; -1: none (the adjoint walks)
-    int4* smp;                     // [cap][2]: {leaf, delta, x, c_r} {c_g, c_b, next (-1: last), 0} (float bits)
+    int4* smp;                     // [cap][2] (32-byte entries). K = 16, C = 8 form, one entry per sample:
+                                   // {leaf, delta, x, c_r} {c_g, c_b, next (-1: last), 0}; per-point form,
+                                   // two: {leaf, delta, x, y} {c_r, c_g, c_b, next} {dz/dgamma [3], 0} {-}
     unsigned long long* counter;   // kQueues counters 128 bytes apart: the first 1024 bytes of a 2048-byte
                                    // header whose second half takes the stores of samples without a slot
     int64_t cap;

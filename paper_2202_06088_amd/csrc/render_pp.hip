@@ -97,12 +97,19 @@ struct PPSample {
 };
 
 template <int DT>
-__device__ __forceinline__ void pp_eval(const TreeArgs& tr, const RaySetup& rs, const float (&Y)[8], const float* s_b,
-                                        const float* s_bg, int leaf, PPSample<DT>& p) {
+__device__ __forceinline__ void pp_load(const TreeArgs& tr, int leaf, PPSample<DT>& p) {
     using namespace pp;
     load_leaf<DT, 3 * K>(tr.hh, tr.n_leaves, leaf, tr.layout, p.wv);
     load_leaf<DT, C>(tr.wsig, tr.n_leaves, leaf, tr.layout, p.sv);
     load_leaf<DT, CG>(tr.wgam, tr.n_leaves, leaf, tr.layout, p.gv);
+}
+
+// The sample's logits x, y, hyperangle factors g, g' and basis h, and the
+// colour logits z (Eq. 2-6), from the payload pp_load fetched.
+template <int DT>
+__device__ __forceinline__ void pp_compute(const TreeArgs& tr, const RaySetup& rs, const float (&Y)[8],
+                                           const float* s_b, const float* s_bg, PPSample<DT>& p) {
+    using namespace pp;
     p.x = basis_dot<C>(p.sv, s_b, tr.basis, rs.i0, rs.i1, rs.f);
     p.y = basis_dot<CG>(p.gv, s_bg, tr.basis_g, rs.i0, rs.i1, rs.f);
     const float gam = kPi * sigmoid_f(p.y);
@@ -119,10 +126,38 @@ __device__ __forceinline__ void pp_eval(const TreeArgs& tr, const RaySetup& rs, 
     }
 }
 
+// dz_ch/dgamma = sum_k W_ch,k g'_nl(gamma) Y_k for the three colour channels.
+template <int DT>
+__device__ __forceinline__ void pp_dz_dgamma(const PPSample<DT>& p, const float (&Y)[8], float& q0, float& q1,
+                                             float& q2) {
+    using namespace pp;
+    float dh[K];
+    hh14(p.dg, Y, dh);
+    q0 = q1 = q2 = 0.0f;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        q0 = fmaf(p.wv[k], dh[k], q0);
+        q1 = fmaf(p.wv[K + k], dh[k], q1);
+        q2 = fmaf(p.wv[2 * K + k], dh[k], q2);
+    }
+}
+
+// A per-point trace entry is 64 bytes (two entries of the trace's room):
+// {leaf, delta, x, y} {c_r, c_g, c_b, next} {dz_r/dgamma, dz_g/dgamma,
+// dz_b/dgamma, -}, the fourth 16 bytes unused.
+constexpr int kPPTraceInt4 = 4;
+
 // ----------------------------------------------------------------------------
 // forward
 
-template <int DT, bool IDENT>
+// TRACE: every sample is also written to out.trace (leaf, segment length,
+// logits x and y, colours, dz/dgamma; linked in ray order) for the adjoint of
+// the same call, as in render.hip: entries of one iteration at consecutive
+// slots in lane order, a sample's entry stored one sample later (when the
+// slot it links to is known) right after that sample's payload loads, the
+// last one when the ray finishes; a ray whose samples do not all fit gets
+// head -1. The room in samples is half the trace's room in 32-byte entries.
+template <int DT, bool IDENT, bool TRACE>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) void render_pp_fwd_kernel(
     TreeArgs tr, InstArgs in, RayArgs ra, float t_stop, RenderOut out) {
     if (no_candidates(ra)) return;
@@ -146,6 +181,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) 
     float Y[8];
     float Tr = 1.0f, acc0 = 0.0f, acc1 = 0.0f, acc2 = 0.0f, wsum = 0.0f, dsum = 0.0f;
     int ns = 0;
+    int t_first = -1;                // trace: the ray's first entry; -2: incomplete
+    int64_t tcur = 0, tend = 0;      // trace: what is left of the wavefront's block (wave-uniform)
+    const int64_t t_room = out.trace.cap / 2;
+    // trace: the previous sample, stored once the slot of the next is known
+    int pslot = -1, pleaf = 0;
+    float pdelta = 0.0f, px = 0.0f, py = 0.0f, pc0 = 0.0f, pc1 = 0.0f, pc2 = 0.0f, pq0 = 0.0f, pq1 = 0.0f,
+          pq2 = 0.0f;
 
     for (;;) {
         const uint64_t idle = __ballot(!alive);
@@ -184,6 +226,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) 
                     sh_deg2(rs.dir[0], rs.dir[1], rs.dir[2], Y);
                     walk_begin(tr, rs, w);
                     alive = true;
+                    t_first = -1;
+                    pslot = -1;
                 } else {
                     write_miss(out, ray);
                 }
@@ -191,34 +235,79 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) 
             continue;
         }
         if (n_idle == kWave) break;
+        bool finish = false;
+        int leaf = -1;
+        float delta = 0.0f, umid = 0.0f;
         if (alive) {
-            float delta, umid;
-            const int leaf = walk_next<kWalkBudget>(tr, s_nodes, n_lds, path, kBlock, rs, w, delta, umid);
-            bool finish = leaf == -1;
+            leaf = walk_next<kWalkBudget>(tr, s_nodes, n_lds, path, kBlock, rs, w, delta, umid);
+            finish = leaf == -1;
+        }
+        int cur = -1;
+        if constexpr (TRACE) {
+            const uint64_t hm = __ballot(leaf >= 0);
+            const int n_s = __popcll(hm);
+            const int64_t at = n_s > 0 ? take_items(out.trace.counter, t_room, cc.home, n_s, tcur, tend) : -1;
             if (leaf >= 0) {
-                PPSample<DT> p;
-                pp_eval<DT>(tr, rs, Y, s_b, s_bg, leaf, p);
-                const float sig = softplus_f(p.x);
-                const float od = sig * delta;
-                float a, e_od;
-                absorb(od, a, e_od);
-                const float wt = Tr * a;
-                acc0 = fmaf(wt, sigmoid_f(p.z0), acc0);
-                acc1 = fmaf(wt, sigmoid_f(p.z1), acc1);
-                acc2 = fmaf(wt, sigmoid_f(p.z2), acc2);
-                wsum += wt;
-                dsum = fmaf(wt, umid * rs.len_world, dsum);
-                Tr *= e_od;
-                ++ns;
-                finish = t_stop > 0.0f && Tr < t_stop;
+                if (at >= 0 && t_first != -2) {
+                    cur = (int)(at + lane_rank(hm));
+                    if (t_first == -1) t_first = cur;
+                } else {
+                    t_first = -2;   // incomplete: the adjoint walks this ray
+                }
             }
-            if (finish) {
-                out.rgb[3 * ray] = acc0; out.rgb[3 * ray + 1] = acc1; out.rgb[3 * ray + 2] = acc2;
-                out.alpha[ray] = 1.0f - Tr;
-                if (out.depth) out.depth[ray] = wsum > 0.0f ? dsum / wsum : INFINITY;
-                out.nsamp[ray] = ns;
-                alive = false;
+        }
+        if (leaf >= 0) {
+            PPSample<DT> p;
+            pp_load<DT>(tr, leaf, p);
+            if constexpr (TRACE) {
+                // the previous sample's entry, linked to this one; a ray's first
+                // sample stores a placeholder into its own slot (overwritten by this
+                // lane later), an incomplete trace into its last slot or the spare
+                // half of the trace header
+                const int tgt = pslot >= 0 ? pslot : cur;
+                int4* dst = tgt >= 0 ? out.trace.smp + kPPTraceInt4 * (int64_t)tgt
+                                     : reinterpret_cast<int4*>(reinterpret_cast<char*>(out.trace.counter) + 1024) +
+                                           kPPTraceInt4 * (threadIdx.x & 15);
+                dst[0] = make_int4(pleaf, __float_as_int(pdelta), __float_as_int(px), __float_as_int(py));
+                dst[1] = make_int4(__float_as_int(pc0), __float_as_int(pc1), __float_as_int(pc2), cur);
+                dst[2] = make_int4(__float_as_int(pq0), __float_as_int(pq1), __float_as_int(pq2), 0);
             }
+            pp_compute<DT>(tr, rs, Y, s_b, s_bg, p);
+            const float sig = softplus_f(p.x);
+            const float od = sig * delta;
+            float a, e_od;
+            absorb(od, a, e_od);
+            const float wt = Tr * a;
+            const float c0 = sigmoid_f(p.z0), c1 = sigmoid_f(p.z1), c2 = sigmoid_f(p.z2);
+            acc0 = fmaf(wt, c0, acc0);
+            acc1 = fmaf(wt, c1, acc1);
+            acc2 = fmaf(wt, c2, acc2);
+            wsum += wt;
+            dsum = fmaf(wt, umid * rs.len_world, dsum);
+            Tr *= e_od;
+            ++ns;
+            finish = t_stop > 0.0f && Tr < t_stop;
+            if constexpr (TRACE) {
+                if (cur >= 0) pslot = cur;
+                pleaf = leaf; pdelta = delta; px = p.x; py = p.y; pc0 = c0; pc1 = c1; pc2 = c2;
+                pp_dz_dgamma<DT>(p, Y, pq0, pq1, pq2);
+            }
+        }
+        if (alive && finish) {
+            out.rgb[3 * ray] = acc0; out.rgb[3 * ray + 1] = acc1; out.rgb[3 * ray + 2] = acc2;
+            out.alpha[ray] = 1.0f - Tr;
+            if (out.depth) out.depth[ray] = wsum > 0.0f ? dsum / wsum : INFINITY;
+            out.nsamp[ray] = ns;
+            if constexpr (TRACE) {
+                if (t_first >= 0) {
+                    int4* dst = out.trace.smp + kPPTraceInt4 * (int64_t)pslot;
+                    dst[0] = make_int4(pleaf, __float_as_int(pdelta), __float_as_int(px), __float_as_int(py));
+                    dst[1] = make_int4(__float_as_int(pc0), __float_as_int(pc1), __float_as_int(pc2), -1);
+                    dst[2] = make_int4(__float_as_int(pq0), __float_as_int(pq1), __float_as_int(pq2), 0);
+                }
+                out.trace.head[ray] = t_first >= 0 ? t_first : -1;
+            }
+            alive = false;
         }
     }
 }
@@ -237,26 +326,33 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) 
 // Component of lane slot j (0, 1) of the gradient row.
 __device__ __forceinline__ int pp_component(int j, int lane) { return j * kWave + lane; }
 
-template <int DT, bool IDENT>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) void render_pp_bwd_kernel(
+// REPLAY: every ray of the launch has a trace in io.trace (the forward's
+// samples) and replays it without walking the tree or reading the leaf
+// payload: dL/dgamma = sum_ch gz_ch dz_ch/dgamma comes from the traced
+// derivatives, and h is recomputed from y only for samples without a record.
+template <int DT, bool IDENT, bool REPLAY>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(REPLAY ? 3 : 2, 8))) void render_pp_bwd_kernel(
     TreeArgs tr, InstArgs in, RayArgs ra, BackwardIO io, RecordArgs rec) {
     if (no_candidates(ra)) return;
     using namespace pp;
-    __shared__ int4 s_nodes[kLdsNodes];
-    __shared__ int s_path[kMaxLevels * kBlock];
+    // a replaying launch does not walk: no node rows or paths
+    constexpr int kNodes = REPLAY ? 1 : kLdsNodes;
+    __shared__ int4 s_nodes[kNodes];
+    __shared__ int s_path[REPLAY ? 1 : kMaxLevels * kBlock];
     __shared__ float s_h[kBlock * K];
     __shared__ float s_brow[C], s_bgrow[CG];
     __shared__ float s_acc[2 * kWave];   // block sum of the lanes' basis-gradient components
     const bool common_t = ra.t == nullptr;
     if (common_t) stage_common_rows(tr, in, ra.t_scalar, s_brow, s_bgrow);
     if (threadIdx.x < 2 * kWave) s_acc[threadIdx.x] = 0.0f;
-    const int n_lds = stage_top_nodes<kLdsNodes>(tr, s_nodes);
+    const int n_lds = stage_top_nodes<kNodes>(tr, s_nodes);
     const float* s_b = common_t ? s_brow : nullptr;
     const float* s_bg = common_t ? s_bgrow : nullptr;
     int* path = s_path + threadIdx.x;
     ChunkCursor cc = chunk_cursor();
     bool more = true;
     const int64_t N = tr.n_leaves;
+    int tnext = -1;   // replay: the ray's next sample
     const int lane = threadIdx.x & 63;
     const int wbase = threadIdx.x - lane;
 
@@ -305,7 +401,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) 
                 ray_setup<IDENT>(tr, in, o, d, t, rs);
                 if (rs.hit) {
                     sh_deg2(rs.dir[0], rs.dir[1], rs.dir[2], Y);
-                    walk_begin(tr, rs, w);
+                    if constexpr (REPLAY) tnext = io.trace.head[ray];
+                    else walk_begin(tr, rs, w);
                     ns_fwd = io.nsamp[ray];
                     ns = 0;
                     Tr = 1.0f;
@@ -322,42 +419,67 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) 
         if (n_idle == kWave) break;
         bool has = false;
         int leaf = -1, my_rec = -1;
-        float gz0 = 0.0f, gz1 = 0.0f, gz2 = 0.0f, gx = 0.0f, gy = 0.0f;
+        float gz0 = 0.0f, gz1 = 0.0f, gz2 = 0.0f, gx = 0.0f, gy = 0.0f, y = 0.0f;
         if (alive) {
-            float delta, umid;
-            leaf = walk_next<kWalkBudgetBwd>(tr, s_nodes, n_lds, path, kBlock, rs, w, delta, umid);
-            bool finish = leaf == -1;
+            float delta = 0.0f, x = 0.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f, q0 = 0.0f, q1 = 0.0f, q2 = 0.0f;
+            bool finish;
+            if constexpr (REPLAY) {
+                // replay the forward's sample
+                if (tnext >= 0) {
+                    const int4* e = io.trace.smp + kPPTraceInt4 * (int64_t)tnext;
+                    const int4 A = e[0], B = e[1], Q = e[2];
+                    leaf = A.x;
+                    delta = __int_as_float(A.y);
+                    x = __int_as_float(A.z);
+                    y = __int_as_float(A.w);
+                    c0 = __int_as_float(B.x);
+                    c1 = __int_as_float(B.y);
+                    c2 = __int_as_float(B.z);
+                    tnext = B.w;
+                    q0 = __int_as_float(Q.x);
+                    q1 = __int_as_float(Q.y);
+                    q2 = __int_as_float(Q.z);
+                }
+                finish = leaf < 0;
+            } else {
+                float umid;
+                leaf = walk_next<kWalkBudgetBwd>(tr, s_nodes, n_lds, path, kBlock, rs, w, delta, umid);
+                finish = leaf == -1;
+                if (leaf >= 0) {
+                    PPSample<DT> p;
+                    pp_load<DT>(tr, leaf, p);
+                    pp_compute<DT>(tr, rs, Y, s_b, s_bg, p);
+                    x = p.x;
+                    y = p.y;
+                    c0 = sigmoid_f(p.z0);
+                    c1 = sigmoid_f(p.z1);
+                    c2 = sigmoid_f(p.z2);
+                    pp_dz_dgamma<DT>(p, Y, q0, q1, q2);
+#pragma unroll
+                    for (int k = 0; k < K; ++k) s_h[threadIdx.x * K + k] = p.h[k];
+                }
+            }
             if (leaf >= 0) {
-                PPSample<DT> p;
-                pp_eval<DT>(tr, rs, Y, s_b, s_bg, leaf, p);
-                const float sig = softplus_f(p.x);
+                const float sig = softplus_f(x);
                 const float od = sig * delta;
                 float a, e;
                 absorb(od, a, e);
                 const float wt = Tr * a;
                 const float Tn = Tr * e;
-                const float c0 = sigmoid_f(p.z0), c1 = sigmoid_f(p.z1), c2 = sigmoid_f(p.z2);
                 p0 = fmaf(wt, c0, p0);
                 p1 = fmaf(wt, c1, p1);
                 p2 = fmaf(wt, c2, p2);
                 const float gdotc = g0 * c0 + g1 * c1 + g2 * c2;
                 const float gsuf = g0 * (F0 - p0) + g1 * (F1 - p1) + g2 * (F2 - p2);
                 const float gsig = delta * (Tn * gdotc - gsuf) + ga * delta * Tfin;
-                gx = gsig * sigmoid_f(p.x);
+                gx = gsig * sigmoid_f(x);
                 gz0 = g0 * wt * c0 * (1.0f - c0);
                 gz1 = g1 * wt * c1 * (1.0f - c1);
                 gz2 = g2 * wt * c2 * (1.0f - c2);
                 // dL/dgamma through every h_k = g_nl(gamma) Y_k
-                float dh[K];
-                hh14(p.dg, Y, dh);
-                float ggam = 0.0f;
-#pragma unroll
-                for (int k = 0; k < K; ++k)
-                    ggam = fmaf(dh[k], gz0 * p.wv[k] + gz1 * p.wv[K + k] + gz2 * p.wv[2 * K + k], ggam);
-                const float sg = sigmoid_f(p.y);
+                const float ggam = gz0 * q0 + gz1 * q1 + gz2 * q2;
+                const float sg = sigmoid_f(y);
                 gy = ggam * kPi * sg * (1.0f - sg);
-#pragma unroll
-                for (int k = 0; k < K; ++k) s_h[threadIdx.x * K + k] = p.h[k];
                 has = true;
                 Tr = Tn;
                 ++ns;
@@ -383,6 +505,17 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) 
         }
         // samples without a record: basis gradients and the atomic row scatter
         has = has && my_rec < 0;
+        if constexpr (REPLAY) {
+            if (has) {
+                // the sample's basis h, for the scatter below (Eq. 2-4, 6)
+                float g[6], dg[6], h[K], sn, cs;
+                sincosf(kPi * sigmoid_f(y), &sn, &cs);
+                radial_n2(sn, cs, g, dg);
+                hh14(g, Y, h);
+#pragma unroll
+                for (int k = 0; k < K; ++k) s_h[threadIdx.x * K + k] = h[k];
+            }
+        }
         uint64_t m = __ballot(has);
         if (common_t && m) {
             // basis gradients of this step: sum over the wavefront's samples of
@@ -634,15 +767,38 @@ __global__ __launch_bounds__(kBlock) void reduce_pp_records_kernel(TreeArgs tr, 
 // ----------------------------------------------------------------------------
 // launchers
 
+template <int DT, bool TRACE>
+static hipError_t pp_fwd_e(const TreeArgs& tr, const InstArgs& in, const RayArgs& ra, float t_stop,
+                           const RenderOut& o, hipStream_t st) {
+    if constexpr (TRACE) {
+        // the trace's allocation counters start at zero
+        hipLaunchKernelGGL(zero_queue_kernel, dim3(1), dim3(kQueues * kQueueStride), 0, st, o.trace.counter);
+    }
+    if (in.identity) {
+        auto kern = render_pp_fwd_kernel<DT, true, TRACE>;
+        hipLaunchKernelGGL(kern, dim3(grid_for(kern, ra)), dim3(kBlock), 0, st, tr, in, ra, t_stop, o);
+    } else {
+        auto kern = render_pp_fwd_kernel<DT, false, TRACE>;
+        hipLaunchKernelGGL(kern, dim3(grid_for(kern, ra)), dim3(kBlock), 0, st, tr, in, ra, t_stop, o);
+    }
+    return hipGetLastError();
+}
+
 template <int DT>
 static hipError_t pp_fwd_t(const TreeArgs& tr, const InstArgs& in, const RayArgs& ra, float t_stop,
                            const RenderOut& o, hipStream_t st) {
+    return o.trace.head ? pp_fwd_e<DT, true>(tr, in, ra, t_stop, o, st) : pp_fwd_e<DT, false>(tr, in, ra, t_stop, o, st);
+}
+
+template <int DT, bool REPLAY>
+static hipError_t pp_bwd_k(const TreeArgs& tr, const InstArgs& in, const RayArgs& ra, const BackwardIO& io,
+                           const RecordArgs& rec, hipStream_t st) {
     if (in.identity) {
-        auto kern = render_pp_fwd_kernel<DT, true>;
-        hipLaunchKernelGGL(kern, dim3(grid_for(kern, ra)), dim3(kBlock), 0, st, tr, in, ra, t_stop, o);
+        auto kern = render_pp_bwd_kernel<DT, true, REPLAY>;
+        hipLaunchKernelGGL(kern, dim3(grid_for(kern, ra)), dim3(kBlock), 0, st, tr, in, ra, io, rec);
     } else {
-        auto kern = render_pp_fwd_kernel<DT, false>;
-        hipLaunchKernelGGL(kern, dim3(grid_for(kern, ra)), dim3(kBlock), 0, st, tr, in, ra, t_stop, o);
+        auto kern = render_pp_bwd_kernel<DT, false, REPLAY>;
+        hipLaunchKernelGGL(kern, dim3(grid_for(kern, ra)), dim3(kBlock), 0, st, tr, in, ra, io, rec);
     }
     return hipGetLastError();
 }
@@ -659,14 +815,17 @@ static hipError_t pp_bwd_t(const TreeArgs& tr, const InstArgs& in, const RayArgs
     void* mem = nullptr;
     hipError_t e = records_begin(tr, cap, st, rec, mem);
     if (e == hipSuccess) {
-        if (in.identity) {
-            auto kern = render_pp_bwd_kernel<DT, true>;
-            hipLaunchKernelGGL(kern, dim3(grid_for(kern, ra)), dim3(kBlock), 0, st, tr, in, ra, io, rec);
+        // one cull pass and adjoint per source of samples: rays that walk, and
+        // (traced forward) rays that replay their trace
+        auto walk = [&](const RayArgs& r) { return pp_bwd_k<DT, false>(tr, in, r, io, rec, st); };
+        auto replay = [&](const RayArgs& r) { return pp_bwd_k<DT, true>(tr, in, r, io, rec, st); };
+        if (io.trace.head) {
+            if (ra.n > (int64_t)INT32_MAX) e = hipErrorInvalidValue;   // traced calls take candidate lists
+            if (e == hipSuccess) e = with_candidates<2>(tr, in, ra, RenderOut{}, io.nsamp, st, walk, io.trace.head);
+            if (e == hipSuccess) e = with_candidates<3>(tr, in, ra, RenderOut{}, io.nsamp, st, replay, io.trace.head);
         } else {
-            auto kern = render_pp_bwd_kernel<DT, false>;
-            hipLaunchKernelGGL(kern, dim3(grid_for(kern, ra)), dim3(kBlock), 0, st, tr, in, ra, io, rec);
+            e = with_candidates<1>(tr, in, ra, RenderOut{}, io.nsamp, st, walk);
         }
-        e = hipGetLastError();
     }
     if (e == hipSuccess && cap > 0) {
         int64_t blocks = (tr.n_leaves + kBlock - 1) / kBlock;
@@ -701,9 +860,9 @@ hipError_t launch_render_pp_bwd(int dtype, const TreeArgs& tr, const InstArgs& i
                                 const BackwardIO& io, hipStream_t stream) {
     if (ra.n_slots <= 0) return hipSuccess;
     switch (dtype) {
-        case 0: return with_candidates<1>(tr, in, ra, RenderOut{}, io.nsamp, stream, [&](const RayArgs& r) { return pp_bwd_t<0>(tr, in, r, io, stream); });
-        case 1: return with_candidates<1>(tr, in, ra, RenderOut{}, io.nsamp, stream, [&](const RayArgs& r) { return pp_bwd_t<1>(tr, in, r, io, stream); });
-        default: return with_candidates<1>(tr, in, ra, RenderOut{}, io.nsamp, stream, [&](const RayArgs& r) { return pp_bwd_t<2>(tr, in, r, io, stream); });
+        case 0: return pp_bwd_t<0>(tr, in, ra, io, stream);
+        case 1: return pp_bwd_t<1>(tr, in, ra, io, stream);
+        default: return pp_bwd_t<2>(tr, in, ra, io, stream);
     }
 }
 

@@ -18,8 +18,9 @@ def _dev(x: torch.Tensor):
 
 class Trace:
     """Per-sample trace of one forward call (neuvv_render_trace), replayed by the adjoint of the
-    same call (neuvv_render_backward_trace). Room for `cap` samples; rays whose samples do not
-    fit are walked again by the adjoint."""
+    same call (neuvv_render_backward_trace). Room for `cap` 32-byte entries (a sample takes one in
+    the K = 16, C = 8 form and two in the per-point form); rays whose samples do not fit are
+    walked again by the adjoint."""
 
     def __init__(self, n_rays: int, cap: int, device):
         self.n_rays = int(n_rays)
@@ -69,7 +70,8 @@ def render_backward(tree: VOctree, ray_o, ray_d, rgb, alpha, nsamp, grad_rgb, gr
     if trace is not None:
         _lib.neuvv_render_backward_trace(tree.struct(), inst, ray_o.shape[0], ray_o, ray_d, ray_t, t_scalar,
                                          image_width, t_stop, rgb, alpha, nsamp, grad_rgb, grad_alpha, gl,
-                                         gb if want_basis else None, trace.buf, trace.cap, stream)
+                                         gb if want_basis else None, gbg if want_basis else None, trace.buf,
+                                         trace.cap, stream)
     else:
         _lib.neuvv_render_backward(tree.struct(), inst, ray_o.shape[0], ray_o, ray_d, ray_t, t_scalar, image_width,
                                    t_stop, rgb, alpha, nsamp, grad_rgb, grad_alpha, gl, gb if want_basis else None,

@@ -221,7 +221,7 @@ def test_argument_errors_without_launch(lib):
                                           None) == -2
     assert lib.neuvv_find_terminal_leaves(ctypes.byref(t), None, 0, None, None, None, 0.0, 0, 0.99, None,
                                           None) == 0
-    # traced calls: the trace buffer's size, alignment and room; the K = 16, C = 8 form only
+    # traced calls: the trace buffer's size, alignment and room; both forms
     assert _lib.neuvv_trace_bytes(10, 5) == 2048 + 256 + 5 * 32
     assert lib.neuvv_trace_bytes(-1, 5) == -1
     args = (None, 0, None, None, None, 0.0, 0, 0.0, None, None, None, None)
@@ -231,13 +231,14 @@ def test_argument_errors_without_launch(lib):
     assert lib.neuvv_render_trace(ctypes.byref(t), *args, 256, -1, None) == -2
     assert lib.neuvv_render_trace(ctypes.byref(t), *args, 256, 2 ** 31, None) == -2
     assert lib.neuvv_render_trace(ctypes.byref(t), *args, 256, 16, None) == 0
-    bargs = (None, 0, None, None, None, 0.0, 0, 0.0, None, None, None, None, None, None, None)
+    bargs = (None, 0, None, None, None, 0.0, 0, 0.0, None, None, None, None, None, None, None, None)
     assert lib.neuvv_render_backward_trace(ctypes.byref(t), *bargs, None, 16, None) == -1
     assert lib.neuvv_render_backward_trace(ctypes.byref(t), *bargs, 256, -3, None) == -2
     assert lib.neuvv_render_backward_trace(ctypes.byref(t), *bargs, 256, 16, None) == 0
     t.K, t.C, t.Cg, t.basis_g = 14, 31, 31, 8
-    assert lib.neuvv_render_trace(ctypes.byref(t), *args, 256, 16, None) == -5
-    assert lib.neuvv_render_backward_trace(ctypes.byref(t), *bargs, 256, 16, None) == -5
+    assert lib.neuvv_render_trace(ctypes.byref(t), *args, 256, 16, None) == 0
+    assert lib.neuvv_render_backward_trace(ctypes.byref(t), *bargs, 256, 16, None) == 0
+    assert lib.neuvv_render_backward_trace(ctypes.byref(t), *bargs, 256, -1, None) == -2
     t.K, t.C, t.Cg, t.basis_g = 16, 8, 0, None
     assert lib.neuvv_paint(3, None, None, 1.0, 0.0, 10, None, None) == -1
     assert lib.neuvv_paint(-1, None, None, 1.0, 0.0, 10, None, None) == -2

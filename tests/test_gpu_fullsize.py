@@ -1,4 +1,6 @@
-"""Full-size parity in the launch configuration bench.py times.
+"""Full-size parity in the launch configuration bench.py times: the traced pair
+(neuvv_render_trace, then neuvv_render_backward_trace replaying its samples)
+with the bench's trace room.
 
 Forward-render workload: depth-9 humanoid VOctree (~2M leaves), 8 cameras at
 1920x1080 rendered in one launch (16.6 M rays, 8x8 tiles, t_stop = 1e-4), with
@@ -35,8 +37,8 @@ def ring(request):
 
 
 def test_full_ring_forward_and_adjoint_sampled(ring):
-    """The bench's launch configuration (the whole ring in one launch, 8x8 tiles), both
-    hyperangle forms; parity on sampled rays the oracle renders one by one."""
+    """The bench's launch configuration (the whole ring in one traced launch, 8x8 tiles),
+    both hyperangle forms; parity on sampled rays the oracle renders one by one."""
     sc, cams, t = ring
     W, H = 1920, 1080
     n_cam = W * H
@@ -47,8 +49,10 @@ def test_full_ring_forward_and_adjoint_sampled(ring):
     for i, c in enumerate(cams):
         cs = _lib.make_camera(c.width, c.height, c.fx, c.fy, c.cx, c.cy, c.c2w)
         _lib.neuvv_pinhole_rays(cs, n_cam, None, o[i * n_cam:(i + 1) * n_cam], d[i * n_cam:(i + 1) * n_cam])
-    announce(f"full size: render {n} rays, {sc.n_leaves} leaves")
-    rgb, alpha, depth, nsamp = ops.render(tree, o, d, t, None, 1e-4, W)
+    announce(f"full size: traced render {n} rays, {sc.n_leaves} leaves")
+    # room for one sample per ray, as bench.py gives it (a per-point sample takes two entries)
+    trace = ops.Trace(n, n * (2 if tree.Cg > 0 else 1), DEV)
+    rgb, alpha, depth, nsamp = ops.render(tree, o, d, t, None, 1e-4, W, trace=trace)
     torch.cuda.synchronize()
     ns = nsamp.cpu().numpy()
     hit = np.nonzero(ns > 0)[0]
@@ -84,8 +88,8 @@ def test_full_ring_forward_and_adjoint_sampled(ring):
     g_alpha = torch.zeros(n, device=DEV)
     g_rgb[sidx] = tdev(gC)
     g_alpha[sidx] = tdev(gA)
-    announce("full size: adjoint")
-    out = ops.render_backward(tree, o, d, rgb, alpha, nsamp, g_rgb, g_alpha, t, None, 1e-4, W)
+    announce("full size: adjoint replayed from the trace")
+    out = ops.render_backward(tree, o, d, rgb, alpha, nsamp, g_rgb, g_alpha, t, None, 1e-4, W, trace=trace)
     torch.cuda.synchronize()
     parts = tree.unpack_grad(out[0])
     e = [rel_err(parts[0].cpu().numpy(), ref["grad_hh"]), rel_err(parts[1].cpu().numpy(), ref["grad_wsig"]),

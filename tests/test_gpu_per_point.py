@@ -169,3 +169,72 @@ def test_per_point_autograd_matches_direct_calls(scene):
     assert rel_err(tree.basis.grad.cpu().numpy(), gb.cpu().numpy()) < 1e-5
     assert rel_err(tree.basis_g.grad.cpu().numpy(), gbg.cpu().numpy()) < 1e-5
     assert float(tree.wgam.grad.abs().max()) > 0
+
+
+@pytest.mark.parametrize("cap", [None, 700, 0])
+def test_per_point_traced_step(scene, cap):
+    """neuvv_render_trace / neuvv_render_backward_trace for the per-point form: the traced forward
+    gives the plain forward's outputs bit for bit; the adjoint replayed from the trace (dz/dgamma
+    traced, two 32-byte entries per sample) matches the oracle with room for every sample, for
+    350 samples (most rays walk again) and for none; scalar time (records), per-ray time (the
+    replay's own scatter, with h recomputed from the traced logit y) and a placed instance."""
+    from oracle import core as OC
+    tree = upload(scene)
+    cam = config1_camera(scene)
+    o, d = OC.pinhole_rays(64, 64, cam.intr(), cam.c2w)
+    n = o.shape[0]
+    rng = np.random.default_rng(38)
+    gC = rng.normal(size=(n, 3)).astype(np.float32)
+    gA = rng.normal(size=n).astype(np.float32)
+    tr = rng.uniform(0, scene.T - 1, n).astype(np.float32)
+    R = np.array([[0.0, -1.0, 0.0], [1.0, 0.0, 0.0], [0.0, 0.0, 1.0]], np.float32)
+    oi, gi = inst_pair(R, [float(scene.G), 0.0, 0.0], 1.0, 0.5, 0)
+    oo, dd = tdev(o), tdev(d)
+    for t, inst, ginst in ((4.0, None, None), (tr, None, None), (2.0, oi, gi)):
+        per_ray = isinstance(t, np.ndarray)
+        tt = tdev(t) if per_ray else t
+        label = f"pp trace cap={cap} t={'per-ray' if per_ray else t} inst={inst is not None}"
+        announce(label)
+        plain = ops.render(tree, oo, dd, tt, ginst, 1e-4, 64)
+        trace = ops.Trace(n, 4 * n if cap is None else cap, oo.device)
+        traced = ops.render(tree, oo, dd, tt, ginst, 1e-4, 64, trace=trace)
+        torch.cuda.synchronize()
+        for a, b in zip(plain, traced):
+            assert torch.equal(a, b)
+        rgb, alpha, depth, nsamp = traced
+        assert int(nsamp.sum()) > 2000
+        fwd = oracle_render(scene, o, d, t if per_ray else None, 0.0 if per_ray else t, 1e-4, inst=inst)
+        amb = fwd["margin"][:, 1] < 1e-3        # stop decision within rounding: no gradient on those rays
+        gC2, gA2 = gC.copy(), gA.copy()
+        gC2[amb], gA2[amb] = 0.0, 0.0
+        ref = oracle_render(scene, o, d, t if per_ray else None, 0.0 if per_ray else t, 1e-4, inst=inst,
+                            g_rgb=gC2, g_alpha=gA2)
+        gl, gb, gbg = ops.render_backward(tree, oo, dd, rgb, alpha, nsamp, tdev(gC2), tdev(gA2), tt, ginst, 1e-4,
+                                          64, trace=trace)
+        torch.cuda.synchronize()
+        hh, ws, wg = tree.unpack_grad(gl)
+        gpu = [x.cpu().numpy() for x in (hh, ws, wg, gb, gbg)]
+        check_grads(gpu, ref, label=label)
+
+
+def test_per_point_traced_step_without_records(scene, monkeypatch):
+    """The replayed per-point adjoint with records off (every sample takes the per-sample scatter,
+    its basis h recomputed from the traced hyperangle logit)."""
+    from oracle import core as OC
+    monkeypatch.setenv("NEUVV_BWD_RECORDS", "0")
+    tree = upload(scene)
+    cam = config1_camera(scene)
+    o, d = OC.pinhole_rays(64, 64, cam.intr(), cam.c2w)
+    n = o.shape[0]
+    rng = np.random.default_rng(39)
+    gC = rng.normal(size=(n, 3)).astype(np.float32)
+    oo, dd = tdev(o), tdev(d)
+    announce("pp trace, records off")
+    trace = ops.Trace(n, 4 * n, oo.device)
+    rgb, alpha, depth, nsamp = ops.render(tree, oo, dd, 6.5, None, 0.0, 64, trace=trace)
+    ref = oracle_render(scene, o, d, None, 6.5, 0.0, g_rgb=gC)
+    gl, gb, gbg = ops.render_backward(tree, oo, dd, rgb, alpha, nsamp, tdev(gC), None, 6.5, None, 0.0, 64,
+                                      trace=trace)
+    torch.cuda.synchronize()
+    hh, ws, wg = tree.unpack_grad(gl)
+    check_grads([x.cpu().numpy() for x in (hh, ws, wg, gb, gbg)], ref, label="pp trace, records off")
