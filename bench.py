@@ -116,15 +116,15 @@ def main():
     import torch
     from paper_2202_06088_amd import _lib, ops
     from paper_2202_06088_amd.voctree import VOctree
-    from workloads import CONFIGS, make_scene_per_point, ring_cameras, scene_for_config
+    from workloads import WORKLOADS, make_scene_per_point, ring_cameras, scene_for_workload
 
     dt = {"f32": _lib.F32, "f16": _lib.F16, "bf16": _lib.BF16}[args.dtype]
     t0 = time.time()
     log(f"generating the depth-9 humanoid scene (seeded, {args.form} hyperangle)")
     if args.form == "global":
-        sc = scene_for_config(2)
+        sc = scene_for_workload("forward")
     else:
-        c2 = CONFIGS[2]
+        c2 = WORKLOADS["forward"]
         sc = make_scene_per_point(c2["depth"], c2["target"], c2["kind"], T=c2["T"], seed=c2["seed"])
     cams = ring_cameras(sc, 8, 1920, 1080, 40.0, 10.0, seed=2)
     t_frame = float(np.random.default_rng(2002).uniform(0, sc.T))
@@ -300,7 +300,7 @@ def workload_bench(args):
     one JSON line each, value = rays per second of the timed unit."""
     import torch
     from paper_2202_06088_amd import _lib, ops
-    from workloads import config5_instances, make_scene, orbit_camera, ring_cameras, scene_for_config, stereo_cameras
+    from workloads import multi_instances, make_scene, orbit_camera, ring_cameras, scene_for_workload, stereo_cameras
     from paper_2202_06088_amd.voctree import VOctree
     if args.gpus != 1:
         log("one GPU only")
@@ -315,7 +315,7 @@ def workload_bench(args):
     out = {"metric": METRIC, "unit": "Mrays/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "data": "synthetic"}
     if args.workload == "train":
-        sc = scene_for_config(3)
+        sc = scene_for_workload("train")
         rng = np.random.default_rng(1003)
         tgt = type(sc)(sc.depth, sc.leaf_ijk, rng.normal(0, 0.3, sc.hh.shape).astype(np.float32), sc.wsig,
                        sc.basis, sc.gamma)
@@ -351,7 +351,7 @@ def workload_bench(args):
                            "step": "traced render + L2 loss gradient + adjoint, per-ray t"})
         log(f"train: {ms:.3f} ms per step ({n} rays, {sc.n_leaves} leaves)")
     elif args.workload == "mixed":
-        sc = scene_for_config(4)
+        sc = scene_for_workload("mixed")
         W = H = 2048
         eyes = stereo_cameras(sc, W, H, 90.0, seed=4)
         t = float(np.random.default_rng(4004).uniform(0, sc.T))
@@ -384,7 +384,7 @@ def workload_bench(args):
         scenes = [make_scene(9, 2_000_000, "human", K=16, C=8, T=300, seed=50 + i) for i in range(4)]
         G = scenes[0].G
         insts = [_lib.make_instance(p["rot"], p["trans"], p["scale"], p["time_offset"], p["wrap"])
-                 for p in config5_instances(G, 4, seed=55)]
+                 for p in multi_instances(G, 4, seed=55)]
         cam = orbit_camera((0.0, 0.0, 0.45 * G), 3.2 * G, 0.4, 0.25, W, H, 50.0)
         o, d = ops.pinhole_rays(_lib.make_camera(W, H, cam.fx, cam.fy, cam.cx, cam.cy, cam.c2w))
         t = 37.5

@@ -13,11 +13,12 @@
  *     pointers named "host" are host memory owned by the caller. The library
  *     keeps no pointer after a call returns. The only device memory it
  *     allocates is per-call scratch of the render calls: neuvv_render,
- *     neuvv_render_backward and neuvv_find_terminal_leaves take 2 KiB of
- *     work-queue counters plus a candidate list of 4 bytes per work slot
- *     (rounded up to 64 slots); neuvv_render_backward also takes the records
- *     of its two-phase adjoint (4 bytes per leaf plus 32 bytes per record of
- *     room, see there); neuvv_render_multi takes the counters only. Scratch
+ *     neuvv_render_trace, neuvv_render_multi, neuvv_render_backward,
+ *     neuvv_render_backward_trace and neuvv_find_terminal_leaves take 2 KiB
+ *     of work-queue counters plus a candidate list of 4 bytes per work slot
+ *     (rounded up to 64 slots; the adjoint of a traced forward takes two);
+ *     the adjoints also take the records of their two-phase reduction (4
+ *     bytes per leaf plus 32 bytes per record of room, see there). Scratch
  *     is taken in stream order on the call's stream from a memory pool the
  *     library keeps per device (it keeps freed memory for later calls) and
  *     freed in stream order after the kernels; each call has its own, so

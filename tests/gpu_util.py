@@ -107,7 +107,7 @@ def rel_err(a, b):
                  max(np.abs(np.asarray(b, np.float64)).max(initial=0.0), 1e-30))
 
 
-def config1_camera(scene, seed=11):
+def tiny_camera(scene, seed=11):
     from workloads import orbit_camera
     """64x64 pinhole, hfov 30 degrees, seeded direction, 2.5 G from the centroid of the leaves."""
     rng = np.random.default_rng(seed)

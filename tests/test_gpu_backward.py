@@ -8,20 +8,24 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_util import DEV, announce, cam_struct, config1_camera, inst_pair, oracle_render, rel_err, tdev, upload
+from gpu_util import DEV, announce, cam_struct, tiny_camera, inst_pair, oracle_render, rel_err, tdev, upload
 from oracle import core as OC
 from paper_2202_06088_amd import _lib, autograd, ops
-from workloads import make_scene, ring_cameras, scene_for_config
+from workloads import make_scene, ring_cameras, scene_for_workload
 
 pytestmark = pytest.mark.gpu
 
 
-def run_backward(tree, o, d, t, t_scalar, t_stop, g_rgb, g_alpha, inst=None, image_width=0):
+def run_backward(tree, o, d, t, t_scalar, t_stop, g_rgb, g_alpha, inst=None, image_width=0, traced=False):
+    """Forward then adjoint; traced: the pair neuvv_render_trace / neuvv_render_backward_trace with
+    room for two samples per ray."""
     tt = tdev(t) if t is not None else t_scalar
     oo, dd = tdev(o), tdev(d)
-    rgb, alpha, depth, nsamp = ops.render(tree, oo, dd, tt, inst, t_stop, image_width)
+    trace = ops.Trace(oo.shape[0], 2 * oo.shape[0], oo.device) if traced else None
+    rgb, alpha, depth, nsamp = ops.render(tree, oo, dd, tt, inst, t_stop, image_width, trace=trace)
     gl, gb = ops.render_backward(tree, oo, dd, rgb, alpha, nsamp, tdev(g_rgb),
-                                 None if g_alpha is None else tdev(g_alpha), tt, inst, t_stop, image_width)
+                                 None if g_alpha is None else tdev(g_alpha), tt, inst, t_stop, image_width,
+                                 trace=trace)
     torch.cuda.synchronize()
     hh, ws = tree.unpack_grad(gl)
     pad = gl[:, 3 * tree.K + tree.C:]
@@ -37,10 +41,10 @@ def check(gpu, ref, tol=1e-4, label=""):
 
 
 @pytest.mark.parametrize("layout", [_lib.LAYOUT_LEAF_ROWS, _lib.LAYOUT_VEC_SOA])
-def test_backward_config1_scalar_time(layout):
-    sc = scene_for_config(1)
+def test_backward_tiny_scalar_time(layout):
+    sc = scene_for_workload("tiny")
     tree = upload(sc, layout=layout)
-    cam = config1_camera(sc)
+    cam = tiny_camera(sc)
     o, d = OC.pinhole_rays(64, 64, cam.intr(), cam.c2w)
     rng = np.random.default_rng(41)
     gC = rng.normal(size=(o.shape[0], 3)).astype(np.float32)
@@ -49,7 +53,7 @@ def test_backward_config1_scalar_time(layout):
         announce(f"config-1 backward t={t} layout={layout}")
         ref = oracle_render(sc, o, d, None, t, 0.0, g_rgb=gC, g_alpha=gA)
         gpu = run_backward(tree, o, d, None, t, 0.0, gC, gA, image_width=64)
-        check(gpu, ref, label=f"cfg1 t={t}")
+        check(gpu, ref, label=f"tiny_scene t={t}")
 
 
 @pytest.mark.parametrize("records", ["0", "777", None])
@@ -62,9 +66,9 @@ def test_backward_record_modes(records, monkeypatch):
         monkeypatch.delenv("NEUVV_BWD_RECORDS", raising=False)
     else:
         monkeypatch.setenv("NEUVV_BWD_RECORDS", records)
-    sc = scene_for_config(1)
+    sc = scene_for_workload("tiny")
     tree = upload(sc)
-    cam = config1_camera(sc)
+    cam = tiny_camera(sc)
     o, d = OC.pinhole_rays(64, 64, cam.intr(), cam.c2w)
     rng = np.random.default_rng(47)
     gC = rng.normal(size=(o.shape[0], 3)).astype(np.float32)
@@ -80,25 +84,26 @@ def test_backward_record_modes(records, monkeypatch):
     check(gpu, ref, label=f"records={records} per-ray t")
 
 
-def test_backward_ragged_image():
+@pytest.mark.parametrize("traced", [False, True])
+def test_backward_ragged_image(traced):
     """Rays as a 67-wide image with a partial last row: 8x8 tiles that overhang the image and XCD
-    parts that cut tile rows, for the adjoint's cull and records."""
-    sc = scene_for_config(1)
+    parts that cut tile rows, for the adjoint's cull and records (plain and traced pair)."""
+    sc = scene_for_workload("tiny")
     tree = upload(sc)
     rng = np.random.default_rng(48)
-    cam = config1_camera(sc)
+    cam = tiny_camera(sc)
     o, d = OC.pinhole_rays(64, 64, cam.intr(), cam.c2w)
     n = 67 * 44 + 13
     sel = rng.choice(o.shape[0], n, replace=False)
     o, d = o[sel], d[sel]
     gC = rng.normal(size=(n, 3)).astype(np.float32)
-    announce("ragged-image backward 67 wide")
+    announce(f"ragged-image backward 67 wide traced={traced}")
     ref = oracle_render(sc, o, d, None, 3.0, 1e-4, g_rgb=gC)
     gC[ref["margin"][:, 1] < 1e-3] = 0.0
     ref = oracle_render(sc, o, d, None, 3.0, 1e-4, g_rgb=gC)
-    gpu = run_backward(tree, o, d, None, 3.0, 1e-4, gC, None, image_width=67)
+    gpu = run_backward(tree, o, d, None, 3.0, 1e-4, gC, None, image_width=67, traced=traced)
     assert int(gpu[3].sum()) > 3000
-    check(gpu, ref, label="ragged image")
+    check(gpu, ref, label=f"ragged image traced={traced}")
 
 
 @pytest.mark.parametrize("cap", [None, 500, 0])
@@ -107,9 +112,9 @@ def test_traced_step(cap):
     forward's outputs bit for bit; the adjoint replayed from the trace matches the oracle, with
     room for every sample, for 500 (most rays walk again) and for none; scalar and per-ray time,
     identity and a placed instance."""
-    sc = scene_for_config(1)
+    sc = scene_for_workload("tiny")
     tree = upload(sc)
-    cam = config1_camera(sc)
+    cam = tiny_camera(sc)
     o, d = OC.pinhole_rays(64, 64, cam.intr(), cam.c2w)
     n = o.shape[0]
     rng = np.random.default_rng(49)
@@ -179,19 +184,20 @@ def test_backward_training_step_per_ray_time():
     check(gpu, ref, label="train")
 
 
-def test_backward_with_early_stop_and_16bit():
-    sc = scene_for_config(1)
-    cam = config1_camera(sc)
+@pytest.mark.parametrize("traced", [False, True])
+def test_backward_with_early_stop_and_16bit(traced):
+    sc = scene_for_workload("tiny")
+    cam = tiny_camera(sc)
     o, d = OC.pinhole_rays(64, 64, cam.intr(), cam.c2w)
     rng = np.random.default_rng(43)
     gC = rng.normal(size=(o.shape[0], 3)).astype(np.float32)
     fwd = oracle_render(sc, o, d, None, 2.0, 1e-4)
     gC[fwd["margin"][:, 1] < 1e-3] = 0.0             # rays whose stop decision is within rounding
     for dtype in (_lib.F32, _lib.F16, _lib.BF16):
-        announce(f"backward with t_stop=1e-4, storage {dtype}")
+        announce(f"backward with t_stop=1e-4, storage {dtype}, traced={traced}")
         ref = oracle_render(sc, o, d, None, 2.0, 1e-4, dtype=dtype, g_rgb=gC)
-        gpu = run_backward(upload(sc, dtype), o, d, None, 2.0, 1e-4, gC, None)
-        check(gpu, ref, label=f"stop dtype={dtype}")
+        gpu = run_backward(upload(sc, dtype), o, d, None, 2.0, 1e-4, gC, None, traced=traced)
+        check(gpu, ref, label=f"stop dtype={dtype} traced={traced}")
 
 
 def test_backward_instance():
@@ -216,9 +222,9 @@ def test_backward_instance():
 
 @pytest.mark.parametrize("layout", [_lib.LAYOUT_LEAF_ROWS, _lib.LAYOUT_VEC_SOA])
 def test_autograd_function_matches_direct_calls(layout):
-    sc = scene_for_config(1)
+    sc = scene_for_workload("tiny")
     tree = upload(sc, layout=layout)
-    cam = config1_camera(sc)
+    cam = tiny_camera(sc)
     o, d = ops.pinhole_rays(cam_struct(cam))
     tree.hh.requires_grad_(True)
     tree.wsig.requires_grad_(True)

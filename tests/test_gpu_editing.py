@@ -8,11 +8,11 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_util import announce, compare, config1_camera, gpu_render, inst_pair, oracle_render, tdev, upload
+from gpu_util import announce, compare, tiny_camera, gpu_render, inst_pair, oracle_render, tdev, upload
 from oracle import core as OC
 from oracle import editing as OE
 from paper_2202_06088_amd import _lib, ops
-from workloads import orbit_camera, scene_for_config
+from workloads import orbit_camera, scene_for_workload
 
 pytestmark = pytest.mark.gpu
 
@@ -26,7 +26,7 @@ def oracle_with_edits(sc, o, d, t_scalar, t_stop, edit, inst=None):
 def painted():
     """Paint a seeded pattern at t = 2 (active from frame 2) from a close view where several
     pixels end in the same leaf (so the lowest-ray rule decides), 96x96."""
-    sc = scene_for_config(1)
+    sc = scene_for_workload("tiny")
     tree = upload(sc)
     cen = sc.leaf_ijk.mean(0) + 0.5
     cam = orbit_camera(cen, 1.2 * sc.G, 0.4, math.radians(10.0), 96, 96, 40.0)
@@ -82,7 +82,7 @@ def test_edits_follow_instance_time(painted):
     sc, tree, oe = painted
     R = np.eye(3, dtype=np.float32)
     oi, gi = inst_pair(R, [0.0, 0.0, 0.0], 1.0, 1.5, 0)       # local time = t + 1.5
-    cam = config1_camera(sc)
+    cam = tiny_camera(sc)
     o, d = OC.pinhole_rays(64, 64, cam.intr(), cam.c2w)
     for t in (0.25, 0.75):                                     # local 1.75 (inactive), 2.25 (active)
         announce(f"edits under an instance time offset, t={t}")

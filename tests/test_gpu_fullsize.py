@@ -18,7 +18,7 @@ import torch
 from gpu_util import DEV, announce, compare, oracle_render, rel_err, tdev, upload
 from oracle import core as OC
 from paper_2202_06088_amd import _lib, ops
-from workloads import CONFIGS, make_scene_per_point, ring_cameras, scene_for_config
+from workloads import WORKLOADS, make_scene_per_point, ring_cameras, scene_for_workload
 
 pytestmark = pytest.mark.gpu
 
@@ -27,9 +27,9 @@ pytestmark = pytest.mark.gpu
 def ring(request):
     announce(f"full size: generating the depth-9 scene ({request.param} hyperangle)")
     if request.param == "global":
-        sc = scene_for_config(2)
+        sc = scene_for_workload("forward")
     else:
-        c2 = CONFIGS[2]
+        c2 = WORKLOADS["forward"]
         sc = make_scene_per_point(c2["depth"], c2["target"], c2["kind"], T=c2["T"], seed=c2["seed"])
     cams = ring_cameras(sc, 8, 1920, 1080, 40.0, 10.0, seed=2)
     t = float(np.random.default_rng(2002).uniform(0, sc.T))

@@ -12,7 +12,7 @@ from gpu_util import announce, oracle_render, tdev, upload
 from oracle import core as OC
 from oracle import lighting as OL
 from paper_2202_06088_amd import _lib, ops
-from workloads import look_at, orbit_camera, scene_for_config
+from workloads import look_at, orbit_camera, scene_for_workload
 
 pytestmark = pytest.mark.gpu
 
@@ -53,7 +53,7 @@ def viewer_rays(sc, W=96, H=72):
 @pytest.mark.parametrize("k,r0", [(0.75, 0.0), (1.0, 40.0), (0.0, 25.0)])
 def test_shade_kernel_on_identical_inputs(k, r0):
     """Oracle-made maps fed to both sides: isolates the shading arithmetic."""
-    sc = scene_for_config(1)
+    sc = scene_for_workload("tiny")
     ol, gl = make_light(sc, k=k, r0=r0)
     lo, ld = OC.pinhole_rays(ol.width, ol.height, ol.intr, ol.c2w)
     lmap = oracle_render(sc, lo, ld, None, 3.0, 1e-4)["alpha"].reshape(ol.height, ol.width)
@@ -76,7 +76,7 @@ def test_shade_kernel_on_identical_inputs(k, r0):
 def test_shadow_and_falloff_chain():
     """The whole effect: the light's alpha map rendered and low-passed, the viewer image
     rendered with depth, then shaded; GPU chain against the oracle's chain."""
-    sc = scene_for_config(1)
+    sc = scene_for_workload("tiny")
     tree = upload(sc)
     ol, gl = make_light(sc, k=0.8, r0=30.0)
     announce("lighting chain: light map render + blur + viewer render + shade")

@@ -8,11 +8,11 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_util import announce, compare, config1_camera, inst_pair, round_storage, tdev, upload
+from gpu_util import announce, compare, tiny_camera, inst_pair, round_storage, tdev, upload
 from oracle import core as OC
 from oracle import multi as OM
 from paper_2202_06088_amd import _lib
-from workloads import make_scene, random_rays, scene_for_config
+from workloads import make_scene, random_rays, scene_for_workload
 
 pytestmark = pytest.mark.gpu
 
@@ -55,13 +55,13 @@ def ref_multi(scenes, oinsts, o, d, t, t_stop, dtype=_lib.F32):
 @pytest.fixture(scope="module")
 def scenes():
     announce("multi: two scenes (tiny workload and a depth-6 humanoid)")
-    return scene_for_config(1), make_scene(6, 15_000, "human", seed=71, T=30)
+    return scene_for_workload("tiny"), make_scene(6, 15_000, "human", seed=71, T=30)
 
 
 def test_single_instance_equals_render(scenes):
     sc = scenes[0]
     tree = upload(sc)
-    cam = config1_camera(sc)
+    cam = tiny_camera(sc)
     o, d = OC.pinhole_rays(64, 64, cam.intr(), cam.c2w)
     oi, gi = around_centre(sc, 0.3, [1.0, -0.5, 0.25], 1.1, 2.5, 1)
     announce("multi L=1")
@@ -74,7 +74,7 @@ def test_single_instance_equals_render(scenes):
 def test_two_interpenetrating_instances(scenes, t_stop):
     sc = scenes[0]
     tree = upload(sc)
-    cam = config1_camera(sc)
+    cam = tiny_camera(sc)
     o, d = OC.pinhole_rays(64, 64, cam.intr(), cam.c2w)
     a = around_centre(sc, 0.0, [0.0, 0.0, 0.0])
     b = around_centre(sc, 0.8, [2.0, 1.0, -1.0], 0.9, 7.0, 1)
@@ -104,7 +104,7 @@ def test_four_instances_two_trees_duplicates_and_random_rays(scenes):
 def test_multi_16bit(scenes, dtype):
     sc = scenes[1]
     tree = upload(sc, dtype)
-    cam = config1_camera(sc)
+    cam = tiny_camera(sc)
     o, d = OC.pinhole_rays(64, 64, cam.intr(), cam.c2w)
     a = around_centre(sc, 0.0, [0, 0, 0])
     b = around_centre(sc, 0.5, [1.5, 0.0, 0.0], 1.0, 3.0, 0)

@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_util import (DEV, announce, cam_struct, compare, config1_camera, gpu_render, inst_pair, oracle_render,
+from gpu_util import (DEV, announce, cam_struct, compare, tiny_camera, gpu_render, inst_pair, oracle_render,
                       rel_err, tdev, upload)
 from paper_2202_06088_amd import _lib, autograd, ops
 from workloads import make_scene_per_point, random_rays, special_rays
@@ -24,12 +24,16 @@ def scene():
     return make_scene_per_point(6, 20_000, "random", T=30, seed=31)
 
 
-def pp_backward(tree, o, d, t, t_scalar, t_stop, g_rgb, g_alpha, inst=None, image_width=0):
+def pp_backward(tree, o, d, t, t_scalar, t_stop, g_rgb, g_alpha, inst=None, image_width=0, traced=False):
+    """Forward then adjoint; traced: the pair neuvv_render_trace / neuvv_render_backward_trace with
+    room for two samples per ray (four 32-byte entries)."""
     tt = tdev(t) if t is not None else t_scalar
     oo, dd = tdev(o), tdev(d)
-    rgb, alpha, depth, nsamp = ops.render(tree, oo, dd, tt, inst, t_stop, image_width)
+    trace = ops.Trace(oo.shape[0], 4 * oo.shape[0], oo.device) if traced else None
+    rgb, alpha, depth, nsamp = ops.render(tree, oo, dd, tt, inst, t_stop, image_width, trace=trace)
     gl, gb, gbg = ops.render_backward(tree, oo, dd, rgb, alpha, nsamp, tdev(g_rgb),
-                                      None if g_alpha is None else tdev(g_alpha), tt, inst, t_stop, image_width)
+                                      None if g_alpha is None else tdev(g_alpha), tt, inst, t_stop, image_width,
+                                      trace=trace)
     torch.cuda.synchronize()
     hh, ws, wg = tree.unpack_grad(gl)
     pad = gl[:, 3 * tree.K + tree.C + tree.Cg:]
@@ -49,7 +53,7 @@ def check_grads(gpu, ref, tol=1e-4, label=""):
 @pytest.mark.parametrize("layout", [_lib.LAYOUT_LEAF_ROWS, _lib.LAYOUT_VEC_SOA])
 def test_per_point_forward_image(scene, layout):
     tree = upload(scene, layout=layout)
-    cam = config1_camera(scene)
+    cam = tiny_camera(scene)
     from oracle import core as OC
     o, d = OC.pinhole_rays(64, 64, cam.intr(), cam.c2w)
     for t, t_stop in ((0.0, 0.0), (7.25, 0.0), (12.5, 1e-4), (29.0, 1e-4)):
@@ -73,20 +77,21 @@ def test_per_point_forward_random_rays_per_ray_time(scene):
     compare(gpu, ref, label="pp random")
 
 
+@pytest.mark.parametrize("traced", [False, True])
 @pytest.mark.parametrize("layout", [_lib.LAYOUT_LEAF_ROWS, _lib.LAYOUT_VEC_SOA])
-def test_per_point_backward_scalar_time(scene, layout):
+def test_per_point_backward_scalar_time(scene, layout, traced):
     tree = upload(scene, layout=layout)
-    cam = config1_camera(scene)
+    cam = tiny_camera(scene)
     from oracle import core as OC
     o, d = OC.pinhole_rays(64, 64, cam.intr(), cam.c2w)
     rng = np.random.default_rng(33)
     gC = rng.normal(size=(o.shape[0], 3)).astype(np.float32)
     gA = rng.normal(size=o.shape[0]).astype(np.float32)
     for t in (4.0, 17.6):
-        announce(f"per-point backward t={t} layout={layout}")
+        announce(f"per-point backward t={t} layout={layout} traced={traced} (no early stop)")
         ref = oracle_render(scene, o, d, None, t, 0.0, g_rgb=gC, g_alpha=gA)
-        gpu = pp_backward(tree, o, d, None, t, 0.0, gC, gA, image_width=64)
-        check_grads(gpu, ref, label=f"pp t={t}")
+        gpu = pp_backward(tree, o, d, None, t, 0.0, gC, gA, image_width=64, traced=traced)
+        check_grads(gpu, ref, label=f"pp t={t} traced={traced}")
 
 
 def test_per_point_backward_per_ray_time_and_early_stop(scene):
@@ -103,10 +108,11 @@ def test_per_point_backward_per_ray_time_and_early_stop(scene):
     check_grads(gpu, ref, label="pp per-ray t")
 
 
+@pytest.mark.parametrize("traced", [False, True])
 @pytest.mark.parametrize("dtype", [_lib.F16, _lib.BF16])
-def test_per_point_16bit_storage(scene, dtype):
+def test_per_point_16bit_storage(scene, dtype, traced):
     tree = upload(scene, dtype)
-    cam = config1_camera(scene)
+    cam = tiny_camera(scene)
     from oracle import core as OC
     o, d = OC.pinhole_rays(64, 64, cam.intr(), cam.c2w)
     rng = np.random.default_rng(35)
@@ -115,8 +121,8 @@ def test_per_point_16bit_storage(scene, dtype):
     ref = oracle_render(scene, o, d, None, 9.0, 0.0, dtype=dtype, g_rgb=gC)
     gpu = gpu_render(tree, o, d, None, 9.0, 0.0, image_width=64)
     compare(gpu, ref, label=f"pp dtype={dtype}")
-    g = pp_backward(tree, o, d, None, 9.0, 0.0, gC, None, image_width=64)
-    check_grads(g, ref, label=f"pp dtype={dtype}")
+    g = pp_backward(tree, o, d, None, 9.0, 0.0, gC, None, image_width=64, traced=traced)
+    check_grads(g, ref, label=f"pp dtype={dtype} traced={traced}")
     # against the unrounded payload: the storage error itself
     full = oracle_render(scene, o, d, None, 9.0, 0.0)
     err = float(np.abs(gpu["rgb"] - full["rgb"]).max())
@@ -148,7 +154,7 @@ def test_per_point_instance(scene):
 
 def test_per_point_autograd_matches_direct_calls(scene):
     tree = upload(scene)
-    cam = config1_camera(scene)
+    cam = tiny_camera(scene)
     o, d = ops.pinhole_rays(cam_struct(cam))
     for x in (tree.hh, tree.wsig, tree.basis, tree.wgam, tree.basis_g):
         x.requires_grad_(True)
@@ -180,7 +186,7 @@ def test_per_point_traced_step(scene, cap):
     replay's own scatter, with h recomputed from the traced logit y) and a placed instance."""
     from oracle import core as OC
     tree = upload(scene)
-    cam = config1_camera(scene)
+    cam = tiny_camera(scene)
     o, d = OC.pinhole_rays(64, 64, cam.intr(), cam.c2w)
     n = o.shape[0]
     rng = np.random.default_rng(38)
@@ -223,7 +229,7 @@ def test_per_point_traced_step_without_records(scene, monkeypatch):
     from oracle import core as OC
     monkeypatch.setenv("NEUVV_BWD_RECORDS", "0")
     tree = upload(scene)
-    cam = config1_camera(scene)
+    cam = tiny_camera(scene)
     o, d = OC.pinhole_rays(64, 64, cam.intr(), cam.c2w)
     n = o.shape[0]
     rng = np.random.default_rng(39)

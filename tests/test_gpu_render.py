@@ -12,24 +12,24 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_util import (DEV, announce, cam_struct, compare, config1_camera, gpu_render, inst_pair, oracle_render,
+from gpu_util import (DEV, announce, cam_struct, compare, tiny_camera, gpu_render, inst_pair, oracle_render,
                       rel_err, round_storage, tdev, upload)
 from oracle import core as OC
 from oracle.hh import hh_basis
 from paper_2202_06088_amd import _lib, ops
-from workloads import make_scene, random_rays, scene_for_config, special_rays
+from workloads import make_scene, random_rays, scene_for_workload, special_rays
 
 pytestmark = pytest.mark.gpu
 
 
 @pytest.fixture(scope="module")
-def cfg1():
-    return scene_for_config(1)
+def tiny_scene():
+    return scene_for_workload("tiny")
 
 
 @pytest.fixture(scope="module")
-def cfg1_tree(cfg1):
-    return upload(cfg1)
+def tiny_tree(tiny_scene):
+    return upload(tiny_scene)
 
 
 def test_eval_hh_matches_oracle():
@@ -63,22 +63,22 @@ def test_pinhole_matches_oracle():
 
 
 @pytest.mark.parametrize("t_stop", [0.0, 1e-4])
-def test_render_config1_fp32(cfg1, cfg1_tree, t_stop):
+def test_render_tiny_fp32(tiny_scene, tiny_tree, t_stop):
     """Tiny VOctree: depth 6, ~20k leaves, 64x64 pinhole view, one seeded frame."""
-    cam = config1_camera(cfg1)
-    t = float(np.random.default_rng(12).integers(0, cfg1.T))
+    cam = tiny_camera(tiny_scene)
+    t = float(np.random.default_rng(12).integers(0, tiny_scene.T))
     announce(f"config-1 render t_stop={t_stop} t={t}")
     o, d = OC.pinhole_rays(64, 64, cam.intr(), cam.c2w)
     go, gd = ops.pinhole_rays(cam_struct(cam))
     assert np.array_equal(go.cpu().numpy(), o) and np.array_equal(gd.cpu().numpy(), d)
-    ref = oracle_render(cfg1, o, d, None, t, t_stop)
+    ref = oracle_render(tiny_scene, o, d, None, t, t_stop)
     # rays as a row-major 64-wide image (8x8 tiles per wavefront) and as a flat list
     for iw in (64, 0):
-        rgb, alpha, depth, nsamp = ops.render(cfg1_tree, go, gd, t, None, t_stop, iw)
+        rgb, alpha, depth, nsamp = ops.render(tiny_tree, go, gd, t, None, t_stop, iw)
         torch.cuda.synchronize()
         gpu = dict(rgb=rgb.cpu().numpy().astype(np.float64), alpha=alpha.cpu().numpy().astype(np.float64),
                    depth=depth.cpu().numpy().astype(np.float64), nsamp=nsamp.cpu().numpy())
-        st = compare(gpu, ref, label=f"cfg1 iw={iw}")
+        st = compare(gpu, ref, label=f"tiny_scene iw={iw}")
         assert st["hit"] > 500
 
 
@@ -153,15 +153,15 @@ def test_render_edge_cases():
 
 
 @pytest.mark.parametrize("dtype", [_lib.F16, _lib.BF16])
-def test_render_16bit_storage(cfg1, dtype):
-    cam = config1_camera(cfg1)
+def test_render_16bit_storage(tiny_scene, dtype):
+    cam = tiny_camera(tiny_scene)
     o, d = OC.pinhole_rays(64, 64, cam.intr(), cam.c2w)
-    tree = upload(cfg1, dtype)
+    tree = upload(tiny_scene, dtype)
     announce(f"16-bit storage dtype={dtype}")
     gpu = gpu_render(tree, o, d, None, 3.0, 1e-4)
-    ref_r = oracle_render(cfg1, o, d, None, 3.0, 1e-4, dtype=dtype)
+    ref_r = oracle_render(tiny_scene, o, d, None, 3.0, 1e-4, dtype=dtype)
     compare(gpu, ref_r, label=f"dtype{dtype} vs rounded payload")
-    ref = oracle_render(cfg1, o, d, None, 3.0, 1e-4)
+    ref = oracle_render(tiny_scene, o, d, None, 3.0, 1e-4)
     err = np.abs(gpu["rgb"] - ref["rgb"]).max()
     mse = np.mean((gpu["rgb"] - ref["rgb"]) ** 2)
     psnr = 10 * math.log10(1.0 / mse) if mse > 0 else math.inf
@@ -218,13 +218,13 @@ def test_compose_matches_oracle():
 
 
 @pytest.mark.parametrize("dtype", [_lib.F32, _lib.F16, _lib.BF16])
-def test_leaf_rows_layout_same_results(cfg1, dtype):
+def test_leaf_rows_layout_same_results(tiny_scene, dtype):
     """The leaf-major payload layout loads the same values: forward outputs are bitwise
     equal to the vector-SoA layout, adjoints equal up to the order of atomic additions."""
     from paper_2202_06088_amd.voctree import VOctree
-    cam = config1_camera(cfg1)
+    cam = tiny_camera(tiny_scene)
     o, d = ops.pinhole_rays(cam_struct(cam))
-    trees = [VOctree.build(cfg1.depth, cfg1.leaf_ijk, cfg1.hh, cfg1.wsig, cfg1.basis, cfg1.gamma, dtype, DEV,
+    trees = [VOctree.build(tiny_scene.depth, tiny_scene.leaf_ijk, tiny_scene.hh, tiny_scene.wsig, tiny_scene.basis, tiny_scene.gamma, dtype, DEV,
                            layout=lay) for lay in (_lib.LAYOUT_VEC_SOA, _lib.LAYOUT_LEAF_ROWS)]
     announce(f"leaf-rows layout, dtype {dtype}")
     outs = [ops.render(tr, o, d, 6.0, None, 1e-4, 64) for tr in trees]

@@ -21,14 +21,14 @@ import torch
 from gpu_util import DEV, announce, compare, oracle_render, rel_err, round_storage, tdev, upload
 from oracle import core as OC
 from paper_2202_06088_amd import _lib, ops
-from workloads import (config5_instances, make_scene, orbit_camera, ring_cameras, scene_for_config,
+from workloads import (multi_instances, make_scene, orbit_camera, ring_cameras, scene_for_workload,
                        stereo_cameras)
 
 pytestmark = pytest.mark.gpu
 
 
 def test_training_step_full_size():
-    sc = scene_for_config(3)
+    sc = scene_for_workload("train")
     announce(f"training step: {sc.n_leaves} leaves")
     rng = np.random.default_rng(1003)
     tgt_hh = rng.normal(0, 0.3, sc.hh.shape).astype(np.float32)
@@ -82,7 +82,7 @@ def test_training_step_full_size():
 
 
 def test_mixed_precision_stereo_full_size():
-    sc = scene_for_config(4)
+    sc = scene_for_workload("mixed")
     announce(f"mixed precision: {sc.n_leaves} leaves, depth {sc.depth}")
     W = H = 2048
     eyes = stereo_cameras(sc, W, H, 90.0, seed=4)
@@ -132,7 +132,7 @@ def test_multi_primitive_composition_full_size():
     W, H = 1920, 1080
     scenes = [make_scene(9, 2_000_000, "human", K=16, C=8, T=300, seed=50 + i) for i in range(4)]
     G = scenes[0].G
-    places = config5_instances(G, 4, seed=55)
+    places = multi_instances(G, 4, seed=55)
     insts = [(OC.Instance(p["rot"], p["trans"], p["scale"], p["time_offset"], p["wrap"]),
               _lib.make_instance(p["rot"], p["trans"], p["scale"], p["time_offset"], p["wrap"])) for p in places]
     cam = orbit_camera((0.0, 0.0, 0.45 * G), 3.2 * G, 0.4, 0.25, W, H, 50.0)

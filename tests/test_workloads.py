@@ -1,7 +1,7 @@
 """Seeded workload generators: determinism, target leaf counts, camera framing."""
 import numpy as np
 
-from workloads import CONFIGS, make_scene, ring_cameras, scene_for_config
+from workloads import WORKLOADS, make_scene, ring_cameras, scene_for_workload
 
 
 def test_seeded_and_deterministic():
@@ -13,8 +13,8 @@ def test_seeded_and_deterministic():
     assert not np.array_equal(a.hh[:10], c.hh[:10])
 
 
-def test_config1_and_reduced_humanoid_counts():
-    s1 = scene_for_config(1)
+def test_tiny_and_reduced_humanoid_counts():
+    s1 = scene_for_workload("tiny")
     assert abs(s1.n_leaves - 20_000) <= 0.02 * 20_000
     assert s1.hh.shape == (s1.n_leaves, 3, 16) and s1.wsig.shape == (s1.n_leaves, 8)
     assert s1.basis.shape == (30, 8) and s1.gamma.shape == (30,)
@@ -35,4 +35,4 @@ def test_ring_cameras_look_at_blob():
         fwd = c.c2w[:, 2].astype(np.float64)
         v = ctr - eye
         assert np.dot(v / np.linalg.norm(v), fwd) > 0.999
-    assert set(CONFIGS) == {1, 2, 3, 4, 5}
+    assert set(WORKLOADS) == {"tiny", "forward", "train", "mixed", "multi"}

@@ -17,10 +17,10 @@ from typing import Dict, List, Optional, Tuple
 
 import numpy as np
 
-__all__ = ["Scene", "Camera", "Ellipsoid", "CONFIGS", "make_scene", "make_scene_per_point", "make_payload",
-           "scene_for_config",
+__all__ = ["Scene", "Camera", "Ellipsoid", "WORKLOADS", "make_scene", "make_scene_per_point", "make_payload",
+           "scene_for_workload",
            "look_at", "ring_cameras", "orbit_camera", "random_rays", "special_rays", "stereo_cameras",
-           "config5_instances", "random_rotation", "humanoid_ellipsoids", "random_ellipsoids",
+           "multi_instances", "random_rotation", "humanoid_ellipsoids", "random_ellipsoids",
            "occupancy_from_ellipsoids", "default_gamma"]
 
 
@@ -232,19 +232,21 @@ def make_scene_per_point(depth: int, target_leaves: int, kind: str = "human", T:
                  wgam, basis_g)
 
 
-# The five workloads (depth, target leaves, kind, K, C, T, seed).
-CONFIGS = {
-    1: dict(name="tiny", depth=6, target=20_000, kind="random", K=16, C=8, T=30, seed=1),
-    2: dict(name="forward", depth=9, target=2_000_000, kind="human", K=16, C=8, T=300, seed=2),
-    3: dict(name="train", depth=8, target=500_000, kind="human", K=16, C=8, T=300, seed=3),
-    4: dict(name="mixed", depth=10, target=8_000_000, kind="human", K=16, C=8, T=300, seed=4),
-    5: dict(name="multi", depth=9, target=2_000_000, kind="human", K=16, C=8, T=300, seed=50),
+# The five workloads by name (depth, target leaves, kind, K, C, T, seed): tiny (depth 6, ~20k random
+# leaves), forward (depth-9 humanoid, ~2M leaves), train (depth 8, ~500k), mixed (depth 10, ~8M) and
+# multi (depth-9 primitives placed four times).
+WORKLOADS = {
+    "tiny": dict(depth=6, target=20_000, kind="random", K=16, C=8, T=30, seed=1),
+    "forward": dict(depth=9, target=2_000_000, kind="human", K=16, C=8, T=300, seed=2),
+    "train": dict(depth=8, target=500_000, kind="human", K=16, C=8, T=300, seed=3),
+    "mixed": dict(depth=10, target=8_000_000, kind="human", K=16, C=8, T=300, seed=4),
+    "multi": dict(depth=9, target=2_000_000, kind="human", K=16, C=8, T=300, seed=50),
 }
 
 
-def scene_for_config(cfg: int, depth: Optional[int] = None, target: Optional[int] = None,
-                     seed: Optional[int] = None) -> Scene:
-    c = CONFIGS[cfg]
+def scene_for_workload(name: str, depth: Optional[int] = None, target: Optional[int] = None,
+                       seed: Optional[int] = None) -> Scene:
+    c = WORKLOADS[name]
     d = c["depth"] if depth is None else depth
     if target is None:
         target = c["target"] if depth is None else max(64, int(c["target"] * 8.0 ** (d - c["depth"])))
@@ -373,7 +375,7 @@ def special_rays(G: int):
     return np.asarray(o, np.float32), np.asarray(d, np.float32)
 
 
-def config5_instances(G: int, n: int, seed: int):
+def multi_instances(G: int, n: int, seed: int):
     """Seeded placements for n trees: rotation about z ~ U[0,2pi), scale ~ U[0.5,2],
     standing on the ground plane z = 0 around the origin, time offset ~ U[0,150], looping."""
     rng = np.random.default_rng(seed)
