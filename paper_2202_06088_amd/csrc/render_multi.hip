@@ -14,9 +14,10 @@
 // float32 relative accuracy.
 //
 // Per lane and instance, the ray setup, walk state and current segment stay
-// in registers (the HH basis is recomputed at each segment fetch); with 4
-// instances that needs the accumulation registers too, so the kernel runs one
-// wavefront per SIMD. Work distribution is that of render.hip: a cull pass
+// in registers (the HH basis is recomputed at each segment fetch). Up to 3
+// instances the kernel runs two wavefronts per SIMD: at 256 registers some of
+// that state spills, but the second wavefront hides more memory latency than
+// the spills cost. With 4 instances it runs one. Work distribution is that of render.hip: a cull pass
 // (here: may the ray hit any instance) lists the candidate rays per XCD
 // part, and persistent wavefronts take 64-ray chunks of the lists.
 #include <hip/hip_runtime.h>
@@ -88,7 +89,7 @@ struct AnyTreeHit {
 };
 
 template <int L, int DT>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 8))) void render_multi_kernel(
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(L <= 3 ? 2 : 1, 8))) void render_multi_kernel(
     MultiArgs ma, RayArgs ra, float t_stop, RenderOut out) {
     if (no_candidates(ra)) return;
     __shared__ int4 s_nodes[L][kLdsNodesMulti];

@@ -41,7 +41,9 @@ def check(gpu, ref, tol=1e-4, label=""):
 
 
 @pytest.mark.parametrize("layout", [_lib.LAYOUT_LEAF_ROWS, _lib.LAYOUT_VEC_SOA])
-def test_backward_tiny_scalar_time(layout):
+@pytest.mark.parametrize("traced", [False, True])
+def test_backward_tiny_scalar_time(layout, traced):
+    """The tiny workload without early stop, both payload layouts, plain and traced pair."""
     sc = scene_for_workload("tiny")
     tree = upload(sc, layout=layout)
     cam = tiny_camera(sc)
@@ -50,10 +52,10 @@ def test_backward_tiny_scalar_time(layout):
     gC = rng.normal(size=(o.shape[0], 3)).astype(np.float32)
     gA = rng.normal(size=o.shape[0]).astype(np.float32)
     for t in (4.0, 7.25):
-        announce(f"config-1 backward t={t} layout={layout}")
+        announce(f"tiny backward t={t} layout={layout} traced={traced}")
         ref = oracle_render(sc, o, d, None, t, 0.0, g_rgb=gC, g_alpha=gA)
-        gpu = run_backward(tree, o, d, None, t, 0.0, gC, gA, image_width=64)
-        check(gpu, ref, label=f"tiny_scene t={t}")
+        gpu = run_backward(tree, o, d, None, t, 0.0, gC, gA, image_width=64, traced=traced)
+        check(gpu, ref, label=f"tiny t={t} traced={traced}")
 
 
 @pytest.mark.parametrize("records", ["0", "777", None])

@@ -67,7 +67,7 @@ def test_render_tiny_fp32(tiny_scene, tiny_tree, t_stop):
     """Tiny VOctree: depth 6, ~20k leaves, 64x64 pinhole view, one seeded frame."""
     cam = tiny_camera(tiny_scene)
     t = float(np.random.default_rng(12).integers(0, tiny_scene.T))
-    announce(f"config-1 render t_stop={t_stop} t={t}")
+    announce(f"tiny render t_stop={t_stop} t={t}")
     o, d = OC.pinhole_rays(64, 64, cam.intr(), cam.c2w)
     go, gd = ops.pinhole_rays(cam_struct(cam))
     assert np.array_equal(go.cpu().numpy(), o) and np.array_equal(gd.cpu().numpy(), d)
