@@ -79,7 +79,7 @@ _SIGNATURES = {
     "neuvv_pinhole_rays": [ctypes.POINTER(neuvv_camera), _I64, _P, _P, _P, _P],
     "neuvv_eval_hh": [_I32, _I64, _P, _P, _P, _P],
 }
-EXPORTS = list(_SIGNATURES) + ["neuvv_last_error", "neuvv_version"]
+EXPORTS = list(_SIGNATURES) + ["neuvv_last_error", "neuvv_version", "neuvv_trace_bytes"]
 
 _lib: Optional[ctypes.CDLL] = None
 

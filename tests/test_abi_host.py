@@ -24,7 +24,7 @@ def lib():
 def declared_functions():
     src = open(os.path.join(ROOT, "include", "neuvv.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(neuvv_\w+)\s*\(", src, flags=re.M)))
+    return sorted(set(re.findall(r"^\s*(?:int64_t|int32_t|int|const char\*)\s+(neuvv_\w+)\s*\(", src, flags=re.M)))
 
 
 def test_every_declared_symbol_is_exported(lib):
