@@ -11,7 +11,10 @@
 // Work distribution, traversal and compositing are those of render.hip. The
 // interpolated basis rows are common to all rays when the time is one scalar
 // and are then staged once per block in LDS; with a time per ray they are
-// read per sample from the basis tables, which stay in cache.
+// read per sample from the basis tables, which stay in cache. A traced
+// forward also records every sample, with the three dz/dgamma its colour
+// logits need, so that the adjoint of the same call replays the samples
+// without walking the tree or reading the payload.
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -154,9 +157,10 @@ constexpr int kPPTraceInt4 = 4;
 // logits x and y, colours, dz/dgamma; linked in ray order) for the adjoint of
 // the same call, as in render.hip: entries of one iteration at consecutive
 // slots in lane order, a sample's entry stored one sample later (when the
-// slot it links to is known) right after that sample's payload loads, the
-// last one when the ray finishes; a ray whose samples do not all fit gets
-// head -1. The room in samples is half the trace's room in 32-byte entries.
+// slot it links to is known) right after the next sample's payload loads,
+// the last one when the ray finishes; a ray whose samples do not all fit
+// gets head -1. The room in samples is half the trace's room in 32-byte
+// entries.
 template <int DT, bool IDENT, bool TRACE>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) void render_pp_fwd_kernel(
     TreeArgs tr, InstArgs in, RayArgs ra, float t_stop, RenderOut out) {
