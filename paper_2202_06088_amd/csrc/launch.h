@@ -54,7 +54,9 @@ struct BackwardIO {
 struct RecordArgs {
     int32_t* head;                 // [n_leaves] first record of the leaf's list, -1: none
     int4* rec;                     // [cap][2]: {dL/dz_r, dL/dz_g, dL/dz_b, dL/dx} (float bits),
-                                   //           {next record of the same leaf (-1: end), ray, 0, 0}
+                                   //           {next record of the same leaf (-1: end), ray, 0, 0};
+                                   // K = 16, C = 8 form with one time for every ray: {next, ray
+                                   // direction (world, float bits)} instead
     unsigned long long* counter;   // records handed out so far, one counter per XCD part of the room
     unsigned long long* leaf_cursor;   // second pass: leaves handed out so far
     int64_t cap;

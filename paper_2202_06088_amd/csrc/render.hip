@@ -317,6 +317,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(REPLAY ?
     float g0 = 0.0f, g1 = 0.0f, g2 = 0.0f, ga = 0.0f;
     int ns = 0, ns_fwd = 0;
     int tnext = -1;        // replay: the ray's next sample
+    float dw0 = 0.0f, dw1 = 0.0f, dw2 = 0.0f;   // the ray's direction (world), for its records
     // records: the wavefront fills blocks of kRecBlock consecutive records,
     // taken from its XCD's part of the room; [wrec, wend) is what is left of
     // the current block (wave-uniform)
@@ -353,6 +354,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(REPLAY ?
                 const float d[3] = {ra.d[3 * ray], ra.d[3 * ray + 1], ra.d[3 * ray + 2]};
                 const float t = per_ray_t ? ra.t[ray] : ra.t_scalar;
                 ray_setup<IDENT>(tr, in, o, d, t, rs);
+                dw0 = d[0];
+                dw1 = d[1];
+                dw2 = d[2];
                 if (rs.hit) {
                     {
                         float h[K], bv[C];
@@ -479,7 +483,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(REPLAY ?
                     rec.rec[2 * (int64_t)my_rec] =
                         make_int4(__float_as_int(gz0), __float_as_int(gz1), __float_as_int(gz2), __float_as_int(gx));
                     const int nxt = atomicExch(rec.head + leaf, my_rec);
-                    rec.rec[2 * (int64_t)my_rec + 1] = make_int4(nxt, (int)ray, 0, 0);
+                    // one time for every ray: the record carries the ray's direction
+                    // (all the reduction needs of the ray), else the ray's index
+                    rec.rec[2 * (int64_t)my_rec + 1] =
+                        per_ray_t ? make_int4(nxt, (int)ray, 0, 0)
+                                  : make_int4(nxt, __float_as_int(dw0), __float_as_int(dw1), __float_as_int(dw2));
                 }
             }
         }
@@ -616,8 +624,17 @@ __global__ __launch_bounds__(kBlock) void reduce_records_kernel(TreeArgs tr, Ins
             }
             const float4 g = make_float4(__int_as_float(ra0.x), __int_as_float(ra0.y), __int_as_float(ra0.z),
                                          __int_as_float(ra0.w));
-            const f3v dv = load3(ra.d + 3 * ray);
-            const float d[3] = {dv.x, dv.y, dv.z};
+            float d[3];
+            if constexpr (COMMON_T) {
+                d[0] = __int_as_float(ra1.y);
+                d[1] = __int_as_float(ra1.z);
+                d[2] = __int_as_float(ra1.w);
+            } else {
+                const f3v dv = load3(ra.d + 3 * ray);
+                d[0] = dv.x;
+                d[1] = dv.y;
+                d[2] = dv.z;
+            }
             RaySetup rs;
             float dmax;
             ray_direction<IDENT>(in, d, rs, dmax);
