@@ -11,7 +11,7 @@ import torch
 from gpu_util import DEV, announce, cam_struct, tiny_camera, inst_pair, oracle_render, rel_err, tdev, upload
 from oracle import core as OC
 from paper_2202_06088_amd import _lib, autograd, ops
-from workloads import make_scene, ring_cameras, scene_for_workload
+from workloads import make_scene, orbit_camera, ring_cameras, scene_for_workload
 
 pytestmark = pytest.mark.gpu
 
@@ -262,3 +262,31 @@ def test_autograd_function_matches_direct_calls(layout):
     gp, ga = ops.compose_backward(P.detach(), A.detach(), D, torch.full((500, 3), 2.0, device=DEV),
                                   torch.ones(500, device=DEV))
     assert torch.allclose(P.grad, gp) and torch.allclose(A.grad, ga)
+
+
+def test_trace_buffer_reused_across_calls():
+    """One trace buffer serves two traced steps in a row (a denser view first, then another view and
+    time): what the first call left in it (heads of rays the second call misses, entries beyond the
+    second call's samples) must not reach the second adjoint."""
+    sc = scene_for_workload("tiny")
+    tree = upload(sc)
+    cam_a = orbit_camera(sc.leaf_ijk.mean(0) + 0.5, 1.6 * sc.G, 0.3, 0.2, 64, 64, 40.0)
+    cam_b = tiny_camera(sc)
+    n = 64 * 64
+    trace = ops.Trace(n, 2 * n, DEV)
+    rng = np.random.default_rng(45)
+    for cam, t in ((cam_a, 1.5), (cam_b, 5.0)):
+        o, d = OC.pinhole_rays(64, 64, cam.intr(), cam.c2w)
+        oo, dd = tdev(o), tdev(d)
+        gC = rng.normal(size=(n, 3)).astype(np.float32)
+        fwd = oracle_render(sc, o, d, None, t, 1e-4)
+        gC[fwd["margin"][:, 1] < 1e-3] = 0.0
+        announce(f"trace reuse t={t}")
+        rgb, alpha, depth, nsamp = ops.render(tree, oo, dd, t, None, 1e-4, 64, trace=trace)
+        gl, gb = ops.render_backward(tree, oo, dd, rgb, alpha, nsamp, tdev(gC), None, t, None, 1e-4, 64,
+                                     trace=trace)
+        torch.cuda.synchronize()
+        hh, ws = tree.unpack_grad(gl)
+        ref = oracle_render(sc, o, d, None, t, 1e-4, g_rgb=gC)
+        assert int(nsamp.sum()) > 1000
+        check((hh.cpu().numpy(), ws.cpu().numpy(), gb.cpu().numpy()), ref, label=f"trace reuse t={t}")
