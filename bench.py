@@ -211,29 +211,44 @@ def main():
     # leaf its gradient row, read and written once, and its density and hyperangle weights (the
     # basis gradients are summed per leaf); per ray nsamp, per hit ray its inputs
     per_leaf = touched * (2 * 4 * values + (tree.C + tree.Cg) * elem)
+    # the method's bytes (what Eq. 8 and its adjoint must move whatever the implementation): the
+    # forward reads every sample's leaf payload once and every ray's input and output; the adjoint
+    # needs every sample's payload again (its colour and density), each touched gradient row once
+    # and the rays' inputs. The trace of the traced step is state this implementation keeps
+    # between the passes (written by the forward, read by the adjoint in place of the payload):
+    # reported beside, not counted.
     fwd_bytes = total_samples * payload_b + n * FWD_RAY_IO_B
     bwd_bytes = total_samples * payload_b + per_leaf + n * BWD_RAY_NSAMP_B + hit * BWD_HIT_IO_B
-    if traced:
-        # the trace is state kept between the passes: written per sample by the forward, read in
-        # place of the payload by the adjoint
-        tb = TRACE_SAMPLE_B[tree.Cg]
-        fwd_bytes += total_samples * tb
-        bwd_bytes += total_samples * (tb - payload_b)
+    trace_b = total_samples * TRACE_SAMPLE_B[tree.Cg] if traced else 0
     log(f"fwd {fwd_ms:.3f} ms, bwd {bwd_ms:.3f} ms per launch; step {ms_step:.3f} ms; "
         f"{total_samples} samples, {hit} hit rays")
     kern = {"render_fwd": (fwd_ms, fwd_bytes), "render_bwd": (bwd_ms, bwd_bytes)}
     dom = max(kern, key=lambda k: kern[k][0])
-    dms, dbytes = kern[dom]
-    achieved = dbytes / (dms * 1e-3) / 1e9
     workload = "forward_ring_d9_2M_8x1080p" + ("" if args.form == "global" else "_per_point")
-    roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(f"{dom}/{args.layout}/{args.dtype}{'/traced' if traced else ''}", workload),
-            "algorithmic_bytes_per_launch": dbytes, "launch_ms": round(dms, 4)}
+    tkey = f"/{args.layout}/{args.dtype}{'/traced' if traced else ''}"
+
+    def roof_of(k):
+        ms, b = kern[k]
+        traffic = measured_traffic(k + tkey, workload)
+        r = {"kernel": k, "bound": "hbm", "achieved": round(b / (ms * 1e-3) / 1e9, 1), "peak": PEAK_HBM_GBS,
+             "unit": "GB/s", "frac": round(b / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4), "traffic": traffic,
+             "algorithmic_bytes_per_launch": b, "launch_ms": round(ms, 4),
+             "trace_bytes_per_launch": trace_b}
+        if traffic:
+            # HBM bytes the counters saw (FETCH_SIZE + WRITE_SIZE, calibrated) over the same duration
+            r["dram_gbs"] = round(traffic / (ms * 1e-3) / 1e9, 1)
+            r["dram_frac"] = round(traffic / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)
+        return r
+
+    roof = roof_of(dom)
     other = [k for k in kern if k != dom][0]
-    roof_other = {"kernel": other, "achieved": round(kern[other][1] / (kern[other][0] * 1e-3) / 1e9, 1),
-                  "launch_ms": round(kern[other][0], 4), "algorithmic_bytes_per_launch": kern[other][1],
-                  "traffic": measured_traffic(f"{other}/{args.layout}/{args.dtype}{'/traced' if traced else ''}",
-                                              workload)}
+    roof_other = roof_of(other)
+    # samples per ray over the rays that composited any (bins: 1, 2, 3-4, 5-8, ..., 129+)
+    hs = ns[ns > 0]
+    edges = [1, 2, 3, 5, 9, 17, 33, 65, 129, 1 << 30]
+    hist = {f"{a}-{b - 1}" if b - 1 > a else f"{a}": int(((hs >= a) & (hs < b)).sum())
+            for a, b in zip(edges[:-1], edges[1:])}
+    hist = {k.replace(f"-{(1 << 30) - 1}", "+"): v for k, v in hist.items() if v}
 
     result = {
         "metric": METRIC, "value": round(n / (ms_step * 1e-3) / 1e6, 2), "unit": "Mrays/s", "n_gpus": 1,
@@ -245,7 +260,10 @@ def main():
                    "step": "render fwd + adjoint" + (" (traced)" if traced else ""), "layout": args.layout},
         "fwd_mrays_s": round(n / (fwd_ms * 1e-3) / 1e6, 2),
         "samples_per_step": total_samples, "hit_rays": hit, "leaves_touched": touched,
+        "hit_fraction": round(hit / n, 5), "samples_per_hit_ray": round(total_samples / max(hit, 1), 3),
+        "samples_per_ray_histogram": hist,
         "roofline": roof, "roofline_other_kernel": roof_other,
+        "stream_ceiling": stream_ceiling(stream),
     }
 
     # the legs below compare against a plain forward (neuvv_render, no trace written)
@@ -554,7 +572,7 @@ def cpu_leg(sc, cams, t_frame, t_stop, rgb_gpu, g_rgb, grads, tree, budget_s):
     threads = OC.default_threads()
     OC.build(force=False)
 
-    def run(stride, offset=0):
+    def run(stride, offset=0, threads=threads):
         g_idx = np.arange(offset, n_all, stride, dtype=np.int64)
         cam_of = g_idx // n_cam
         o = np.zeros((g_idx.size, 3), np.float32)
@@ -582,11 +600,18 @@ def cpu_leg(sc, cams, t_frame, t_stop, rgb_gpu, g_rgb, grads, tree, budget_s):
     mse = float(np.mean(err ** 2)) if err.size else 0.0
     psnr = 10 * math.log10(1.0 / mse) if mse > 0 else float("inf")
     log(f"oracle {len(g_idx)} rays fwd+grad in {dt:.2f}s; GPU max-abs {err.max(initial=0):.3e} PSNR {psnr:.1f} dB")
+    # one core: the same oracle on a smaller strided sample (~a third of the budget)
+    stride1 = max(1, int(n_all / max(rate / threads * budget_s / 3, 1.0)))
+    g1, _, dt1 = run(stride1, 2, threads=1)
+    log(f"oracle on 1 thread: {len(g1)} rays in {dt1:.2f}s")
     return {
         "cpu_baseline": {"value": round(len(g_idx) / dt / 1e6, 5), "unit": "Mrays/s", "cores": threads,
                          "kind": "oracle",
                          "sample": (f"every {stride}th ray of" if stride > 1 else "all rays of") +
-                                   f" the 8-camera ring ({len(g_idx)} rays), FP64 forward + gradient"},
+                                   f" the 8-camera ring ({len(g_idx)} rays), FP64 forward + gradient",
+                         "one_core_value": round(len(g1) / dt1 / 1e6, 5),
+                         "one_core_sample": f"every {stride1}th ray of the ring ({len(g1)} rays)",
+                         "host": OC.host_description()},
         "psnr_vs_fp64_db": None if math.isinf(psnr) else round(psnr, 2),
         "maxabs_vs_fp64": float(f"{err.max(initial=0):.3e}"),
         "fp64_compare_rays": int(ok.sum()),
@@ -596,6 +621,32 @@ def cpu_leg(sc, cams, t_frame, t_stop, rgb_gpu, g_rgb, grads, tree, budget_s):
 def torch_index(idx, device):
     import torch
     return torch.from_numpy(idx).to(device)
+
+
+def stream_ceiling(stream, nbytes=1 << 30, reps=10):
+    """Measured streaming rates on this GPU beside the 8 TB/s datasheet peak: a 1 GiB
+    device-to-device copy (read + write bytes) and a read-only pass (a sum over 1 GiB), HIP
+    events on the launch stream."""
+    import torch
+    a = torch.ones(nbytes // 4, device="cuda")
+    b = torch.empty_like(a)
+    r = torch.empty((), device="cuda")
+    out = {}
+    for name, fn, moved in (("copy_gbs", lambda: b.copy_(a), 2 * nbytes),
+                            ("read_gbs", lambda: torch.sum(a, out=r), nbytes)):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        out[name] = round(moved * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
+    del a, b
+    torch.cuda.empty_cache()
+    log(f"stream ceiling: copy {out['copy_gbs']} GB/s, read {out['read_gbs']} GB/s")
+    return out
 
 
 def calibrate_copy(nbytes=1 << 30):

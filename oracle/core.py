@@ -65,7 +65,28 @@ def _c(a, dt):
 
 
 def default_threads() -> int:
-    return max(1, min(len(os.sched_getaffinity(0)), 16))
+    """Every CPU this process may use: its affinity set, bounded by OMP_NUM_THREADS when the
+    environment sets it (a GPU host may allot each GPU a share of its cores that way)."""
+    n = len(os.sched_getaffinity(0))
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    return max(1, n)
+
+
+def host_description() -> dict:
+    """CPU model, online CPUs, the affinity set and the OpenMP limit of this host."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(), "affinity_cpus": len(os.sched_getaffinity(0)),
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
 
 
 def hh_basis_c(K: int, dirs: np.ndarray, gam: np.ndarray) -> np.ndarray:

@@ -36,10 +36,19 @@ def round_storage(x: np.ndarray, dtype: int) -> np.ndarray:
     if dtype == _lib.F32:
         return x.astype(np.float64)
     if dtype == _lib.F16:
-        return x.astype(np.float16).astype(np.float64)
+        with np.errstate(over="ignore"):   # beyond the largest float16: +-inf, as the format rounds
+            return x.astype(np.float16).astype(np.float64)
+    # bfloat16 keeps the top 16 bits of the float32 pattern: add half an ulp of
+    # the kept part minus one, plus the kept part's lowest bit (ties to even),
+    # then truncate. A carry out of the mantissa moves the exponent, which is
+    # the correct rounding (up to +inf past the largest finite value). NaN stays
+    # NaN (the addition could carry a NaN pattern into the sign bit).
     u = x.view(np.uint32).astype(np.uint64)
     u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
-    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+    with np.errstate(invalid="ignore"):
+        out = u.astype(np.uint32).view(np.float32).astype(np.float64)
+    out[np.isnan(x)] = np.nan
+    return out
 
 
 def oracle_render(scene, o, d, t=None, t_scalar=0.0, t_stop=1e-4, inst=None, dtype=_lib.F32, g_rgb=None,

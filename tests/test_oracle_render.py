@@ -261,6 +261,32 @@ def test_pinhole_rays(oracle_lib):
     assert np.array_equal(d2, d[pix]) and np.array_equal(o2, o[pix])
 
 
+def test_pinhole_focal_scaling(oracle_lib):
+    """Corner and edge pixels of a camera with fx != fy and an off-centre principal
+    point: in the camera frame the ray of pixel (u, v) makes the angle
+    atan((u + 1/2 - cx) / fx) with the optical axis in the x-z plane and
+    atan((v + 1/2 - cy) / fy) in the y-z plane (OpenCV axes). Swapping fx and fy,
+    dropping the half-pixel offset or the division by the focal length fails."""
+    W, H = 40, 24
+    fx, fy, cx, cy = 30.0, 55.0, 21.0, 11.5
+    ang = 0.4
+    R = np.array([[np.cos(ang), 0.0, np.sin(ang)], [0.0, 1.0, 0.0], [-np.sin(ang), 0.0, np.cos(ang)]])
+    c2w = np.concatenate([R, np.array([[1.0], [-2.0], [3.0]])], axis=1).astype(np.float32)
+    uv = [(0, 0), (W - 1, 0), (0, H - 1), (W - 1, H - 1), (0, H // 2), (W - 1, H // 2), (W // 2, 0),
+          (W // 2, H - 1)]
+    pix = np.array([v * W + u for u, v in uv], np.int32)
+    o, d = oracle_lib.pinhole_rays(W, H, (fx, fy, cx, cy), c2w, pix)
+    dc = d.astype(np.float64) @ c2w[:, :3].astype(np.float64)    # camera frame: R^T d
+    for i, (u, v) in enumerate(uv):
+        ax = math.atan2(dc[i, 0], dc[i, 2])
+        ay = math.atan2(dc[i, 1], dc[i, 2])
+        assert abs(ax - math.atan((u + 0.5 - cx) / fx)) < 2e-7, (u, v)
+        assert abs(ay - math.atan((v + 0.5 - cy) / fy)) < 2e-7, (u, v)
+        # angle from the optical axis
+        full = math.atan(math.hypot((u + 0.5 - cx) / fx, (v + 0.5 - cy) / fy))
+        assert abs(math.acos(min(1.0, dc[i, 2] / np.linalg.norm(dc[i]))) - full) < 2e-6, (u, v)
+
+
 # ---------------------------------------------------------------------------
 # per-point hyperangle (Eq. 6): gamma = pi * sigmoid(sum_c wgam_c B_c(t))
 
