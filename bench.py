@@ -633,7 +633,7 @@ def stream_ceiling(stream, nbytes=1 << 30, reps=10):
     r = torch.empty((), device="cuda")
     out = {}
     for name, fn, moved in (("copy_gbs", lambda: b.copy_(a), 2 * nbytes),
-                            ("read_gbs", lambda: torch.sum(a, out=r), nbytes)):
+                            ("read_gbs", lambda: torch.sum(a, 0, out=r), nbytes)):
         fn()
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
