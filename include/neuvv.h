@@ -60,6 +60,12 @@ typedef enum { NEUVV_LAYOUT_VEC_SOA = 0, NEUVV_LAYOUT_LEAF_ROWS = 1 } neuvv_layo
    always float32; 16-bit storage is converted with round-to-nearest-even. */
 typedef enum { NEUVV_F32 = 0, NEUVV_F16 = 1, NEUVV_BF16 = 2 } neuvv_dtype;
 
+/* Density activation of Eq. 5 (Sec. 4.2): sigma = act(sum_c wsig_c b_c).
+   SOFTPLUS (log(1 + e^x), derivative sigmoid(x)) is the default; RELU is
+   max(x, 0) as Eq. 5 prints it, with derivative 1 for x > 0 and 0 otherwise
+   (a leaf whose logit is <= 0 is transparent and takes no gradient). */
+typedef enum { NEUVV_DENSITY_SOFTPLUS = 0, NEUVV_DENSITY_RELU = 1 } neuvv_density;
+
 /*
  * Leaf payload layout. A leaf has R_hh = 3K colour coefficients, value
  * r = ch*K + k for colour channel ch and HH function k (Eq. 4), R_sig = C
@@ -113,6 +119,7 @@ typedef struct {
                              leaf's own); first frame t_d (the edit is active at local times
                              tau >= t_d, +inf: never); a word used by neuvv_paint; 2 unused. K = 16,
                              C = 8 form only; neuvv_render_backward rejects trees with edits */
+    int32_t density;      /* neuvv_density: the activation of Eq. 5 (0 = softplus) */
 } neuvv_tree;
 
 /* Placement and re-timing of one tree instance (Eq. 13). A world point x is

@@ -47,7 +47,8 @@ def _load():
         lib.oracle_render.argtypes = [ctypes.c_int, ctypes.c_int64, P, ctypes.c_int, ctypes.c_int, P, P,
                                       ctypes.c_int, P, P, ctypes.c_int, P, P, P, P, P, ctypes.c_int64, P, P, P,
                                       ctypes.c_double, ctypes.c_double, P, P,
-                                      P, P, P, P, P, P, P, P, P, P, P, ctypes.c_int, P, P, ctypes.c_int]
+                                      P, P, P, P, P, P, P, P, P, P, P, ctypes.c_int, P, P, ctypes.c_int,
+                                      ctypes.c_int]
         lib.oracle_pinhole_rays.restype = None
         lib.oracle_pinhole_rays.argtypes = [ctypes.c_int, ctypes.c_int, P, P, ctypes.c_int64, P, P, P]
         lib.oracle_hh_basis.restype = None
@@ -123,7 +124,7 @@ class Instance:
 def render(depth: int, leaf_ijk, hh, wsig, basis, gamma, ray_o, ray_d, ray_t=None, t_scalar=0.0,
            t_stop=1e-4, inst: Optional[Instance] = None, g_rgb=None, g_alpha=None,
            want_grad_basis=True, threads: Optional[int] = None, wgam=None, basis_g=None, edit=None,
-           segments: bool = False):
+           segments: bool = False, density: str = "softplus"):
     """FP64 render of float32 rays through a tree given by its leaf cells.
 
     leaf_ijk [N,3] int; hh [N,3,K]; wsig [N,C]; basis [T,C]; gamma [T] (all as
@@ -142,7 +143,11 @@ def render(depth: int, leaf_ijk, hh, wsig, basis, gamma, ray_o, ray_d, ray_t=Non
     edit [N,5] (target rgb, target density or < 0 to keep it, first frame t_d)
     replaces a leaf's colour (and density) at local times tau >= t_d, the
     appearance edit of Sec. 5.2; no gradient is taken with edits.
+    density: the activation of Eq. 5, "softplus" (the workloads' reading) or "relu" (as Eq. 5
+    prints it; derivative 0 at a logit of exactly 0).
     """
+    if density not in ("softplus", "relu"):
+        raise ValueError(f"unknown density activation {density!r}")
     lib = _load()
     leaf_ijk = _c(leaf_ijk, np.int32).reshape(-1, 3)
     hh = _c(hh, np.float64)
@@ -191,7 +196,7 @@ def render(depth: int, leaf_ijk, hh, wsig, basis, gamma, ray_o, ray_d, ray_t=Non
                            _p(out["nsamp"]), _p(out["tfinal"]), _p(out["margin"]),
                            _p(out.get("grad_hh")), _p(out.get("grad_wsig")), _p(out.get("grad_basis")),
                            _p(edit), _p(out["last_leaf"]), int(cap), _p(out.get("seg")), _p(out.get("len")),
-                           int(threads or default_threads()))
+                           1 if density == "relu" else 0, int(threads or default_threads()))
     if rc != 0:
         raise RuntimeError(f"oracle_render failed with code {rc}")
     return out

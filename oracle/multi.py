@@ -29,11 +29,12 @@ from . import core as OC
 
 
 def render_multi(scenes: Sequence, insts: Sequence[Optional[OC.Instance]], ray_o, ray_d, t_scalar: float,
-                 t_stop: float, dtypes_round=None):
+                 t_stop: float, dtypes_round=None, density: str = "softplus"):
     """scenes: objects with depth, leaf_ijk, hh, wsig, basis, gamma (and optionally the rounded payload via
     dtypes_round: a function scene -> (hh, wsig)); returns rgb [n,3], alpha, depth, nsamp, margin [n]
     (smallest relative distance of T to t_stop at a stop test) and min_piece [n] (shortest composited
-    piece, in leaf units of the finest instance)."""
+    piece, in leaf units of the finest instance). density: the activation of Eq. 5 ("softplus" or
+    "relu")."""
     o = np.asarray(ray_o, np.float32)
     d = np.asarray(ray_d, np.float32)
     n = o.shape[0]
@@ -41,7 +42,7 @@ def render_multi(scenes: Sequence, insts: Sequence[Optional[OC.Instance]], ray_o
     for sc, inst in zip(scenes, insts):
         hh, ws = (sc.hh, sc.wsig) if dtypes_round is None else dtypes_round(sc)
         r = OC.render(sc.depth, sc.leaf_ijk, hh, ws, sc.basis, sc.gamma, o, d, None, t_scalar, 0.0, inst,
-                      segments=True)
+                      segments=True, density=density)
         per.append(r)
     dw = np.linalg.norm(d.astype(np.float64), axis=1)
     out = dict(rgb=np.zeros((n, 3)), alpha=np.zeros(n), depth=np.full(n, np.inf), nsamp=np.zeros(n, np.int32),

@@ -20,7 +20,8 @@
  *      direction and gamma = lerp of the hyperangle table at tau (Eq. 2-4),
  *      and b = lerp of the density basis rows at tau (Eq. 5);
  *   4. per occupied segment, in order of increasing u:
- *        sigma = softplus(sum_c wsig_c b_c)          (Eq. 5, softplus reading)
+ *        sigma = softplus(sum_c wsig_c b_c)          (Eq. 5, softplus reading;
+ *                or relu(...), the activation Eq. 5 prints, with density_act = 1)
  *        c_ch  = sigmoid(sum_k hh_ch,k h_k)            (Eq. 4 + sigmoid)
  *        delta = segment length in leaf units
  *        alpha_i = 1 - exp(-sigma delta), w = T alpha_i, T *= exp(-sigma delta)
@@ -163,6 +164,8 @@ static int64_t hs_find(const hashset* h, int64_t i, int64_t j, int64_t k) {
 /* ------------------------------------------------------------------ */
 
 static double softplus(double x) { return (x > 0 ? x : 0.0) + log1p(exp(-fabs(x))); }
+/* density activation of Eq. 5 and its derivative: 0 softplus, 1 relu (derivative 0 at x = 0) */
+static double density_of(double x, int act) { return act ? (x > 0 ? x : 0.0) : softplus(x); }
 static double sigmoid(double x) { return 1.0 / (1.0 + exp(-x)); }
 
 typedef struct { int64_t leaf; double delta, smid, x, sig, z[3], c[3], Tin, alpha, yg, gam, ua, ub; } sample_t;
@@ -200,6 +203,7 @@ int oracle_render(int depth, int64_t n_leaves, const int32_t* leaf_ijk,
                   int seg_cap, double* seg_out /* NULL or [n][seg_cap][6]: every sample's ray interval
                                                    [u_in, u_out), density (per leaf unit), colour */,
                   double* len_out /* NULL or [n]: leaf units per unit of the ray parameter */,
+                  int density_act /* 0: sigma = softplus(x), 1: sigma = relu(x) */,
                   int n_threads) {
     if (depth < 1 || depth > 20 || K < 1 || K > 64 || C < 1 || C > 64 || T < 1) return -3;
     if (wgam && (Cg < 1 || Cg > 64 || !basis_g)) return -3;
@@ -300,7 +304,7 @@ int oracle_render(int depth, int64_t n_leaves, const int32_t* leaf_ijk,
                             s->smid = 0.5 * (u + un) * dwlen;
                             double x = 0.0;
                             for (int c = 0; c < C; ++c) x += wsig[q * C + c] * b[c];
-                            s->x = x; s->sig = softplus(x);
+                            s->x = x; s->sig = density_of(x, density_act);
                             double hs[64];
                             const double* hk = h;
                             if (wgam) {
@@ -390,7 +394,7 @@ int oracle_render(int depth, int64_t n_leaves, const int32_t* leaf_ijk,
                     }
                     /* dC/dsigma_k = delta_k (T_{k+1} c_k - sum_{i>k} w_i c_i); dA/dsigma_k = delta_k T_final */
                     double gsig = s->delta * (Tnext * gdotc - gdotsuf) + gA * s->delta * Tfin;
-                    double gx = gsig * sigmoid(s->x);
+                    double gx = gsig * (density_act ? (s->x > 0 ? 1.0 : 0.0) : sigmoid(s->x));
                     double hs[64], dhs[64];
                     const double* hk = h;
                     if (wgam) {

@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(HERE, "libneuvv.so")
 NEUVV_OK = 0
 F32, F16, BF16 = 0, 1, 2
 LAYOUT_VEC_SOA, LAYOUT_LEAF_ROWS = 0, 1
+DENSITY_SOFTPLUS, DENSITY_RELU = 0, 1
 
 
 class NeuvvError(RuntimeError):
@@ -29,7 +30,8 @@ class neuvv_tree(ctypes.Structure):
                 ("nodes", ctypes.c_void_p), ("hh", ctypes.c_void_p), ("wsig", ctypes.c_void_p),
                 ("T", ctypes.c_int32), ("box", ctypes.c_int32 * 6), ("layout", ctypes.c_int32),
                 ("basis", ctypes.c_void_p), ("gamma", ctypes.c_void_p), ("Cg", ctypes.c_int32),
-                ("wgam", ctypes.c_void_p), ("basis_g", ctypes.c_void_p), ("edit", ctypes.c_void_p)]
+                ("wgam", ctypes.c_void_p), ("basis_g", ctypes.c_void_p), ("edit", ctypes.c_void_p),
+                ("density", ctypes.c_int32)]
 
 
 class neuvv_instance(ctypes.Structure):

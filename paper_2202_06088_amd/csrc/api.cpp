@@ -76,6 +76,8 @@ int check_tree(const neuvv_tree* t) {
         return fail(NEUVV_ERR_ARG, "tree edit rows must be 16-byte aligned");
     if (t->edit && t->Cg > 0)
         return fail(NEUVV_ERR_UNSUPPORTED, "appearance edits are compiled for the K=16 C=8 form only");
+    if (t->density != NEUVV_DENSITY_SOFTPLUS && t->density != NEUVV_DENSITY_RELU)
+        return fail(NEUVV_ERR_ARG, "unknown density activation %d", t->density);
     return NEUVV_OK;
 }
 
@@ -167,6 +169,7 @@ neuvv::TreeArgs tree_args(const neuvv_tree* t) {
         a.box_hi[i] = box_unset ? (1 << t->depth) : t->box[3 + i];
     }
     a.layout = t->layout;
+    a.relu = t->density == NEUVV_DENSITY_RELU;
     return a;
 }
 

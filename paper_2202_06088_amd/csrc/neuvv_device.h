@@ -220,6 +220,7 @@ struct TreeArgs {
     const void* wgam;    // [N] rows of Cg weights, storage dtype and layout of wsig
     const float* basis_g;   // [T][Cg] hyperangle basis
     const float4* edit;     // nullptr, or [N][2] rows {r, g, b, sigma_d}, {t_d, owner, 0, 0} (appearance edits)
+    int32_t relu;           // density activation of Eq. 5: 0 softplus, 1 ReLU
 };
 
 struct InstArgs {

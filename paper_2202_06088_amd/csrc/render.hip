@@ -203,7 +203,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
                     z1 = fmaf(wv[K + k], hk, z1);
                     z2 = fmaf(wv[2 * K + k], hk, z2);
                 }
-                float sig = softplus_f(x);
+                float sig = density_f(x, tr.relu);
                 float c0 = sigmoid_f(z0), c1 = sigmoid_f(z1), c2 = sigmoid_f(z2);
                 if constexpr (EDIT) {
                     const float4 e0 = tr.edit[2 * (int64_t)leaf], e1 = tr.edit[2 * (int64_t)leaf + 1];
@@ -434,7 +434,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(REPLAY ?
                 }
             }
             if (leaf >= 0) {
-                const float sig = softplus_f(x);
+                const float sig = density_f(x, tr.relu);
                 const float od = sig * delta;
                 float a, e;
                 absorb(od, a, e);
@@ -447,7 +447,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(REPLAY ?
                 const float gsuf = g0 * (F0 - p0) + g1 * (F1 - p1) + g2 * (F2 - p2);
                 // dL/dsigma = delta (T_{k+1} <g, c_k> - <g, rgb - rgb_<=k>) + g_a delta T_final
                 const float gsig = delta * (Tn * gdotc - gsuf) + ga * delta * Tfin;
-                gx = gsig * sigmoid_f(x);
+                gx = gsig * density_dx(x, tr.relu);
                 gz0 = g0 * wt * c0 * (1.0f - c0);
                 gz1 = g1 * wt * c1 * (1.0f - c1);
                 gz2 = g2 * wt * c2 * (1.0f - c2);

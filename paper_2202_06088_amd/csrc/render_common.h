@@ -90,6 +90,11 @@ __device__ __forceinline__ float log1p_hw(float e) {
     return u == 1.0f ? e : lg * (e * __builtin_amdgcn_rcpf(u - 1.0f));
 }
 __device__ __forceinline__ float softplus_f(float x) { return fmaxf(x, 0.0f) + log1p_hw(exp_hw(-fabsf(x))); }
+// Density activation of Eq. 5 (relu = 0: softplus, the workloads' reading;
+// relu != 0: ReLU as Eq. 5 prints it) and its derivative (0 at x <= 0 for ReLU).
+// relu is a kernel argument, so the branch is uniform.
+__device__ __forceinline__ float density_f(float x, int relu) { return relu ? fmaxf(x, 0.0f) : softplus_f(x); }
+__device__ __forceinline__ float density_dx(float x, int relu) { return relu ? (x > 0.0f ? 1.0f : 0.0f) : sigmoid_f(x); }
 // Opacity a = 1 - e^-od and transmittance factor e = e^-od of an optical
 // depth od >= 0 (Eq. 8). Below od = 1/4 the series of 1 - e^-od to the
 // seventh power (truncation below 2e-9 relative) keeps a accurate where

@@ -69,7 +69,7 @@ __device__ __forceinline__ void fetch_segment(const TreeArgs& tr, const int4* s_
     }
     sg.a = a;
     sg.b = b;
-    sg.kap = softplus_f(x) * rs.len_local;
+    sg.kap = density_f(x, tr.relu) * rs.len_local;
     sg.c0 = sigmoid_f(z0);
     sg.c1 = sigmoid_f(z1);
     sg.c2 = sigmoid_f(z2);

@@ -277,7 +277,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) 
                 dst[2] = make_int4(__float_as_int(pq0), __float_as_int(pq1), __float_as_int(pq2), 0);
             }
             pp_compute<DT>(tr, rs, Y, s_b, s_bg, p);
-            const float sig = softplus_f(p.x);
+            const float sig = density_f(p.x, tr.relu);
             const float od = sig * delta;
             float a, e_od;
             absorb(od, a, e_od);
@@ -464,7 +464,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(REPLAY ?
                 }
             }
             if (leaf >= 0) {
-                const float sig = softplus_f(x);
+                const float sig = density_f(x, tr.relu);
                 const float od = sig * delta;
                 float a, e;
                 absorb(od, a, e);
@@ -476,7 +476,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(REPLAY ?
                 const float gdotc = g0 * c0 + g1 * c1 + g2 * c2;
                 const float gsuf = g0 * (F0 - p0) + g1 * (F1 - p1) + g2 * (F2 - p2);
                 const float gsig = delta * (Tn * gdotc - gsuf) + ga * delta * Tfin;
-                gx = gsig * sigmoid_f(x);
+                gx = gsig * density_dx(x, tr.relu);
                 gz0 = g0 * wt * c0 * (1.0f - c0);
                 gz1 = g1 * wt * c1 * (1.0f - c1);
                 gz2 = g2 * wt * c2 * (1.0f - c2);

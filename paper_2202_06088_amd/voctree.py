@@ -46,11 +46,12 @@ class VOctree:
     wgam: Optional[torch.Tensor] = None     # packed hyperangle weights (storage dtype)
     basis_g: Optional[torch.Tensor] = None  # [T, Cg] float32 hyperangle basis
     edit: Optional[torch.Tensor] = None     # [N, 8] float32 appearance-edit rows (slot order), or None
+    density: int = _lib.DENSITY_SOFTPLUS    # activation of Eq. 5 (softplus, or ReLU as Eq. 5 prints it)
 
     @classmethod
     def build(cls, depth: int, leaf_ijk, hh, wsig, basis, gamma, dtype: int = _lib.F32,
               device: str = "cuda", stream=None, layout: int = _lib.LAYOUT_LEAF_ROWS, wgam=None,
-              basis_g=None) -> "VOctree":
+              basis_g=None, density: int = _lib.DENSITY_SOFTPLUS) -> "VOctree":
         """leaf_ijk [N,3]; hh [N,3,K] and wsig [N,C] float32 per input leaf; basis [T,C]; gamma [T]
         (or None with the per-point form); wgam [N,Cg] and basis_g [T,Cg] for the per-point
         hyperangle of Eq. 6."""
@@ -70,6 +71,7 @@ class VOctree:
                 torch.from_numpy(np.ascontiguousarray(basis, np.float32)).to(dev),
                 torch.from_numpy(np.ascontiguousarray(gamma, np.float32)).to(dev),
                 torch.from_numpy(slots).to(dev), tuple(int(v) for v in box), layout)
+        t.density = int(density)
         wg = None
         if wgam is not None:
             wgam = np.ascontiguousarray(wgam, np.float32)
@@ -116,6 +118,7 @@ class VOctree:
         if self.Cg > 0:
             s.wgam, s.basis_g = self.wgam.data_ptr(), self.basis_g.data_ptr()
         s.edit = None if self.edit is None else self.edit.data_ptr()
+        s.density = self.density
         return s
 
     def enable_edits(self):

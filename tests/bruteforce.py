@@ -53,9 +53,10 @@ def sigmoid(x):
     return 1.0 / (1.0 + math.exp(-x))
 
 
-def render(depth, leaf_ijk, hh, wsig, basis, gamma, o, d, t, t_stop, wgam=None, basis_g=None):
+def render(depth, leaf_ijk, hh, wsig, basis, gamma, o, d, t, t_stop, wgam=None, basis_g=None, density="softplus"):
     """Single identity-instance ray, t an exact frame index or fraction in [0, T-1].
-    With wgam/basis_g the hyperangle of each sample is pi * sigmoid(wgam . basis_g(t)) (Eq. 6)."""
+    With wgam/basis_g the hyperangle of each sample is pi * sigmoid(wgam . basis_g(t)) (Eq. 6).
+    density: "softplus" or "relu" (Eq. 5 as printed)."""
     G = 1 << depth
     occ = np.zeros((G, G, G), bool)
     idx = -np.ones((G, G, G), np.int64)
@@ -85,7 +86,8 @@ def render(depth, leaf_ijk, hh, wsig, basis, gamma, o, d, t, t_stop, wgam=None, 
         if wgam is not None:
             gq = math.pi * sigmoid(float(np.dot(wgam[q].astype(np.float64), bg)))
             h = hh_basis(K, d / n, gq)
-        sig = softplus(float(np.dot(wsig[q].astype(np.float64), b)))
+        x = float(np.dot(wsig[q].astype(np.float64), b))
+        sig = max(x, 0.0) if density == "relu" else softplus(x)
         c = np.array([sigmoid(float(np.dot(hh[q, ch].astype(np.float64), h))) for ch in range(3)])
         sig_del.append(sig * (u1 - u0) * n)
         cols.append(c)

@@ -8,7 +8,8 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_util import DEV, announce, cam_struct, tiny_camera, inst_pair, oracle_render, rel_err, tdev, upload
+from gpu_util import (DEV, announce, cam_struct, tiny_camera, inst_pair, oracle_render, rel_err, stop_ambiguous,
+                      tdev, upload)
 from oracle import core as OC
 from paper_2202_06088_amd import _lib, autograd, ops
 from workloads import make_scene, orbit_camera, ring_cameras, scene_for_workload
@@ -101,7 +102,7 @@ def test_backward_ragged_image(traced):
     gC = rng.normal(size=(n, 3)).astype(np.float32)
     announce(f"ragged-image backward 67 wide traced={traced}")
     ref = oracle_render(sc, o, d, None, 3.0, 1e-4, g_rgb=gC)
-    gC[ref["margin"][:, 1] < 1e-3] = 0.0
+    gC[stop_ambiguous(ref, label="ragged image")] = 0.0
     ref = oracle_render(sc, o, d, None, 3.0, 1e-4, g_rgb=gC)
     gpu = run_backward(tree, o, d, None, 3.0, 1e-4, gC, None, image_width=67, traced=traced)
     assert int(gpu[3].sum()) > 3000
@@ -144,7 +145,7 @@ def test_traced_step(cap):
         gpu = (hh.cpu().numpy(), ws.cpu().numpy(), gb.cpu().numpy())
         ref = oracle_render(sc, o, d, t if isinstance(t, np.ndarray) else None,
                             0.0 if isinstance(t, np.ndarray) else t, 1e-4, inst=inst, g_rgb=gC, g_alpha=gA)
-        amb = ref["margin"][:, 1] < 1e-3
+        amb = stop_ambiguous(ref, label=label)
         if amb.any():   # rays whose stop decision is within rounding: compare without their gradient
             gC2, gA2 = gC.copy(), gA.copy()
             gC2[amb], gA2[amb] = 0.0, 0.0
@@ -194,7 +195,7 @@ def test_backward_with_early_stop_and_16bit(traced):
     rng = np.random.default_rng(43)
     gC = rng.normal(size=(o.shape[0], 3)).astype(np.float32)
     fwd = oracle_render(sc, o, d, None, 2.0, 1e-4)
-    gC[fwd["margin"][:, 1] < 1e-3] = 0.0             # rays whose stop decision is within rounding
+    gC[stop_ambiguous(fwd, label="early stop")] = 0.0   # rays whose stop decision is within rounding
     for dtype in (_lib.F32, _lib.F16, _lib.BF16):
         announce(f"backward with t_stop=1e-4, storage {dtype}, traced={traced}")
         ref = oracle_render(sc, o, d, None, 2.0, 1e-4, dtype=dtype, g_rgb=gC)
@@ -280,7 +281,7 @@ def test_trace_buffer_reused_across_calls():
         oo, dd = tdev(o), tdev(d)
         gC = rng.normal(size=(n, 3)).astype(np.float32)
         fwd = oracle_render(sc, o, d, None, t, 1e-4)
-        gC[fwd["margin"][:, 1] < 1e-3] = 0.0
+        gC[stop_ambiguous(fwd, label=f"trace reuse t={t}")] = 0.0
         announce(f"trace reuse t={t}")
         rgb, alpha, depth, nsamp = ops.render(tree, oo, dd, t, None, 1e-4, 64, trace=trace)
         gl, gb = ops.render_backward(tree, oo, dd, rgb, alpha, nsamp, tdev(gC), None, t, None, 1e-4, 64,

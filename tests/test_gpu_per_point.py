@@ -11,7 +11,7 @@ import pytest
 import torch
 
 from gpu_util import (DEV, announce, cam_struct, compare, tiny_camera, gpu_render, inst_pair, oracle_render,
-                      rel_err, tdev, upload)
+                      rel_err, stop_ambiguous, tdev, upload)
 from paper_2202_06088_amd import _lib, autograd, ops
 from workloads import make_scene_per_point, random_rays, special_rays
 
@@ -101,7 +101,7 @@ def test_per_point_backward_per_ray_time_and_early_stop(scene):
     t = rng.uniform(0, 30, o.shape[0]).astype(np.float32)
     gC = rng.normal(size=(o.shape[0], 3)).astype(np.float32)
     fwd = oracle_render(scene, o, d, t, 0.0, 1e-4)
-    gC[fwd["margin"][:, 1] < 1e-3] = 0.0         # rays whose stop decision is within rounding
+    gC[stop_ambiguous(fwd, label="pp per-ray t")] = 0.0   # rays whose stop decision is within rounding
     announce("per-point backward, per-ray time, t_stop=1e-4")
     ref = oracle_render(scene, o, d, t, 0.0, 1e-4, g_rgb=gC)
     gpu = pp_backward(tree, o, d, t, 0.0, 1e-4, gC, None)
@@ -210,7 +210,7 @@ def test_per_point_traced_step(scene, cap):
         rgb, alpha, depth, nsamp = traced
         assert int(nsamp.sum()) > 2000
         fwd = oracle_render(scene, o, d, t if per_ray else None, 0.0 if per_ray else t, 1e-4, inst=inst)
-        amb = fwd["margin"][:, 1] < 1e-3        # stop decision within rounding: no gradient on those rays
+        amb = stop_ambiguous(fwd, label=label)   # stop decision within rounding: no gradient on those rays
         gC2, gA2 = gC.copy(), gA.copy()
         gC2[amb], gA2[amb] = 0.0, 0.0
         ref = oracle_render(scene, o, d, t if per_ray else None, 0.0 if per_ray else t, 1e-4, inst=inst,

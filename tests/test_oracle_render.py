@@ -359,3 +359,107 @@ def test_per_point_hyperangle_gradient_finite_differences(oracle_lib):
             b = bg.copy(); b[i, c] -= eps
             fd = (run(hh, wg, a)[0] - run(hh, wg, b)[0]) / (2 * eps)
             assert abs(fd - res["grad_basis_g"][i, c]) < 1e-7 * max(1, abs(fd))
+
+
+# ---------------------------------------------------------------------------
+# ReLU density (Eq. 5 as printed): the same pins for the second activation
+
+@pytest.mark.parametrize("depth,t_stop,seed", [(3, 0.0, 21), (4, 1e-3, 22)])
+def test_relu_density_matches_bruteforce(oracle_lib, depth, t_stop, seed):
+    ijk, hh, wsig, basis, gamma = tiny_scene(depth, seed=seed)
+    G = 1 << depth
+    rng = np.random.default_rng(seed + 100)
+    o1, d1 = random_rays(G, 40, rng, inside_frac=0.25)
+    o2, d2 = special_rays(G)
+    o = np.concatenate([o1, o2])
+    d = np.concatenate([d1, d2])
+    res = oracle_lib.render(depth, ijk, hh, wsig, basis, gamma, o, d, None, 2.0, t_stop, density="relu")
+    soft = oracle_lib.render(depth, ijk, hh, wsig, basis, gamma, o, d, None, 2.0, t_stop)
+    assert np.abs(res["alpha"] - soft["alpha"]).max() > 1e-3   # the activation reaches the output
+    for r in range(o.shape[0]):
+        C, A, D, ns = BF.render(depth, ijk, hh, wsig, basis, gamma, o[r].astype(np.float64),
+                                d[r].astype(np.float64), 2.0, t_stop, density="relu")
+        assert np.allclose(res["rgb"][r], C, rtol=0, atol=1e-12), r
+        assert abs(res["alpha"][r] - A) < 1e-12, r
+        assert (math.isinf(D) and math.isinf(res["depth"][r])) or abs(res["depth"][r] - D) < 1e-9, r
+        assert res["nsamp"][r] == ns, (r, res["nsamp"][r], ns)
+
+
+def test_relu_single_voxel_closed_form(oracle_lib):
+    """alpha = 1 - exp(-max(x, 0) l) exactly; a voxel with a negative logit is a composited sample of
+    zero weight (transparent: no colour, no alpha, depth +inf)."""
+    ijk = np.array([[1, 2, 3]], np.int32)
+    hh = np.array([[[0.7], [-0.4], [1.3]]], np.float32)
+    basis = np.array([[1.0, 2.0], [0.5, -1.0]], np.float32)
+    gamma = np.array([0.4, 1.1], np.float32)
+    h0 = 1.0 / (math.pi * math.sqrt(2.0))
+    c = np.array([1 / (1 + math.exp(-float(v) * h0)) for v in hh[0, :, 0]])
+    o, d, ell = (0.0, 1.0, 2.0), (1, 1, 1), math.sqrt(3.0)
+    for wsig in (np.array([[0.9, -0.3]], np.float32), np.array([[0.25, 0.5]], np.float32),
+                 np.array([[-0.9, 0.3]], np.float32)):
+        x = float(wsig[0, 0]) * 1.0 + float(wsig[0, 1]) * 2.0
+        res = oracle_lib.render(3, ijk, hh, wsig, basis, gamma, np.array([o]), np.array([d]), None, 0.0, 0.0,
+                                density="relu")
+        a = 1 - math.exp(-max(x, 0.0) * ell)
+        assert abs(res["alpha"][0] - a) < 1e-14
+        assert np.abs(res["rgb"][0] - a * c).max() < 1e-14
+        assert res["nsamp"][0] == 1
+        if x < 0:
+            assert res["alpha"][0] == 0.0 and np.all(res["rgb"][0] == 0.0) and math.isinf(res["depth"][0])
+
+
+def test_relu_gradient_matches_finite_differences(oracle_lib):
+    """Central differences of the ReLU-density loss, on rays and leaves whose density logits stay
+    farther than the step from the kink at 0 (elsewhere the derivative is one-sided)."""
+    ijk, hh, wsig, basis, gamma = tiny_scene(3, n_leaves=60, seed=13, T=5)
+    hh = hh.astype(np.float64)
+    wsig = wsig.astype(np.float64)
+    basis = basis.astype(np.float64)
+    rng = np.random.default_rng(14)
+    o, d = random_rays(8, 30, rng)
+    t = np.full(30, 2.0, np.float32)   # one frame: b = basis[2], so every logit is wsig . basis[2]
+    x = wsig @ basis[2]
+    far = np.abs(x) > 1e-3
+    gC = rng.normal(size=(30, 3))
+    gA = rng.normal(size=30)
+
+    def loss(hh_, wsig_, basis_):
+        r = oracle_lib.render(3, ijk, hh_, wsig_, basis_, gamma, o, d, t, 0.0, 0.0, g_rgb=gC, g_alpha=gA,
+                              density="relu")
+        return float((r["rgb"] * gC).sum() + (r["alpha"] * gA).sum()), r
+
+    L0, res = loss(hh, wsig, basis)
+    eps = 1e-6
+    # leaves the rays sample (every sampled leaf has a colour gradient with the softplus density)
+    soft = oracle_lib.render(3, ijk, hh, wsig, basis, gamma, o, d, t, 0.0, 0.0, g_rgb=gC, g_alpha=gA)
+    visited = np.unique(np.nonzero(np.abs(soft["grad_hh"]).sum((1, 2)))[0])
+    # sampled leaves with a negative logit are transparent: no gradient to their colour or density
+    neg = visited[x[visited] < 0]
+    assert neg.size > 3
+    assert np.all(res["grad_wsig"][neg] == 0.0) and np.all(res["grad_hh"][neg] == 0.0)
+    touched = visited[x[visited] > 0]
+    assert touched.size > 5
+    checked = 0
+    for q in touched[:10]:
+        if not far[q]:
+            continue
+        for idx in ((q, 0, 0), (q, 2, 15)):
+            a = hh.copy(); a[idx] += eps
+            b = hh.copy(); b[idx] -= eps
+            fd = (loss(a, wsig, basis)[0] - loss(b, wsig, basis)[0]) / (2 * eps)
+            assert abs(fd - res["grad_hh"][idx]) < 1e-7 * max(1, abs(res["grad_hh"][idx]))
+        for cc in range(wsig.shape[1]):
+            a = wsig.copy(); a[q, cc] += eps
+            b = wsig.copy(); b[q, cc] -= eps
+            fd = (loss(hh, a, basis)[0] - loss(hh, b, basis)[0]) / (2 * eps)
+            assert abs(fd - res["grad_wsig"][q, cc]) < 1e-7 * max(1, abs(res["grad_wsig"][q, cc]))
+        checked += 1
+    assert checked >= 4
+    # basis row 2 (the only one used): every logit moves with it; keep the step below the
+    # smallest distance of a touched logit from the kink
+    step = min(eps, 0.1 * np.abs(x[touched]).min())
+    for cc in (0, 5):
+        a = basis.copy(); a[2, cc] += step
+        b = basis.copy(); b[2, cc] -= step
+        fd = (loss(hh, wsig, a)[0] - loss(hh, wsig, b)[0]) / (2 * step)
+        assert abs(fd - res["grad_basis"][2, cc]) < 1e-6 * max(1, abs(res["grad_basis"][2, cc]))
