@@ -269,6 +269,28 @@ int neuvv_render(const neuvv_tree* tree, const neuvv_instance* inst, int64_t n_r
                  float* rgb, float* alpha, float* depth, int32_t* nsamp, void* stream);
 
 /*
+ * neuvv_render_noalloc - neuvv_render for callers that cannot allocate device
+ * memory: code under stream or graph capture, serving loops and harnesses
+ * that forbid allocation. Same arguments, kernels and results (bit for bit)
+ * as neuvv_render, which takes its scratch (work-queue counters and the
+ * candidate list of the cull pass) from a stream-ordered pool; this call
+ * takes it instead from one fixed device array that the library holds on
+ * every device it runs on until the process ends (64 MiB + 2 KiB), and
+ * calls no allocating routine. The array fits launches of at most 2^24 work
+ * slots: n_rays, or with image_width = W > 0, ceil(W/8) * ceil(rows/8) * 64
+ * for rows = ceil(n_rays/W) (the 8-camera 1920x1080 ring stacked as one
+ * image is 16,588,800). Larger launches return NEUVV_ERR_CAPACITY before
+ * anything is queued. Every call on a device shares that device's array
+ * (the counters are cleared by a kernel at the start of each call): calls
+ * that may overlap on one device, on different streams or from different
+ * threads, race and give wrong results; serialise them.
+ * Errors: those of neuvv_render, and CAPACITY.
+ */
+int neuvv_render_noalloc(const neuvv_tree* tree, const neuvv_instance* inst, int64_t n_rays, const float* ray_o,
+                         const float* ray_d, const float* ray_t, float t_scalar, int32_t image_width, float t_stop,
+                         float* rgb, float* alpha, float* depth, int32_t* nsamp, void* stream);
+
+/*
  * neuvv_render_backward - adjoint of neuvv_render (Sec. 4.3 "Optimization")
  * for L = sum_r <grad_rgb_r, rgb_r> + grad_alpha_r alpha_r. Each ray replays
  * its nsamp samples front to back with the transmittance recomputed (nothing

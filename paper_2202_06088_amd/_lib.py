@@ -62,6 +62,8 @@ _SIGNATURES = {
     "neuvv_pack_leaves": [_I32, _I32, _I32, _I32, _I64, _P, _P, _P, _P, _P, _P],
     "neuvv_render": [ctypes.POINTER(neuvv_tree), ctypes.POINTER(neuvv_instance), _I64, _P, _P, _P, _F, _I32, _F,
                      _P, _P, _P, _P, _P],
+    "neuvv_render_noalloc": [ctypes.POINTER(neuvv_tree), ctypes.POINTER(neuvv_instance), _I64, _P, _P, _P, _F, _I32,
+                             _F, _P, _P, _P, _P, _P],
     "neuvv_render_backward": [ctypes.POINTER(neuvv_tree), ctypes.POINTER(neuvv_instance), _I64, _P, _P, _P, _F,
                               _I32, _F, _P, _P, _P, _P, _P, _P, _P, _P, _P],
     "neuvv_render_trace": [ctypes.POINTER(neuvv_tree), ctypes.POINTER(neuvv_instance), _I64, _P, _P, _P, _F, _I32,
@@ -190,6 +192,13 @@ def _inst_ptr(inst: Optional[neuvv_instance]):
 def neuvv_render(tree: neuvv_tree, inst, n_rays, ray_o, ray_d, ray_t, t_scalar, image_width, t_stop,
                  rgb, alpha, depth, nsamp, stream=None):
     _check("neuvv_render", load().neuvv_render(
+        ctypes.byref(tree), _inst_ptr(inst), int(n_rays), _ptr(ray_o), _ptr(ray_d), _ptr(ray_t), float(t_scalar),
+        int(image_width), float(t_stop), _ptr(rgb), _ptr(alpha), _ptr(depth), _ptr(nsamp), _stream(stream)))
+
+
+def neuvv_render_noalloc(tree: neuvv_tree, inst, n_rays, ray_o, ray_d, ray_t, t_scalar, image_width, t_stop,
+                         rgb, alpha, depth, nsamp, stream=None):
+    _check("neuvv_render_noalloc", load().neuvv_render_noalloc(
         ctypes.byref(tree), _inst_ptr(inst), int(n_rays), _ptr(ray_o), _ptr(ray_d), _ptr(ray_t), float(t_scalar),
         int(image_width), float(t_stop), _ptr(rgb), _ptr(alpha), _ptr(depth), _ptr(nsamp), _stream(stream)))
 

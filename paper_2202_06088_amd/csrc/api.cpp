@@ -260,9 +260,12 @@ static int check_trace(int64_t n_rays, const void* trace, int64_t trace_cap) {
     return NEUVV_OK;
 }
 
+// fixed: take the call's scratch from the library's fixed device array (no
+// allocation) instead of the pool; launches beyond its room are rejected.
 static int render_impl(const neuvv_tree* tree, const neuvv_instance* inst, int64_t n_rays, const float* ray_o,
                 const float* ray_d, const float* ray_t, float t_scalar, int32_t image_width, float t_stop, float* rgb,
-                float* alpha, float* depth, int32_t* nsamp, void* trace, int64_t trace_cap, void* stream) {
+                float* alpha, float* depth, int32_t* nsamp, void* trace, int64_t trace_cap, void* stream,
+                bool fixed = false) {
     int rc = check_tree(tree);
     if (rc) return rc;
     neuvv::InstArgs in;
@@ -271,13 +274,24 @@ static int render_impl(const neuvv_tree* tree, const neuvv_instance* inst, int64
     if ((rc = make_rays(n_rays, ray_o, ray_d, ray_t, t_scalar, image_width, ra))) return rc;
     if (!(t_stop >= 0.0f) || !std::isfinite(t_stop)) return fail(NEUVV_ERR_RANGE, "t_stop must be >= 0");
     if (n_rays > 0 && (!rgb || !alpha || !nsamp)) return fail(NEUVV_ERR_ARG, "rgb / alpha / nsamp is NULL");
+    void* ws = nullptr;
+    if (fixed) {
+        if (ra.n_slots > neuvv::kFixedScratchSlots)
+            return fail(NEUVV_ERR_CAPACITY,
+                        "neuvv_render_noalloc takes at most %lld work slots (rays, or 8x8 tiles x 64 with "
+                        "image_width); this call has %lld",
+                        (long long)neuvv::kFixedScratchSlots, (long long)ra.n_slots);
+        if (ra.n_slots == 0) return NEUVV_OK;
+        rc = hip_status(neuvv::fixed_scratch(&ws), "device address of the fixed scratch");
+        if (rc) return rc;
+    }
     neuvv::RenderOut out{rgb, alpha, depth, nsamp, nullptr};
     if (trace) out.trace = neuvv::trace_layout(trace, n_rays, trace_cap);
     const hipError_t e = tree->Cg > 0
                              ? neuvv::launch_render_pp_fwd(tree->dtype, tree_args(tree), in, ra, t_stop, out,
-                                                           (hipStream_t)stream)
+                                                           (hipStream_t)stream, ws)
                              : neuvv::launch_render_fwd(tree->K, tree->C, tree->dtype, tree_args(tree), in, ra,
-                                                        t_stop, out, (hipStream_t)stream);
+                                                        t_stop, out, (hipStream_t)stream, ws);
     return hip_status(e, "render launch");
 }
 
@@ -314,6 +328,15 @@ int neuvv_render(const neuvv_tree* tree, const neuvv_instance* inst, int64_t n_r
     NEUVV_GUARD_BEGIN
     return render_impl(tree, inst, n_rays, ray_o, ray_d, ray_t, t_scalar, image_width, t_stop, rgb, alpha, depth,
                        nsamp, nullptr, 0, stream);
+    NEUVV_GUARD_END
+}
+
+int neuvv_render_noalloc(const neuvv_tree* tree, const neuvv_instance* inst, int64_t n_rays, const float* ray_o,
+                         const float* ray_d, const float* ray_t, float t_scalar, int32_t image_width, float t_stop,
+                         float* rgb, float* alpha, float* depth, int32_t* nsamp, void* stream) {
+    NEUVV_GUARD_BEGIN
+    return render_impl(tree, inst, n_rays, ray_o, ray_d, ray_t, t_scalar, image_width, t_stop, rgb, alpha, depth,
+                       nsamp, nullptr, 0, stream, true);
     NEUVV_GUARD_END
 }
 

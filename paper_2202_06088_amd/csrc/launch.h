@@ -67,8 +67,11 @@ struct RecordArgs {
 bool render_supported(int K, int C, int Cg, int dtype);
 // Floats per row of the leaf-major gradient array: 3K + C + Cg rounded up to 64.
 int grad_row_elems(int K, int C, int Cg);
+// ws: scratch of at least list_scratch_bytes(ra.n_slots) bytes that the call
+// uses instead of taking its own from the pool (nothing is then allocated),
+// or nullptr.
 hipError_t launch_render_fwd(int K, int C, int dtype, const TreeArgs& tr, const InstArgs& in, const RayArgs& ra,
-                             float t_stop, const RenderOut& out, hipStream_t stream);
+                             float t_stop, const RenderOut& out, hipStream_t stream, void* ws = nullptr);
 hipError_t launch_render_bwd(int K, int C, int dtype, const TreeArgs& tr, const InstArgs& in, const RayArgs& ra,
                              const BackwardIO& io, hipStream_t stream);
 // Exact merge of up to 4 instances along each ray (K = 16, C = 8 form).
@@ -80,7 +83,7 @@ hipError_t launch_render_multi(int L, int dtype, const MultiArgs& ma, const RayA
                                const RenderOut& out, hipStream_t stream);
 // Per-point hyperangle form (K = 14, C = 31, Cg = 31).
 hipError_t launch_render_pp_fwd(int dtype, const TreeArgs& tr, const InstArgs& in, const RayArgs& ra, float t_stop,
-                                const RenderOut& out, hipStream_t stream);
+                                const RenderOut& out, hipStream_t stream, void* ws = nullptr);
 hipError_t launch_render_pp_bwd(int dtype, const TreeArgs& tr, const InstArgs& in, const RayArgs& ra,
                                 const BackwardIO& io, hipStream_t stream);
 hipError_t launch_compose_fwd(int L, int64_t n, const float* rgb, const float* alpha, const float* depth,
@@ -119,6 +122,23 @@ hipError_t launch_paint(int64_t n, const int32_t* last_leaf, const float* colour
 
 // Device properties used to size persistent grids (cached per device).
 int device_cu_count();
+
+// Scratch of a forward launch in the candidate form: a 2 KiB header (the
+// work-queue counters, then the per-part list counts, 128 bytes apart) and
+// one int32 list entry per work slot.
+constexpr size_t kListHeaderBytes = 2048;
+inline size_t list_scratch_bytes(int64_t n_slots) {
+    return kListHeaderBytes + (size_t)((n_slots + 63) >> 6) * 64 * sizeof(int32_t);
+}
+
+// The fixed device scratch of neuvv_render_noalloc: room for the candidate
+// form of launches of at most kFixedScratchSlots work slots (64 MiB + 2 KiB,
+// held by every device the library runs on until the process ends).
+constexpr int64_t kFixedScratchSlots = (int64_t)1 << 24;
+constexpr size_t kFixedScratchBytes = kListHeaderBytes + (size_t)kFixedScratchSlots * sizeof(int32_t);
+// Device address of that array on the current device (looked up once per
+// device; the array's host-side name is not a device address).
+hipError_t fixed_scratch(void** p);
 
 // Stream-ordered scratch of a launch (work-queue counters, candidate lists):
 // taken from a memory pool the library keeps per device, which holds on to

@@ -882,15 +882,44 @@ static hipError_t bwd_t(const TreeArgs& tr, const InstArgs& in, const RayArgs& r
 }
 
 hipError_t launch_render_fwd(int K, int C, int dtype, const TreeArgs& tr, const InstArgs& in, const RayArgs& ra,
-                             float t_stop, const RenderOut& out, hipStream_t stream) {
+                             float t_stop, const RenderOut& out, hipStream_t stream, void* ws) {
     (void)K;
     (void)C;
     if (ra.n_slots <= 0) return hipSuccess;
     switch (dtype) {
-        case 0: return with_candidates<0>(tr, in, ra, out, nullptr, stream, [&](const RayArgs& r) { return fwd_t<16, 8, 0>(tr, in, r, t_stop, out, stream); });
-        case 1: return with_candidates<0>(tr, in, ra, out, nullptr, stream, [&](const RayArgs& r) { return fwd_t<16, 8, 1>(tr, in, r, t_stop, out, stream); });
-        default: return with_candidates<0>(tr, in, ra, out, nullptr, stream, [&](const RayArgs& r) { return fwd_t<16, 8, 2>(tr, in, r, t_stop, out, stream); });
+        case 0: return with_candidates<0>(tr, in, ra, out, nullptr, stream, [&](const RayArgs& r) { return fwd_t<16, 8, 0>(tr, in, r, t_stop, out, stream); }, nullptr, ws);
+        case 1: return with_candidates<0>(tr, in, ra, out, nullptr, stream, [&](const RayArgs& r) { return fwd_t<16, 8, 1>(tr, in, r, t_stop, out, stream); }, nullptr, ws);
+        default: return with_candidates<0>(tr, in, ra, out, nullptr, stream, [&](const RayArgs& r) { return fwd_t<16, 8, 2>(tr, in, r, t_stop, out, stream); }, nullptr, ws);
     }
+}
+
+// The fixed scratch of neuvv_render_noalloc. Host code never uses the
+// array's name as an address: fixed_scratch() looks its device address up
+// once per device (with that device current) and the launches take that.
+// Calls that overlap on one device share the array and race.
+static __device__ __align__(256) unsigned char scratch[kFixedScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[64] = {};
+}  // namespace
+
+hipError_t fixed_scratch(void** p) {
+    *p = nullptr;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* q = nullptr;
+        e = hipGetSymbolAddress(&q, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!q) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = q;
+    }
+    *p = g_scratch_ptr[dev];
+    return hipSuccess;
 }
 
 hipError_t launch_render_bwd(int K, int C, int dtype, const TreeArgs& tr, const InstArgs& in, const RayArgs& ra,

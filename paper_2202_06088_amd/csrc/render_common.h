@@ -427,31 +427,36 @@ static hipError_t launch_cull(const TreeArgs& tr, const InstArgs& in, const RayA
 }
 
 // Runs launch(ra) with the launch's queue counters set; rays are the slots.
+// ws: caller-provided scratch of at least list_scratch_bytes(n_slots) bytes
+// (nothing is allocated), or nullptr to take it from the pool.
 template <typename Launch>
-static hipError_t with_queue(const RayArgs& ra_in, hipStream_t st, Launch&& launch) {
+static hipError_t with_queue(const RayArgs& ra_in, hipStream_t st, Launch&& launch, void* ws = nullptr) {
     RayArgs ra = ra_in;
-    void* q = nullptr;
-    hipError_t e = work_alloc(&q, kQueues * kQueueStride * sizeof(unsigned long long), st);
+    void* q = ws;
+    hipError_t e = ws ? hipSuccess : work_alloc(&q, kQueues * kQueueStride * sizeof(unsigned long long), st);
     if (e != hipSuccess) return e;
     ra.queue = static_cast<unsigned long long*>(q);
     hipLaunchKernelGGL(zero_queue_kernel, dim3(1), dim3(kQueues * kQueueStride), 0, st, ra.queue);
     e = hipGetLastError();
     if (e == hipSuccess) e = launch(ra);
-    const hipError_t f = work_free(q, st);
+    const hipError_t f = ws ? hipSuccess : work_free(q, st);
     return e != hipSuccess ? e : f;
 }
 
+static_assert(2 * kQueues * kQueueStride * sizeof(unsigned long long) == kListHeaderBytes,
+              "candidate-list header size");
+
 // Candidate form: cull(list, count) lists the rays, then launch(ra) runs over
 // them. Ray indices must fit int32; larger launches take the slot form (the
-// render kernels then test every ray themselves).
+// render kernels then test every ray themselves). ws as in with_queue.
 template <typename Cull, typename Launch>
-static hipError_t with_list(const RayArgs& ra_in, hipStream_t st, Cull&& cull, Launch&& launch) {
-    if (ra_in.n > (int64_t)INT32_MAX) return with_queue(ra_in, st, launch);
-    const int64_t n_chunks = (ra_in.n_slots + 63) >> 6;
-    const size_t qbytes = 2 * kQueues * kQueueStride * sizeof(unsigned long long);
+static hipError_t with_list(const RayArgs& ra_in, hipStream_t st, Cull&& cull, Launch&& launch,
+                            void* ws = nullptr) {
+    if (ra_in.n > (int64_t)INT32_MAX) return with_queue(ra_in, st, launch, ws);
+    const size_t qbytes = kListHeaderBytes;
     RayArgs ra = ra_in;
-    void* q = nullptr;
-    hipError_t e = work_alloc(&q, qbytes + (size_t)n_chunks * 64 * sizeof(int32_t), st);
+    void* q = ws;
+    hipError_t e = ws ? hipSuccess : work_alloc(&q, list_scratch_bytes(ra_in.n_slots), st);
     if (e != hipSuccess) return e;
     ra.queue = static_cast<unsigned long long*>(q);
     unsigned long long* count = ra.queue + kQueues * kQueueStride;
@@ -462,7 +467,7 @@ static hipError_t with_list(const RayArgs& ra_in, hipStream_t st, Cull&& cull, L
     e = hipGetLastError();
     if (e == hipSuccess) e = cull(list, count);
     if (e == hipSuccess) e = launch(ra);
-    const hipError_t f = work_free(q, st);
+    const hipError_t f = ws ? hipSuccess : work_free(q, st);
     return e != hipSuccess ? e : f;
 }
 
@@ -470,13 +475,13 @@ static hipError_t with_list(const RayArgs& ra_in, hipStream_t st, Cull&& cull, L
 template <int MODE, typename Launch>
 static hipError_t with_candidates(const TreeArgs& tr, const InstArgs& in, const RayArgs& ra_in,
                                   const RenderOut& out, const int32_t* nsamp, hipStream_t st, Launch&& launch,
-                                  const int32_t* head = nullptr) {
+                                  const int32_t* head = nullptr, void* ws = nullptr) {
     return with_list(
         ra_in, st,
         [&](int32_t* list, unsigned long long* count) {
             return launch_cull<MODE>(tr, in, ra_in, out, nsamp, head, list, count, st);
         },
-        launch);
+        launch, ws);
 }
 
 // ----------------------------------------------------------------------------

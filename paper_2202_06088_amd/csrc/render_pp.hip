@@ -851,12 +851,12 @@ static hipError_t pp_bwd_t(const TreeArgs& tr, const InstArgs& in, const RayArgs
 }
 
 hipError_t launch_render_pp_fwd(int dtype, const TreeArgs& tr, const InstArgs& in, const RayArgs& ra, float t_stop,
-                                const RenderOut& out, hipStream_t stream) {
+                                const RenderOut& out, hipStream_t stream, void* ws) {
     if (ra.n_slots <= 0) return hipSuccess;
     switch (dtype) {
-        case 0: return with_candidates<0>(tr, in, ra, out, nullptr, stream, [&](const RayArgs& r) { return pp_fwd_t<0>(tr, in, r, t_stop, out, stream); });
-        case 1: return with_candidates<0>(tr, in, ra, out, nullptr, stream, [&](const RayArgs& r) { return pp_fwd_t<1>(tr, in, r, t_stop, out, stream); });
-        default: return with_candidates<0>(tr, in, ra, out, nullptr, stream, [&](const RayArgs& r) { return pp_fwd_t<2>(tr, in, r, t_stop, out, stream); });
+        case 0: return with_candidates<0>(tr, in, ra, out, nullptr, stream, [&](const RayArgs& r) { return pp_fwd_t<0>(tr, in, r, t_stop, out, stream); }, nullptr, ws);
+        case 1: return with_candidates<0>(tr, in, ra, out, nullptr, stream, [&](const RayArgs& r) { return pp_fwd_t<1>(tr, in, r, t_stop, out, stream); }, nullptr, ws);
+        default: return with_candidates<0>(tr, in, ra, out, nullptr, stream, [&](const RayArgs& r) { return pp_fwd_t<2>(tr, in, r, t_stop, out, stream); }, nullptr, ws);
     }
 }
 
