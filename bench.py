@@ -46,7 +46,7 @@ def log(msg):
 def kernel_source_hash(workload: str) -> str:
     """Hash of the sources the workload's render kernels are built from, comments and blank lines
     left out (a comment edit does not change the kernels)."""
-    main = "render_pp.hip" if workload.endswith("per_point") else "render.hip"
+    main = "render_pp.hip" if workload.endswith("per_point") else "render_kernels.h"
     h = hashlib.sha256()
     for f in (main, "render_common.h", "neuvv_device.h"):
         with open(os.path.join(ROOT, "paper_2202_06088_amd", "csrc", f), encoding="utf-8") as fh:

@@ -13,8 +13,9 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libneuvv.so")
-SOURCES = ["render.hip", "render_pp.hip", "render_multi.hip", "misc.hip", "lighting.hip", "api.cpp",
-           "build_voctree.cpp"]
+# the shape files first: they take longest
+SOURCES = ["render_k16.hip", "render_k14.hip", "render_k30.hip", "render_kc31.hip", "render_pp.hip", "render.hip",
+           "render_multi.hip", "misc.hip", "lighting.hip", "api.cpp", "build_voctree.cpp"]
 ARCH = os.environ.get("NEUVV_ARCH", "gfx950")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function"]
@@ -49,7 +50,7 @@ def build_library(verbose: bool = False) -> str:
             print(r.stderr, file=sys.stderr)
         return obj
 
-    with ThreadPoolExecutor(max_workers=min(4, len(SOURCES))) as ex:
+    with ThreadPoolExecutor(max_workers=min(max(os.cpu_count() or 4, 4), 8, len(SOURCES))) as ex:
         objs = list(ex.map(compile_one, SOURCES))
     tmp = LIB + ".tmp"
     cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]

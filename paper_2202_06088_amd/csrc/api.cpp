@@ -1,6 +1,9 @@
 // C ABI of libneuvv.so (declared in include/neuvv.h): argument validation,
 // dtype/K/C dispatch and error reporting around the kernels. Nothing here
-// allocates device memory or keeps pointers beyond a call.
+// keeps pointers to caller buffers beyond a call. The render calls take
+// their scratch (work-queue counters, candidate lists, adjoint records) from
+// a stream-ordered memory pool the library keeps per device (render.hip),
+// except neuvv_render_noalloc, which uses a fixed device array.
 #include <hip/hip_runtime.h>
 #include <stdarg.h>
 #include <stdio.h>
@@ -55,7 +58,8 @@ int check_tree(const neuvv_tree* t) {
     if (t->layout < 0 || t->layout > 1) return fail(NEUVV_ERR_ARG, "unknown layout %d", t->layout);
     if (!neuvv::render_supported(t->K, t->C, t->Cg, t->dtype))
         return fail(NEUVV_ERR_UNSUPPORTED,
-                    "no kernel compiled for K=%d C=%d Cg=%d (have K=16 C=8 Cg=0 and K=14 C=31 Cg=31)", t->K, t->C,
+                    "no kernel compiled for K=%d C=%d Cg=%d (have K in {14,16,30} x C in {8,31} with Cg=0, and "
+                    "K=14 C=31 Cg=31)", t->K, t->C,
                     t->Cg);
     if (t->n_nodes < 1 || t->n_nodes > INT32_MAX) return fail(NEUVV_ERR_RANGE, "n_nodes %lld", (long long)t->n_nodes);
     if (t->n_leaves < 0 || t->n_leaves > INT32_MAX)
@@ -74,7 +78,7 @@ int check_tree(const neuvv_tree* t) {
         return fail(NEUVV_ERR_ARG, "tree payload pointer is NULL");
     if (t->edit && reinterpret_cast<uintptr_t>(t->edit) % 16 != 0)
         return fail(NEUVV_ERR_ARG, "tree edit rows must be 16-byte aligned");
-    if (t->edit && t->Cg > 0)
+    if (t->edit && (t->Cg > 0 || t->K != 16 || t->C != 8))
         return fail(NEUVV_ERR_UNSUPPORTED, "appearance edits are compiled for the K=16 C=8 form only");
     if (t->density != NEUVV_DENSITY_SOFTPLUS && t->density != NEUVV_DENSITY_RELU)
         return fail(NEUVV_ERR_ARG, "unknown density activation %d", t->density);
@@ -479,7 +483,8 @@ int neuvv_find_terminal_leaves(const neuvv_tree* tree, const neuvv_instance* ins
     NEUVV_GUARD_BEGIN
     int rc = check_tree(tree);
     if (rc) return rc;
-    if (tree->Cg > 0) return fail(NEUVV_ERR_UNSUPPORTED, "terminal leaves are compiled for the K=16 C=8 form only");
+    if (tree->Cg > 0)
+        return fail(NEUVV_ERR_UNSUPPORTED, "terminal leaves are compiled for the global-hyperangle form only");
     neuvv::InstArgs in;
     if ((rc = make_inst(inst, in))) return rc;
     neuvv::RayArgs ra;

@@ -74,6 +74,13 @@ hipError_t launch_render_fwd(int K, int C, int dtype, const TreeArgs& tr, const 
                              float t_stop, const RenderOut& out, hipStream_t stream, void* ws = nullptr);
 hipError_t launch_render_bwd(int K, int C, int dtype, const TreeArgs& tr, const InstArgs& in, const RayArgs& ra,
                              const BackwardIO& io, hipStream_t stream);
+// The same for one compiled shape (instantiated in render_k*.hip).
+template <int K, int C>
+hipError_t launch_render_fwd_shape(int dtype, const TreeArgs& tr, const InstArgs& in, const RayArgs& ra,
+                                   float t_stop, const RenderOut& out, hipStream_t stream, void* ws);
+template <int K, int C>
+hipError_t launch_render_bwd_shape(int dtype, const TreeArgs& tr, const InstArgs& in, const RayArgs& ra,
+                                   const BackwardIO& io, hipStream_t stream);
 // Exact merge of up to 4 instances along each ray (K = 16, C = 8 form).
 struct MultiArgs {
     TreeArgs tr[4];

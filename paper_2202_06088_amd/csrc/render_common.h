@@ -1,4 +1,4 @@
-// Building blocks shared by the render kernels (render.hip, render_pp.hip):
+// Building blocks shared by the render kernels (render_kernels.h, render_pp.hip):
 // payload gathers, work queues, LDS staging of the top node rows, launch
 // sizing. Device code for gfx950.
 #pragma once

@@ -17,7 +17,7 @@
 // in registers (the HH basis is recomputed at each segment fetch). Up to 3
 // instances the kernel runs two wavefronts per SIMD: at 256 registers some of
 // that state spills, but the second wavefront hides more memory latency than
-// the spills cost. With 4 instances it runs one. Work distribution is that of render.hip: a cull pass
+// the spills cost. With 4 instances it runs one. Work distribution is that of render_kernels.h: a cull pass
 // (here: may the ray hit any instance) lists the candidate rays per XCD
 // part, and persistent wavefronts take 64-ray chunks of the lists.
 #include <hip/hip_runtime.h>

@@ -8,7 +8,7 @@
 // adjoint (Sec. 4.3 "Optimization"), whose chain rule gains the hyperangle
 // path dL/dgamma -> dL/dwgam and dL/dBg.
 //
-// Work distribution, traversal and compositing are those of render.hip. The
+// Work distribution, traversal and compositing are those of render_kernels.h. The
 // interpolated basis rows are common to all rays when the time is one scalar
 // and are then staged once per block in LDS; with a time per ray they are
 // read per sample from the basis tables, which stay in cache. A traced
@@ -155,7 +155,7 @@ constexpr int kPPTraceInt4 = 4;
 
 // TRACE: every sample is also written to out.trace (leaf, segment length,
 // logits x and y, colours, dz/dgamma; linked in ray order) for the adjoint of
-// the same call, as in render.hip: entries of one iteration at consecutive
+// the same call, as in render_kernels.h: entries of one iteration at consecutive
 // slots in lane order, a sample's entry stored one sample later (when the
 // slot it links to is known) right after the next sample's payload loads,
 // the last one when the ray finishes; a ray whose samples do not all fit

@@ -168,9 +168,25 @@ def test_argument_errors_without_launch(lib):
     # failures detected on the host before anything touches a device
     assert lib.neuvv_render(None, None, 1, None, None, None, 0.0, 0, 0.0, None, None, None, None, None) == -1
     t = _lib.neuvv_tree()
-    t.depth, t.K, t.C, t.dtype, t.n_nodes, t.n_leaves, t.T = 9, 14, 8, 0, 1, 0, 1
+    t.depth, t.K, t.C, t.dtype, t.n_nodes, t.n_leaves, t.T = 9, 15, 8, 0, 1, 0, 1
     assert lib.neuvv_render(ctypes.byref(t), None, 0, None, None, None, 0.0, 0, 0.0, None, None, None, None,
                             None) == -5
+    t.K, t.C = 16, 12
+    assert lib.neuvv_render(ctypes.byref(t), None, 0, None, None, None, 0.0, 0, 0.0, None, None, None, None,
+                            None) == -5
+    # the compiled shapes of the global-hyperangle form (K in {14, 16, 30}, C in {8, 31}): a call
+    # with no rays passes the checks and launches nothing
+    t.nodes, t.basis, t.gamma = 16, 8, 8             # non-NULL placeholders, never dereferenced
+    for K in (14, 16, 30):
+        for C in (8, 31):
+            t.K, t.C = K, C
+            assert lib.neuvv_render(ctypes.byref(t), None, 0, None, None, None, 0.0, 0, 0.0, None, None, None,
+                                    None, None) == 0, (K, C, _lib.neuvv_last_error())
+    t.density = 2                                    # no such activation
+    assert lib.neuvv_render(ctypes.byref(t), None, 0, None, None, None, 0.0, 0, 0.0, None, None, None, None,
+                            None) == -1
+    t.density = 0
+    t.nodes, t.basis, t.gamma = None, None, None
     t.K, t.depth = 16, 13
     assert lib.neuvv_render(ctypes.byref(t), None, 0, None, None, None, 0.0, 0, 0.0, None, None, None, None,
                             None) == -2
@@ -206,9 +222,14 @@ def test_argument_errors_without_launch(lib):
     t.basis_g = 8
     assert lib.neuvv_render(ctypes.byref(t), None, 0, None, None, None, 0.0, 0, 0.0, None, None, None, None,
                             None) == 0
-    t.Cg = 0
+    t.Cg = 0                                        # the global form of K = 14, C = 31 needs its gamma table
+    assert lib.neuvv_render(ctypes.byref(t), None, 0, None, None, None, 0.0, 0, 0.0, None, None, None, None,
+                            None) == -1
+    assert "gamma" in _lib.neuvv_last_error()
+    t.K, t.C, t.Cg, t.edit, t.gamma = 30, 8, 0, 64, 8  # edits are compiled for K = 16, C = 8 only
     assert lib.neuvv_render(ctypes.byref(t), None, 0, None, None, None, 0.0, 0, 0.0, None, None, None, None,
                             None) == -5
+    t.gamma = None
     # appearance edits: K=16 C=8 form only, 16-byte aligned rows; terminal-leaf and paint arguments
     t.K, t.C, t.Cg, t.edit = 14, 31, 31, 64
     assert lib.neuvv_render(ctypes.byref(t), None, 0, None, None, None, 0.0, 0, 0.0, None, None, None, None,

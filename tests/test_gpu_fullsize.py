@@ -4,8 +4,8 @@ with the bench's trace room.
 
 Forward-render workload: depth-9 humanoid VOctree (~2M leaves), 8 cameras at
 1920x1080 rendered in one launch (16.6 M rays, 8x8 tiles, t_stop = 1e-4), with
-the global hyperangle table (K=16, C=8) and with the paper's per-point leaf
-(K=14, C=31, Cg=31).
+the global hyperangle table (K=16, C=8; and K=30, Table 3's N=30) and with
+the paper's per-point leaf (K=14, C=31, Cg=31).
 Outputs are checked on a seeded sample of pixels that the FP64 oracle
 renders one by one. The adjoint is checked in the same launch with the
 upstream gradient non-zero only on the sampled pixels, so the oracle's
@@ -18,16 +18,20 @@ import torch
 from gpu_util import DEV, announce, compare, oracle_render, rel_err, stop_ambiguous, tdev, upload
 from oracle import core as OC
 from paper_2202_06088_amd import _lib, ops
-from workloads import WORKLOADS, make_scene_per_point, ring_cameras, scene_for_workload
+from workloads import WORKLOADS, make_scene, make_scene_per_point, ring_cameras, scene_for_workload
 
 pytestmark = pytest.mark.gpu
 
 
-@pytest.fixture(scope="module", params=["global", "per-point"])
+@pytest.fixture(scope="module", params=["global", "global-k30", "per-point"])
 def ring(request):
     announce(f"full size: generating the depth-9 scene ({request.param} hyperangle)")
     if request.param == "global":
         sc = scene_for_workload("forward")
+    elif request.param == "global-k30":
+        # Table 3's N = 30 (every HH function with n <= 3) on the same occupancy
+        c2 = WORKLOADS["forward"]
+        sc = make_scene(c2["depth"], c2["target"], c2["kind"], K=30, C=8, T=c2["T"], seed=c2["seed"])
     else:
         c2 = WORKLOADS["forward"]
         sc = make_scene_per_point(c2["depth"], c2["target"], c2["kind"], T=c2["T"], seed=c2["seed"])
