@@ -441,7 +441,8 @@ struct Walk {
     int steps;
     int entry_axis;  // the entry point is the crossing of plane entry_plane on this axis; -1: u_in
     int entry_plane;
-    float u_est;     // float estimate of the entry parameter
+    df u_entry;      // the exact entry parameter when u_entry_ok (the previous step computed it)
+    bool u_entry_ok;
     bool done;
     int brick;       // row of the last-level node held below, -1: none
     uint32_t bm_lo, bm_hi;
@@ -470,7 +471,8 @@ __device__ __forceinline__ void walk_begin(const TreeArgs& tr, const RaySetup& r
     w.steps = 0;
     w.entry_axis = -1;
     w.entry_plane = 0;
-    w.u_est = df_f(rs.u_in);
+    w.u_entry = rs.u_in;
+    w.u_entry_ok = true;
     w.done = !rs.hit;
     w.brick = -1;
     w.bm_lo = w.bm_hi = 0u;
@@ -564,48 +566,46 @@ __device__ __forceinline__ int walk_next(const TreeArgs& tr, const int4* __restr
             path[lvl * stride] = idx;
         }
         const int S = 1 << sh;
+        // Exit face of the cell (or empty node) of edge S: per axis the float
+        // estimate of the crossing of its far plane and the bound on its error,
+        // computed for every axis without branches (zero direction components
+        // never exit); the smallest estimate wins, and the decision is redone in
+        // compensated arithmetic only when another axis is within the bounds.
         int corner[3], plane[3];
         float est[3], tol[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             corner[a] = w.cell[a] & ~(S - 1);
             plane[a] = corner[a] + (rs.sgn[a] > 0 ? S : 0);
-            if (rs.sgn[a] == 0) {
-                est[a] = INFINITY;
-                tol[a] = 0.0f;
-            } else {
-                const float of = rs.O[a].hi, iv = rs.inv[a].hi;
-                est[a] = ((float)plane[a] - of) * iv;
-                tol[a] = kRel * (fabsf((float)plane[a]) + fabsf(of)) * fabsf(iv) + 1.0e-30f;
-            }
+            const float pf = (float)plane[a], of = rs.O[a].hi, iv = rs.inv[a].hi;
+            const float e = (pf - of) * iv;
+            const float t = kRel * (fabsf(pf) + fabsf(of)) * fabsf(iv) + 1.0e-30f;
+            est[a] = rs.sgn[a] != 0 ? e : INFINITY;
+            tol[a] = rs.sgn[a] != 0 ? t : 0.0f;
         }
-        // exit face: smallest estimate, resolved exactly when another is within the bounds
         int am = 0;
-        {
-            float e = est[0];
-            if (est[1] < e) { am = 1; e = est[1]; }
-            if (est[2] < e) am = 2;
-        }
-        const float e_am = NEUVV_SEL3(est, am), t_am = NEUVV_SEL3(tol, am);
+        float e_am = est[0], t_am = tol[0];
+        if (est[1] < e_am) { am = 1; e_am = est[1]; t_am = tol[1]; }
+        if (est[2] < e_am) { am = 2; e_am = est[2]; t_am = tol[2]; }
         bool exact_ue = false;
-        df ue;
-        {
-            bool near = false;
+        df ue = df_from(0.0f);
+        const bool near = (am != 0 && rs.sgn[0] != 0 && est[0] - e_am <= tol[0] + t_am) ||
+                          (am != 1 && rs.sgn[1] != 0 && est[1] - e_am <= tol[1] + t_am) ||
+                          (am != 2 && rs.sgn[2] != 0 && est[2] - e_am <= tol[2] + t_am);
+        if (near) {
+            // exact: the smallest crossing among the axes within the bounds (first axis on a tie)
+            int best = -1;
 #pragma unroll
-            for (int a = 0; a < 3; ++a)
-                if (a != am && rs.sgn[a] != 0 && est[a] - e_am <= tol[a] + t_am) near = true;
-            if (near) {
-                int best = -1;
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    if (rs.sgn[a] == 0 || est[a] - e_am > tol[a] + t_am) continue;
-                    const df ua = crossing(rs, a, plane[a]);
-                    if (best < 0 || df_lt(ua, ue)) { ue = ua; best = a; }
-                }
-                am = best;
-                exact_ue = true;
+            for (int a = 0; a < 3; ++a) {
+                if (rs.sgn[a] == 0 || est[a] - e_am > tol[a] + t_am) continue;
+                const df ua = crossing(rs, a, plane[a]);
+                if (best < 0 || df_lt(ua, ue)) { ue = ua; best = a; }
             }
+            am = best;
+            exact_ue = true;
         }
+        const int p_am = NEUVV_SEL3(plane, am);
+        const int c_am = NEUVV_SEL3(corner, am);
         float ue_est = exact_ue ? df_f(ue) : e_am;
         const float ue_tol = exact_ue ? 0.0f : t_am;
         // leaving the box?
@@ -616,7 +616,7 @@ __device__ __forceinline__ int walk_next(const TreeArgs& tr, const int4* __restr
         } else if (ue_est + ue_tol < uo - kRel * fabsf(uo)) {
             last = false;
         } else {
-            if (!exact_ue) { ue = crossing(rs, am, NEUVV_SEL3(plane, am)); exact_ue = true; }
+            if (!exact_ue) { ue = crossing(rs, am, p_am); exact_ue = true; }
             last = !df_lt(ue, rs.u_out);
         }
         bool produced = false;
@@ -624,8 +624,8 @@ __device__ __forceinline__ int walk_next(const TreeArgs& tr, const int4* __restr
             df ux;
             if (last) ux = rs.u_out;
             else if (exact_ue) ux = ue;
-            else ux = crossing(rs, am, NEUVV_SEL3(plane, am));
-            const df u0 = entry_param(rs, w);
+            else ux = crossing(rs, am, p_am);
+            const df u0 = w.u_entry_ok ? w.u_entry : entry_param(rs, w);
             if (df_lt(u0, ux)) {
                 delta = df_f(df_sub(ux, u0)) * rs.len_local;
                 umid = 0.5f * (df_f(u0) + df_f(ux));
@@ -638,33 +638,35 @@ __device__ __forceinline__ int walk_next(const TreeArgs& tr, const int4* __restr
         if (last) {
             w.done = true;
         } else {
+            // The next cell: across the exit plane on the exit axis; on the other
+            // axes the cell of the float position at the estimated exit, unless
+            // that position is within its error bound of a cell face, where the
+            // exact position decides.
             int nc[3];
-            bool out = false;
+            bool amb[3];
 #pragma unroll
             for (int b = 0; b < 3; ++b) {
-                int c;
-                if (b == am) {
-                    c = rs.sgn[b] > 0 ? corner[b] + S : corner[b] - 1;
-                    out = c < 0 || c >= G;
-                } else if (rs.sgn[b] == 0) {
-                    c = w.cell[b];
-                } else {
-                    const float of = rs.O[b].hi, dfb = rs.D[b].hi;
-                    const float pf = __builtin_fmaf(ue_est, dfb, of);
-                    const float err = ue_tol * fabsf(dfb) + kRel * (fabsf(of) + fabsf(ue_est * dfb)) + 1.0e-30f;
-                    const float r = rintf(pf);
-                    if (fabsf(pf - r) > err) {
-                        c = rs.sgn[b] > 0 ? (int)floorf(pf) : (int)ceilf(pf) - 1;
-                    } else {
-                        if (!exact_ue) { ue = crossing(rs, am, NEUVV_SEL3(plane, am)); exact_ue = true; }
-                        const df p = df_add(rs.O[b], df_mul(ue, rs.D[b]));
-                        c = df_cell(p, rs.sgn[b]);
-                    }
-                    c = c < corner[b] ? corner[b] : (c > corner[b] + S - 1 ? corner[b] + S - 1 : c);
-                }
-                nc[b] = c;
+                const float of = rs.O[b].hi, dfb = rs.D[b].hi;
+                const float pf = __builtin_fmaf(ue_est, dfb, of);
+                const float err = ue_tol * fabsf(dfb) + kRel * (fabsf(of) + fabsf(ue_est * dfb)) + 1.0e-30f;
+                const float r = rintf(pf);
+                const int cf = rs.sgn[b] > 0 ? (int)floorf(pf) : (int)ceilf(pf) - 1;
+                const bool free_axis = b != am && rs.sgn[b] != 0;
+                amb[b] = free_axis && !(fabsf(pf - r) > err);
+                nc[b] = b == am ? (rs.sgn[b] > 0 ? corner[b] + S : corner[b] - 1) : (rs.sgn[b] == 0 ? w.cell[b] : cf);
             }
-            if (out) {
+            if (amb[0] || amb[1] || amb[2]) {
+                if (!exact_ue) { ue = crossing(rs, am, p_am); exact_ue = true; }
+#pragma unroll
+                for (int b = 0; b < 3; ++b)
+                    if (amb[b]) nc[b] = df_cell(df_add(rs.O[b], df_mul(ue, rs.D[b])), rs.sgn[b]);
+            }
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+                if (b != am && rs.sgn[b] != 0)
+                    nc[b] = nc[b] < corner[b] ? corner[b] : (nc[b] > corner[b] + S - 1 ? corner[b] + S - 1 : nc[b]);
+            const int n_am = NEUVV_SEL3(rs.sgn, am) > 0 ? c_am + S : c_am - 1;
+            if (n_am < 0 || n_am >= G) {
                 w.done = true;
             } else {
                 const unsigned x = (unsigned)((w.cell[0] ^ nc[0]) | (w.cell[1] ^ nc[1]) | (w.cell[2] ^ nc[2]));
@@ -675,8 +677,10 @@ __device__ __forceinline__ int walk_next(const TreeArgs& tr, const int4* __restr
                 w.cell[1] = nc[1];
                 w.cell[2] = nc[2];
                 w.entry_axis = am;
-                w.entry_plane = NEUVV_SEL3(plane, am);
-                w.u_est = ue_est;
+                w.entry_plane = p_am;
+                // the next step's entry parameter is this exit, when it was computed exactly
+                w.u_entry = ue;
+                w.u_entry_ok = exact_ue;
             }
         }
         if (produced) return leaf;
