@@ -18,7 +18,8 @@
  *     of work-queue counters plus a candidate list of 4 bytes per work slot
  *     (rounded up to 64 slots; the adjoint of a traced forward takes two);
  *     the adjoints also take the records of their two-phase reduction (4
- *     bytes per leaf plus 32 bytes per record of room, see there). Scratch
+ *     bytes per leaf plus 32 bytes per record of room, see there), and
+ *     neuvv_render_multi the segment lists of its instances (see there). Scratch
  *     is taken in stream order on the call's stream from a memory pool the
  *     library keeps per device (it keeps freed memory for later calls) and
  *     freed in stream order after the kernels; each call has its own, so
@@ -428,6 +429,12 @@ const char* neuvv_last_error(void);
  * as in neuvv_render (Eq. 8; same early stop; nsamp counts pieces; depth is
  * the weighted mean world distance of the piece midpoints). With one
  * instance the result is neuvv_render's.
+ * Scratch: besides the work-queue counters and candidate lists, 4 KiB, 4
+ * bytes per ray and instance, 4 bytes per work slot, and room for 2 list
+ * entries of 32 bytes per ray and instance (each instance's segments along a
+ * ray, written by a walk of that instance, then merged). Rays whose lists do
+ * not fit that room are rendered by a kernel that walks every instance of the
+ * ray together; the result is the same either way.
  * trees           host array of n_inst tree pointers (the same tree may appear
  *                 several times); K = 16, C = 8, no per-point hyperangle, no
  *                 edits, one storage dtype.

@@ -112,3 +112,39 @@ def test_multi_16bit(scenes, dtype):
     ref = ref_multi([sc, sc, sc], [a[0], b[0], a[0]], o, d, 2.0, 1e-4, dtype)
     gpu = gpu_multi([tree, tree, tree], [a[1], b[1], a[1]], o, d, 2.0, 1e-4, 64)
     compare(gpu, ref, label=f"multi dtype={dtype}")
+
+
+def test_lists_and_fused_fallback_agree(scenes):
+    """The two-phase merge gives every ray 2 list entries per instance of room; rays whose
+    lists do not fit are rendered by the fused kernel instead. Rays with at least 8 composited
+    intervals, rendered alone, cannot all fit (each composited interval ends at a list entry of
+    some instance), so part of them take the fused kernel; rendered among 100x as many rays that
+    miss every instance, their lists fit. Both calls must agree, and match the oracle."""
+    sc = scenes[0]
+    tree = upload(sc)
+    cam = tiny_camera(sc)
+    o, d = OC.pinhole_rays(64, 64, cam.intr(), cam.c2w)
+    a = around_centre(sc, 0.0, [0.0, 0.0, 0.0])
+    b = around_centre(sc, 0.8, [2.0, 1.0, -1.0], 0.9, 7.0, 1)
+    first = gpu_multi([tree, tree], [a[1], b[1]], o, d, 4.0, 1e-4)
+    keep = first["nsamp"] >= 8
+    o, d = o[keep], d[keep]
+    n = o.shape[0]
+    assert n >= 200, n
+    announce(f"multi L=2: {n} rays alone and among {100 * n} missing rays")
+    alone = gpu_multi([tree, tree], [a[1], b[1]], o, d, 4.0, 1e-4)
+    assert alone["nsamp"].sum() > 2 * 2 * n            # more intervals than the room of the call holds
+    om = np.tile(np.array([[-1.0e4, -1.0e4, -1.0e4]], np.float32), (100 * n, 1))
+    dm = np.tile(np.array([[-1.0, 0.25, 0.0]], np.float32), (100 * n, 1))
+    among = gpu_multi([tree, tree], [a[1], b[1]], np.concatenate([o, om]), np.concatenate([d, dm]), 4.0, 1e-4)
+    assert np.all(among["nsamp"][n:] == 0) and np.all(among["alpha"][n:] == 0.0)
+    for k in ("rgb", "alpha", "depth", "nsamp"):
+        x, y = alone[k], among[k][:n]
+        fin = np.isfinite(y)
+        assert np.array_equal(np.isfinite(x), fin), k
+        err = np.abs(x[fin] - y[fin]).max() if fin.any() else 0.0
+        announce(f"alone vs among, {k}: max-abs {err:.2e}")
+        assert err <= (0 if k == "nsamp" else 1e-6 * max(1.0, np.abs(y[fin]).max())), (k, err)
+    ref = ref_multi([sc, sc], [a[0], b[0]], o, d, 4.0, 1e-4)
+    compare(alone, ref, label="multi L=2 rays alone")
+    compare({k: v[:n] for k, v in among.items()}, ref, label="multi L=2 rays among missing rays")
