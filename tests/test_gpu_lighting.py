@@ -96,3 +96,48 @@ def test_shadow_and_falloff_chain():
     announce(f"lighting chain max-abs {err:.2e}; shadowed ground pixels {int(sh.sum())}")
     assert sh.sum() > 50
     assert err <= 2e-5, err
+
+
+def test_light_map_on_a_second_stream():
+    """The lit frame as the benchmark times it: the light map and its low-pass on a second
+    stream while the viewer render runs, the shading waiting for both. Bit-identical to the
+    same calls made one after the other."""
+    import torch
+    sc = scene_for_workload("tiny")
+    tree = upload(sc)
+    ol, gl = make_light(sc, k=0.8, r0=30.0)
+    lo, ld = ops.pinhole_rays(gl.camera)
+    o, d = viewer_rays(sc)
+    oo, dd = tdev(o), tdev(d)
+    announce("lighting chain with the light map on a second stream")
+    _, la, _, _ = ops.render(tree, lo, ld, 3.0, None, 1e-4, ol.width)
+    ref_map = ops.blur(la.view(ol.height, ol.width), 1.5)
+    rgb, alpha, depth, ns = ops.render(tree, oo, dd, 3.0, None, 1e-4, 96)
+    ref = ops.shade(gl, ref_map, oo, dd, rgb, alpha, depth)
+    torch.cuda.synchronize()
+    main = torch.cuda.current_stream()
+    side = torch.cuda.Stream()
+    la2 = torch.full_like(la, -1.0)
+    lrgb2 = torch.empty(la.shape[0], 3, device=la.device)
+    lns2 = torch.empty(la.shape[0], dtype=torch.int32, device=la.device)
+    smap2 = torch.full_like(ref_map, -1.0)
+    rgb2, alpha2, depth2 = torch.full_like(rgb, -1.0), torch.full_like(alpha, -1.0), torch.full_like(depth, -1.0)
+    ns2 = torch.full_like(ns, -1)
+    out2 = torch.full_like(ref, -1.0)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        go, ready = torch.cuda.Event(), torch.cuda.Event()
+        go.record(main)
+        side.wait_event(go)
+        _lib.neuvv_render(tree.struct(), None, la.shape[0], lo, ld, None, 3.0, ol.width, 1e-4, lrgb2, la2, None,
+                          lns2, side)
+        _lib.neuvv_blur(ol.height, ol.width, la2, 1.5, smap2, side)
+        ready.record(side)
+        _lib.neuvv_render(tree.struct(), None, oo.shape[0], oo, dd, None, 3.0, 96, 1e-4, rgb2, alpha2, depth2, ns2,
+                          main)
+        main.wait_event(ready)
+        _lib.neuvv_shade(gl, smap2, oo.shape[0], oo, dd, rgb2, alpha2, depth2, out2, main)
+        torch.cuda.synchronize()
+        assert torch.equal(smap2, ref_map)
+        assert torch.equal(rgb2, rgb) and torch.equal(alpha2, alpha) and torch.equal(ns2, ns)
+        assert torch.equal(out2, ref)

@@ -66,9 +66,9 @@ def test_training_step_full_size():
     ref = oracle_render(sc, ro, rd, t, 0.0, 1e-4, g_rgb=gC)
     amb_dev = torch.from_numpy(amb).to(DEV)
     # the plain calls, then the traced pair exactly as the benchmark's training step runs it
-    # (trace room for two samples per ray, the loss gradient from the traced forward's output)
+    # (trace room for sixteen samples per ray, the loss gradient from the traced forward's output)
     for traced in (False, True):
-        trace = ops.Trace(n, 2 * n, DEV) if traced else None
+        trace = ops.Trace(n, 16 * n, DEV) if traced else None
         announce(f"training step, traced={traced}")
         rgb, alpha, depth, nsamp = ops.render(tree, o, d, tt, None, 1e-4, trace=trace)
         g = 2.0 * (rgb - target)                     # d/dC of sum ||C - C*||^2 (Eq. 10)
@@ -78,6 +78,8 @@ def test_training_step_full_size():
         torch.cuda.synchronize()
         gpu = dict(rgb=rgb.cpu().numpy().astype(np.float64), alpha=alpha.cpu().numpy().astype(np.float64),
                    depth=depth.cpu().numpy().astype(np.float64), nsamp=nsamp.cpu().numpy())
+        if traced:   # the room holds every sample with margin: the adjoint replays every ray
+            assert 2 * int(gpu["nsamp"].sum()) <= trace.cap, (int(gpu["nsamp"].sum()), trace.cap)
         compare({k: v[same] for k, v in gpu.items()}, {k: v[same] for k, v in ref_f.items()},
                 label=f"train fwd traced={traced}")
         hh, ws = tree.unpack_grad(gl)
@@ -151,9 +153,12 @@ def test_multi_primitive_composition_full_size():
     cs = _lib.make_camera(W, H, cam.fx, cam.fy, cam.cx, cam.cy, cam.c2w)
     o, d = ops.pinhole_rays(cs)
     t = 37.5
-    announce("multi-primitive: rendering 4 layers")
+    announce("multi-primitive: rendering 4 layers (traced, as the benchmark's step)")
     trees = [upload(s, _lib.F16) for s in scenes]
-    layers = [ops.render(tr, o, d, t, ins[1], 1e-4, W) for tr, ins in zip(trees, insts)]
+    traces = [ops.Trace(W * H, 4 * W * H, DEV) for _ in trees]
+    layers = [ops.render(tr, o, d, t, ins[1], 1e-4, W, trace=tc) for tr, ins, tc in zip(trees, insts, traces)]
+    for l, tc in zip(layers, traces):   # the room holds every sample: the adjoints replay every ray
+        assert 2 * int(l[3].sum()) <= tc.cap
     rgb_l = torch.stack([l[0] for l in layers])
     a_l = torch.stack([l[1] for l in layers])
     d_l = torch.stack([l[2] for l in layers])
@@ -214,7 +219,7 @@ def test_multi_primitive_composition_full_size():
     for i, (tr, ins, s) in enumerate(zip(trees, insts, scenes)):
         l = layers[i]
         gl, gb = ops.render_backward(tr, o, d, l[0], l[1], l[3], g_rgb_l[i].contiguous(), g_a_l[i].contiguous(), t,
-                                     ins[1], 1e-4, W)
+                                     ins[1], 1e-4, W, trace=traces[i])
         torch.cuda.synchronize()
         ref = oracle_render(s, ro, rd, None, t, 1e-4, inst=ins[0], dtype=_lib.F16, g_rgb=q_rgb[i], g_alpha=q_a[i])
         hh, ws = tr.unpack_grad(gl)
