@@ -267,7 +267,8 @@ static __global__ void zero_queue_kernel(unsigned long long* q) { q[threadIdx.x]
 // write the miss outputs of the others. MODE 1 (adjoint): keep the rays whose
 // forward composited a sample (the others carry no gradient); MODE 2 and 3
 // (adjoint of a traced forward): of those, the rays without a trace (head
-// < 0) and the rays with one. The
+// < 0) and the rays with one. MODE 4: keep the rays hit.keep(ray) accepts
+// and write the miss outputs of the others (no ray loads). The
 // pass is bound by the 24 bytes of ray per slot it reads; at high occupancy
 // it runs near HBM bandwidth, where the render kernel's refill rounds would
 // take one memory latency per round for every ray.
@@ -328,6 +329,9 @@ static __global__ __launch_bounds__(kBlock) void cull_kernel(Hit hit, RayArgs ra
                         const float d[3] = {dv.x, dv.y, dv.z};
                         k = hit(o, d);
                         if (!k) write_miss(out, ray);
+                    } else if constexpr (MODE == 4) {
+                        k = hit.keep(ray);
+                        if (!k) write_miss(out, ray);
                     } else {
                         k = nsamp[ray] > 0;
                         if constexpr (MODE == 2) k = k && head[ray] < 0;
@@ -379,6 +383,9 @@ static __global__ __launch_bounds__(kBlock) void cull_kernel(Hit hit, RayArgs ra
                     const float o[3] = {ov.x, ov.y, ov.z};
                     const float d[3] = {dv.x, dv.y, dv.z};
                     k = hit(o, d);
+                    if (!k) write_miss(out, ray);
+                } else if constexpr (MODE == 4) {
+                    k = hit.keep(ray);
                     if (!k) write_miss(out, ray);
                 } else {
                     k = nsamp[ray] > 0;

@@ -423,6 +423,20 @@ __device__ __forceinline__ void load_entry(const int4* __restrict__ ent, int slo
     next = B.z;
 }
 
+// Cull of phase 2: a ray is worth merging when some instance gave it a list
+// (or ran out of room for it); the others get the miss outputs.
+template <int L>
+struct AnyList {
+    const int32_t* head;
+    int64_t n;
+    __device__ __forceinline__ bool keep(int64_t ray) const {
+        bool k = false;
+#pragma unroll
+        for (int i = 0; i < L; ++i) k = k || head[(int64_t)i * n + ray] != -1;
+        return k;
+    }
+};
+
 template <int L>
 __global__ __launch_bounds__(kBlock) void merge_lists_kernel(RayArgs ra, const int32_t* __restrict__ head,
                                                              const int4* __restrict__ ent, float t_stop,
@@ -471,7 +485,7 @@ __global__ __launch_bounds__(kBlock) void merge_lists_kernel(RayArgs ra, const i
                             }
                             if (!fb) {
                                 if (any) cand = true;
-                                else write_miss(out, ray);
+                                else write_miss(out, ray);   // (the cull pass has listed only rays with lists)
                             }
                         }
                     }
@@ -567,9 +581,9 @@ static hipError_t multi_lists(const MultiArgs& ma, const RayArgs& ra, float t_st
                               hipStream_t st) {
     const int64_t n = ra.n;
     const int64_t cap = kMergeRoomPerRay * L * n;
-    // scratch: 4 KiB of counters (entries handed out; phase 2's work queue; the
+    // scratch: 4 KiB of counters (entries handed out; 1 KiB unused; the
     // fallback launch's work queue and list counts), the heads, the fallback
-    // list, the entries
+    // list, the entries (phase 2's candidate list comes from with_list)
     constexpr size_t hdr = 4096;
     const size_t head_b = ((size_t)L * n * sizeof(int32_t) + 255) & ~(size_t)255;
     const size_t list_b = ((size_t)((ra.n_slots + 63) >> 6) * 64 * sizeof(int32_t) + 255) & ~(size_t)255;
@@ -578,7 +592,6 @@ static hipError_t multi_lists(const MultiArgs& ma, const RayArgs& ra, float t_st
     if (e != hipSuccess) return e;
     char* p = static_cast<char*>(mem);
     auto* counter = reinterpret_cast<unsigned long long*>(p);
-    auto* q_merge = reinterpret_cast<unsigned long long*>(p + 1024);
     auto* q_fb = reinterpret_cast<unsigned long long*>(p + 2048);
     auto* cnt_fb = reinterpret_cast<unsigned long long*>(p + 3072);
     auto* head = reinterpret_cast<int32_t*>(p + hdr);
@@ -604,14 +617,18 @@ static hipError_t multi_lists(const MultiArgs& ma, const RayArgs& ra, float t_st
         });
     }
     if (e == hipSuccess) {
-        RayArgs rm = ra;
-        rm.queue = q_merge;
-        rm.list = nullptr;
-        rm.count = nullptr;
-        auto kern = merge_lists_kernel<L>;
-        hipLaunchKernelGGL(kern, dim3(grid_for(kern, rm)), dim3(kBlock), 0, st, rm, head, ent, t_stop, o, fb_list,
-                           cnt_fb);
-        e = hipGetLastError();
+        // phase 2 over the rays with lists (a cull pass lists them and writes the misses)
+        e = with_list(
+            ra, st,
+            [&](int32_t* list, unsigned long long* count) {
+                return launch_cull_hit<4>(AnyList<L>{head, n}, ra, o, nullptr, nullptr, list, count, st);
+            },
+            [&](const RayArgs& rm) {
+                auto kern = merge_lists_kernel<L>;
+                hipLaunchKernelGGL(kern, dim3(grid_for(kern, rm)), dim3(kBlock), 0, st, rm, head, ent, t_stop, o,
+                                   fb_list, cnt_fb);
+                return hipGetLastError();
+            });
     }
     if (e == hipSuccess) {
         // the rays listed by phase 2 (all in the first part of the list)
