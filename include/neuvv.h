@@ -302,7 +302,9 @@ int neuvv_render_noalloc(const neuvv_tree* tree, const neuvv_instance* inst, int
  * Two-phase adjoint: each sample's dL/dz and dL/dsigma (and dL/dy, Cg > 0)
  * are written once as a 32-byte record linked into its leaf's list; a second
  * kernel sums every list and adds each touched leaf's row once. The room for
- * records is 2 per ray, at least 2^20, at most 2^31 - 1 (the environment
+ * records is 2 per ray, or the trace's room (trace_cap) in
+ * neuvv_render_backward_trace when that is more, at least 2^20, at most
+ * 2^31 - 1 (the environment
  * variable NEUVV_BWD_RECORDS, read at every call, sets it; 0 turns records
  * off); samples beyond it are added per sample in the same call. Records
  * are used with image_width or not, for n_rays and n_leaves below 2^31, and

@@ -140,11 +140,13 @@ int make_rays(int64_t n, const float* o, const float* d, const float* t, float t
 }
 
 // Sample records of the two-phase adjoint: NEUVV_BWD_RECORDS overrides (0
-// turns the records off); by default room for two samples per ray, at least
-// 2^20, at most 2^31 - 1. Samples beyond the room take per-sample atomics.
-int64_t record_cap(int64_t n_rays) {
+// turns the records off); by default room for two samples per ray or, after a
+// traced forward, for as many samples as the trace has room for if that is
+// more (every replayed sample has a trace entry); at least 2^20, at most
+// 2^31 - 1. Samples beyond the room take per-sample atomics.
+int64_t record_cap(int64_t n_rays, int64_t trace_cap) {
     const char* e = getenv("NEUVV_BWD_RECORDS");
-    int64_t cap = 2 * n_rays;
+    int64_t cap = 2 * n_rays > trace_cap ? 2 * n_rays : trace_cap;
     if (cap < (int64_t)1 << 20) cap = (int64_t)1 << 20;
     if (e && *e) cap = atoll(e);
     if (cap < 0) cap = 0;
@@ -316,7 +318,7 @@ static int backward_impl(const neuvv_tree* tree, const neuvv_instance* inst, int
     if (tree->n_leaves > 0 && !grad_leaf) return fail(NEUVV_ERR_ARG, "grad_leaf is NULL");
     if (tree->edit) return fail(NEUVV_ERR_UNSUPPORTED, "no adjoint through appearance edits");
     neuvv::BackwardIO io{rgb, alpha, nsamp, grad_rgb, grad_alpha, grad_leaf, grad_basis,
-                         tree->Cg > 0 ? grad_basis_g : nullptr, record_cap(n_rays)};
+                         tree->Cg > 0 ? grad_basis_g : nullptr, record_cap(n_rays, trace ? trace_cap : 0)};
     if (trace) io.trace = neuvv::trace_layout(const_cast<void*>(trace), n_rays, trace_cap);
     const hipError_t e = tree->Cg > 0
                              ? neuvv::launch_render_pp_bwd(tree->dtype, tree_args(tree), in, ra, io,
