@@ -368,6 +368,8 @@ def workload_bench(args):
                    config={"workload": "train_d8_500k_65536rays", "leaves": sc.n_leaves, "rays_per_step": n,
                            "step": "traced render + L2 loss gradient + adjoint, per-ray t"})
         log(f"train: {ms:.3f} ms per step ({n} rays, {sc.n_leaves} leaves)")
+        if not args.no_cpu_baseline:
+            out["cpu_baseline"] = train_cpu(sc, tgt, cams, ci, pix, t.cpu().numpy(), t_stop)
     elif args.workload == "mixed":
         sc = scene_for_workload("mixed")
         W = H = 2048
@@ -397,6 +399,8 @@ def workload_bench(args):
         out.update(value=per["f16"]["mrays_s"], ms_per_step=per["f16"]["ms_per_stereo_frame"], dtype="f16",
                    config={"workload": "mixed_d10_8M_stereo2048", "leaves": sc.n_leaves, "rays_per_step": n,
                            "step": "forward of one stereo frame", "per_dtype": per})
+        if not args.no_cpu_baseline:
+            out["cpu_baseline"] = mixed_cpu(sc, eyes, W, H, t, t_stop)
     else:
         W, H = 1920, 1080
         scenes = [make_scene(9, 2_000_000, "human", K=16, C=8, T=300, seed=50 + i) for i in range(4)]
@@ -434,7 +438,82 @@ def workload_bench(args):
                            "rays_per_step": n,
                            "step": "4 traced layer renders + compose + compose adjoint + 4 replaying adjoints"})
         log(f"multi: {ms:.3f} ms per step (4 layers of {n} rays)")
+        if not args.no_cpu_baseline:
+            out["cpu_baseline"] = multi_cpu(scenes, multi_instances(G, 4, seed=55), cam, W, H, t, t_stop)
     print(json.dumps(out), flush=True)
+
+
+def _oracle_threads():
+    from oracle import core as OC
+    OC.build(force=False)
+    return OC, OC.default_threads()
+
+
+def train_cpu(sc, tgt, cams, ci, pix, t, t_stop):
+    """The training step on the host: the FP64 oracle's forward of the step's rays, the L2 loss
+    gradient against the oracle's target render, and the oracle's forward + gradient."""
+    OC, threads = _oracle_threads()
+    W, H = 960, 540
+    o = np.zeros((pix.size, 3), np.float32)
+    d = np.zeros((pix.size, 3), np.float32)
+    for c in range(len(cams)):
+        m = ci == c
+        o[m], d[m] = OC.pinhole_rays(W, H, cams[c].intr(), cams[c].c2w, pix[m])
+    target = OC.render(tgt.depth, tgt.leaf_ijk, tgt.hh, tgt.wsig, tgt.basis, tgt.gamma, o, d, t, 0.0, t_stop,
+                       threads=threads)["rgb"]
+    t0 = time.perf_counter()
+    fwd = OC.render(sc.depth, sc.leaf_ijk, sc.hh, sc.wsig, sc.basis, sc.gamma, o, d, t, 0.0, t_stop, threads=threads)
+    OC.render(sc.depth, sc.leaf_ijk, sc.hh, sc.wsig, sc.basis, sc.gamma, o, d, t, 0.0, t_stop,
+              g_rgb=2.0 * (fwd["rgb"] - target), threads=threads)
+    dt = time.perf_counter() - t0
+    log(f"train on the host: {pix.size} rays in {dt:.2f}s")
+    return {"value": round(pix.size / dt / 1e6, 5), "unit": "Mrays/s", "cores": threads, "kind": "oracle",
+            "sample": f"one step's {pix.size} rays: FP64 forward, loss gradient, forward + gradient",
+            "host": OC.host_description()}
+
+
+def mixed_cpu(sc, eyes, W, H, t, t_stop, stride=61):
+    """The stereo frame's forward on the host: the FP64 oracle on every stride-th pixel of both eyes."""
+    OC, threads = _oracle_threads()
+    pix = np.arange(0, W * H, stride, dtype=np.int32)
+    dt = 0.0
+    for cam in eyes:
+        o, d = OC.pinhole_rays(W, H, cam.intr(), cam.c2w, pix)
+        t0 = time.perf_counter()
+        OC.render(sc.depth, sc.leaf_ijk, sc.hh, sc.wsig, sc.basis, sc.gamma, o, d, None, t, t_stop, threads=threads)
+        dt += time.perf_counter() - t0
+    n = 2 * pix.size
+    log(f"mixed on the host: {n} rays in {dt:.2f}s")
+    return {"value": round(n / dt / 1e6, 5), "unit": "Mrays/s", "cores": threads, "kind": "oracle",
+            "sample": f"every {stride}th pixel of both eyes ({n} rays), FP64 forward on the unrounded payload",
+            "host": OC.host_description()}
+
+
+def multi_cpu(scenes, places, cam, W, H, t, t_stop, stride=31):
+    """The multi-primitive step on the host for every stride-th pixel: the FP64 oracle's four
+    layer renders, compose (Alg. 1) and its adjoint, and the four layers' forward + gradient."""
+    OC, threads = _oracle_threads()
+    pix = np.arange(0, W * H, stride, dtype=np.int32)
+    o, d = OC.pinhole_rays(W, H, cam.intr(), cam.c2w, pix)
+    insts = [OC.Instance(np.asarray(p["rot"], np.float32), np.asarray(p["trans"], np.float32), p["scale"],
+                         p["time_offset"], p["wrap"]) for p in places]
+    g_out = np.random.default_rng(5005).normal(size=(pix.size, 3))
+    t0 = time.perf_counter()
+    layers = [OC.render(s.depth, s.leaf_ijk, s.hh, s.wsig, s.basis, s.gamma, o, d, None, t, t_stop, inst,
+                        threads=threads) for s, inst in zip(scenes, insts)]
+    R = np.stack([l["rgb"] for l in layers]); A = np.stack([l["alpha"] for l in layers])
+    D = np.stack([l["depth"] for l in layers])
+    OC.compose(R, A, D)
+    q_rgb, q_a = OC.compose_grad(R, A, D, g_out, np.zeros(pix.size))
+    for i, (s, inst) in enumerate(zip(scenes, insts)):
+        OC.render(s.depth, s.leaf_ijk, s.hh, s.wsig, s.basis, s.gamma, o, d, None, t, t_stop, inst,
+                  g_rgb=q_rgb[i], g_alpha=q_a[i], threads=threads)
+    dt = time.perf_counter() - t0
+    log(f"multi on the host: {pix.size} pixels in {dt:.2f}s")
+    return {"value": round(pix.size / dt / 1e6, 5), "unit": "Mrays/s", "cores": threads, "kind": "oracle",
+            "sample": f"every {stride}th pixel ({pix.size} pixels): FP64 layer renders, compose and its adjoint, "
+                      "layer forward + gradient, on the unrounded payload",
+            "host": OC.host_description()}
 
 
 def multi_leg(sc, tree, L, ray_o, ray_d, t_frame, t_stop, W, fwd_ms, stream, steps):
