@@ -530,6 +530,34 @@ __device__ __forceinline__ int64_t take_items(unsigned long long* counter, int64
     return at;
 }
 
+// Linking one iteration's records into their leaves' lists. The records of
+// the lanes with a sample (mask hm) are consecutive in lane order. A run is a
+// maximal sequence of such lanes, consecutive in that order, on one leaf: its
+// first lane links the whole run with one atomic exchange of the leaf's head
+// (the head becomes the run's last record, and the first record links to the
+// old head), and every other lane links its record to the record before it.
+// count: the run's length for its first lane, 0 for the others. Call with
+// every lane of the wavefront active.
+struct RecordRun {
+    int count;
+};
+__device__ __forceinline__ RecordRun record_run(uint64_t hm, bool has, int leaf) {
+    const int lane = threadIdx.x & 63;
+    const uint64_t below = (1ull << lane) - 1ull;
+    const uint64_t hb = hm & below;
+    const int pred = hb ? 63 - __builtin_clzll(hb) : lane;   // the previous lane with a sample
+    const int pleaf = __builtin_amdgcn_ds_bpermute(pred << 2, leaf);
+    const bool start = has && (hb == 0ull || pleaf != leaf);
+    const uint64_t starts = __ballot(start);
+    RecordRun r{0};
+    if (start) {
+        const uint64_t later = starts & ~((2ull << lane) - 1ull);   // starts above this lane (none: lane 63)
+        const uint64_t upto = later ? (1ull << __builtin_ctzll(later)) - 1ull : ~0ull;
+        r.count = __popcll(hm & upto & ~below);
+    }
+    return r;
+}
+
 // Hands leaves with records to the idle lanes of a reduction wavefront.
 // Wavefront w takes 64-leaf batches w, w + W, ...; a batch's heads are read in
 // one load (lane = leaf) and its leaves with records are compacted into a

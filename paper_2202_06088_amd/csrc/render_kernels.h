@@ -490,11 +490,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(min_wave
             const int n_has = __popcll(hm);
             const int64_t at = n_has > 0 ? take_items(rec.counter, rec.cap, cc.home, n_has, wrec, wend) : -1;
             if (at >= 0) {
+                const RecordRun run = record_run(hm, has, leaf);
                 if (has) {
                     my_rec = (int)(at + lane_rank(hm));
                     rec.rec[2 * (int64_t)my_rec] =
                         make_int4(__float_as_int(gz0), __float_as_int(gz1), __float_as_int(gz2), __float_as_int(gx));
-                    const int nxt = atomicExch(rec.head + leaf, my_rec);
+                    const int nxt = run.count > 0 ? atomicExch(rec.head + leaf, my_rec + run.count - 1) : my_rec - 1;
                     // one time for every ray: the record carries the ray's direction
                     // (all the reduction needs of the ray), else the ray's index
                     rec.rec[2 * (int64_t)my_rec + 1] =

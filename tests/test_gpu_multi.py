@@ -148,3 +148,32 @@ def test_lists_and_fused_fallback_agree(scenes):
     ref = ref_multi([sc, sc], [a[0], b[0]], o, d, 4.0, 1e-4)
     compare(alone, ref, label="multi L=2 rays alone")
     compare({k: v[:n] for k, v in among.items()}, ref, label="multi L=2 rays among missing rays")
+
+
+def test_multi_per_ray_time(scenes):
+    """Rays with their own time: each ray takes one of three times, and every group matches the
+    merge oracle run with that time for all its rays."""
+    sc = scenes[0]
+    tree = upload(sc)
+    cam = tiny_camera(sc)
+    o, d = OC.pinhole_rays(64, 64, cam.intr(), cam.c2w)
+    a = around_centre(sc, 0.0, [0.0, 0.0, 0.0], 1.0, 0.0, 1)
+    b = around_centre(sc, 0.8, [2.0, 1.0, -1.0], 0.9, 7.0, 1)
+    times = np.array([0.0, 4.25, 17.5], np.float32)
+    which = np.arange(o.shape[0]) % 3
+    t = times[which]
+    n = o.shape[0]
+    announce("multi L=2 with per-ray times")
+    rgb = torch.empty(n, 3, device="cuda")
+    alpha = torch.empty(n, device="cuda")
+    depth = torch.empty(n, device="cuda")
+    nsamp = torch.empty(n, dtype=torch.int32, device="cuda")
+    _lib.neuvv_render_multi([tree.struct(), tree.struct()], [a[1], b[1]], n, tdev(o), tdev(d), tdev(t), 0.0, 0,
+                            1e-4, rgb, alpha, depth, nsamp)
+    torch.cuda.synchronize()
+    gpu = dict(rgb=rgb.cpu().numpy().astype(np.float64), alpha=alpha.cpu().numpy().astype(np.float64),
+               depth=depth.cpu().numpy().astype(np.float64), nsamp=nsamp.cpu().numpy())
+    for k, tk in enumerate(times):
+        m = which == k
+        ref = ref_multi([sc, sc], [a[0], b[0]], o[m], d[m], float(tk), 1e-4)
+        compare({key: v[m] for key, v in gpu.items()}, ref, label=f"multi per-ray t = {tk}")
