@@ -267,7 +267,8 @@ static __global__ void zero_queue_kernel(unsigned long long* q) { q[threadIdx.x]
 // write the miss outputs of the others. MODE 1 (adjoint): keep the rays whose
 // forward composited a sample (the others carry no gradient); MODE 2 and 3
 // (adjoint of a traced forward): of those, the rays without a trace (head
-// < 0) and the rays with one. MODE 4: keep the rays hit.keep(ray) accepts
+// < 0, none when out.trace says every trace is complete) and the rays with
+// one. MODE 4: keep the rays hit.keep(ray) accepts
 // and write the miss outputs of the others (no ray loads). The
 // pass is bound by the 24 bytes of ray per slot it reads; at high occupancy
 // it runs near HBM bandwidth, where the render kernel's refill rounds would
@@ -289,6 +290,10 @@ static __global__ __launch_bounds__(kBlock) void cull_kernel(Hit hit, RayArgs ra
                                                               const int32_t* nsamp, const int32_t* head,
                                                               int32_t* list,
                                                               unsigned long long* count) {
+    if constexpr (MODE == 2) {
+        // after a traced forward whose traces are all complete no ray walks
+        if (out.trace.counter && out.trace.counter[kTraceBroken] == 0ull) return;
+    }
     const int lane = threadIdx.x & 63;
     const int x = (int)(blockIdx.x & (kQueues - 1));
     const int64_t n_chunks = (ra.n_slots + 63) >> 6;

@@ -255,8 +255,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) 
                 if (at >= 0 && t_first != -2) {
                     cur = (int)(at + lane_rank(hm));
                     if (t_first == -1) t_first = cur;
-                } else {
+                } else if (t_first != -2) {
                     t_first = -2;   // incomplete: the adjoint walks this ray
+                    out.trace.counter[kTraceBroken] = 1ull;
                 }
             }
         }
@@ -824,9 +825,11 @@ static hipError_t pp_bwd_t(const TreeArgs& tr, const InstArgs& in, const RayArgs
         // (traced forward) rays that replay their trace
         auto walk = [&](const RayArgs& r) { return pp_bwd_k<DT, false>(tr, in, r, io, rec, st); };
         auto replay = [&](const RayArgs& r) { return pp_bwd_k<DT, true>(tr, in, r, io, rec, st); };
+        // the walking adjoint's cull reads whether the forward's traces are all complete
+        const RenderOut trace_out{nullptr, nullptr, nullptr, nullptr, nullptr, io.trace};
         if (io.trace.head) {
             if (ra.n > (int64_t)INT32_MAX) e = hipErrorInvalidValue;   // traced calls take candidate lists
-            if (e == hipSuccess) e = with_candidates<2>(tr, in, ra, RenderOut{}, io.nsamp, st, walk, io.trace.head);
+            if (e == hipSuccess) e = with_candidates<2>(tr, in, ra, trace_out, io.nsamp, st, walk, io.trace.head);
             if (e == hipSuccess) e = with_candidates<3>(tr, in, ra, RenderOut{}, io.nsamp, st, replay, io.trace.head);
         } else {
             e = with_candidates<1>(tr, in, ra, RenderOut{}, io.nsamp, st, walk);
