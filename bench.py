@@ -108,7 +108,7 @@ def main():
         calibrate_copy()
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}). "
+        print(f"bench.py measures one GPU: the library has no multi-GPU path (asked for --gpus {args.gpus}). "
               "Rays are independent, so N GPUs would each render a share of the ring; run with --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
