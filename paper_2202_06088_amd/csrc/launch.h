@@ -18,14 +18,9 @@ struct TraceArgs {
                                    // {leaf, delta, x, c_r} {c_g, c_b, next (-1: last), 0}; per-point form,
                                    // two: {leaf, delta, x, y} {c_r, c_g, c_b, next} {dz/dgamma [3], 0} {-}
     unsigned long long* counter;   // kQueues counters 128 bytes apart: the first 1024 bytes of a 2048-byte
-                                   // header whose second half takes the stores of samples without a slot;
-                                   // counter[kTraceBroken] becomes 1 when a ray's samples did not all fit
+                                   // header whose second half takes the stores of samples without a slot
     int64_t cap;
 };
-// Word of the trace header (between the first two counters) that the traced
-// forward sets when some ray's trace is incomplete; while it is 0 the adjoint
-// has no ray to walk and its cull pass for such rays ends at once.
-constexpr int kTraceBroken = 1;
 // Bytes of a trace buffer for n rays and room for cap samples, and its layout.
 size_t trace_bytes(int64_t n, int64_t cap);
 TraceArgs trace_layout(void* buf, int64_t n, int64_t cap);

@@ -267,8 +267,8 @@ static __global__ void zero_queue_kernel(unsigned long long* q) { q[threadIdx.x]
 // write the miss outputs of the others. MODE 1 (adjoint): keep the rays whose
 // forward composited a sample (the others carry no gradient); MODE 2 and 3
 // (adjoint of a traced forward): of those, the rays without a trace (head
-// < 0, none when out.trace says every trace is complete) and the rays with
-// one. MODE 4: keep the rays hit.keep(ray) accepts
+// < 0, none when out.trace's counters show that every request for trace
+// room was met) and the rays with one. MODE 4: keep the rays hit.keep(ray) accepts
 // and write the miss outputs of the others (no ray loads). The
 // pass is bound by the 24 bytes of ray per slot it reads; at high occupancy
 // it runs near HBM bandwidth, where the render kernel's refill rounds would
@@ -291,8 +291,18 @@ static __global__ __launch_bounds__(kBlock) void cull_kernel(Hit hit, RayArgs ra
                                                               int32_t* list,
                                                               unsigned long long* count) {
     if constexpr (MODE == 2) {
-        // after a traced forward whose traces are all complete no ray walks
-        if (out.trace.counter && out.trace.counter[kTraceBroken] == 0ull) return;
+        // After a traced forward, out.trace holds its allocation counters and the
+        // room in samples. A trace is incomplete only where a block request of its
+        // XCD part went past the part's end; with none, no ray walks.
+        if (out.trace.counter) {
+            bool over = false;
+#pragma unroll
+            for (int p = 0; p < kQueues; ++p) {
+                const int64_t part = out.trace.cap * (p + 1) / kQueues - out.trace.cap * p / kQueues;
+                over = over || (int64_t)out.trace.counter[p * kQueueStride] > part;
+            }
+            if (!over) return;
+        }
     }
     const int lane = threadIdx.x & 63;
     const int x = (int)(blockIdx.x & (kQueues - 1));

@@ -185,9 +185,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(min_wave
                 if (at >= 0 && t_first != -2) {
                     cur = (int)(at + lane_rank(hm));
                     if (t_first == -1) t_first = cur;
-                } else if (t_first != -2) {
+                } else {
                     t_first = -2;   // incomplete: the adjoint walks this ray
-                    out.trace.counter[kTraceBroken] = 1ull;
                 }
             }
         }

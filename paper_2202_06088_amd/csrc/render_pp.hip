@@ -255,9 +255,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) 
                 if (at >= 0 && t_first != -2) {
                     cur = (int)(at + lane_rank(hm));
                     if (t_first == -1) t_first = cur;
-                } else if (t_first != -2) {
+                } else {
                     t_first = -2;   // incomplete: the adjoint walks this ray
-                    out.trace.counter[kTraceBroken] = 1ull;
                 }
             }
         }
@@ -826,7 +825,9 @@ static hipError_t pp_bwd_t(const TreeArgs& tr, const InstArgs& in, const RayArgs
         auto walk = [&](const RayArgs& r) { return pp_bwd_k<DT, false>(tr, in, r, io, rec, st); };
         auto replay = [&](const RayArgs& r) { return pp_bwd_k<DT, true>(tr, in, r, io, rec, st); };
         // the walking adjoint's cull reads whether the forward's traces are all complete
-        const RenderOut trace_out{nullptr, nullptr, nullptr, nullptr, nullptr, io.trace};
+        TraceArgs room = io.trace;
+        room.cap = io.trace.cap / 2;   // two entries per sample
+        const RenderOut trace_out{nullptr, nullptr, nullptr, nullptr, nullptr, room};
         if (io.trace.head) {
             if (ra.n > (int64_t)INT32_MAX) e = hipErrorInvalidValue;   // traced calls take candidate lists
             if (e == hipSuccess) e = with_candidates<2>(tr, in, ra, trace_out, io.nsamp, st, walk, io.trace.head);
