@@ -236,7 +236,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(L <= 3 ?
 // ----------------------------------------------------------------------------
 // Two-phase form, used when the rays' lists fit their room.
 //
-// Phase 1 (merge_emit_kernel, one launch per instance) walks the rays through
+// Phase 1 (merge_emit_kernel, one launch per instance over the list of one
+// cull pass for all instances) walks the rays through
 // one instance, as the forward does, and writes that instance's segments
 // along each ray as a linked list of 32-byte entries in increasing u:
 // {b.hi, b.lo, kappa, c_r} {c_g, c_b, next (-1: last), 0}, where b is the
@@ -324,7 +325,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
                             o[0] = ra.o[3 * ray]; o[1] = ra.o[3 * ray + 1]; o[2] = ra.o[3 * ray + 2];
                             d[0] = ra.d[3 * ray]; d[1] = ra.d[3 * ray + 1]; d[2] = ra.d[3 * ray + 2];
                             t = ra.t ? ra.t[ray] : ra.t_scalar;
-                            cand = ra.list != nullptr || ray_may_hit<IDENT>(tr, in, o, d);
+                            cand = ray_may_hit<IDENT>(tr, in, o, d);   // (the list holds rays of any instance)
                         }
                     }
                 }
@@ -581,10 +582,11 @@ static hipError_t multi_lists(const MultiArgs& ma, const RayArgs& ra, float t_st
                               hipStream_t st) {
     const int64_t n = ra.n;
     const int64_t cap = kMergeRoomPerRay * L * n;
-    // scratch: 4 KiB of counters (entries handed out; 1 KiB unused; the
-    // fallback launch's work queue and list counts), the heads, the fallback
-    // list, the entries (phase 2's candidate list comes from with_list)
-    constexpr size_t hdr = 4096;
+    // scratch: 8 KiB of counters (entries handed out; 1 KiB unused; the
+    // fallback launch's work queue and list counts; a work queue per
+    // instance's walk), the heads, the fallback list, the entries (the
+    // candidate lists of both phases come from with_list)
+    constexpr size_t hdr = 4096 + 4 * 1024;
     const size_t head_b = ((size_t)L * n * sizeof(int32_t) + 255) & ~(size_t)255;
     const size_t list_b = ((size_t)((ra.n_slots + 63) >> 6) * 64 * sizeof(int32_t) + 255) & ~(size_t)255;
     void* mem = nullptr;
@@ -594,6 +596,7 @@ static hipError_t multi_lists(const MultiArgs& ma, const RayArgs& ra, float t_st
     auto* counter = reinterpret_cast<unsigned long long*>(p);
     auto* q_fb = reinterpret_cast<unsigned long long*>(p + 2048);
     auto* cnt_fb = reinterpret_cast<unsigned long long*>(p + 3072);
+    auto* q_emit = reinterpret_cast<unsigned long long*>(p + 4096);
     auto* head = reinterpret_cast<int32_t*>(p + hdr);
     auto* fb_list = reinterpret_cast<int32_t*>(p + hdr + head_b);
     auto* ent = reinterpret_cast<int4*>(p + hdr + head_b + list_b);
@@ -601,20 +604,33 @@ static hipError_t multi_lists(const MultiArgs& ma, const RayArgs& ra, float t_st
     hipLaunchKernelGGL(merge_init_kernel, dim3((unsigned)((init_n + 255) / 256)), dim3(256), 0, st, head, L * n,
                        counter, (int)(hdr / 8));
     e = hipGetLastError();
-    for (int k = 0; k < L && e == hipSuccess; ++k) {
-        const MergeLists ml{head + (int64_t)k * n, ent, counter, cap};
-        e = with_candidates<0>(ma.tr[k], ma.in[k], ra, RenderOut{}, nullptr, st, [&](const RayArgs& r) {
-            if (ma.in[k].identity) {
-                auto kern = merge_emit_kernel<DT, true>;
-                hipLaunchKernelGGL(kern, dim3(grid_for(kern, r)), dim3(kBlock), 0, st, ma.tr[k], ma.in[k], r, t_stop,
-                                   ml);
-            } else {
-                auto kern = merge_emit_kernel<DT, false>;
-                hipLaunchKernelGGL(kern, dim3(grid_for(kern, r)), dim3(kBlock), 0, st, ma.tr[k], ma.in[k], r, t_stop,
-                                   ml);
-            }
-            return hipGetLastError();
-        });
+    if (e == hipSuccess) {
+        // phase 1: one cull pass lists the rays that may hit any instance; each
+        // instance's walk takes that list through a work queue of its own
+        e = with_list(
+            ra, st,
+            [&](int32_t* list, unsigned long long* count) {
+                return launch_cull_hit<0>(AnyTreeHit<L>{ma}, ra, RenderOut{}, nullptr, nullptr, list, count, st);
+            },
+            [&](const RayArgs& r) {
+                hipError_t le = hipSuccess;
+                for (int k = 0; k < L && le == hipSuccess; ++k) {
+                    RayArgs rk = r;
+                    rk.queue = q_emit + (size_t)k * 128;
+                    const MergeLists ml{head + (int64_t)k * n, ent, counter, cap};
+                    if (ma.in[k].identity) {
+                        auto kern = merge_emit_kernel<DT, true>;
+                        hipLaunchKernelGGL(kern, dim3(grid_for(kern, rk)), dim3(kBlock), 0, st, ma.tr[k], ma.in[k],
+                                           rk, t_stop, ml);
+                    } else {
+                        auto kern = merge_emit_kernel<DT, false>;
+                        hipLaunchKernelGGL(kern, dim3(grid_for(kern, rk)), dim3(kBlock), 0, st, ma.tr[k], ma.in[k],
+                                           rk, t_stop, ml);
+                    }
+                    le = hipGetLastError();
+                }
+                return le;
+            });
     }
     if (e == hipSuccess) {
         // phase 2 over the rays with lists (a cull pass lists them and writes the misses)
