@@ -272,8 +272,13 @@ static __global__ void zero_queue_kernel(unsigned long long* q) { q[threadIdx.x]
 // and write the miss outputs of the others (no ray loads). The
 // pass is bound by the 24 bytes of ray per slot it reads; at high occupancy
 // it runs near HBM bandwidth, where the render kernel's refill rounds would
-// take one memory latency per round for every ray.
+// take one memory latency per round for every ray. Launches of fewer than
+// kCullSmall chunks that are not images use groups of kCullGroupSmall chunks,
+// so that they still spread over many wavefronts (each group is a chain of
+// dependent loads).
 constexpr int kCullGroup = 32;
+constexpr int kCullGroupSmall = 4;
+constexpr int64_t kCullSmall = 16384;
 
 // Coarse test of one placed tree (the forward's cull).
 template <bool IDENT>
@@ -285,7 +290,7 @@ struct TreeHit {
     }
 };
 
-template <int MODE, class Hit>
+template <int MODE, class Hit, int GROUP = kCullGroup>
 static __global__ __launch_bounds__(kBlock) void cull_kernel(Hit hit, RayArgs ra, RenderOut out,
                                                               const int32_t* nsamp, const int32_t* head,
                                                               int32_t* list,
@@ -383,12 +388,12 @@ static __global__ __launch_bounds__(kBlock) void cull_kernel(Hit hit, RayArgs ra
         }
         return;
     }
-    for (int64_t c0 = lo + wi * kCullGroup; c0 < hi; c0 += nw * kCullGroup) {
-        uint64_t keep[kCullGroup];
-        int32_t rays[kCullGroup];
+    for (int64_t c0 = lo + wi * GROUP; c0 < hi; c0 += nw * GROUP) {
+        uint64_t keep[GROUP];
+        int32_t rays[GROUP];
         int total = 0;
 #pragma unroll
-        for (int j = 0; j < kCullGroup; ++j) {
+        for (int j = 0; j < GROUP; ++j) {
             const int64_t c = c0 + j;
             const int64_t ray = c < hi ? slot_to_ray(ra, c * 64 + lane) : -1;
             bool k = false;
@@ -419,7 +424,7 @@ static __global__ __launch_bounds__(kBlock) void cull_kernel(Hit hit, RayArgs ra
         const uint32_t b_hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(b >> 32));
         int64_t at = lo * 64 + (int64_t)(((uint64_t)b_hi << 32) | b_lo);
 #pragma unroll
-        for (int j = 0; j < kCullGroup; ++j) {
+        for (int j = 0; j < GROUP; ++j) {
             if ((keep[j] >> lane) & 1ull) list[at + lane_rank(keep[j])] = rays[j];
             at += __popcll(keep[j]);
         }
@@ -430,13 +435,19 @@ template <int MODE, class Hit>
 static hipError_t launch_cull_hit(const Hit& hit, const RayArgs& ra, const RenderOut& out, const int32_t* nsamp,
                                   const int32_t* head, int32_t* list, unsigned long long* count, hipStream_t st) {
     const int64_t n_chunks = (ra.n_slots + 63) >> 6;
-    const int64_t groups = (n_chunks / kQueues + 1 + kCullGroup - 1) / kCullGroup;   // per part, at most
+    const bool small = ra.img_w <= 0 && n_chunks < kCullSmall;
+    const int group = small ? kCullGroupSmall : kCullGroup;
+    const int64_t groups = (n_chunks / kQueues + 1 + group - 1) / group;   // per part, at most
     int64_t blocks = (groups + (kBlock / kWave) - 1) / (kBlock / kWave);
     const int64_t cap = (int64_t)device_cu_count() * 2;
     if (blocks > cap) blocks = cap;
     if (blocks < 1) blocks = 1;
     const dim3 grid((unsigned)(blocks * kQueues));
-    hipLaunchKernelGGL((cull_kernel<MODE, Hit>), grid, dim3(kBlock), 0, st, hit, ra, out, nsamp, head, list, count);
+    if (small)
+        hipLaunchKernelGGL((cull_kernel<MODE, Hit, kCullGroupSmall>), grid, dim3(kBlock), 0, st, hit, ra, out, nsamp,
+                           head, list, count);
+    else
+        hipLaunchKernelGGL((cull_kernel<MODE, Hit>), grid, dim3(kBlock), 0, st, hit, ra, out, nsamp, head, list, count);
     return hipGetLastError();
 }
 
