@@ -271,7 +271,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(min_wave
 // density logit, linked into the list of its leaf; reduce_records_kernel
 // below then sums every leaf's list and adds the leaf's row once. Records
 // are taken in blocks per wavefront and written at consecutive indices, so
-// the record stores of a wavefront are contiguous.
+// the record stores of a wavefront are contiguous, and lanes next to each
+// other on one leaf link their records with one atomic exchange (record_run).
 //
 // Samples without a record (the room is full, or records are off) take the
 // per-sample scatter: a sample's 3K + C gradient values form one row of the
