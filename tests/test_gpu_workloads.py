@@ -153,17 +153,28 @@ def test_multi_primitive_composition_full_size():
     cs = _lib.make_camera(W, H, cam.fx, cam.fy, cam.cx, cam.cy, cam.c2w)
     o, d = ops.pinhole_rays(cs)
     t = 37.5
-    announce("multi-primitive: rendering 4 layers (traced, as the benchmark's step)")
+    announce("multi-primitive: rendering 4 layers (traced, each on its own stream, as the benchmark's step)")
     trees = [upload(s, _lib.F16) for s in scenes]
     traces = [ops.Trace(W * H, 4 * W * H, DEV) for _ in trees]
-    layers = [ops.render(tr, o, d, t, ins[1], 1e-4, W, trace=tc) for tr, ins, tc in zip(trees, insts, traces)]
-    for l, tc in zip(layers, traces):   # the room holds every sample: the adjoints replay every ray
-        assert 2 * int(l[3].sum()) <= tc.cap
-    rgb_l = torch.stack([l[0] for l in layers])
-    a_l = torch.stack([l[1] for l in layers])
-    d_l = torch.stack([l[2] for l in layers])
+    rgb_l = torch.empty(4, W * H, 3, device=DEV)
+    a_l = torch.empty(4, W * H, device=DEV)
+    d_l = torch.empty(4, W * H, device=DEV)
+    n_l = torch.empty(4, W * H, dtype=torch.int32, device=DEV)
+    main = torch.cuda.current_stream()
+    sides = [torch.cuda.Stream() for _ in trees]
+    go = torch.cuda.Event()
+    go.record(main)
+    for i, (tr, ins, tc, sd) in enumerate(zip(trees, insts, traces, sides)):
+        sd.wait_event(go)
+        ops.render(tr, o, d, t, ins[1], 1e-4, W, stream=sd, out=(rgb_l[i], a_l[i], d_l[i], n_l[i]), trace=tc)
+        ev = torch.cuda.Event()
+        ev.record(sd)
+        main.wait_event(ev)
+    layers = [(rgb_l[i], a_l[i], d_l[i], n_l[i]) for i in range(4)]
     c_rgb, c_a, c_d = ops.compose(rgb_l, a_l, d_l)
     torch.cuda.synchronize()
+    for l, tc in zip(layers, traces):   # the room holds every sample: the adjoints replay every ray
+        assert 2 * int(l[3].sum()) <= tc.cap
     covered = np.nonzero(c_a.cpu().numpy() > 1e-3)[0]
     assert covered.size > 50_000
     rng = np.random.default_rng(56)
@@ -216,11 +227,17 @@ def test_multi_primitive_composition_full_size():
     q_rgb, q_a = OC.compose_grad(R, A, Dp, gvals.astype(np.float64), gavals.astype(np.float64))
     assert rel_err(g_rgb_l[:, pidx].cpu().numpy(), q_rgb) <= 1e-4
     assert rel_err(g_a_l[:, pidx].cpu().numpy(), q_a) <= 1e-4
-    for i, (tr, ins, s) in enumerate(zip(trees, insts, scenes)):
+    grads = [tr.zero_grads() for tr in trees]   # zeroed on the main stream before the side streams wait
+    go2 = torch.cuda.Event()
+    go2.record(main)
+    for i, (tr, ins, sd) in enumerate(zip(trees, insts, sides)):
+        sd.wait_event(go2)
         l = layers[i]
-        gl, gb = ops.render_backward(tr, o, d, l[0], l[1], l[3], g_rgb_l[i].contiguous(), g_a_l[i].contiguous(), t,
-                                     ins[1], 1e-4, W, trace=traces[i])
-        torch.cuda.synchronize()
+        ops.render_backward(tr, o, d, l[0], l[1], l[3], g_rgb_l[i], g_a_l[i], t, ins[1], 1e-4, W,
+                            grads=grads[i], trace=traces[i], stream=sd)
+    torch.cuda.synchronize()
+    for i, (tr, ins, s) in enumerate(zip(trees, insts, scenes)):
+        gl, gb = grads[i][0], grads[i][1]
         ref = oracle_render(s, ro, rd, None, t, 1e-4, inst=ins[0], dtype=_lib.F16, g_rgb=q_rgb[i], g_alpha=q_a[i])
         hh, ws = tr.unpack_grad(gl)
         e = [rel_err(hh.cpu().numpy(), ref["grad_hh"]), rel_err(ws.cpu().numpy(), ref["grad_wsig"]),
