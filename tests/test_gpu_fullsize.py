@@ -6,8 +6,9 @@ Forward-render workload: depth-9 humanoid VOctree (~2M leaves), 8 cameras at
 1920x1080 rendered in one launch (16.6 M rays, 8x8 tiles, t_stop = 1e-4), with
 the global hyperangle table (K=16, C=8; and K=30, Table 3's N=30) and with
 the paper's per-point leaf (K=14, C=31, Cg=31).
-Outputs are checked on a seeded sample of pixels that the FP64 oracle
-renders one by one. The adjoint is checked in the same launch with the
+The exact merge of L placements is run over the same ring as bench.py
+--multi L times it. Outputs are checked on a seeded sample of pixels that the
+FP64 oracle renders one by one. The adjoint is checked in the same launch with the
 upstream gradient non-zero only on the sampled pixels, so the oracle's
 gradient over those rays is the exact expected result.
 """
@@ -102,3 +103,62 @@ def test_full_ring_forward_and_adjoint_sampled(ring):
         e += [rel_err(parts[2].cpu().numpy(), ref["grad_wgam"]), rel_err(out[2].cpu().numpy(), ref["grad_basis_g"])]
     announce(f"full size adjoint rel errors {e}")
     assert max(e) <= 1e-4
+
+
+@pytest.mark.parametrize("L", [2, 4])
+def test_full_ring_exact_merge_sampled(L):
+    """The exact merge as bench.py --multi L times it: L placements of the ring's tree (rotated
+    about the vertical axis through the leaves' centroid, shifted, re-timed), the whole ring in
+    one launch; parity on sampled rays against the merge oracle."""
+    import math
+    from oracle import multi as OM
+    sc = scene_for_workload("forward")
+    cams = ring_cameras(sc, 8, 1920, 1080, 40.0, 10.0, seed=2)
+    t = float(np.random.default_rng(2002).uniform(0, sc.T))
+    W, H = 1920, 1080
+    n_cam = W * H
+    n = 8 * n_cam
+    tree = upload(sc)
+    c = sc.leaf_ijk.mean(0) + 0.5
+    g_insts, o_insts = [], []
+    for k in range(L):
+        th = 2 * math.pi * k / (3 * L)
+        R = np.array([[math.cos(th), -math.sin(th), 0], [math.sin(th), math.cos(th), 0], [0, 0, 1]], np.float32)
+        trans = (c - R @ c + np.array([0.04 * sc.G * k, -0.03 * sc.G * k, 0.0])).astype(np.float32)
+        g_insts.append(_lib.make_instance(R, trans, 1.0, 37.0 * k, 1))
+        o_insts.append(OC.Instance(R, trans, 1.0, 37.0 * k, 1))
+    o = torch.empty(n, 3, device=DEV)
+    d = torch.empty(n, 3, device=DEV)
+    for i, cm in enumerate(cams):
+        cs = _lib.make_camera(cm.width, cm.height, cm.fx, cm.fy, cm.cx, cm.cy, cm.c2w)
+        _lib.neuvv_pinhole_rays(cs, n_cam, None, o[i * n_cam:(i + 1) * n_cam], d[i * n_cam:(i + 1) * n_cam])
+    rgb = torch.empty(n, 3, device=DEV)
+    alpha = torch.empty(n, device=DEV)
+    depth = torch.empty(n, device=DEV)
+    nsamp = torch.empty(n, dtype=torch.int32, device=DEV)
+    announce(f"full size: exact merge of {L} placements over {n} rays")
+    _lib.neuvv_render_multi([tree.struct()] * L, g_insts, n, o, d, None, t, W, 1e-4, rgb, alpha, depth, nsamp)
+    torch.cuda.synchronize()
+    ns = nsamp.cpu().numpy()
+    hit = np.nonzero(ns > 0)[0]
+    announce(f"full size merge: {hit.size} rays with pieces, {int(ns.sum())} pieces")
+    assert hit.size > 100_000
+    rng = np.random.default_rng(90 + L)
+    sample = np.unique(np.concatenate([rng.choice(hit, 1200, replace=False), rng.choice(n, 300, replace=False)]))
+    cam_idx = sample // n_cam
+    pix = (sample % n_cam).astype(np.int32)
+    ro = np.zeros((sample.size, 3), np.float32)
+    rd = np.zeros((sample.size, 3), np.float32)
+    for cc in range(8):
+        m = cam_idx == cc
+        if m.any():
+            ro[m], rd[m] = OC.pinhole_rays(W, H, cams[cc].intr(), cams[cc].c2w, pix[m])
+    same = np.all(o[sample].cpu().numpy() == ro, axis=1) & np.all(d[sample].cpu().numpy() == rd, axis=1)
+    assert same.mean() > 0.999, same.mean()
+    sample, ro, rd = sample[same], ro[same], rd[same]
+    ref = OM.render_multi([sc] * L, o_insts, ro, rd, t, 1e-4)
+    ref["margin"] = np.stack([ref["min_piece"], ref["margin"]], 1)
+    idx = torch.from_numpy(sample).to(DEV)
+    gpu = dict(rgb=rgb[idx].cpu().numpy().astype(np.float64), alpha=alpha[idx].cpu().numpy().astype(np.float64),
+               depth=depth[idx].cpu().numpy().astype(np.float64), nsamp=nsamp[idx].cpu().numpy())
+    compare(gpu, ref, label=f"full-size merge L={L}")
