@@ -6,8 +6,9 @@ Forward-render workload: depth-9 humanoid VOctree (~2M leaves), 8 cameras at
 1920x1080 rendered in one launch (16.6 M rays, 8x8 tiles, t_stop = 1e-4), with
 the global hyperangle table (K=16, C=8; and K=30, Table 3's N=30) and with
 the paper's per-point leaf (K=14, C=31, Cg=31).
-The exact merge of L placements is run over the same ring as bench.py
---multi L times it. Outputs are checked on a seeded sample of pixels that the
+The exact merge of L placements, and the lit frame (the light map on a second
+stream, then the shading), run over the same ring as bench.py --multi L and
+--lighting time them. Outputs are checked on a seeded sample of pixels that the
 FP64 oracle renders one by one. The adjoint is checked in the same launch with the
 upstream gradient non-zero only on the sampled pixels, so the oracle's
 gradient over those rays is the exact expected result.
@@ -162,3 +163,86 @@ def test_full_ring_exact_merge_sampled(L):
     gpu = dict(rgb=rgb[idx].cpu().numpy().astype(np.float64), alpha=alpha[idx].cpu().numpy().astype(np.float64),
                depth=depth[idx].cpu().numpy().astype(np.float64), nsamp=nsamp[idx].cpu().numpy())
     compare(gpu, ref, label=f"full-size merge L={L}")
+
+
+def test_full_ring_lit_frame_sampled():
+    """The lit frame as bench.py --lighting times it: the light's 256 x 256 alpha map and its
+    low-pass on a second stream while the ring renders on the first, then the shading of every
+    ring pixel; sampled pixels against the lighting oracle's own chain (its light map rendered
+    by the FP64 oracle, low-passed, the viewer pixels rendered by the oracle, shaded)."""
+    import math
+    from oracle import lighting as OL
+    from workloads import look_at
+    sc = scene_for_workload("forward")
+    cams = ring_cameras(sc, 8, 1920, 1080, 40.0, 10.0, seed=2)
+    t = float(np.random.default_rng(2002).uniform(0, sc.T))
+    W, H = 1920, 1080
+    n_cam = W * H
+    n = 8 * n_cam
+    tree = upload(sc)
+    LW = LH = 256
+    cen = sc.leaf_ijk.mean(0) + 0.5
+    pos = cen + np.array([0.35 * sc.G, -0.25 * sc.G, 0.9 * sc.G])
+    c2w = np.asarray(look_at(pos, cen), np.float32)
+    f = 0.5 * LW / math.tan(math.radians(35.0))
+    gz = float(sc.leaf_ijk[:, 2].min())
+    cam = _lib.make_camera(LW, LH, f, f, LW / 2, LH / 2, c2w)
+    light = _lib.make_light(cam, gz, (0.7, 0.65, 0.6), (0.05, 0.1, 0.2), 0.8, 0.5 * sc.G)
+    ol = OL.Light(LW, LH, (f, f, LW / 2, LH / 2), c2w, gz, (0.7, 0.65, 0.6), (0.05, 0.1, 0.2), 0.8, 0.5 * sc.G)
+    lo, ld = ops.pinhole_rays(cam)
+    o = torch.empty(n, 3, device=DEV)
+    d = torch.empty(n, 3, device=DEV)
+    for i, cm in enumerate(cams):
+        cs = _lib.make_camera(cm.width, cm.height, cm.fx, cm.fy, cm.cx, cm.cy, cm.c2w)
+        _lib.neuvv_pinhole_rays(cs, n_cam, None, o[i * n_cam:(i + 1) * n_cam], d[i * n_cam:(i + 1) * n_cam])
+    la = torch.empty(LW * LH, device=DEV)
+    lrgb = torch.empty(LW * LH, 3, device=DEV)
+    lns = torch.empty(LW * LH, dtype=torch.int32, device=DEV)
+    smap = torch.empty(LH, LW, device=DEV)
+    rgb = torch.empty(n, 3, device=DEV)
+    alpha = torch.empty(n, device=DEV)
+    depth = torch.empty(n, device=DEV)
+    nsamp = torch.empty(n, dtype=torch.int32, device=DEV)
+    out = torch.empty(n, 3, device=DEV)
+    announce(f"full size: lit frame over {n} rays, light map {LW}x{LH} on a second stream")
+    torch.cuda.synchronize()
+    main = torch.cuda.current_stream()
+    side = torch.cuda.Stream()
+    go, ready = torch.cuda.Event(), torch.cuda.Event()
+    go.record(main)
+    side.wait_event(go)
+    _lib.neuvv_render(tree.struct(), None, LW * LH, lo, ld, None, t, LW, 1e-4, lrgb, la, None, lns, side)
+    _lib.neuvv_blur(LH, LW, la, 1.5, smap, side)
+    ready.record(side)
+    _lib.neuvv_render(tree.struct(), None, n, o, d, None, t, W, 1e-4, rgb, alpha, depth, nsamp, main)
+    main.wait_event(ready)
+    _lib.neuvv_shade(light, smap, n, o, d, rgb, alpha, depth, out, main)
+    torch.cuda.synchronize()
+    # the oracle's chain
+    lo_h, ld_h = OC.pinhole_rays(LW, LH, ol.intr, ol.c2w)
+    lmap = oracle_render(sc, lo_h, ld_h, None, t, 1e-4)["alpha"].reshape(LH, LW)
+    smap_ref = OL.blur(lmap, 1.5)
+    ns = nsamp.cpu().numpy()
+    rng = np.random.default_rng(95)
+    hit = np.nonzero(ns > 0)[0]
+    sample = np.unique(np.concatenate([rng.choice(hit, 700, replace=False), rng.choice(n, 1300, replace=False)]))
+    cam_idx = sample // n_cam
+    pix = (sample % n_cam).astype(np.int32)
+    ro = np.zeros((sample.size, 3), np.float32)
+    rd = np.zeros((sample.size, 3), np.float32)
+    for cc in range(8):
+        m = cam_idx == cc
+        if m.any():
+            ro[m], rd[m] = OC.pinhole_rays(W, H, cams[cc].intr(), cams[cc].c2w, pix[m])
+    same = np.all(o[sample].cpu().numpy() == ro, axis=1) & np.all(d[sample].cpu().numpy() == rd, axis=1)
+    assert same.mean() > 0.999, same.mean()
+    sample, ro, rd = sample[same], ro[same], rd[same]
+    v = oracle_render(sc, ro, rd, None, t, 1e-4)
+    ref = OL.shade(ol, smap_ref, ro, rd, v["rgb"], v["alpha"], v["depth"])
+    amb = stop_ambiguous(v, label="lit frame")
+    gpu = out[torch.from_numpy(sample).to(DEV)].cpu().numpy().astype(np.float64)
+    err = np.abs(gpu - ref)[~amb].max()
+    shadowed = ((ref < 0.95 * np.asarray(ol.ground_rgb)).all(1) & (v["alpha"] == 0)).sum()
+    announce(f"full-size lit frame: max-abs {err:.2e} over {int((~amb).sum())} pixels, {int(shadowed)} shadowed ground")
+    assert shadowed > 20
+    assert err <= 2e-5, err
