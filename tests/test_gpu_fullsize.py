@@ -8,7 +8,8 @@ the global hyperangle table (K=16, C=8; and K=30, Table 3's N=30) and with
 the paper's per-point leaf (K=14, C=31, Cg=31).
 The exact merge of L placements, and the lit frame (the light map on a second
 stream, then the shading), run over the same ring as bench.py --multi L and
---lighting time them. Outputs are checked on a seeded sample of pixels that the
+--lighting time them, and so does appearance editing as --editing runs it (the
+terminal leaves of one whole camera, the paint table, the edited ring). Outputs are checked on a seeded sample of pixels that the
 FP64 oracle renders one by one. The adjoint is checked in the same launch with the
 upstream gradient non-zero only on the sampled pixels, so the oracle's
 gradient over those rays is the exact expected result.
@@ -246,3 +247,92 @@ def test_full_ring_lit_frame_sampled():
     announce(f"full-size lit frame: max-abs {err:.2e} over {int((~amb).sum())} pixels, {int(shadowed)} shadowed ground")
     assert shadowed > 20
     assert err <= 2e-5, err
+
+
+def test_full_ring_editing():
+    """Appearance editing (Sec. 5.2) as bench.py --editing times it: the terminal leaves of
+    the ring's first camera (accumulated alpha beyond 0.99) over its whole 1920 x 1080 image,
+    the paint of a seeded pattern (lowest ray wins), then the ring rendered in one launch with
+    the edits active. The oracle finds every terminal leaf of that camera itself; the paint
+    table must match its paint bit for bit, and sampled ring pixels its render with edits."""
+    from oracle import editing as OE
+    sc = scene_for_workload("forward")
+    cams = ring_cameras(sc, 8, 1920, 1080, 40.0, 10.0, seed=2)
+    t = float(np.random.default_rng(2002).uniform(0, sc.T))
+    W, H = 1920, 1080
+    n_cam = W * H
+    n = 8 * n_cam
+    tree = upload(sc)
+    o = torch.empty(n, 3, device=DEV)
+    d = torch.empty(n, 3, device=DEV)
+    for i, cm in enumerate(cams):
+        cs = _lib.make_camera(cm.width, cm.height, cm.fx, cm.fy, cm.cx, cm.cy, cm.c2w)
+        _lib.neuvv_pinhole_rays(cs, n_cam, None, o[i * n_cam:(i + 1) * n_cam], d[i * n_cam:(i + 1) * n_cam])
+    # the painting camera's rays as the oracle generates them, so both sides trace the same rays
+    o0, d0 = OC.pinhole_rays(W, H, cams[0].intr(), cams[0].c2w)
+    same = np.all(o[:n_cam].cpu().numpy() == o0, axis=1) & np.all(d[:n_cam].cpu().numpy() == d0, axis=1)
+    assert same.mean() > 0.999, same.mean()
+    o[:n_cam] = tdev(o0)
+    d[:n_cam] = tdev(d0)
+    announce(f"full size: terminal leaves of a {W}x{H} camera, {sc.n_leaves} leaves")
+    last = torch.empty(n_cam, dtype=torch.int32, device=DEV)
+    _lib.neuvv_find_terminal_leaves(tree.struct(), None, n_cam, o[:n_cam], d[:n_cam], None, t, W, 0.99, last)
+    torch.cuda.synchronize()
+    g = last.cpu().numpy().astype(np.int64)
+    ref = oracle_render(sc, o0, d0, None, t, 0.01)          # stops where the alpha passes 0.99
+    slots = tree.slot_of_input.cpu().numpy()
+    amb = ref["margin"][:, 1] < 1e-4
+    want = np.where(ref["last_leaf"] >= 0, slots[np.maximum(ref["last_leaf"], 0)], -1)
+    announce(f"full-size terminal leaves: {int((want >= 0).sum())} rays pass 0.99, {int(amb.sum())} ambiguous")
+    assert amb.sum() <= 0.002 * n_cam
+    assert (want >= 0).sum() > 50_000
+    assert np.array_equal(g[~amb], want[~amb])
+    # paint with the stop-ambiguous rays left out on both sides
+    colours = np.random.default_rng(2004).random((n_cam, 3)).astype(np.float32)
+    g[amb] = -1
+    tree.enable_edits()
+    _lib.neuvv_paint(n_cam, torch.from_numpy(g.astype(np.int32)).to(DEV), tdev(colours), -1.0, 0.0, tree.n_leaves,
+                     tree.edit)
+    oe = OE.paint(OE.empty_edits(sc.n_leaves), np.where(amb, -1, ref["last_leaf"]), colours, -1.0, 0.0)
+    torch.cuda.synchronize()
+    ge = tree.edits_per_input().cpu().numpy().astype(np.float64)
+    edited = np.isfinite(oe[:, 4])
+    announce(f"full-size paint: {int(edited.sum())} leaves painted")
+    assert edited.sum() > 10_000
+    assert np.array_equal(np.isfinite(ge[:, 4]), edited)
+    assert np.array_equal(ge[edited], oe[edited])
+    assert np.all(ge[~edited, 3] == -1.0)
+    # the ring with the edits active, in one launch
+    rgb = torch.empty(n, 3, device=DEV)
+    alpha = torch.empty(n, device=DEV)
+    depth = torch.empty(n, device=DEV)
+    nsamp = torch.empty(n, dtype=torch.int32, device=DEV)
+    announce(f"full size: edited render of {n} rays")
+    _lib.neuvv_render(tree.struct(), None, n, o, d, None, t, W, 1e-4, rgb, alpha, depth, nsamp)
+    torch.cuda.synchronize()
+    ns = nsamp.cpu().numpy()
+    rng = np.random.default_rng(97)
+    painted = np.nonzero(g >= 0)[0]
+    hit = np.nonzero(ns > 0)[0]
+    sample = np.unique(np.concatenate([rng.choice(painted, 800, replace=False), rng.choice(hit, 700, replace=False),
+                                       rng.choice(n, 500, replace=False)]))
+    cam_idx = sample // n_cam
+    pix = (sample % n_cam).astype(np.int32)
+    ro = np.zeros((sample.size, 3), np.float32)
+    rd = np.zeros((sample.size, 3), np.float32)
+    for cc in range(8):
+        m = cam_idx == cc
+        if m.any():
+            ro[m], rd[m] = OC.pinhole_rays(W, H, cams[cc].intr(), cams[cc].c2w, pix[m])
+    same = np.all(o[sample].cpu().numpy() == ro, axis=1) & np.all(d[sample].cpu().numpy() == rd, axis=1)
+    assert same.mean() > 0.999, same.mean()
+    sample, ro, rd = sample[same], ro[same], rd[same]
+    vref = OC.render(sc.depth, sc.leaf_ijk, sc.hh, sc.wsig, sc.basis, sc.gamma, ro, rd, None, t, 1e-4, edit=oe)
+    idx = torch.from_numpy(sample).to(DEV)
+    gpu = dict(rgb=rgb[idx].cpu().numpy().astype(np.float64), alpha=alpha[idx].cpu().numpy().astype(np.float64),
+               depth=depth[idx].cpu().numpy().astype(np.float64), nsamp=nsamp[idx].cpu().numpy())
+    compare(gpu, vref, label="full-size edited ring")
+    plain = oracle_render(sc, ro, rd, None, t, 1e-4)
+    changed = (np.abs(vref["rgb"] - plain["rgb"]).max(1) > 1e-3).sum()
+    announce(f"full-size edited ring: {int(changed)} of {sample.size} sampled pixels changed by the edits")
+    assert changed > 500
