@@ -59,6 +59,46 @@ def test_backward_tiny_scalar_time(layout, traced):
         check(gpu, ref, label=f"tiny t={t} traced={traced}")
 
 
+@pytest.mark.parametrize("traced", [False, True])
+def test_backward_long_leaf_lists(traced):
+    """Every ray crosses the same few leaves: a 2 x 2 column of 8 leaves in a depth-3 tree and
+    16,381 rays (a ragged last wavefront) running along it, ordered by the column they take. Whole
+    wavefronts then sample one leaf together, so the records of a wavefront iteration form one run
+    linked by one atomic exchange, each leaf collects about 4,000 records, and the reduction
+    follows lists that long. The plain pair has record room for 2 samples per ray (the other 6 take
+    the per-sample scatter, all 64 lanes on one gradient row); the traced pair has room for all."""
+    from workloads.scenes import Scene
+    base = scene_for_workload("tiny")
+    G = 8
+    ijk = np.array([(i, j, k) for k in range(G) for j in (3, 4) for i in (3, 4)], np.int32)
+    ijk = ijk[np.argsort(ijk[:, 0] + G * (ijk[:, 1] + G * ijk[:, 2]), kind="stable")]
+    N = ijk.shape[0]
+    sc = Scene(3, ijk, base.hh[:N].copy(), (0.3 * base.wsig[:N]).astype(np.float32), base.basis, base.gamma)
+    tree = upload(sc)
+    n = 16381
+    rng = np.random.default_rng(47)
+    quad = np.sort(rng.integers(0, 4, n))             # column of each ray, in ray order
+    xy = 3.0 + (quad[:, None] >> np.array([0, 1]) & 1) + rng.uniform(0.02, 0.98, (n, 2))
+    o = np.concatenate([xy, np.full((n, 1), -0.5)], 1).astype(np.float32)
+    d = np.tile(np.array([0.003, -0.002, 1.0], np.float32), (n, 1))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    gC = rng.normal(size=(n, 3)).astype(np.float32)
+    gA = rng.normal(size=n).astype(np.float32)
+    t = 4.0
+    announce(f"long leaf lists: {n} rays through {N} leaves, traced={traced}")
+    ref = oracle_render(sc, o, d, None, t, 0.0, g_rgb=gC, g_alpha=gA)
+    assert ref["nsamp"].min() >= 7 and ref["nsamp"].sum() > 7.5 * n
+    oo, dd = tdev(o), tdev(d)
+    trace = ops.Trace(n, 9 * n, oo.device) if traced else None
+    rgb, alpha, depth, nsamp = ops.render(tree, oo, dd, t, None, 0.0, trace=trace)
+    gl, gb = ops.render_backward(tree, oo, dd, rgb, alpha, nsamp, tdev(gC), tdev(gA), t, None, 0.0, trace=trace)
+    torch.cuda.synchronize()
+    same = nsamp.cpu().numpy() == ref["nsamp"]
+    assert np.all(same | (ref["margin"][:, 0] < 1e-5))     # a crossing within rounding of a cell edge
+    hh, ws = tree.unpack_grad(gl)
+    check((hh.cpu().numpy(), ws.cpu().numpy(), gb.cpu().numpy()), ref, label=f"long lists traced={traced}")
+
+
 @pytest.mark.parametrize("records", ["0", "777", None])
 def test_backward_record_modes(records, monkeypatch):
     """The two-phase adjoint (per-sample records summed per leaf) against the oracle,
