@@ -313,6 +313,28 @@ def _timed(fn, steps, stream):
     return e0.elapsed_time(e1) / steps
 
 
+def _sample_stats(nsamp_list):
+    """Samples, hit rays and their ratios over the rays of one step (a list of nsamp tensors)."""
+    s = sum(int(x.sum().item()) for x in nsamp_list)
+    hit = sum(int((x > 0).sum().item()) for x in nsamp_list)
+    n = sum(int(x.numel()) for x in nsamp_list)
+    return {"samples_per_step": s, "hit_rays": hit, "hit_fraction": round(hit / max(n, 1), 5),
+            "samples_per_hit_ray": round(s / max(hit, 1), 3)}
+
+
+def _step_roofline(method_bytes, ms, parts):
+    """The method's bytes of one step (the accounting of the main workload's roofline, summed over
+    the step's calls) over the step time, against the HBM peak."""
+    gbs = method_bytes / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "method_bytes_per_step": int(method_bytes), "achieved": round(gbs, 1),
+            "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4), "parts": parts}
+
+
+def _touched(grad_rows, values):
+    """Leaves whose gradient row the adjoint changed."""
+    return int((grad_rows[:, :values] != 0).any(dim=1).sum().item())
+
+
 def workload_bench(args):
     """The other workloads (parity-tested in tests/test_gpu_workloads.py), timed with the library's calls:
     one JSON line each, value = rays per second of the timed unit."""
@@ -367,6 +389,18 @@ def workload_bench(args):
         out.update(value=round(n / (ms * 1e-3) / 1e6, 2), ms_per_step=round(ms, 4), dtype="f32",
                    config={"workload": "train_d8_500k_65536rays", "leaves": sc.n_leaves, "rays_per_step": n,
                            "step": "traced render + L2 loss gradient + adjoint, per-ray t"})
+        nsamp = ops.render(tree, o, d, t, None, t_stop)[3]
+        st = _sample_stats([nsamp])
+        values = 3 * tree.K + tree.C
+        pay = values * 4
+        touched = _touched(grads[0], values)
+        # per-ray time: 4 more input bytes per ray in both calls
+        fb = st["samples_per_step"] * pay + n * (FWD_RAY_IO_B + 4)
+        bb = (st["samples_per_step"] * pay + touched * (2 * 4 * values + tree.C * 4) + n * BWD_RAY_NSAMP_B +
+              st["hit_rays"] * (BWD_HIT_IO_B + 4))
+        out.update(st)
+        out["step_roofline"] = _step_roofline(fb + bb, ms, {"render": fb, "render_backward": bb,
+                                                             "leaves_touched": touched})
         log(f"train: {ms:.3f} ms per step ({n} rays, {sc.n_leaves} leaves)")
         if not args.no_cpu_baseline:
             out["cpu_baseline"] = train_cpu(sc, tgt, cams, ci, pix, t.cpu().numpy(), t_stop)
@@ -375,30 +409,36 @@ def workload_bench(args):
         W = H = 2048
         eyes = stereo_cameras(sc, W, H, 90.0, seed=4)
         t = float(np.random.default_rng(4004).uniform(0, sc.T))
-        rays = []
-        for cam in eyes:
-            cs = _lib.make_camera(W, H, cam.fx, cam.fy, cam.cx, cam.cy, cam.c2w)
-            rays.append(ops.pinhole_rays(cs))
+        # a stereo frame is one launch: the two eyes' rays stacked as one 2048 x 4096 image (the
+        # tiles of 8 x 8 pixels never straddle the eyes), so that the hit rays of both share the GPU
+        rays = [ops.pinhole_rays(_lib.make_camera(W, H, c.fx, c.fy, c.cx, c.cy, c.c2w)) for c in eyes]
+        o2 = torch.cat([r[0] for r in rays])
+        d2 = torch.cat([r[1] for r in rays])
+        del rays
         n = 2 * W * H
         per = {}
         for name, dt in (("f32", _lib.F32), ("f16", _lib.F16), ("bf16", _lib.BF16)):
             tree = upload(sc, dt)
-            bufs = [(torch.empty(W * H, 3, device=dev), torch.empty(W * H, device=dev), torch.empty(W * H, device=dev),
-                     torch.empty(W * H, dtype=torch.int32, device=dev)) for _ in eyes]
+            buf = (torch.empty(n, 3, device=dev), torch.empty(n, device=dev), torch.empty(n, device=dev),
+                   torch.empty(n, dtype=torch.int32, device=dev))
 
             def frame():
-                for (o, d), b in zip(rays, bufs):
-                    ops.render(tree, o, d, t, None, t_stop, W, out=b)
+                ops.render(tree, o2, d2, t, None, t_stop, W, out=buf)
 
             for _ in range(args.warmup):
                 frame()
             ms = _timed(frame, args.steps, stream)
-            per[name] = {"ms_per_stereo_frame": round(ms, 4), "mrays_s": round(n / (ms * 1e-3) / 1e6, 2)}
+            st = _sample_stats([buf[3]])
+            mb = st["samples_per_step"] * (3 * tree.K + tree.C) * (4 if dt == _lib.F32 else 2) + n * FWD_RAY_IO_B
+            per[name] = {"ms_per_stereo_frame": round(ms, 4), "mrays_s": round(n / (ms * 1e-3) / 1e6, 2),
+                         "step_roofline": _step_roofline(mb, ms, {"render": mb})}
+            if name == "f16":
+                out.update(st)
             log(f"mixed {name}: {ms:.3f} ms per stereo frame")
             del tree
         out.update(value=per["f16"]["mrays_s"], ms_per_step=per["f16"]["ms_per_stereo_frame"], dtype="f16",
                    config={"workload": "mixed_d10_8M_stereo2048", "leaves": sc.n_leaves, "rays_per_step": n,
-                           "step": "forward of one stereo frame", "per_dtype": per})
+                           "step": "forward of one stereo frame (both eyes in one launch)", "per_dtype": per})
         if not args.no_cpu_baseline:
             out["cpu_baseline"] = mixed_cpu(sc, eyes, W, H, t, t_stop)
     else:
@@ -456,6 +496,21 @@ def workload_bench(args):
             step()
         ms = _timed(step, args.steps, stream)
         n = W * H
+        st = _sample_stats([n_l[i] for i in range(4)])
+        values = 3 * trees[0].K + trees[0].C
+        pay = values * 2
+        touched = [_touched(g[0], values) for g in grads]
+        hits = [int((n_l[i] > 0).sum().item()) for i in range(4)]
+        fb = st["samples_per_step"] * pay + 4 * n * FWD_RAY_IO_B
+        bb = (st["samples_per_step"] * pay + sum(touched) * (2 * 4 * values + trees[0].C * 2) +
+              4 * n * BWD_RAY_NSAMP_B + sum(hits) * BWD_HIT_IO_B)
+        # compose: rgb, alpha, depth of every layer in, one pixel out; its adjoint reads them and the
+        # output gradient and writes the layers' rgb and alpha gradients
+        cb = n * (4 * 20 + 20) + n * (4 * 20 + 12 + 4 * 16)
+        out.update(st)
+        out["step_roofline"] = _step_roofline(fb + bb + cb, ms, {"layer_renders": fb, "layer_adjoints": bb,
+                                                                  "compose_and_adjoint": cb,
+                                                                  "leaves_touched": touched})
         out.update(value=round(n / (ms * 1e-3) / 1e6, 2), ms_per_step=round(ms, 4), dtype="f16",
                    config={"workload": "multi_4xd9_1080p_fp16", "leaves": [s.n_leaves for s in scenes],
                            "rays_per_step": n,

@@ -4,7 +4,7 @@
   seeded cameras at 960x540 with per-ray t in [0, 300), L2 loss against a
   target render of a second payload draw; forward + adjoint against FP64.
 * mixed precision: depth-10 humanoid (~8M leaves), stereo 2048x2048 per eye,
-  FP16 / BF16 / FP32 leaf storage; per image (4 seeded frames x 2 eyes) the
+  both eyes in one launch as the benchmark renders a stereo frame, FP16 / BF16 / FP32 leaf storage; per image (4 seeded frames x 2 eyes) the
   max-abs error and PSNR of rgb over the whole image against the FP64 oracle
   on the unrounded payload, and parity on the rounded payload, on a seeded
   pixel sample.
@@ -90,6 +90,8 @@ def test_training_step_full_size():
 
 
 def test_mixed_precision_stereo_full_size():
+    """Both eyes in one launch, stacked as one 2048 x 4096 image (the benchmark's stereo frame);
+    errors are taken per eye image."""
     sc = scene_for_workload("mixed")
     announce(f"mixed precision: {sc.n_leaves} leaves, depth {sc.depth}")
     W = H = 2048
@@ -97,16 +99,22 @@ def test_mixed_precision_stereo_full_size():
     frames = np.random.default_rng(4004).uniform(0, sc.T, 4)
     rng = np.random.default_rng(4005)
     trees = {dt: upload(sc, dt) for dt in (_lib.F32, _lib.F16, _lib.BF16)}
-    report = []
+    gpu_rays = [ops.pinhole_rays(_lib.make_camera(W, H, c.fx, c.fy, c.cx, c.cy, c.c2w)) for c in eyes]
+    o = torch.cat([r[0] for r in gpu_rays])
+    d = torch.cat([r[1] for r in gpu_rays])
+    host_rays, same_eye = [], []
     for ei, cam in enumerate(eyes):
-        cs = _lib.make_camera(W, H, cam.fx, cam.fy, cam.cx, cam.cy, cam.c2w)
-        o, d = ops.pinhole_rays(cs)
         ro, rd = OC.pinhole_rays(W, H, cam.intr(), cam.c2w)
-        same = np.all(o.cpu().numpy() == ro, axis=1) & np.all(d.cpu().numpy() == rd, axis=1)
+        same = np.all(gpu_rays[ei][0].cpu().numpy() == ro, axis=1) & np.all(gpu_rays[ei][1].cpu().numpy() == rd, axis=1)
         assert same.mean() > 0.999
-        for t in frames:
-            outs = {dt: ops.render(tr, o, d, float(t), None, 1e-4, W) for dt, tr in trees.items()}
-            torch.cuda.synchronize()
+        host_rays.append((ro, rd))
+        same_eye.append(same)
+    report = []
+    for t in frames:
+        outs = {dt: ops.render(tr, o, d, float(t), None, 1e-4, W) for dt, tr in trees.items()}
+        torch.cuda.synchronize()
+        for ei, ((ro, rd), same) in enumerate(zip(host_rays, same_eye)):
+            eye = slice(ei * W * H, (ei + 1) * W * H)
             # the whole image against FP64 on the unrounded payload: per image max-abs and PSNR of
             # rgb over every pixel except those whose stop decision is within rounding of t_stop
             # (counted) and the few whose GPU ray differs from the oracle's in the last bit
@@ -115,7 +123,7 @@ def test_mixed_precision_stereo_full_size():
             ok = same & (ref64["margin"][:, 1] >= 1e-4)
             assert (~ok).sum() <= 0.002 * ok.size, int((~ok).sum())
             for dt, (rgb, alpha, depth, nsamp) in outs.items():
-                err = np.abs(rgb.cpu().numpy().astype(np.float64) - ref64["rgb"])[ok]
+                err = np.abs(rgb[eye].cpu().numpy().astype(np.float64) - ref64["rgb"])[ok]
                 mse = float(np.mean(err ** 2))
                 psnr = 10 * math.log10(1.0 / mse) if mse > 0 else math.inf
                 report.append((ei, float(t), dt, float(err.max()), psnr, int((~ok).sum())))
@@ -125,11 +133,11 @@ def test_mixed_precision_stereo_full_size():
                     assert err.max() <= 1e-5 * max(np.abs(ref64["rgb"]).max(), 1e-30)
             del ref64
             # 16-bit storage on the rounded payload (the arithmetic alone), on a seeded pixel sample
-            ns = outs[_lib.F32][3].cpu().numpy()
+            ns = outs[_lib.F32][3][eye].cpu().numpy()
             hit = np.nonzero((ns > 0) & same)[0]
             pix = np.unique(np.concatenate([rng.choice(hit, min(1500, hit.size), replace=False),
                                             rng.choice(np.nonzero(same)[0], 300, replace=False)])).astype(np.int64)
-            pidx = torch.from_numpy(pix).to(DEV)
+            pidx = torch.from_numpy(pix + ei * W * H).to(DEV)
             for dt in (_lib.F16, _lib.BF16):
                 rgb, alpha, depth, nsamp = outs[dt]
                 g = dict(rgb=rgb[pidx].cpu().numpy().astype(np.float64),
