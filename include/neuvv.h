@@ -121,6 +121,7 @@ typedef struct {
                              tau >= t_d, +inf: never); a word used by neuvv_paint; 2 unused. K = 16,
                              C = 8 form only; neuvv_render_backward rejects trees with edits */
     int32_t density;      /* neuvv_density: the activation of Eq. 5 (0 = softplus) */
+    const int32_t* dir;   /* the brick directory of nodes, from neuvv_build_directory (required) */
 } neuvv_tree;
 
 /* Placement and re-timing of one tree instance (Eq. 13). A world point x is
@@ -183,6 +184,40 @@ typedef struct {
  */
 int neuvv_build_voctree(int32_t depth, int64_t n_leaves, const int32_t* leaf_ijk, int32_t* nodes,
                         int64_t node_capacity, int64_t* n_nodes_out, int64_t* slot_of_input, int32_t* box_out);
+
+/*
+ * neuvv_directory_entries - entries of the brick directory of a depth-D
+ * tree: E^3 with E = 2^(D-2) (E = 1 for D <= 2), 4 bytes each (8 MiB at
+ * D = 9, 64 MiB at D = 10, 4 GiB at D = 12). -1 for D outside [1, 12].
+ */
+int64_t neuvv_directory_entries(int32_t depth);
+
+/*
+ * neuvv_build_directory - fills the brick directory that the octree walk of
+ * every render call reads (Sec. 4.3 "Rendering": it serves the same walk as
+ * the node table, so that leaving a 4^3 region of leaf cells costs at most
+ * two dependent reads instead of one per node level). Entry (k E + j) E + i
+ * describes the region of cells [4i, 4i+4) x [4j, 4j+4) x [4k, 4k+4):
+ *   >= 0       the row of nodes of the region's last-level node (the region
+ *              holds a leaf; for D <= 2, row 0, the root);
+ *   -(1 + s)   the region holds no leaf; 2^s (2 <= s < D) is the edge of the
+ *              largest aligned cube around it that holds none, at the node
+ *              levels of neuvv_build_voctree (a child cell, or a 2^3 group of
+ *              child cells of a 2-bit node).
+ * Build it once per node table, after uploading the nodes; the renders then
+ * take it in neuvv_tree.dir. Queued on stream; nodes must be the table of
+ * neuvv_build_voctree for this depth (its child indices are followed as they
+ * are).
+ * depth      D in [1, 12].
+ * n_nodes    rows of nodes.
+ * nodes      device [n_nodes][4] int32, 16-byte aligned.
+ * dir        device int32 [capacity] output, 4-byte aligned.
+ * capacity   entries available, >= neuvv_directory_entries(depth).
+ * Errors: RANGE (depth, n_nodes), ARG (NULL or misaligned buffer), CAPACITY,
+ * HIP (launch).
+ */
+int neuvv_build_directory(int32_t depth, int64_t n_nodes, const int32_t* nodes, int32_t* dir, int64_t capacity,
+                          void* stream);
 
 /*
  * neuvv_payload_words - element counts of the payload arrays for n_leaves

@@ -31,7 +31,7 @@ class neuvv_tree(ctypes.Structure):
                 ("T", ctypes.c_int32), ("box", ctypes.c_int32 * 6), ("layout", ctypes.c_int32),
                 ("basis", ctypes.c_void_p), ("gamma", ctypes.c_void_p), ("Cg", ctypes.c_int32),
                 ("wgam", ctypes.c_void_p), ("basis_g", ctypes.c_void_p), ("edit", ctypes.c_void_p),
-                ("density", ctypes.c_int32)]
+                ("density", ctypes.c_int32), ("dir", ctypes.c_void_p)]
 
 
 class neuvv_instance(ctypes.Structure):
@@ -59,6 +59,7 @@ _F = ctypes.c_float
 _SIGNATURES = {
     "neuvv_build_voctree": [_I32, _I64, _P, _P, _I64, _P, _P, _P],
     "neuvv_payload_words": [_I32, _I32, _I32, _I64, _P, _P],
+    "neuvv_build_directory": [_I32, _I64, _P, _P, _I64, _P],
     "neuvv_pack_leaves": [_I32, _I32, _I32, _I32, _I64, _P, _P, _P, _P, _P, _P],
     "neuvv_render": [ctypes.POINTER(neuvv_tree), ctypes.POINTER(neuvv_instance), _I64, _P, _P, _P, _F, _I32, _F,
                      _P, _P, _P, _P, _P],
@@ -83,7 +84,7 @@ _SIGNATURES = {
     "neuvv_pinhole_rays": [ctypes.POINTER(neuvv_camera), _I64, _P, _P, _P, _P],
     "neuvv_eval_hh": [_I32, _I64, _P, _P, _P, _P],
 }
-EXPORTS = list(_SIGNATURES) + ["neuvv_last_error", "neuvv_version", "neuvv_trace_bytes"]
+EXPORTS = list(_SIGNATURES) + ["neuvv_last_error", "neuvv_version", "neuvv_trace_bytes", "neuvv_directory_entries"]
 
 _lib: Optional[ctypes.CDLL] = None
 
@@ -111,6 +112,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.neuvv_version.argtypes = []
     lib.neuvv_trace_bytes.restype = ctypes.c_int64
     lib.neuvv_trace_bytes.argtypes = [_I64, _I64]
+    lib.neuvv_directory_entries.restype = ctypes.c_int64
+    lib.neuvv_directory_entries.argtypes = [_I32]
     _lib = lib
     return lib
 
@@ -210,6 +213,18 @@ def neuvv_render_backward(tree: neuvv_tree, inst, n_rays, ray_o, ray_d, ray_t, t
         ctypes.byref(tree), _inst_ptr(inst), int(n_rays), _ptr(ray_o), _ptr(ray_d), _ptr(ray_t), float(t_scalar),
         int(image_width), float(t_stop), _ptr(rgb), _ptr(alpha), _ptr(nsamp), _ptr(grad_rgb), _ptr(grad_alpha),
         _ptr(grad_leaf), _ptr(grad_basis), _ptr(grad_basis_g), _stream(stream)))
+
+
+def neuvv_directory_entries(depth: int) -> int:
+    v = load().neuvv_directory_entries(int(depth))
+    if v < 0:
+        raise NeuvvError("neuvv_directory_entries", -2, f"depth {depth} outside [1, 12]")
+    return v
+
+
+def neuvv_build_directory(depth, n_nodes, nodes, dir_out, capacity, stream=None):
+    _check("neuvv_build_directory", load().neuvv_build_directory(int(depth), int(n_nodes), _ptr(nodes), _ptr(dir_out),
+                                                                 int(capacity), _stream(stream)))
 
 
 def neuvv_trace_bytes(n_rays: int, trace_cap: int) -> int:

@@ -66,6 +66,8 @@ int check_tree(const neuvv_tree* t) {
         return fail(NEUVV_ERR_RANGE, "n_leaves %lld", (long long)t->n_leaves);
     if (t->T < 1) return fail(NEUVV_ERR_RANGE, "T = %d must be >= 1", t->T);
     if (!t->nodes || !t->basis) return fail(NEUVV_ERR_ARG, "tree nodes/basis pointer is NULL");
+    if (!t->dir) return fail(NEUVV_ERR_ARG, "tree dir is NULL (neuvv_build_directory fills it)");
+    if (reinterpret_cast<uintptr_t>(t->dir) % 4 != 0) return fail(NEUVV_ERR_ARG, "tree dir must be 4-byte aligned");
     if (t->Cg == 0 && !t->gamma) return fail(NEUVV_ERR_ARG, "tree gamma pointer is NULL");
     if (t->Cg > 0 && !t->basis_g) return fail(NEUVV_ERR_ARG, "tree basis_g pointer is NULL");
     if (reinterpret_cast<uintptr_t>(t->nodes) % 16 != 0) return fail(NEUVV_ERR_ARG, "tree nodes must be 16-byte aligned");
@@ -165,6 +167,7 @@ neuvv::TreeArgs tree_args(const neuvv_tree* t) {
     a.wgam = t->wgam;
     a.basis_g = t->basis_g;
     a.edit = reinterpret_cast<const float4*>(t->edit);
+    a.dir = t->dir;
     a.n_nodes = t->n_nodes;
     a.n_leaves = t->n_leaves;
     a.depth = t->depth;
@@ -254,6 +257,29 @@ int neuvv_pack_leaves(int32_t K, int32_t C, int32_t dtype, int32_t layout, int64
     return hip_status(neuvv::launch_pack(K, C, dtype, layout, n_leaves, hh_in, wsig_in, slot_of_input, hh_out, wsig_out,
                                          (hipStream_t)stream),
                       "pack_leaves launch");
+    NEUVV_GUARD_END
+}
+
+int64_t neuvv_directory_entries(int32_t depth) {
+    if (depth < 1 || depth > neuvv::kMaxDepth) return -1;
+    return neuvv::directory_entries(depth);
+}
+
+int neuvv_build_directory(int32_t depth, int64_t n_nodes, const int32_t* nodes, int32_t* dir, int64_t capacity,
+                          void* stream) {
+    NEUVV_GUARD_BEGIN
+    if (depth < 1 || depth > neuvv::kMaxDepth) return fail(NEUVV_ERR_RANGE, "depth %d outside [1, 12]", depth);
+    if (n_nodes < 1 || n_nodes > INT32_MAX) return fail(NEUVV_ERR_RANGE, "n_nodes %lld", (long long)n_nodes);
+    if (!nodes || !dir) return fail(NEUVV_ERR_ARG, "NULL buffer");
+    if (reinterpret_cast<uintptr_t>(nodes) % 16 != 0) return fail(NEUVV_ERR_ARG, "nodes must be 16-byte aligned");
+    if (reinterpret_cast<uintptr_t>(dir) % 4 != 0) return fail(NEUVV_ERR_ARG, "dir must be 4-byte aligned");
+    const int64_t need = neuvv::directory_entries(depth);
+    if (capacity < need)
+        return fail(NEUVV_ERR_CAPACITY, "dir holds %lld entries, depth %d needs %lld", (long long)capacity, depth,
+                    (long long)need);
+    return hip_status(neuvv::launch_build_directory(reinterpret_cast<const int4*>(nodes), depth, dir,
+                                                    (hipStream_t)stream),
+                      "build_directory launch");
     NEUVV_GUARD_END
 }
 

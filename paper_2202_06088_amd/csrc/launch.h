@@ -105,6 +105,8 @@ hipError_t launch_pack_rows(int R, int dtype, int layout, int64_t n, const float
                             void* out, hipStream_t stream);
 hipError_t launch_pack(int K, int C, int dtype, int layout, int64_t n, const float* hh_in, const float* wsig_in,
                        const int64_t* slot_of_input, void* hh_out, void* wsig_out, hipStream_t stream);
+// The brick directory of a depth-D node table (directory_entries(D) entries).
+hipError_t launch_build_directory(const int4* nodes, int depth, int32_t* dir, hipStream_t stream);
 
 // Lighting (Sec. 5.2): Gaussian taps of the shadow-map low-pass, and the light.
 constexpr int kMaxBlurRadius = 48;

@@ -4,7 +4,9 @@
 //  * pinhole: camera rays, compensated arithmetic rounded once;
 //  * eval_hh: the per-ray HH basis on its own (Eq. 2-4), a test hook;
 //  * pack: leaf coefficients into the 16-byte-vector structure-of-arrays
-//    storage layout, with round-to-nearest-even for 16-bit storage.
+//    storage layout, with round-to-nearest-even for 16-bit storage;
+//  * directory: the brick directory of a node table (one descent per 4^3
+//    region of leaf cells, done once per tree).
 // All are memory-bound streaming kernels: one thread per pixel / ray / leaf,
 // grid-stride loops over a grid sized to the device.
 #include <hip/hip_runtime.h>
@@ -351,6 +353,50 @@ hipError_t launch_pack(int K, int C, int dtype, int layout, int64_t n, const flo
 }  // namespace neuvv
 
 namespace neuvv {
+
+// ----------------------------------------------------------------------------
+// brick directory: entry (k E + j) E + i for the 4^3 region with corner
+// (4i, 4j, 4k) descends from the root through the node levels above the last
+// one. It stops at the first child cell (edge 2^cs) that holds no leaf and
+// records -(1 + s), s = cs + 1 when the child's 2^3 group (one byte of a
+// 2-bit node's mask) is empty as well, else s = cs: the cube at which a walk
+// descending to any cell of the region would stop. A region that holds a
+// leaf gets the row of its last-level node. With D <= 2 the root is that node.
+
+__global__ __launch_bounds__(kEwBlock) void directory_kernel(const int4* __restrict__ nodes, int D, int64_t n,
+                                                             int32_t* __restrict__ dir) {
+    const int64_t E = directory_edge(D);
+    const int last = (D + 1) / 2 - 1;
+    for (int64_t i = (int64_t)blockIdx.x * kEwBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kEwBlock) {
+        const int x = (int)(i % E) << 2, y = (int)((i / E) % E) << 2, z = (int)(i / (E * E)) << 2;
+        int node = 0;
+        int entry = 0;
+        bool empty = false;
+        for (int w = 0; w < last && !empty; ++w) {
+            const int bits = node_bits(D, w);
+            const int cs = node_edge(D, w) - bits;
+            const int xs = x >> cs, ys = y >> cs, zs = z >> cs;
+            int q = (xs & 1) | ((ys & 1) << 1) | ((zs & 1) << 2);
+            if (bits == 2) q |= ((xs & 2) << 2) | ((ys & 2) << 3) | ((zs & 2) << 4);
+            const int4 v = nodes[node];
+            const uint64_t m = ((uint64_t)(uint32_t)v.y << 32) | (uint32_t)v.x;
+            if ((m >> q) & 1ull) {
+                node = v.z + (int)__builtin_popcountll(m & ((1ull << q) - 1ull));
+            } else {
+                const int s = (bits == 2 && ((m >> (q & 56)) & 0xffull) == 0ull) ? cs + 1 : cs;
+                entry = -(1 + s);
+                empty = true;
+            }
+        }
+        dir[i] = empty ? entry : node;
+    }
+}
+
+hipError_t launch_build_directory(const int4* nodes, int depth, int32_t* dir, hipStream_t stream) {
+    const int64_t n = directory_entries(depth);
+    hipLaunchKernelGGL(directory_kernel, dim3(ew_grid(n)), dim3(kEwBlock), 0, stream, nodes, depth, n, dir);
+    return hipGetLastError();
+}
 
 // ----------------------------------------------------------------------------
 // appearance edits (Sec. 5.2 "Appearance editing"): every ray that ended in a

@@ -8,11 +8,12 @@
 //               Eq. 2-3, Appendix A.2) as closed-form polynomials;
 //  * RaySetup:  instance transform and re-timing of one ray (Eq. 13), clip to
 //               the tree box, per-ray HH basis and density-basis row (Eq. 4, 5);
-//  * walk_next: octree descent to the next occupied leaf along the ray
-//               (Sec. 4.3 "Rendering"), skipping whole empty octree nodes;
-//               the octree is stored two levels per node (64-bit occupancy
-//               mask + base index), and the node of the current 4^3 brick of
-//               leaves is kept in registers.
+//  * walk_next: the next occupied leaf along the ray (Sec. 4.3 "Rendering"),
+//               skipping whole empty octree cubes; the octree is stored two
+//               levels per node (64-bit occupancy mask + base index), a
+//               directory maps each 4^3 region of leaf cells to its
+//               last-level node (a "brick") or to the largest empty cube
+//               around it, and the current brick's node is kept in registers.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -21,7 +22,6 @@
 namespace neuvv {
 
 constexpr int kMaxDepth = 12;
-constexpr int kMaxLevels = (kMaxDepth + 1) / 2;   // node levels (two octree levels each)
 constexpr int kWave = 64;
 
 // ----------------------------------------------------------------------------
@@ -221,6 +221,7 @@ struct TreeArgs {
     const float* basis_g;   // [T][Cg] hyperangle basis
     const float4* edit;     // nullptr, or [N][2] rows {r, g, b, sigma_d}, {t_d, owner, 0, 0} (appearance edits)
     int32_t relu;           // density activation of Eq. 5: 0 softplus, 1 ReLU
+    const int32_t* dir;     // brick directory (directory_entries(depth) entries; see walk_next)
 };
 
 struct InstArgs {
@@ -437,14 +438,13 @@ __device__ __forceinline__ void ray_setup(const TreeArgs& tr, const InstArgs& in
 
 struct Walk {
     int cell[3];     // leaf-level cell containing the ray just after the entry point
-    int lvl;         // node level of the deepest ancestor of cell known in path[]
     int steps;
     int entry_axis;  // the entry point is the crossing of plane entry_plane on this axis; -1: u_in
     int entry_plane;
     df u_entry;      // the exact entry parameter when u_entry_ok (the previous step computed it)
     bool u_entry_ok;
     bool done;
-    int brick;       // row of the last-level node held below, -1: none
+    int brick;       // directory entry of the brick whose node is held below, -1: none
     uint32_t bm_lo, bm_hi;
     int bbase;
 };
@@ -453,11 +453,16 @@ struct Walk {
 // 2^node_edge(D, w) split into child cells of edge 2^(node_edge - node_bits).
 __device__ __forceinline__ int node_bits(int D, int w) { return (w == 0 && (D & 1)) ? 1 : 2; }
 __device__ __forceinline__ int node_edge(int D, int w) { return w == 0 ? D : D - (D & 1 ? 1 : 2) - 2 * (w - 1); }
-// Deepest node level whose node still contains two cells whose coordinates
-// first differ in bit hb.
-__device__ __forceinline__ int common_level(int D, int hb) {
-    const int top = (D & 1) ? 1 : 2;
-    return D - top > hb ? ((D - top - hb - 1) >> 1) + 1 : 0;
+// The brick directory: one int32 per 4^3 region of leaf cells, E^3 entries
+// with E = 2^(D-2) (E = 1 for D <= 2, where the root is the only node),
+// entry (k E + j) E + i for the region with corner (4i, 4j, 4k): the row of
+// the region's last-level node when the region holds a leaf, else -(1 + s)
+// where 2^s is the edge of the largest aligned cube around the region that
+// holds no leaf, the cube at which a descent from the root would stop.
+__host__ __device__ __forceinline__ int64_t directory_edge(int D) { return D <= 2 ? 1 : (int64_t)1 << (D - 2); }
+__host__ __device__ __forceinline__ int64_t directory_entries(int D) {
+    const int64_t e = directory_edge(D);
+    return e * e * e;
 }
 
 __device__ __forceinline__ void walk_begin(const TreeArgs& tr, const RaySetup& rs, Walk& w) {
@@ -467,7 +472,6 @@ __device__ __forceinline__ void walk_begin(const TreeArgs& tr, const RaySetup& r
         int c = df_cell(p, rs.sgn[a]);
         w.cell[a] = c < tr.box_lo[a] ? tr.box_lo[a] : (c > tr.box_hi[a] - 1 ? tr.box_hi[a] - 1 : c);
     }
-    w.lvl = 0;
     w.steps = 0;
     w.entry_axis = -1;
     w.entry_plane = 0;
@@ -508,9 +512,14 @@ __device__ __forceinline__ df entry_param(const RaySetup& rs, const Walk& w) {
 // most kBudget cells are visited per call, and -2 says that the budget ran out
 // before a segment was found (the next call resumes the walk): lanes of a
 // wavefront in long empty stretches then stop holding back the lanes that
-// have a sample to evaluate. path points at this
-// lane's column of a [kMaxLevels][stride] LDS array of node rows; s_nodes
-// holds the first n_lds rows of the node table.
+// have a sample to evaluate.
+//
+// A cell visit reads nothing while the walk stays in the brick whose node it
+// holds. Entering another 4^3 region, it reads the region's directory entry
+// and, when the region holds a leaf, the brick's node row: at most two
+// dependent loads, where a descent from the deepest common ancestor took up
+// to one per node level (and a wavefront as many loop iterations as its
+// deepest lane).
 //
 // Every decision of the walk (which face a node is left through, which cell
 // the ray enters, whether it leaves the box) is taken on float estimates
@@ -519,51 +528,47 @@ __device__ __forceinline__ df entry_param(const RaySetup& rs, const Walk& w) {
 // Segment lengths of leaves always come from compensated entry and exit
 // parameters. The sequence of cells is therefore that of the exact walk.
 template <int kBudget = 0>
-__device__ __forceinline__ int walk_next(const TreeArgs& tr, const int4* __restrict__ s_nodes, int n_lds,
-                                         int* path, int stride, const RaySetup& rs, Walk& w, float& delta,
+__device__ __forceinline__ int walk_next(const TreeArgs& tr, const RaySetup& rs, Walk& w, float& delta,
                                          float& umid, df& seg_a, df& seg_b) {
     const int Dp = tr.depth;
     const int G = 1 << Dp;
-    const int last = (Dp + 1) / 2 - 1;   // last node level
+    const int E = (int)directory_edge(Dp);
     const int max_steps = 3 * G + 16;
     constexpr float kRel = 1.0e-6f;   // bound on the relative error of a float estimate (~16 ulp)
     int budget = kBudget;
     while (!w.done) {
         if (kBudget > 0 && budget-- == 0) return -2;
         if (++w.steps > max_steps) { w.done = true; break; }
-        // descend from the deepest valid ancestor; sh = log2 of the edge of the
-        // empty octree node or leaf reached
-        int lvl = w.lvl;
-        int node = lvl == 0 ? 0 : path[lvl * stride];
+        // the cell's brick, or the empty cube around its region; sh = log2 of the
+        // edge of the empty cube or cell reached (0 for a leaf)
         int leaf = -1;
-        int sh;
-        for (;;) {
-            uint32_t mlo, mhi;
-            int base;
-            if (lvl == last && node == w.brick) {
-                mlo = w.bm_lo; mhi = w.bm_hi; base = w.bbase;
-            } else {
-                const int4 v = node < n_lds ? s_nodes[node] : tr.nodes[node];
-                mlo = (uint32_t)v.x; mhi = (uint32_t)v.y; base = v.z;
-                if (lvl == last) { w.brick = node; w.bm_lo = mlo; w.bm_hi = mhi; w.bbase = base; }
+        int sh = 0;
+        {
+            const int bid = ((w.cell[2] >> 2) * E + (w.cell[1] >> 2)) * E + (w.cell[0] >> 2);
+            bool held = bid == w.brick;
+            if (!held) {
+                const int e = tr.dir[bid];
+                if (e >= 0) {
+                    const int4 v = tr.nodes[e];
+                    w.brick = bid;
+                    w.bm_lo = (uint32_t)v.x;
+                    w.bm_hi = (uint32_t)v.y;
+                    w.bbase = v.z;
+                    held = true;
+                } else {
+                    sh = -e - 1;
+                }
             }
-            const int bits = node_bits(Dp, lvl);
-            const int cs = node_edge(Dp, lvl) - bits;   // log2 child edge
-            const int x = w.cell[0] >> cs, y = w.cell[1] >> cs, z = w.cell[2] >> cs;
-            int q = (x & 1) | ((y & 1) << 1) | ((z & 1) << 2);
-            if (bits == 2) q |= ((x & 2) << 2) | ((y & 2) << 3) | ((z & 2) << 4);
-            const uint64_t m = ((uint64_t)mhi << 32) | mlo;
-            if (!((m >> q) & 1ull)) {
-                // empty child cell; the octree node one level up (its 2^3 group,
-                // one byte of the mask) may be empty as a whole
-                sh = (bits == 2 && ((m >> (q & 56)) & 0xffull) == 0ull) ? cs + 1 : cs;
-                break;
+            if (held) {
+                // child q of the brick node: bit 0 of x, y, z, then bit 1 of x, y, z
+                const int x = w.cell[0], y = w.cell[1], z = w.cell[2];
+                const int q = (x & 1) | ((y & 1) << 1) | ((z & 1) << 2) | ((x & 2) << 2) | ((y & 2) << 3) | ((z & 2) << 4);
+                const uint64_t m = ((uint64_t)w.bm_hi << 32) | w.bm_lo;
+                if ((m >> q) & 1ull)
+                    leaf = w.bbase + (int)__builtin_popcountll(m & ((1ull << q) - 1ull));
+                else   // an empty cell; its 2^3 group (one byte of the mask) may be empty as a whole
+                    sh = ((m >> (q & 56)) & 0xffull) == 0ull ? 1 : 0;
             }
-            const int idx = base + (int)__builtin_popcountll(m & ((1ull << q) - 1ull));
-            if (lvl == last) { leaf = idx; sh = 0; break; }   // occupied leaf
-            ++lvl;
-            node = idx;
-            path[lvl * stride] = idx;
         }
         const int S = 1 << sh;
         // Exit face of the cell (or empty node) of edge S: per axis the float
@@ -669,10 +674,6 @@ __device__ __forceinline__ int walk_next(const TreeArgs& tr, const int4* __restr
             if (n_am < 0 || n_am >= G) {
                 w.done = true;
             } else {
-                const unsigned x = (unsigned)((w.cell[0] ^ nc[0]) | (w.cell[1] ^ nc[1]) | (w.cell[2] ^ nc[2]));
-                const int hb = 31 - __builtin_clz(x);     // x != 0: the exit axis changed
-                const int common = common_level(Dp, hb);
-                w.lvl = common < lvl ? common : lvl;
                 w.cell[0] = nc[0];
                 w.cell[1] = nc[1];
                 w.cell[2] = nc[2];
@@ -690,11 +691,10 @@ __device__ __forceinline__ int walk_next(const TreeArgs& tr, const int4* __restr
 
 // The same without the segment's compensated bounds [seg_a, seg_b).
 template <int kBudget = 0>
-__device__ __forceinline__ int walk_next(const TreeArgs& tr, const int4* __restrict__ s_nodes, int n_lds,
-                                         int* path, int stride, const RaySetup& rs, Walk& w, float& delta,
+__device__ __forceinline__ int walk_next(const TreeArgs& tr, const RaySetup& rs, Walk& w, float& delta,
                                          float& umid) {
     df a, b;
-    return walk_next<kBudget>(tr, s_nodes, n_lds, path, stride, rs, w, delta, umid, a, b);
+    return walk_next<kBudget>(tr, rs, w, delta, umid, a, b);
 }
 
 }  // namespace neuvv

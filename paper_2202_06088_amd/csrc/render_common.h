@@ -1,5 +1,5 @@
 // Building blocks shared by the render kernels (render_kernels.h, render_pp.hip):
-// payload gathers, work queues, LDS staging of the top node rows, launch
+// payload gathers, work queues, cull passes and candidate lists, launch
 // sizing. Device code for gfx950.
 #pragma once
 
@@ -203,16 +203,6 @@ __device__ __forceinline__ bool no_candidates(const RayArgs& ra) {
 #pragma unroll
     for (int x = 0; x < kQueues; ++x) total += ra.count[x * kQueueStride];
     return total == 0;
-}
-
-// Stages the first min(n_nodes, CAP) node rows (the top levels, stored
-// first) in LDS; returns their number.
-template <int CAP>
-__device__ __forceinline__ int stage_top_nodes(const TreeArgs& tr, int4* s_nodes) {
-    const int n_lds = (int)(tr.n_nodes < CAP ? tr.n_nodes : CAP);
-    for (int i = threadIdx.x; i < n_lds; i += kBlock) s_nodes[i] = tr.nodes[i];
-    __syncthreads();
-    return n_lds;
 }
 
 // 12-byte vector access to a ray's origin or direction, or a pixel's colour
@@ -538,8 +528,8 @@ static __global__ void record_init_kernel(int32_t* head, int64_t n, unsigned lon
 // [cap x / kQueues, cap (x + 1) / kQueues). [cur, end) is what is left of the
 // wavefront's current block. Returns the first item, or -1 when the XCD's
 // part is exhausted. Call with every lane of the wavefront active.
-__device__ __forceinline__ int64_t take_items(unsigned long long* counter, int64_t cap, int home, int n, int64_t& cur,
-                                              int64_t& end) {
+__device__ __forceinline__ int take_items(unsigned long long* counter, int64_t cap, int home, int n, int& cur,
+                                          int& end) {
     if (cur + n > end) {
         const int64_t lo = cap * home / kQueues, hi = cap * (home + 1) / kQueues;
         unsigned long long b = 0;
@@ -547,11 +537,12 @@ __device__ __forceinline__ int64_t take_items(unsigned long long* counter, int64
         const uint32_t b_lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)b);
         const uint32_t b_hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(b >> 32));
         const int64_t first = lo + (int64_t)(((uint64_t)b_hi << 32) | b_lo);
-        cur = first;
-        end = first + kRecBlock <= hi ? first + kRecBlock : (first < hi ? hi : first);
+        // the room is below 2^31 items, so the block's bounds fit int32 once clamped to the part
+        cur = (int)(first < hi ? first : hi);
+        end = (int)(first + kRecBlock <= hi ? first + kRecBlock : hi);
     }
     if (cur + n > end) return -1;
-    const int64_t at = cur;
+    const int at = cur;
     cur += n;
     return at;
 }

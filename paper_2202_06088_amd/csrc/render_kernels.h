@@ -15,8 +15,9 @@
 // (wave-uniform) cursor by the popcount.
 //
 // Per lane: each iteration of the wavefront's loop advances the walk by one
-// cell (top node rows from LDS, the rest from L2/HBM, the current brick's
-// node in registers); a lane whose cell is an occupied leaf gathers the
+// cell (the current brick's node in registers; entering another 4^3 region,
+// its directory entry and brick row from L2/HBM); a lane whose cell is an
+// occupied leaf gathers the
 // leaf's payload (one contiguous row per leaf, or 16-byte-vector
 // structure-of-arrays) in 16-byte loads, evaluates colour and density in
 // float32 and composites. The per-sample HH contraction is a 3xK times K
@@ -46,9 +47,6 @@ namespace neuvv {
 template <int K, int C>
 __host__ __device__ constexpr int min_waves(int want) { return 3 * K + C <= 56 ? want : 1; }
 
-// node rows (16 B each) staged in LDS: the top levels of the tree
-constexpr int kLdsNodesFwd = 1024;
-constexpr int kLdsNodesBwd = 1024;
 
 template <int K, int C>
 __device__ __forceinline__ void ray_basis(const TreeArgs& tr, const RaySetup& rs, float (&h)[K], float (&b)[C]) {
@@ -88,12 +86,16 @@ template <int K, int C, int DT, bool IDENT, bool EDIT, bool TRACE>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(min_waves<K, C>(3), 8))) void render_fwd_kernel(
     TreeArgs tr, InstArgs in, RayArgs ra, float t_stop, RenderOut out) {
     if (no_candidates(ra)) return;
-    __shared__ int4 s_nodes[kLdsNodesFwd];
-    __shared__ int s_path[kMaxLevels * kBlock];
     __shared__ float s_h[kBlock * K];
     __shared__ float s_b[kBlock * C];
-    const int n_lds = stage_top_nodes<kLdsNodesFwd>(tr, s_nodes);
-    int* path = s_path + threadIdx.x;
+    // traced: the output addresses, needed once per ray, wait in LDS rather than in scalar
+    // registers, which the trace's allocation takes
+    __shared__ RenderOut s_out;
+    if constexpr (TRACE) {
+        if (threadIdx.x == 0) s_out = out;
+        __syncthreads();
+    }
+    const RenderOut& fo = TRACE ? s_out : out;
     ChunkCursor cc = chunk_cursor();
     bool more = true;   // wave-uniform: chunks may be left
 
@@ -110,7 +112,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(min_wave
     // trace: the previous sample, written once the slot of the next is known
     int pslot = -1, pleaf = 0;
     float pdelta = 0.0f, px = 0.0f, pc0 = 0.0f, pc1 = 0.0f, pc2 = 0.0f;
-    int64_t tcur = 0, tend = 0;      // trace: what is left of the wavefront's block (wave-uniform)
+    int tcur = 0, tend = 0;      // trace: what is left of the wavefront's block (wave-uniform)
 
     for (;;) {
         const uint64_t idle = __ballot(!alive);
@@ -173,14 +175,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(min_wave
         int leaf = -1;
         float delta = 0.0f, umid = 0.0f;
         if (alive) {
-            leaf = walk_next<kWalkBudget>(tr, s_nodes, n_lds, path, kBlock, rs, w, delta, umid);
+            leaf = walk_next<kWalkBudget>(tr, rs, w, delta, umid);
             finish = leaf == -1;
         }
         int cur = -1;
         if constexpr (TRACE) {
             const uint64_t hm = __ballot(leaf >= 0);
             const int n_s = __popcll(hm);
-            const int64_t at = n_s > 0 ? take_items(out.trace.counter, out.trace.cap, cc.home, n_s, tcur, tend) : -1;
+            const int at = n_s > 0 ? take_items(out.trace.counter, out.trace.cap, cc.home, n_s, tcur, tend) : -1;
             if (leaf >= 0) {
                 if (at >= 0 && t_first != -2) {
                     cur = (int)(at + lane_rank(hm));
@@ -245,18 +247,18 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(min_wave
             }
         }
         if (alive && finish) {
-            if (out.rgb) store3(out.rgb + 3 * ray, acc0, acc1, acc2);
-            if (out.alpha) out.alpha[ray] = 1.0f - Tr;
-            if (out.depth) out.depth[ray] = wsum > 0.0f ? dsum / wsum : INFINITY;
-            if (out.nsamp) out.nsamp[ray] = ns;
-            if (out.last_leaf) out.last_leaf[ray] = stopped ? last : -1;
+            if (fo.rgb) store3(fo.rgb + 3 * ray, acc0, acc1, acc2);
+            if (fo.alpha) fo.alpha[ray] = 1.0f - Tr;
+            if (fo.depth) fo.depth[ray] = wsum > 0.0f ? dsum / wsum : INFINITY;
+            if (fo.nsamp) fo.nsamp[ray] = ns;
+            if (fo.last_leaf) fo.last_leaf[ray] = stopped ? last : -1;
             if constexpr (TRACE) {
                 if (t_first >= 0) {
                     out.trace.smp[2 * (int64_t)pslot] =
                         make_int4(pleaf, __float_as_int(pdelta), __float_as_int(px), __float_as_int(pc0));
                     out.trace.smp[2 * (int64_t)pslot + 1] = make_int4(__float_as_int(pc1), __float_as_int(pc2), -1, 0);
                 }
-                out.trace.head[ray] = t_first >= 0 ? t_first : -1;
+                fo.trace.head[ray] = t_first >= 0 ? t_first : -1;
             }
             alive = false;
         }
@@ -296,16 +298,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(min_wave
     TreeArgs tr, InstArgs in, RayArgs ra, BackwardIO io, RecordArgs rec) {
     if (no_candidates(ra)) return;
     constexpr int ROW = grad_row<K, C>();
-    // a replaying launch does not walk: no node rows or paths
-    constexpr int kNodes = REPLAY ? 1 : kLdsNodesBwd;
-    __shared__ int4 s_nodes[kNodes];
-    __shared__ int s_path[REPLAY ? 1 : kMaxLevels * kBlock];
     __shared__ float s_h[kBlock * K];
     __shared__ float s_b[kBlock * C];
     __shared__ float s_gb[C];
-    if (threadIdx.x < C) s_gb[threadIdx.x] = 0.0f;   // made visible by the barrier in stage_top_nodes
-    const int n_lds = stage_top_nodes<kNodes>(tr, s_nodes);
-    int* path = s_path + threadIdx.x;
+    if (threadIdx.x < C) s_gb[threadIdx.x] = 0.0f;
+    __syncthreads();
     ChunkCursor cc = chunk_cursor();
     bool more = true;   // wave-uniform: chunks may be left
     const int64_t N = tr.n_leaves;
@@ -334,7 +331,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(min_wave
     // records: the wavefront fills blocks of kRecBlock consecutive records,
     // taken from its XCD's part of the room; [wrec, wend) is what is left of
     // the current block (wave-uniform)
-    int64_t wrec = 0, wend = 0;
+    int wrec = 0, wend = 0;
 
     for (;;) {
         const uint64_t idle = __ballot(!alive);
@@ -423,7 +420,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(min_wave
                 finish = leaf < 0;
             } else {
                 float umid;
-                leaf = walk_next<kWalkBudget>(tr, s_nodes, n_lds, path, kBlock, rs, w, delta, umid);
+                leaf = walk_next<kWalkBudget>(tr, rs, w, delta, umid);
                 finish = leaf == -1;
                 if (leaf >= 0) {
                     float wv[3 * K];
@@ -489,7 +486,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(min_wave
             // the record stores of the wavefront are contiguous
             const uint64_t hm = __ballot(has);
             const int n_has = __popcll(hm);
-            const int64_t at = n_has > 0 ? take_items(rec.counter, rec.cap, cc.home, n_has, wrec, wend) : -1;
+            const int at = n_has > 0 ? take_items(rec.counter, rec.cap, cc.home, n_has, wrec, wend) : -1;
             if (at >= 0) {
                 const RecordRun run = record_run(hm, has, leaf);
                 if (has) {

@@ -34,8 +34,6 @@
 
 namespace neuvv {
 
-constexpr int kLdsNodesMulti = 512;
-
 struct MSeg {
     df a, b;                  // current segment [a, b) in the ray parameter
     float kap, c0, c1, c2;    // extinction per unit u, colour
@@ -44,11 +42,10 @@ struct MSeg {
 
 // Fetches instance k's next segment: walk, then evaluate the leaf (Eq. 4, 5).
 template <int DT>
-__device__ __forceinline__ void fetch_segment(const TreeArgs& tr, const int4* s_nodes, int n_lds, int* path,
-                                              const RaySetup& rs, Walk& w, MSeg& sg) {
+__device__ __forceinline__ void fetch_segment(const TreeArgs& tr, const RaySetup& rs, Walk& w, MSeg& sg) {
     float delta, umid;
     df a, b;
-    const int leaf = walk_next(tr, s_nodes, n_lds, path, kBlock, rs, w, delta, umid, a, b);
+    const int leaf = walk_next(tr, rs, w, delta, umid, a, b);
     if (leaf < 0) {
         sg.has = false;
         return;
@@ -96,15 +93,6 @@ template <int L, int DT>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(L <= 3 ? 2 : 1, 8))) void render_multi_kernel(
     MultiArgs ma, RayArgs ra, float t_stop, RenderOut out) {
     if (no_candidates(ra)) return;
-    __shared__ int4 s_nodes[L][kLdsNodesMulti];
-    __shared__ int s_path[L][kMaxLevels * kBlock];
-    int n_lds[L];
-#pragma unroll
-    for (int k = 0; k < L; ++k) {
-        n_lds[k] = (int)(ma.tr[k].n_nodes < kLdsNodesMulti ? ma.tr[k].n_nodes : kLdsNodesMulti);
-        for (int i = threadIdx.x; i < n_lds[k]; i += kBlock) s_nodes[k][i] = ma.tr[k].nodes[i];
-    }
-    __syncthreads();
     ChunkCursor cc = chunk_cursor();
     bool more = true;
 
@@ -157,7 +145,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(L <= 3 ?
                     sg[k].has = false;
                     if (rs[k].hit) {
                         walk_begin(ma.tr[k], rs[k], w[k]);
-                        fetch_segment<DT>(ma.tr[k], s_nodes[k], n_lds[k], &s_path[k][threadIdx.x], rs[k], w[k], sg[k]);
+                        fetch_segment<DT>(ma.tr[k], rs[k], w[k], sg[k]);
                         any = any || sg[k].has;
                     }
                 }
@@ -216,8 +204,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(L <= 3 ?
 #pragma unroll
                 for (int k = 0; k < L; ++k) {
                     if (sg[k].has && !df_lt(u, sg[k].b))        // this instance's segment ends here
-                        fetch_segment<DT>(ma.tr[k], s_nodes[k], n_lds[k], &s_path[k][threadIdx.x], rs[k], w[k],
-                                          sg[k]);
+                        fetch_segment<DT>(ma.tr[k], rs[k], w[k], sg[k]);
                     any = any || sg[k].has;
                 }
                 finish = !any;
@@ -258,7 +245,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(L <= 3 ?
 // Rays whose list did not fit the room (head -2) are listed by phase 2 and
 // rendered afterwards by the fused kernel.
 
-constexpr int kLdsNodesEmit = 1024;
 constexpr float kEmitStop = 0.99f;
 constexpr int64_t kMergeRoomPerRay = 2;   // list entries per ray and instance
 
@@ -280,12 +266,8 @@ template <int DT, bool IDENT>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) void merge_emit_kernel(
     TreeArgs tr, InstArgs in, RayArgs ra, float t_stop, MergeLists ml) {
     if (no_candidates(ra)) return;
-    __shared__ int4 s_nodes[kLdsNodesEmit];
-    __shared__ int s_path[kMaxLevels * kBlock];
     __shared__ float s_h[kBlock * 16];
     __shared__ float s_b[kBlock * 8];
-    const int n_lds = stage_top_nodes<kLdsNodesEmit>(tr, s_nodes);
-    int* path = s_path + threadIdx.x;
     ChunkCursor cc = chunk_cursor();
     bool more = true;
 
@@ -300,7 +282,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
     int pslot = -1;               // the last segment's entry, stored once what follows it is known
     df pb = df_from(0.0f);        // that segment's end, extinction and colour
     float pk = 0.0f, pc0 = 0.0f, pc1 = 0.0f, pc2 = 0.0f;
-    int64_t tcur = 0, tend = 0;   // what is left of the wavefront's block of entries (wave-uniform)
+    int tcur = 0, tend = 0;   // what is left of the wavefront's block of entries (wave-uniform)
 
     for (;;) {
         const uint64_t idle = __ballot(!alive);
@@ -358,7 +340,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
         float delta = 0.0f, umid = 0.0f;
         df a = df_from(0.0f), b = df_from(0.0f);
         if (alive) {
-            leaf = walk_next<kWalkBudget>(tr, s_nodes, n_lds, path, kBlock, rs, w, delta, umid, a, b);
+            leaf = walk_next<kWalkBudget>(tr, rs, w, delta, umid, a, b);
             finish = leaf == -1;
         }
         // this iteration's entries: the segment, after a gap entry when it does
@@ -366,7 +348,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
         const bool gap = leaf >= 0 && (pslot < 0 || df_lt(pb, a));
         const uint64_t m1 = __ballot(leaf >= 0), m2 = __ballot(gap);
         const int n_e = __popcll(m1) + __popcll(m2);
-        const int64_t at = n_e > 0 ? take_items(ml.counter, ml.cap, cc.home, n_e, tcur, tend) : -1;
+        const int at = n_e > 0 ? take_items(ml.counter, ml.cap, cc.home, n_e, tcur, tend) : -1;
         if (leaf >= 0) {
             if (at < 0) {
                 first = -2;   // the room ran out: the fused kernel renders this ray

@@ -34,7 +34,6 @@ constexpr int ROW = ((3 * K + C + CG + 63) / 64) * 64;   // 128
 // wavefront-wide butterfly, which made longer strides pay, only runs for
 // samples without a record)
 constexpr int kWalkBudgetBwd = kWalkBudget;
-constexpr int kLdsNodes = 1024;
 constexpr float kPi = 3.14159265358979323846f;
 }  // namespace pp
 
@@ -166,15 +165,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) 
     TreeArgs tr, InstArgs in, RayArgs ra, float t_stop, RenderOut out) {
     if (no_candidates(ra)) return;
     using namespace pp;
-    __shared__ int4 s_nodes[kLdsNodes];
-    __shared__ int s_path[kMaxLevels * kBlock];
     __shared__ float s_brow[C], s_bgrow[CG];
     const bool common_t = ra.t == nullptr;
     if (common_t) stage_common_rows(tr, in, ra.t_scalar, s_brow, s_bgrow);
-    const int n_lds = stage_top_nodes<kLdsNodes>(tr, s_nodes);   // its barrier also covers the rows
+    __syncthreads();
     const float* s_b = common_t ? s_brow : nullptr;
     const float* s_bg = common_t ? s_bgrow : nullptr;
-    int* path = s_path + threadIdx.x;
     ChunkCursor cc = chunk_cursor();
     bool more = true;
 
@@ -186,7 +182,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) 
     float Tr = 1.0f, acc0 = 0.0f, acc1 = 0.0f, acc2 = 0.0f, wsum = 0.0f, dsum = 0.0f;
     int ns = 0;
     int t_first = -1;                // trace: the ray's first entry; -2: incomplete
-    int64_t tcur = 0, tend = 0;      // trace: what is left of the wavefront's block (wave-uniform)
+    int tcur = 0, tend = 0;      // trace: what is left of the wavefront's block (wave-uniform)
     const int64_t t_room = out.trace.cap / 2;
     // trace: the previous sample, stored once the slot of the next is known
     int pslot = -1, pleaf = 0;
@@ -243,14 +239,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) 
         int leaf = -1;
         float delta = 0.0f, umid = 0.0f;
         if (alive) {
-            leaf = walk_next<kWalkBudget>(tr, s_nodes, n_lds, path, kBlock, rs, w, delta, umid);
+            leaf = walk_next<kWalkBudget>(tr, rs, w, delta, umid);
             finish = leaf == -1;
         }
         int cur = -1;
         if constexpr (TRACE) {
             const uint64_t hm = __ballot(leaf >= 0);
             const int n_s = __popcll(hm);
-            const int64_t at = n_s > 0 ? take_items(out.trace.counter, t_room, cc.home, n_s, tcur, tend) : -1;
+            const int at = n_s > 0 ? take_items(out.trace.counter, t_room, cc.home, n_s, tcur, tend) : -1;
             if (leaf >= 0) {
                 if (at >= 0 && t_first != -2) {
                     cur = (int)(at + lane_rank(hm));
@@ -339,20 +335,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(REPLAY ?
     TreeArgs tr, InstArgs in, RayArgs ra, BackwardIO io, RecordArgs rec) {
     if (no_candidates(ra)) return;
     using namespace pp;
-    // a replaying launch does not walk: no node rows or paths
-    constexpr int kNodes = REPLAY ? 1 : kLdsNodes;
-    __shared__ int4 s_nodes[kNodes];
-    __shared__ int s_path[REPLAY ? 1 : kMaxLevels * kBlock];
     __shared__ float s_h[kBlock * K];
     __shared__ float s_brow[C], s_bgrow[CG];
     __shared__ float s_acc[2 * kWave];   // block sum of the lanes' basis-gradient components
     const bool common_t = ra.t == nullptr;
     if (common_t) stage_common_rows(tr, in, ra.t_scalar, s_brow, s_bgrow);
     if (threadIdx.x < 2 * kWave) s_acc[threadIdx.x] = 0.0f;
-    const int n_lds = stage_top_nodes<kNodes>(tr, s_nodes);
+    __syncthreads();
     const float* s_b = common_t ? s_brow : nullptr;
     const float* s_bg = common_t ? s_bgrow : nullptr;
-    int* path = s_path + threadIdx.x;
     ChunkCursor cc = chunk_cursor();
     bool more = true;
     const int64_t N = tr.n_leaves;
@@ -373,7 +364,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(REPLAY ?
     float bacc[2] = {0.0f, 0.0f};
     // records (scalar time only): [wrec, wend) is what is left of the
     // wavefront's current block of records (wave-uniform)
-    int64_t wrec = 0, wend = 0;
+    int wrec = 0, wend = 0;
 
     for (;;) {
         const uint64_t idle = __ballot(!alive);
@@ -447,7 +438,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(REPLAY ?
                 finish = leaf < 0;
             } else {
                 float umid;
-                leaf = walk_next<kWalkBudgetBwd>(tr, s_nodes, n_lds, path, kBlock, rs, w, delta, umid);
+                leaf = walk_next<kWalkBudgetBwd>(tr, rs, w, delta, umid);
                 finish = leaf == -1;
                 if (leaf >= 0) {
                     PPSample<DT> p;
@@ -496,7 +487,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(REPLAY ?
             // order; their leaf rows and basis gradients are summed per leaf later
             const uint64_t hm = __ballot(has);
             const int n_has = __popcll(hm);
-            const int64_t at = n_has > 0 ? take_items(rec.counter, rec.cap, cc.home, n_has, wrec, wend) : -1;
+            const int at = n_has > 0 ? take_items(rec.counter, rec.cap, cc.home, n_has, wrec, wend) : -1;
             if (at >= 0) {
                 const RecordRun run = record_run(hm, has, leaf);
                 if (has) {

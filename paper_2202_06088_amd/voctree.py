@@ -47,6 +47,7 @@ class VOctree:
     basis_g: Optional[torch.Tensor] = None  # [T, Cg] float32 hyperangle basis
     edit: Optional[torch.Tensor] = None     # [N, 8] float32 appearance-edit rows (slot order), or None
     density: int = _lib.DENSITY_SOFTPLUS    # activation of Eq. 5 (softplus, or ReLU as Eq. 5 prints it)
+    dir: Optional[torch.Tensor] = None      # brick directory of the node table (neuvv_build_directory)
 
     @classmethod
     def build(cls, depth: int, leaf_ijk, hh, wsig, basis, gamma, dtype: int = _lib.F32,
@@ -72,6 +73,7 @@ class VOctree:
                 torch.from_numpy(np.ascontiguousarray(gamma, np.float32)).to(dev),
                 torch.from_numpy(slots).to(dev), tuple(int(v) for v in box), layout)
         t.density = int(density)
+        t.build_directory(stream)
         wg = None
         if wgam is not None:
             wgam = np.ascontiguousarray(wgam, np.float32)
@@ -80,6 +82,13 @@ class VOctree:
             wg = torch.from_numpy(wgam).to(dev)
         t.set_payload(torch.from_numpy(hh).to(dev), torch.from_numpy(wsig).to(dev), wg, stream=stream)
         return t
+
+    def build_directory(self, stream=None):
+        """(Re)builds the brick directory the walk reads, from the device node table."""
+        n = _lib.neuvv_directory_entries(self.depth)
+        if self.dir is None or self.dir.numel() != n:
+            self.dir = torch.empty(n, dtype=torch.int32, device=self.nodes.device)
+        _lib.neuvv_build_directory(self.depth, int(self.nodes.shape[0]), self.nodes, self.dir, n, stream)
 
     def payload_elems(self, dtype: Optional[int] = None):
         return _lib.neuvv_payload_words(self.K, self.C, self.dtype if dtype is None else dtype, self.n_leaves)
@@ -119,6 +128,7 @@ class VOctree:
             s.wgam, s.basis_g = self.wgam.data_ptr(), self.basis_g.data_ptr()
         s.edit = None if self.edit is None else self.edit.data_ptr()
         s.density = self.density
+        s.dir = self.dir.data_ptr()
         return s
 
     def enable_edits(self):

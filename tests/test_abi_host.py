@@ -177,6 +177,15 @@ def test_argument_errors_without_launch(lib):
     # the compiled shapes of the global-hyperangle form (K in {14, 16, 30}, C in {8, 31}): a call
     # with no rays passes the checks and launches nothing
     t.nodes, t.basis, t.gamma = 16, 8, 8             # non-NULL placeholders, never dereferenced
+    t.K, t.C = 16, 8
+    assert lib.neuvv_render(ctypes.byref(t), None, 0, None, None, None, 0.0, 0, 0.0, None, None, None, None,
+                            None) == -1                 # the walk needs the brick directory
+    assert "dir" in _lib.neuvv_last_error()
+    t.dir = 6                                        # directory entries are 4-byte aligned
+    assert lib.neuvv_render(ctypes.byref(t), None, 0, None, None, None, 0.0, 0, 0.0, None, None, None, None,
+                            None) == -1
+    assert "aligned" in _lib.neuvv_last_error()
+    t.dir = 16
     for K in (14, 16, 30):
         for C in (8, 31):
             t.K, t.C = K, C
@@ -300,3 +309,19 @@ def test_argument_errors_without_launch(lib):
     assert (a, b) == (6 * 10 * 8, 1 * 10 * 8)
     a, b = _lib.neuvv_payload_words(14, 31, _lib.F32, 3)
     assert (a, b) == (11 * 3 * 4, 8 * 3 * 4)
+
+
+def test_directory_sizes_and_argument_errors(lib):
+    """Brick directory: E^3 entries with E = 2^(D-2) (1 for D <= 2); arguments checked before any
+    launch."""
+    assert [_lib.neuvv_directory_entries(d) for d in (1, 2, 3, 9, 10, 12)] == [1, 1, 8, 128 ** 3, 256 ** 3,
+                                                                              1024 ** 3]
+    for d in (0, 13):
+        assert lib.neuvv_directory_entries(d) == -1
+    assert lib.neuvv_build_directory(9, 1, 16, 16, 128 ** 3 - 1, None) == -4
+    assert "needs" in _lib.neuvv_last_error()
+    assert lib.neuvv_build_directory(13, 1, 16, 16, 1 << 40, None) == -2
+    assert lib.neuvv_build_directory(9, 0, 16, 16, 128 ** 3, None) == -2
+    assert lib.neuvv_build_directory(9, 1, None, 16, 128 ** 3, None) == -1
+    assert lib.neuvv_build_directory(9, 1, 8, 16, 128 ** 3, None) == -1
+    assert lib.neuvv_build_directory(9, 1, 16, 6, 128 ** 3, None) == -1

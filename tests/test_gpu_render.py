@@ -236,3 +236,70 @@ def test_leaf_rows_layout_same_results(tiny_scene, dtype):
     torch.cuda.synchronize()
     assert rel_err(grads[1][0].cpu().numpy(), grads[0][0].cpu().numpy()) < 1e-6
     assert rel_err(grads[1][1].cpu().numpy(), grads[0][1].cpu().numpy()) < 1e-6
+
+
+def _directory_expected(depth, leaf_ijk):
+    """The brick directory from its definition, on the occupancy grid alone: per 4^3 region, whether
+    it holds a leaf, and for one that holds none the largest s in [2, depth) such that the aligned
+    cube of edge 2^s around it holds none."""
+    G = 1 << depth
+    E = max(G >> 2, 1)
+    occ = np.zeros((G, G, G), bool)
+    occ[leaf_ijk[:, 2], leaf_ijk[:, 1], leaf_ijk[:, 0]] = True         # [z, y, x]
+    reg = occ.reshape(E, G // E, E, G // E, E, G // E).any(axis=(1, 3, 5)).ravel()   # entry (k E + j) E + i
+    k, j, i = np.unravel_index(np.arange(E ** 3), (E, E, E))
+    s = np.full(E ** 3, 2)
+    grow = ~reg
+    for lev in range(3, depth):
+        f = 1 << (lev - 2)                        # regions per cube edge at this size
+        n = E // f
+        cube = reg.reshape(n, f, n, f, n, f).any(axis=(1, 3, 5))
+        grow &= ~cube[k // f, j // f, i // f]
+        s = np.where(grow, lev, s)
+    return reg, s, occ
+
+
+@pytest.mark.parametrize("case", ["d1", "d2", "d3", "tiny", "forward"])
+def test_brick_directory_matches_its_definition(case):
+    """neuvv_build_directory bit for bit: regions that hold a leaf name their last-level node, whose
+    mask is the region's occupancy and whose leaves carry the input cells' slots; the others the
+    largest empty aligned cube around them (the walk's skip)."""
+    from paper_2202_06088_amd.voctree import build_node_table
+    rng = np.random.default_rng(71)
+    if case in ("d1", "d2", "d3"):
+        depth = int(case[1])
+        G = 1 << depth
+        cells = np.unique(rng.integers(0, G, (max(G ** 3 // 5, 1), 3)), axis=0).astype(np.int32)
+    else:
+        sc = scene_for_workload(case)
+        depth, cells = sc.depth, sc.leaf_ijk
+    nodes, slots = build_node_table(depth, cells)
+    n = _lib.neuvv_directory_entries(depth)
+    dn = torch.from_numpy(nodes).to(DEV)
+    dd = torch.full((n,), 12345, dtype=torch.int32, device=DEV)
+    announce(f"directory depth {depth}: {cells.shape[0]} leaves, {n} entries")
+    _lib.neuvv_build_directory(depth, nodes.shape[0], dn, dd, n)
+    torch.cuda.synchronize()
+    got = dd.cpu().numpy()
+    if depth <= 2:
+        assert np.array_equal(got, np.zeros(1, np.int32))     # the root is the only node
+        return
+    reg, s, occ = _directory_expected(depth, cells)
+    assert np.array_equal(got >= 0, reg)
+    assert np.array_equal(-got[~reg] - 1, s[~reg])
+    # bricks: mask bit q of the region's cell (x0 | y0<<1 | z0<<2 | x1<<3 | y1<<4 | z1<<5) set exactly
+    # where the cell holds a leaf, and that leaf's slot at base + rank
+    E = (1 << depth) >> 2
+    slot_at = {tuple(c): int(sl) for c, sl in zip(cells.tolist(), slots.tolist())}
+    idx = np.nonzero(reg)[0]
+    for r in rng.choice(idx, min(idx.size, 3000), replace=False):
+        row = nodes[got[r]]
+        m = (int(row[1]) & 0xffffffff) << 32 | (int(row[0]) & 0xffffffff)
+        bx, by, bz = 4 * (r % E), 4 * ((r // E) % E), 4 * (r // (E * E))
+        for q in range(64):
+            x = bx + (q & 1) + ((q >> 3) & 1) * 2
+            y = by + ((q >> 1) & 1) + ((q >> 4) & 1) * 2
+            z = bz + ((q >> 2) & 1) + ((q >> 5) & 1) * 2
+            assert bool((m >> q) & 1) == bool(occ[z, y, x])
+            if (m >> q) & 1:
+                assert int(row[2]) + bin(m & ((1 << q) - 1)).count("1") == slot_at[(x, y, z)]
