@@ -269,8 +269,9 @@ int neuvv_pack_rows(int32_t R, int32_t dtype, int32_t layout, int64_t n_leaves, 
  *
  * For ray r with world origin o, direction d (need not be unit) and time t:
  * the tree-local ray is x_l(u) = R^T (o + u d - trans) / scale, u >= 0; the
- * leaves it crosses are found by descending the octree, empty space being
- * skipped one empty node at a time; delta is the length of the ray inside a
+ * leaves it crosses are found in the octree (its last-level nodes through the
+ * tree's brick directory), empty space being skipped one empty octree node
+ * at a time; delta is the length of the ray inside a
  * leaf in leaf units (cells are half-open [i, i+1); zero-length crossings are
  * not samples). Per ray: h = the first K real HH at the unit local view
  * direction and gamma(tau), b = the density basis at tau, both linearly
